@@ -1,0 +1,146 @@
+"""Throughput of the fused lattice Boltzmann step on one MI355X.
+
+Workload: 4096 x 4096 periodic spinodal decomposition (phi0 i.i.d. uniform in [-0.05, 0.05]
+from SplitMix64 seed 1, rho = 1, v = 0, a = 0.04, gamma = 0.08, M = 0.1, Gamma = 1,
+nu = 0.05 in both phases), FP32 populations.  One step = one launch of the fused step kernel,
+which updates both population sets of every node (one LUP per node).
+
+Prints one JSON line: MLUPS over the timed steps (HIP events on the stream the kernel runs on),
+the HBM roofline of the step kernel (144 algorithmic bytes per LUP: 9 f + 9 g read, 9 f + 9 g
+written, 4 bytes each) and the FP64 CPU oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BASELINE_METRIC = "MLUPS & % of HBM peak (D2Q9 f+g); surrogate speedup at φ L2 err ≤1e-2"
+BYTES_PER_LUP = {"fp64": 288, "fp32": 144, "fp16s": 72, "bf16s": 72}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f32 (f16 storage)", "bf16s": "f32 (bf16 storage)"}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=4096, help="lattice side")
+    ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_LUP))
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps in the CPU sample (0 = skip)")
+    ap.add_argument("--copy-probe", action="store_true", help="also time a plain device copy")
+    return ap.parse_args()
+
+
+def cpu_baseline(n: int, steps: int) -> dict:
+    import numpy as np
+
+    import oracle
+    from paper_1803_11345_amd import inputs
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    p = oracle.Params(n, n, a=0.04, gamma=0.08, mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05,
+                      nthreads=threads)
+    f, g = oracle.init(p, inputs.spinodal(n, n, seed=1))
+    t0 = time.perf_counter()
+    f, g = oracle.run(p, f, g, steps)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(f).all()
+    return {"value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"FP64 oracle, {n}x{n} spinodal (same initial state), {steps} steps after "
+                      f"initialisation, {dt:.1f} s on {threads} OpenMP threads"}
+
+
+def copy_probe(nbytes: int = 1 << 31, reps: int = 20) -> float:
+    import torch
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    return 2 * nbytes / sec / 1e9
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU slab decomposition is a design note, not code", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1803_11345_amd import inputs, lbcm
+
+    torch.cuda.set_device(0)
+    n = args.n
+    phi0 = inputs.spinodal(n, n, seed=1)
+    lat = lbcm.Lattice(n, n, precision=args.precision, tile_rows=args.tile_rows, a=0.04, gamma=0.08,
+                       mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05)
+    lat.init(phi0)
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = lat.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    lat.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = e0.elapsed_time(e1)
+    sec_per_step = ms / 1e3 / args.steps
+    nodes = n * n
+    mlups = nodes / sec_per_step / 1e6
+    d = lat.diag()
+    assert d["nonfinite"] == 0, "non-finite state after the timed steps"
+    achieved = BYTES_PER_LUP[args.precision] * nodes / sec_per_step / 1e9
+    out = {
+        "metric": BASELINE_METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"spinodal decomposition {n}x{n} periodic D2Q9 f+g, "
+                               f"phi0 U[-0.05,0.05] seed 1, a=0.04 gamma=0.08 M=0.1 nu=0.05, "
+                               f"{args.precision} populations",
+                   "nx": n, "ny": n, "precision": args.precision, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step", "bytes_per_lup": BYTES_PER_LUP[args.precision]},
+        "wall_s_timed": round(wall, 3),
+        "sum_phi_drift": abs(d["sum_phi"] - float(np.sum(phi0))) / float(np.sum(np.abs(phi0))),
+    }
+    lat.close()
+    if args.copy_probe:
+        out["copy_probe_gbs"] = round(copy_probe(), 1)
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * lbcm — MI355X (gfx950) library for the hybrid central-moments / BGK lattice Boltzmann scheme
+ * for the coupled Cahn-Hilliard--Navier-Stokes equations of De Rosis, Saito, Kaneko and Abe,
+ * "Central-moments-based lattice Boltzmann scheme for coupled Cahn-Hilliard--Navier-Stokes
+ * equations" (arXiv:1803.11345).
+ *
+ * One handle owns one D2Q9 lattice of nx * ny nodes carrying two population sets: f (flow,
+ * collided in the non-orthogonal central-moment basis of Eq. (15) with relaxation Eq. (17))
+ * and g (order parameter, BGK relaxation Eq. (7) to the equilibrium of Eqs. (9)-(10)).
+ * One call of lbcm_step advances the whole lattice by one time step (Eqs. (4)-(5)).
+ *
+ * Conventions shared by every entry point
+ *   - Planes are row-major [ny][nx], x fastest, node (x, y) at index y * nx + x.
+ *   - Directions i = 0..8 follow the paper: c_x = {0,1,0,-1,0,1,-1,-1,1},
+ *     c_y = {0,0,1,0,-1,1,1,-1,-1}.
+ *   - Every call returns an int status (LBCM_OK or a negative LBCM_E* code); no exception
+ *     crosses the boundary.  After an error lbcm_last_error(h) returns a message.
+ *   - A handle is not thread-safe; separate handles are independent.  Work is queued on the
+ *     handle's HIP stream (params.stream, NULL = the null stream) and runs asynchronously
+ *     unless a call says it synchronises.
+ *   - Host pointers are only read or written during the call; the caller keeps ownership.
+ */
+#ifndef LBCM_H
+#define LBCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBCM_OK = 0,
+    LBCM_EINVAL = -1,    /* bad size, parameter or argument */
+    LBCM_ENOMEM = -2,    /* device allocation failed */
+    LBCM_EHIP = -3,      /* a HIP runtime call failed */
+    LBCM_EDIVERGED = -4, /* a non-finite density or order parameter was detected */
+    LBCM_ESTATE = -5     /* call out of order (e.g. step before init) */
+};
+
+enum { LBCM_BC_PERIODIC = 0, LBCM_BC_WALLS = 1 };
+
+/* Storage precision of the populations.  FP64 computes in double; the others compute in float. */
+enum {
+    LBCM_FP64 = 0,
+    LBCM_FP32 = 1,
+    LBCM_FP16_SHIFTED = 2, /* f_i - w_i and g_i - w_i phi_ref... stored as IEEE half */
+    LBCM_BF16_SHIFTED = 3  /* same offsets, stored as bfloat16 */
+};
+
+typedef struct lbcm_params {
+    int32_t nx, ny;      /* lattice size, >= 1 each */
+    int32_t bc_y;        /* LBCM_BC_PERIODIC, or LBCM_BC_WALLS: half-way bounce-back walls at
+                            y = -1/2 and y = ny - 1/2 for both f and g, phi mirrored into the
+                            ghost rows (zero normal gradient); x is always periodic */
+    int32_t precision;   /* LBCM_FP64 or LBCM_FP32 (others: see the enum) */
+    double a, gamma;     /* free-energy constants: mu = a(-phi + phi^3) - gamma Lap(phi) */
+    double mobility;     /* M = (1/omega_phi - 1/2) Gamma c_s^2 */
+    double Gamma;        /* Gamma of the g equilibrium, Eq. (9) */
+    double nu_l, nu_g;   /* kinematic viscosities at phi = +1 and phi = -1 */
+    double omega3;       /* relaxation rate of k3 (bulk viscosity), in (0, 2); 1 recommended */
+    double force_x, force_y; /* uniform body force (Guo half-step; 0 = the paper's scheme) */
+    int32_t k8_variant;  /* 0: k8 equilibrium from its definition (-gamma |grad phi|^2 / 6);
+                            1: the printed -gamma Lap(phi) / 6 of Eq. (16) */
+    int32_t check_every; /* > 0: lbcm_step synchronises every check_every steps and at its end
+                            and returns LBCM_EDIVERGED once a non-finite rho or phi was seen;
+                            0: no check (lbcm_diag still reports it) */
+    int32_t tile_rows;   /* rows per workgroup of the step kernel, 0 = default */
+    int32_t reserved0;
+    void *stream;        /* hipStream_t to queue work on; NULL = null stream */
+    void *workspace;     /* optional caller-owned device memory of lbcm_workspace_size() bytes,
+                            256-byte aligned; NULL = the library allocates and frees it */
+    size_t workspace_bytes;
+} lbcm_params;
+
+typedef struct lbcm_diagnostics {
+    double sum_phi;      /* sum of phi over the lattice (FP64 accumulation) */
+    double sum_abs_phi;  /* sum of |phi| */
+    double sum_rho;      /* sum of rho */
+    double sum_jx;       /* sum of rho v_x with v = (sum f c + F/2) / rho */
+    double sum_jy;
+    double max_u;        /* max |v| */
+    int64_t nonfinite;   /* number of nodes with a non-finite rho or phi */
+    int64_t step;        /* steps taken since lbcm_init */
+} lbcm_diagnostics;
+
+typedef struct lbcm_handle lbcm_handle;
+
+/* Device bytes needed for a lattice with these parameters (0 if the parameters are invalid). */
+size_t lbcm_workspace_size(const lbcm_params *p);
+
+/* Validate the parameters, allocate (or adopt) device memory and return a handle in *out.
+   Errors: LBCM_EINVAL (nx, ny < 1, plane larger than 4 GiB, nu <= 0, mobility <= 0, Gamma <= 0,
+   omega3 outside (0, 2), unknown bc/precision, workspace too small or misaligned),
+   LBCM_ENOMEM, LBCM_EHIP.  On error *out is NULL. */
+int lbcm_create(const lbcm_params *p, lbcm_handle **out);
+
+/* Set f = f^eq and g = g^eq of the given macroscopic state (Eqs. (8)-(10) with the gradient and
+   Laplacian of phi0 from Eq. (12)): host planes of nx * ny doubles.  rho0, ux0, uy0 may be NULL
+   (meaning 1, 0, 0).  Resets the step counter and the divergence flag.  Synchronises. */
+int lbcm_init(lbcm_handle *h, const double *phi0, const double *rho0, const double *ux0,
+              const double *uy0);
+
+/* As lbcm_init, with the planes in device memory (read on the handle's stream; asynchronous). */
+int lbcm_init_device(lbcm_handle *h, const double *phi0, const double *rho0, const double *ux0,
+                     const double *uy0);
+
+/* Queue nsteps >= 0 time steps (one fused kernel launch per step).  Asynchronous unless
+   check_every > 0.  Errors: LBCM_ESTATE before lbcm_init, LBCM_EINVAL for nsteps < 0,
+   LBCM_EDIVERGED (check_every > 0 only). */
+int lbcm_step(lbcm_handle *h, int64_t nsteps);
+
+/* Macroscopic fields of the current state into host planes of nx * ny doubles (any pointer may
+   be NULL): phi = sum g, rho = sum f, v = (sum f c + F/2) / rho and the bulk pressure p0 of
+   Eq. (13).  Synchronises. */
+int lbcm_fields(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy, double *p0);
+
+/* As lbcm_fields, into device planes (asynchronous). */
+int lbcm_fields_device(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy,
+                       double *p0);
+
+/* The post-streaming populations f_i(x, t) and g_i(x, t) of the current state (the state the
+   paper's step starts from) as 9 host planes each, FP64, layout [i][y][x]; either pointer may be
+   NULL.  Synchronises. */
+int lbcm_populations(lbcm_handle *h, double *f, double *g);
+
+/* FP64 reductions of the current state (deterministic order).  Synchronises. */
+int lbcm_diag(lbcm_handle *h, lbcm_diagnostics *out);
+
+/* Bytes of the raw population state: 18 planes (f_0..f_8 then g_0..g_8) in storage precision. */
+size_t lbcm_state_size(const lbcm_handle *h);
+
+/* Copy the raw populations out of / into the handle (host buffer of lbcm_state_size bytes;
+   values as stored, i.e. shifted for the *_SHIFTED precisions).  lbcm_set_state also marks the
+   handle initialised and sets the step counter to step.  Both synchronise. */
+int lbcm_get_state(lbcm_handle *h, void *host, size_t bytes);
+int lbcm_set_state(lbcm_handle *h, const void *host, size_t bytes, int64_t step);
+
+/* Free the handle and the memory it allocated (a caller workspace is left alone). */
+int lbcm_destroy(lbcm_handle *h);
+
+/* Message of the last error on h (or of the last failed lbcm_create when h is NULL). */
+const char *lbcm_last_error(const lbcm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBCM_H */

@@ -1,0 +1,1038 @@
+// lbcm: hybrid central-moments / BGK lattice Boltzmann step for the coupled
+// Cahn-Hilliard--Navier-Stokes equations (De Rosis, Saito, Kaneko, Abe, arXiv:1803.11345),
+// written for MI355X (gfx950, wave64).
+//
+// Data layout in HBM.  Each population set is 9 planes [i][y][x] (x fastest).  Two copies
+// ("pairs") of (f, g) live back to back in one workspace; a step reads pair `cur` and writes
+// pair 1 - cur.  Streaming is done by pulling: the stored value P[i](x) is the post-collision
+// population f*_i(x, t-1) at its origin node, and the post-streaming population of the paper,
+// f_i(x, t) = f*_i(x - c_i, t - 1) (Eqs. (4)-(5)), is read at x - c_i.  With walls, a link that
+// would come from outside is the same node's opposite post-collision value (half-way
+// bounce-back).  Every reader of the state (step, fields, diagnostics) pulls.
+//
+// The step kernel (k_step) is one fused pass per time step.  A workgroup is one wave of 64
+// lanes that owns a band of 64 columns and walks down a segment of rows.  For row y it
+//   1. pulls g of row y+1 and sums it into phi(y+1) (plus the two halo columns), kept in a
+//      4-row ring in LDS so that the 3x3 phi stencil of row y is available;
+//   2. pulls f of row y;
+//   3. evaluates grad phi and Lap phi (Eq. (12)), mu, p0, p~ and omega_rho;
+//   4. collides f in central moments (Eqs. (15)-(17)) and g with BGK (Eq. (7));
+//   5. stores f* and g* of row y at their own node (coalesced, non-temporal).
+// Each g value is pulled once per segment (+2 rows of priming), so HBM traffic stays near the
+// 36 values per node the step must move.
+//
+// The central-moment collision never forms the 9x9 matrix: the few pre-collision central
+// moments it needs (k3, k4, k5) come from raw moments, and the post-collision populations are
+// rebuilt by shifting the post-collision central moments back to raw moments (binomial
+// expansion in v) and inverting the raw-moment map of D2Q9, which factorises into the 1-D map
+// (m0, m1, m2) -> (f_0, f_+, f_-) = (m0 - m2, (m1 + m2)/2, (m2 - m1)/2) applied along x and y.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+
+#include "lbcm.h"
+
+namespace {
+
+constexpr int kTX = 64;           // lanes per workgroup: one wave, one column per lane
+constexpr int kDefaultRows = 64;  // rows per workgroup segment
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+constexpr int kDiagFields = 7;
+
+// ------------------------------------------------------------------------------------------
+// storage <-> compute precision
+
+template <class S> struct Io;
+template <> struct Io<double> {
+    using R = double;
+    static __device__ __forceinline__ R ld(const double *p) { return *p; }
+    static __device__ __forceinline__ void st(double *p, R v) { __builtin_nontemporal_store(v, p); }
+};
+template <> struct Io<float> {
+    using R = float;
+    static __device__ __forceinline__ R ld(const float *p) { return *p; }
+    static __device__ __forceinline__ void st(float *p, R v) { __builtin_nontemporal_store(v, p); }
+};
+
+// ------------------------------------------------------------------------------------------
+// parameters
+
+struct Geo {
+    int nx, ny;
+    uint32_t plane;  // nx * ny
+    int rows;        // rows per segment
+    int nbands, nsegs;
+    int walls;
+};
+
+template <class R> struct Phys {
+    R a, gamma, Gamma;
+    R w_mid, w_half;  // omega_rho = w_mid + w_half * phi
+    R w3, wphi;
+    R hFx, hFy;       // half of the body force
+    int k8_printed;
+};
+
+// ------------------------------------------------------------------------------------------
+// pull of the 9 post-streaming populations of node (x, y) from the stored post-collision
+// planes.  xl / xr are the periodic neighbours x - 1 / x + 1.  y is uniform across the wave.
+
+template <class S, bool WALLS>
+__device__ __forceinline__ void pull9(const S *__restrict__ P, uint32_t plane, int nx, int ny, int y,
+                                      int x, int xl, int xr, typename Io<S>::R v[9])
+{
+    using IO = Io<S>;
+    int yd = y - 1;  // source row of directions with c_y = +1 (2, 5, 6)
+    int yu = y + 1;  // source row of directions with c_y = -1 (4, 7, 8)
+    bool bot = false, top = false;
+    if (WALLS) {
+        bot = yd < 0;
+        top = yu >= ny;
+    } else {
+        if (yd < 0) yd += ny;
+        if (yu >= ny) yu -= ny;
+    }
+    const uint32_t r0 = (uint32_t)y * (uint32_t)nx;
+    const uint32_t rd = (uint32_t)yd * (uint32_t)nx;
+    const uint32_t ru = (uint32_t)yu * (uint32_t)nx;
+    const S *P0 = P, *P1 = P + (size_t)plane, *P2 = P + 2 * (size_t)plane, *P3 = P + 3 * (size_t)plane,
+            *P4 = P + 4 * (size_t)plane, *P5 = P + 5 * (size_t)plane, *P6 = P + 6 * (size_t)plane,
+            *P7 = P + 7 * (size_t)plane, *P8 = P + 8 * (size_t)plane;
+    v[0] = IO::ld(P0 + (r0 + x));
+    v[1] = IO::ld(P1 + (r0 + xl));
+    v[3] = IO::ld(P3 + (r0 + xr));
+    if (WALLS && bot) {
+        v[2] = IO::ld(P4 + (r0 + x));
+        v[5] = IO::ld(P7 + (r0 + x));
+        v[6] = IO::ld(P8 + (r0 + x));
+    } else {
+        v[2] = IO::ld(P2 + (rd + x));
+        v[5] = IO::ld(P5 + (rd + xl));
+        v[6] = IO::ld(P6 + (rd + xr));
+    }
+    if (WALLS && top) {
+        v[4] = IO::ld(P2 + (r0 + x));
+        v[7] = IO::ld(P5 + (r0 + x));
+        v[8] = IO::ld(P6 + (r0 + x));
+    } else {
+        v[4] = IO::ld(P4 + (ru + x));
+        v[7] = IO::ld(P7 + (ru + xr));
+        v[8] = IO::ld(P8 + (ru + xl));
+    }
+}
+
+template <class R> __device__ __forceinline__ R sum9(const R v[9])
+{
+    R s = v[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) s += v[i];
+    return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// populations from central moments.  k* = (rho, c10, c01, c20, c02, c11, c21, c12, c22) are the
+// central moments about v of the populations to build, in the plain monomial form
+// c_pq = sum f (c_x - v_x)^p (c_y - v_y)^q.
+
+template <class R>
+__device__ __forceinline__ void from_central(R rho, R ux, R uy, R c10, R c01, R c20, R c02, R c11,
+                                             R c21, R c12, R c22, R out[9])
+{
+    const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    // raw moments m_pq = sum f c_x^p c_y^q (binomial shift by v)
+    const R m10 = c10 + ux * rho;
+    const R m01 = c01 + uy * rho;
+    const R m20 = c20 + 2 * ux * c10 + ux2 * rho;
+    const R m02 = c02 + 2 * uy * c01 + uy2 * rho;
+    const R m11 = c11 + ux * c01 + uy * c10 + uxy * rho;
+    const R m21 = c21 + 2 * ux * c11 + uy * c20 + ux2 * c01 + 2 * uxy * c10 + ux2 * uy * rho;
+    const R m12 = c12 + 2 * uy * c11 + ux * c02 + uy2 * c10 + 2 * uxy * c01 + ux * uy2 * rho;
+    const R m22 = c22 + 2 * ux * c12 + 2 * uy * c21 + ux2 * c02 + uy2 * c20 + 4 * uxy * c11 +
+                  2 * ux * uy2 * c10 + 2 * ux2 * uy * c01 + ux2 * uy2 * rho;
+    // inverse along x for each y-order q: h_q(0), h_q(+1), h_q(-1)
+    const R h0z = rho - m20, h0p = (R)0.5 * (m10 + m20), h0m = (R)0.5 * (m20 - m10);
+    const R h1z = m01 - m21, h1p = (R)0.5 * (m11 + m21), h1m = (R)0.5 * (m21 - m11);
+    const R h2z = m02 - m22, h2p = (R)0.5 * (m12 + m22), h2m = (R)0.5 * (m22 - m12);
+    // inverse along y
+    out[0] = h0z - h2z;                 // ( 0,  0)
+    out[1] = h0p - h2p;                 // (+1,  0)
+    out[2] = (R)0.5 * (h1z + h2z);      // ( 0, +1)
+    out[3] = h0m - h2m;                 // (-1,  0)
+    out[4] = (R)0.5 * (h2z - h1z);      // ( 0, -1)
+    out[5] = (R)0.5 * (h1p + h2p);      // (+1, +1)
+    out[6] = (R)0.5 * (h1m + h2m);      // (-1, +1)
+    out[7] = (R)0.5 * (h2m - h1m);      // (-1, -1)
+    out[8] = (R)0.5 * (h2p - h1p);      // (+1, -1)
+}
+
+// Equilibrium central moments (the list ending in Eq. (16)), returned as
+// (c20, c02, c11, c21, c12, c22) = ((k3+k4)/2, (k3-k4)/2, k5, k6, k7, k8).
+template <class R>
+__device__ __forceinline__ void eq_central(R rho, R ux, R uy, R pt, R gamma, R dpx, R dpy, R surf,
+                                           R &k3, R &k4, R &k5, R &k6, R &k7, R &k8)
+{
+    const R third = (R)(1.0 / 3.0);
+    const R ux2 = ux * ux, uy2 = uy * uy;
+    k3 = 2 * pt;
+    k4 = gamma * (dpx * dpx - dpy * dpy);
+    k5 = gamma * dpx * dpy;
+    k6 = -(R)0.5 * uy * k4 - 2 * ux * k5 + rho * uy * (third - ux2) - pt * uy;
+    k7 = (R)0.5 * ux * k4 - 2 * uy * k5 + rho * ux * (third - uy2) - pt * ux;
+    k8 = pt * (third + ux2 + uy2) - rho * third * (ux2 + uy2) + 3 * rho * ux2 * uy2 -
+         (R)(1.0 / 6.0) * gamma * surf + (R)0.5 * k4 * (uy2 - ux2) + 4 * ux * uy * k5;
+}
+
+// g equilibrium (Eqs. (9)-(10)): w_i [Gamma mu + phi (3 c.v + 9/2 (c.v)^2 - 3/2 v^2)], i >= 1,
+// and g0 = phi - sum_{i>=1}, which is phi - (5/9) Gamma mu - (2/3) phi v^2.
+template <class R>
+__device__ __forceinline__ void g_equilibrium(R phi, R gmu, R ux, R uy, R out[9])
+{
+    const R w1 = (R)(1.0 / 9.0), w5 = (R)(1.0 / 36.0);
+    const R u2 = ux * ux + uy * uy;
+    const R base = gmu - (R)1.5 * phi * u2;
+    const R ax = 3 * phi * ux, ay = 3 * phi * uy;
+    const R qx = (R)4.5 * phi * ux * ux, qy = (R)4.5 * phi * uy * uy;
+    const R sp = ux + uy, sm = ux - uy;
+    const R a5 = 3 * phi * sp, a6 = 3 * phi * sm;  // (+1,+1) and (+1,-1) projections
+    const R q5 = (R)4.5 * phi * sp * sp, q6 = (R)4.5 * phi * sm * sm;
+    out[1] = w1 * (base + ax + qx);
+    out[3] = w1 * (base - ax + qx);
+    out[2] = w1 * (base + ay + qy);
+    out[4] = w1 * (base - ay + qy);
+    out[5] = w5 * (base + a5 + q5);
+    out[7] = w5 * (base - a5 + q5);
+    out[8] = w5 * (base + a6 + q6);
+    out[6] = w5 * (base - a6 + q6);
+    out[0] = phi - (R)(5.0 / 9.0) * gmu - (R)(2.0 / 3.0) * phi * u2;
+}
+
+// ------------------------------------------------------------------------------------------
+// one node: CM collision of f (Eq. (17)) and BGK of g (Eq. (7)).
+
+template <class R, bool FORCE>
+__device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, R dpx, R dpy,
+                                             R lap, const Phys<R> &c, R fo[9], R go[9],
+                                             R &rho_out)
+{
+    const R rho = sum9(f);
+    const R jx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
+    const R jy = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
+    const R irho = (R)1 / rho;
+    const R hFx = FORCE ? c.hFx : (R)0, hFy = FORCE ? c.hFy : (R)0;
+    const R ux = (jx + hFx) * irho, uy = (jy + hFy) * irho;
+    rho_out = rho;
+
+    // pre-collision central moments of second order (about v, with m10 = rho ux - hFx)
+    const R sxx = (f[1] + f[3]) + (f[5] + f[6]) + (f[7] + f[8]);
+    const R syy = (f[2] + f[4]) + (f[5] + f[6]) + (f[7] + f[8]);
+    const R sxy = (f[5] - f[6]) + (f[7] - f[8]);
+    R kxx = sxx - rho * ux * ux;
+    R kyy = syy - rho * uy * uy;
+    R kxy = sxy - rho * ux * uy;
+    if (FORCE) {
+        kxx += 2 * ux * hFx;
+        kyy += 2 * uy * hFy;
+        kxy += ux * hFy + uy * hFx;
+    }
+    const R k3 = kxx + kyy, k4 = kxx - kyy, k5 = kxy;
+
+    // thermodynamics
+    const R phi2 = phi * phi;
+    const R mu = c.a * phi * (phi2 - 1) - c.gamma * lap;
+    const R p0 = rho * (R)(1.0 / 3.0) + c.a * phi2 * ((R)0.75 * phi2 - (R)0.5);
+    const R pt = p0 - c.gamma * phi * lap;
+    const R wr = c.w_mid + c.w_half * phi;
+    const R surf = c.k8_printed ? lap : dpx * dpx + dpy * dpy;
+
+    R e3, e4, e5, e6, e7, e8;
+    eq_central(rho, ux, uy, pt, c.gamma, dpx, dpy, surf, e3, e4, e5, e6, e7, e8);
+
+    R s3 = k3 + c.w3 * (e3 - k3);
+    R s4 = k4 + wr * (e4 - k4);
+    R s5 = k5 + wr * (e5 - k5);
+    R s6 = e6, s7 = e7, s8 = e8;
+    if (FORCE) {
+        // central moments of Guo's forcing term, weighted by (1 - omega/2) = 1/2 for k6..k8
+        const R Fx = 2 * hFx, Fy = 2 * hFy;
+        const R third = (R)(1.0 / 3.0);
+        s6 += (R)0.5 * (Fy * (third - ux * ux) - 2 * Fx * ux * uy);
+        s7 += (R)0.5 * (Fx * (third - uy * uy) - 2 * Fy * ux * uy);
+        s8 += (R)0.5 * (4 * ux * uy * (Fx * uy + Fy * ux));
+    }
+    from_central(rho, ux, uy, hFx, hFy, (R)0.5 * (s3 + s4), (R)0.5 * (s3 - s4), s5, s6, s7, s8, fo);
+
+    R geq[9];
+    g_equilibrium(phi, c.Gamma * mu, ux, uy, geq);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) go[i] = g[i] + c.wphi * (geq[i] - g[i]);
+}
+
+// ------------------------------------------------------------------------------------------
+// blockIdx -> tile.  Workgroups are handed to the 8 XCDs round-robin; renumber them so that
+// each XCD gets a contiguous run of tiles (rows), and the halo rows/columns a workgroup shares
+// with its neighbours sit in the same L2.
+
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n >> 3, r = n & 7;
+    const int k = b & 7, j = b >> 3;
+    return k * q + (k < r ? k : r) + j;
+}
+
+template <class S, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(kTX) void k_step(const S *__restrict__ fa, const S *__restrict__ ga,
+                                              S *__restrict__ fb, S *__restrict__ gb, Geo geo,
+                                              Phys<typename Io<S>::R> c, int *__restrict__ flag)
+{
+    using R = typename Io<S>::R;
+    using IO = Io<S>;
+    __shared__ R phs[4][kTX + 2];
+
+    const int lane = threadIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int band = t % geo.nbands, seg = t / geo.nbands;
+    const int nx = geo.nx, ny = geo.ny;
+    const uint32_t plane = geo.plane;
+    const int x0 = band * kTX;
+    const int x1 = min(x0 + kTX, nx);
+    const int w = x1 - x0;
+    const bool valid = lane < w;
+    const int x = valid ? x0 + lane : x0;
+    const int xl = x == 0 ? nx - 1 : x - 1;
+    const int xr = x == nx - 1 ? 0 : x + 1;
+    // halo columns: lane 0 takes x0 - 1, lane 1 takes x1 (both periodic)
+    const int hx = lane == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x1 == nx ? 0 : x1);
+    const int hxl = hx == 0 ? nx - 1 : hx - 1;
+    const int hxr = hx == nx - 1 ? 0 : hx + 1;
+    const int hslot = lane == 0 ? 0 : w + 1;
+    const int y0 = seg * geo.rows;
+    const int y1 = min(y0 + geo.rows, ny);
+
+    // phi of row r (a valid row index) into ring slot s; the row's g is kept in gk.
+    auto phi_row = [&](int r, int s, R gk[9]) {
+        pull9<S, WALLS>(ga, plane, nx, ny, r, x, xl, xr, gk);
+        if (valid) phs[s][lane + 1] = sum9(gk);
+        if (lane < 2) {
+            R hv[9];
+            pull9<S, WALLS>(ga, plane, nx, ny, r, hx, hxl, hxr, hv);
+            phs[s][hslot] = sum9(hv);
+        }
+    };
+    auto mirror_row = [&](int from, int to) {
+        if (valid) phs[to][lane + 1] = phs[from][lane + 1];
+        if (lane < 2) phs[to][hslot] = phs[from][hslot];
+    };
+
+    R gc[9], gn[9];
+    // prime the ring: slot of row y is (y - y0 + 1) & 3
+    if (WALLS && y0 == 0) {
+        phi_row(0, 1, gc);
+        mirror_row(1, 0);
+    } else {
+        phi_row(y0 == 0 ? ny - 1 : y0 - 1, 0, gn);
+        phi_row(y0, 1, gc);
+    }
+
+    int flagged = 0;
+    for (int y = y0; y < y1; ++y) {
+        const int yn = y + 1;
+        const int sc = (y - y0 + 1) & 3, sn = (y - y0 + 2) & 3, sp = (y - y0) & 3;
+        if (WALLS && yn == ny) {
+            mirror_row(sc, sn);
+        } else {
+            phi_row(yn == ny ? 0 : yn, sn, gn);
+        }
+        R f[9];
+        pull9<S, WALLS>(fa, plane, nx, ny, y, x, xl, xr, f);
+        __syncthreads();
+
+        const int l = lane + 1;
+        const R pS = phs[sp][l], pSW = phs[sp][l - 1], pSE = phs[sp][l + 1];
+        const R pC = phs[sc][l], pW = phs[sc][l - 1], pE = phs[sc][l + 1];
+        const R pN = phs[sn][l], pNW = phs[sn][l - 1], pNE = phs[sn][l + 1];
+        const R dpx = ((R)4 * (pE - pW) + (pNE - pNW) + (pSE - pSW)) * (R)(1.0 / 12.0);
+        const R dpy = ((R)4 * (pN - pS) + (pNE - pSE) + (pNW - pSW)) * (R)(1.0 / 12.0);
+        const R lap = ((R)4 * ((pE + pW) + (pN + pS)) + ((pNE + pNW) + (pSE + pSW)) - (R)20 * pC) *
+                      (R)(1.0 / 6.0);
+
+        R fo[9], go[9], rho;
+        collide_node<R, FORCE>(f, gc, pC, dpx, dpy, lap, c, fo, go, rho);
+        if (!(std::isfinite(rho) && std::isfinite(pC))) flagged = 1;
+
+        if (valid) {
+            const uint32_t o = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                IO::st(fb + (size_t)i * plane + o, fo[i]);
+                IO::st(gb + (size_t)i * plane + o, go[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) gc[i] = gn[i];
+    }
+    if (__any(flagged && valid) && lane == 0) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------------------------------------------
+// initialisation.  k_equilibria computes the equilibria of the given macroscopic planes into
+// a post-streaming state (9 + 9 planes, node-local); k_unstream stores them in pull layout:
+// P[i](z) = F[i](z + c_i), or F[opp(i)](z) where z + c_i is behind a wall.
+
+template <class R>
+__device__ __forceinline__ double plane_at(const double *p, int nx, int ny, bool walls, int x, int y)
+{
+    x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    if (walls) {
+        y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+    } else {
+        y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    }
+    return p[(size_t)y * nx + x];
+}
+
+template <class S>
+__global__ void k_equilibria(const double *__restrict__ phi0, const double *__restrict__ rho0,
+                             const double *__restrict__ ux0, const double *__restrict__ uy0,
+                             S *__restrict__ F, S *__restrict__ G, Geo geo,
+                             Phys<typename Io<S>::R> c)
+{
+    using R = typename Io<S>::R;
+    const int nx = geo.nx, ny = geo.ny;
+    const size_t N = geo.plane;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(n / nx), x = (int)(n % nx);
+        const bool wl = geo.walls != 0;
+        double nb[3][3];
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) nb[dy + 1][dx + 1] = plane_at<R>(phi0, nx, ny, wl, x + dx, y + dy);
+        const R pC = (R)nb[1][1], pE = (R)nb[1][2], pW = (R)nb[1][0], pN = (R)nb[2][1], pS = (R)nb[0][1];
+        const R pNE = (R)nb[2][2], pNW = (R)nb[2][0], pSE = (R)nb[0][2], pSW = (R)nb[0][0];
+        const R dpx = ((R)4 * (pE - pW) + (pNE - pNW) + (pSE - pSW)) * (R)(1.0 / 12.0);
+        const R dpy = ((R)4 * (pN - pS) + (pNE - pSE) + (pNW - pSW)) * (R)(1.0 / 12.0);
+        const R lap = ((R)4 * ((pE + pW) + (pN + pS)) + ((pNE + pNW) + (pSE + pSW)) - (R)20 * pC) *
+                      (R)(1.0 / 6.0);
+        const R rho = rho0 ? (R)rho0[n] : (R)1;
+        const R ux = ux0 ? (R)ux0[n] : (R)0, uy = uy0 ? (R)uy0[n] : (R)0;
+        const R phi = pC;
+        const R phi2 = phi * phi;
+        const R mu = c.a * phi * (phi2 - 1) - c.gamma * lap;
+        const R pt = rho * (R)(1.0 / 3.0) + c.a * phi2 * ((R)0.75 * phi2 - (R)0.5) - c.gamma * phi * lap;
+        const R surf = c.k8_printed ? lap : dpx * dpx + dpy * dpy;
+        R e3, e4, e5, e6, e7, e8;
+        eq_central(rho, ux, uy, pt, c.gamma, dpx, dpy, surf, e3, e4, e5, e6, e7, e8);
+        R fe[9], ge[9];
+        from_central(rho, ux, uy, (R)0, (R)0, (R)0.5 * (e3 + e4), (R)0.5 * (e3 - e4), e5, e6, e7, e8, fe);
+        g_equilibrium(phi, c.Gamma * mu, ux, uy, ge);
+        for (int i = 0; i < 9; ++i) {
+            Io<S>::st(F + i * N + n, fe[i]);
+            Io<S>::st(G + i * N + n, ge[i]);
+        }
+    }
+}
+
+__constant__ int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int kCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__constant__ int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+template <class S>
+__global__ void k_unstream(const S *__restrict__ F, S *__restrict__ P, Geo geo)
+{
+    const int nx = geo.nx, ny = geo.ny;
+    const size_t N = geo.plane;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < 9 * N;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t / N);
+        const size_t n = t % N;
+        const int y = (int)(n / nx), x = (int)(n % nx);
+        int xs = x + kCX[i], ys = y + kCY[i];
+        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+        size_t src;
+        if (ys < 0 || ys >= ny) {
+            if (geo.walls) {
+                src = (size_t)kOpp[i] * N + n;
+            } else {
+                ys = ys < 0 ? ys + ny : ys - ny;
+                src = (size_t)i * N + (size_t)ys * nx + xs;
+            }
+        } else {
+            src = (size_t)i * N + (size_t)ys * nx + xs;
+        }
+        P[t] = F[src];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// readers: post-streaming populations, macroscopic fields and FP64 reductions.
+
+template <class S, bool WALLS>
+__device__ __forceinline__ void pull_node(const S *P, const Geo &geo, size_t n, typename Io<S>::R v[9])
+{
+    const int nx = geo.nx;
+    const int y = (int)(n / nx), x = (int)(n % nx);
+    const int xl = x == 0 ? nx - 1 : x - 1, xr = x == nx - 1 ? 0 : x + 1;
+    pull9<S, WALLS>(P, geo.plane, nx, geo.ny, y, x, xl, xr, v);
+}
+
+// which: bit 0 phi, 1 rho, 2 ux, 3 uy, 4 p0
+template <class S, bool WALLS>
+__global__ void k_fields(const S *__restrict__ f, const S *__restrict__ g, Geo geo,
+                         Phys<typename Io<S>::R> c, double *phi, double *rho, double *ux,
+                         double *uy, double *p0)
+{
+    using R = typename Io<S>::R;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
+         n += (size_t)gridDim.x * blockDim.x) {
+        R fv[9], gv[9];
+        pull_node<S, WALLS>(f, geo, n, fv);
+        pull_node<S, WALLS>(g, geo, n, gv);
+        const double r = (double)sum9(fv);
+        const double ph = (double)sum9(gv);
+        const double jx = (double)((fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7]));
+        const double jy = (double)((fv[2] + fv[5] + fv[6]) - (fv[4] + fv[7] + fv[8]));
+        if (phi) phi[n] = ph;
+        if (rho) rho[n] = r;
+        if (ux) ux[n] = (jx + (double)c.hFx) / r;
+        if (uy) uy[n] = (jy + (double)c.hFy) / r;
+        if (p0) p0[n] = r / 3.0 + (double)c.a * (-0.5 * ph * ph + 0.75 * ph * ph * ph * ph);
+    }
+}
+
+// one post-streaming population plane i (0..8 f, 9..17 g) as FP64
+template <class S, bool WALLS>
+__global__ void k_population(const S *__restrict__ f, const S *__restrict__ g, Geo geo, int which,
+                             double *out)
+{
+    using R = typename Io<S>::R;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
+         n += (size_t)gridDim.x * blockDim.x) {
+        R v[9];
+        pull_node<S, WALLS>(which < 9 ? f : g, geo, n, v);
+        out[n] = (double)v[which % 9];
+    }
+}
+
+template <class S, bool WALLS>
+__global__ __launch_bounds__(kReduceThreads) void k_diag(const S *__restrict__ f,
+                                                         const S *__restrict__ g, Geo geo,
+                                                         Phys<typename Io<S>::R> c, double *partial)
+{
+    using R = typename Io<S>::R;
+    double acc[kDiagFields] = {0, 0, 0, 0, 0, 0, 0};  // phi, |phi|, rho, jx, jy, max|u|, nonfinite
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
+         n += (size_t)gridDim.x * blockDim.x) {
+        R fv[9], gv[9];
+        pull_node<S, WALLS>(f, geo, n, fv);
+        pull_node<S, WALLS>(g, geo, n, gv);
+        const double r = (double)sum9(fv), ph = (double)sum9(gv);
+        const double jx = (double)((fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7])) + (double)c.hFx;
+        const double jy = (double)((fv[2] + fv[5] + fv[6]) - (fv[4] + fv[7] + fv[8])) + (double)c.hFy;
+        if (!(std::isfinite(r) && std::isfinite(ph))) {
+            acc[6] += 1;
+            continue;
+        }
+        acc[0] += ph;
+        acc[1] += fabs(ph);
+        acc[2] += r;
+        acc[3] += jx;
+        acc[4] += jy;
+        const double u = sqrt(jx * jx + jy * jy) / r;
+        acc[5] = fmax(acc[5], u);
+    }
+    __shared__ double red[kDiagFields][kReduceThreads];
+    for (int k = 0; k < kDiagFields; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < kDiagFields; ++k)
+                red[k][threadIdx.x] = k == 5 ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + s])
+                                             : red[k][threadIdx.x] + red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < kDiagFields) partial[blockIdx.x * kDiagFields + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_diag_finish(const double *partial, int nblocks,
+                                                                double *out)
+{
+    __shared__ double red[kDiagFields][kReduceThreads];
+    double acc[kDiagFields] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += kReduceThreads)
+        for (int k = 0; k < kDiagFields; ++k) {
+            const double v = partial[b * kDiagFields + k];
+            acc[k] = k == 5 ? fmax(acc[k], v) : acc[k] + v;
+        }
+    for (int k = 0; k < kDiagFields; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < kDiagFields; ++k)
+                red[k][threadIdx.x] = k == 5 ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + s])
+                                             : red[k][threadIdx.x] + red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < kDiagFields) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_clear_int(int *p) { *p = 0; }
+
+}  // namespace
+
+// ==========================================================================================
+// host side
+
+struct lbcm_handle {
+    lbcm_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t elem = 0;         // bytes per stored value
+    size_t pair_bytes = 0;   // bytes of one (f, g) pair
+    char *ws = nullptr;      // workspace base
+    bool owns_ws = false;
+    int cur = 0;             // pair holding the current state
+    bool ready = false;
+    int64_t step = 0;
+    double *diag_partial = nullptr;
+    double *diag_out = nullptr;
+    int *flag = nullptr;
+    std::string err;
+};
+
+namespace {
+
+std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+size_t elem_bytes(int precision)
+{
+    switch (precision) {
+    case LBCM_FP64: return 8;
+    case LBCM_FP32: return 4;
+    default: return 0;
+    }
+}
+
+const char *check_params(const lbcm_params *p)
+{
+    if (!p) return "params is NULL";
+    if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
+    if (p->bc_y != LBCM_BC_PERIODIC && p->bc_y != LBCM_BC_WALLS) return "bc_y must be 0 or 1";
+    if (elem_bytes(p->precision) == 0) return "unsupported precision";
+    const double N = (double)p->nx * (double)p->ny;
+    if (N * (double)elem_bytes(p->precision) > 4294967295.0)
+        return "lattice too large: one plane must stay below 4 GiB";
+    if (!(p->nu_l > 0) || !(p->nu_g > 0)) return "viscosities must be > 0";
+    if (!(p->mobility > 0) || !(p->Gamma > 0)) return "mobility and Gamma must be > 0";
+    if (!(p->omega3 > 0 && p->omega3 < 2)) return "omega3 must lie in (0, 2)";
+    if (!std::isfinite(p->a) || !std::isfinite(p->gamma) || !std::isfinite(p->force_x) ||
+        !std::isfinite(p->force_y))
+        return "a, gamma and the force must be finite";
+    if (p->k8_variant != 0 && p->k8_variant != 1) return "k8_variant must be 0 or 1";
+    if (p->check_every < 0) return "check_every must be >= 0";
+    if (p->tile_rows < 0) return "tile_rows must be >= 0";
+    return nullptr;
+}
+
+size_t pair_bytes_of(const lbcm_params *p)
+{
+    return align_up(18 * (size_t)p->nx * (size_t)p->ny * elem_bytes(p->precision));
+}
+
+size_t tail_bytes() { return align_up(kReduceBlocks * kDiagFields * sizeof(double)) + align_up(kDiagFields * sizeof(double)) + kAlign; }
+
+int fail(lbcm_handle *h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIP_TRY(h, call)                                                                      \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(h, LBCM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+template <class R> Phys<R> make_phys(const lbcm_params &p)
+{
+    const double cs2 = 1.0 / 3.0;
+    const double wl = 1.0 / (p.nu_l / cs2 + 0.5), wg = 1.0 / (p.nu_g / cs2 + 0.5);
+    Phys<R> c;
+    c.a = (R)p.a;
+    c.gamma = (R)p.gamma;
+    c.Gamma = (R)p.Gamma;
+    c.w_mid = (R)(0.5 * (wl + wg));
+    c.w_half = (R)(0.5 * (wl - wg));
+    c.w3 = (R)p.omega3;
+    c.wphi = (R)(1.0 / (p.mobility / (p.Gamma * cs2) + 0.5));
+    c.hFx = (R)(0.5 * p.force_x);
+    c.hFy = (R)(0.5 * p.force_y);
+    c.k8_printed = p.k8_variant;
+    return c;
+}
+
+Geo make_geo(const lbcm_params &p)
+{
+    Geo g;
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.plane = (uint32_t)((size_t)p.nx * p.ny);
+    g.rows = p.tile_rows > 0 ? p.tile_rows : kDefaultRows;
+    if (g.rows > p.ny) g.rows = p.ny;
+    g.nbands = (p.nx + kTX - 1) / kTX;
+    g.nsegs = (p.ny + g.rows - 1) / g.rows;
+    g.walls = p.bc_y;
+    return g;
+}
+
+template <class S> S *pop(lbcm_handle *h, int pair, int set)  // set 0 = f, 1 = g
+{
+    return reinterpret_cast<S *>(h->ws + (size_t)pair * h->pair_bytes) + (size_t)set * 9 * h->p.nx * (size_t)h->p.ny;
+}
+
+int grid_for(size_t n, int threads)
+{
+    size_t b = (n + threads - 1) / threads;
+    if (b > 65535) b = 65535;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <class S> int launch_steps(lbcm_handle *h, int64_t nsteps)
+{
+    using R = typename Io<S>::R;
+    const Geo geo = make_geo(h->p);
+    const Phys<R> c = make_phys<R>(h->p);
+    const bool walls = h->p.bc_y == LBCM_BC_WALLS;
+    const bool force = h->p.force_x != 0 || h->p.force_y != 0;
+    const int64_t nblk = (int64_t)geo.nbands * geo.nsegs;
+    if (nblk > 0x7fffffff) return fail(h, LBCM_EINVAL, "too many tiles");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const S *fa = pop<S>(h, h->cur, 0), *ga = pop<S>(h, h->cur, 1);
+        S *fb = pop<S>(h, 1 - h->cur, 0), *gb = pop<S>(h, 1 - h->cur, 1);
+        dim3 grid((unsigned)nblk), block(kTX);
+        if (walls) {
+            if (force) hipLaunchKernelGGL((k_step<S, true, true>), grid, block, 0, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            else hipLaunchKernelGGL((k_step<S, true, false>), grid, block, 0, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+        } else {
+            if (force) hipLaunchKernelGGL((k_step<S, false, true>), grid, block, 0, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            else hipLaunchKernelGGL((k_step<S, false, false>), grid, block, 0, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+        }
+        HIP_TRY(h, hipGetLastError());
+        h->cur = 1 - h->cur;
+        h->step += 1;
+        if (h->p.check_every > 0 && ((s + 1) % h->p.check_every == 0 || s + 1 == nsteps)) {
+            int flag = 0;
+            HIP_TRY(h, hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            if (flag) return fail(h, LBCM_EDIVERGED, "non-finite rho or phi detected at step " + std::to_string(h->step));
+        }
+    }
+    return LBCM_OK;
+}
+
+template <class S>
+int do_init(lbcm_handle *h, const double *phi0, const double *rho0, const double *ux0, const double *uy0)
+{
+    using R = typename Io<S>::R;
+    const Geo geo = make_geo(h->p);
+    const Phys<R> c = make_phys<R>(h->p);
+    // equilibria into the spare pair, then un-stream into pair 0
+    S *F = pop<S>(h, 1, 0), *G = pop<S>(h, 1, 1);
+    const int gb = grid_for(geo.plane, 256);
+    hipLaunchKernelGGL((k_equilibria<S>), dim3(gb), dim3(256), 0, h->stream, phi0, rho0, ux0, uy0, F, G, geo, c);
+    HIP_TRY(h, hipGetLastError());
+    const int gu = grid_for(9 * (size_t)geo.plane, 256);
+    hipLaunchKernelGGL((k_unstream<S>), dim3(gu), dim3(256), 0, h->stream, F, pop<S>(h, 0, 0), geo);
+    HIP_TRY(h, hipGetLastError());
+    hipLaunchKernelGGL((k_unstream<S>), dim3(gu), dim3(256), 0, h->stream, G, pop<S>(h, 0, 1), geo);
+    HIP_TRY(h, hipGetLastError());
+    hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(1), 0, h->stream, h->flag);
+    HIP_TRY(h, hipGetLastError());
+    h->cur = 0;
+    h->step = 0;
+    h->ready = true;
+    return LBCM_OK;
+}
+
+template <class S>
+int do_fields(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy, double *p0)
+{
+    using R = typename Io<S>::R;
+    const Geo geo = make_geo(h->p);
+    const Phys<R> c = make_phys<R>(h->p);
+    const int gb = grid_for(geo.plane, 256);
+    const S *f = pop<S>(h, h->cur, 0), *g = pop<S>(h, h->cur, 1);
+    if (h->p.bc_y == LBCM_BC_WALLS)
+        hipLaunchKernelGGL((k_fields<S, true>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, c, phi, rho, ux, uy, p0);
+    else
+        hipLaunchKernelGGL((k_fields<S, false>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, c, phi, rho, ux, uy, p0);
+    HIP_TRY(h, hipGetLastError());
+    return LBCM_OK;
+}
+
+template <class S> int do_population(lbcm_handle *h, int which, double *out)
+{
+    const Geo geo = make_geo(h->p);
+    const int gb = grid_for(geo.plane, 256);
+    const S *f = pop<S>(h, h->cur, 0), *g = pop<S>(h, h->cur, 1);
+    if (h->p.bc_y == LBCM_BC_WALLS)
+        hipLaunchKernelGGL((k_population<S, true>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, which, out);
+    else
+        hipLaunchKernelGGL((k_population<S, false>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, which, out);
+    HIP_TRY(h, hipGetLastError());
+    return LBCM_OK;
+}
+
+template <class S> int do_diag(lbcm_handle *h)
+{
+    using R = typename Io<S>::R;
+    const Geo geo = make_geo(h->p);
+    const Phys<R> c = make_phys<R>(h->p);
+    const S *f = pop<S>(h, h->cur, 0), *g = pop<S>(h, h->cur, 1);
+    if (h->p.bc_y == LBCM_BC_WALLS)
+        hipLaunchKernelGGL((k_diag<S, true>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, h->stream, f, g, geo, c, h->diag_partial);
+    else
+        hipLaunchKernelGGL((k_diag<S, false>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, h->stream, f, g, geo, c, h->diag_partial);
+    HIP_TRY(h, hipGetLastError());
+    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(kReduceThreads), 0, h->stream, h->diag_partial, kReduceBlocks, h->diag_out);
+    HIP_TRY(h, hipGetLastError());
+    return LBCM_OK;
+}
+
+// host-side dispatch on the storage precision
+template <class Fn> int dispatch(lbcm_handle *h, Fn &&fn)
+{
+    switch (h->p.precision) {
+    case LBCM_FP64: return fn((double *)nullptr);
+    case LBCM_FP32: return fn((float *)nullptr);
+    default: return fail(h, LBCM_EINVAL, "unsupported precision");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbcm_workspace_size(const lbcm_params *p)
+{
+    if (check_params(p)) return 0;
+    return 2 * pair_bytes_of(p) + tail_bytes();
+}
+
+int lbcm_create(const lbcm_params *p, lbcm_handle **out)
+{
+    if (!out) {
+        g_create_error = "out is NULL";
+        return LBCM_EINVAL;
+    }
+    *out = nullptr;
+    if (const char *m = check_params(p)) {
+        g_create_error = m;
+        return LBCM_EINVAL;
+    }
+    const size_t need = lbcm_workspace_size(p);
+    if (p->workspace) {
+        if (p->workspace_bytes < need) {
+            g_create_error = "workspace too small: need " + std::to_string(need) + " bytes";
+            return LBCM_EINVAL;
+        }
+        if ((uintptr_t)p->workspace % kAlign) {
+            g_create_error = "workspace must be 256-byte aligned";
+            return LBCM_EINVAL;
+        }
+    }
+    lbcm_handle *h = new (std::nothrow) lbcm_handle();
+    if (!h) {
+        g_create_error = "out of host memory";
+        return LBCM_ENOMEM;
+    }
+    h->p = *p;
+    h->stream = (hipStream_t)p->stream;
+    h->elem = elem_bytes(p->precision);
+    h->pair_bytes = pair_bytes_of(p);
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        delete h;
+        return LBCM_EHIP;
+    }
+    if (p->workspace) {
+        h->ws = (char *)p->workspace;
+    } else {
+        e = hipMalloc((void **)&h->ws, need);
+        if (e != hipSuccess) {
+            g_create_error = std::string("hipMalloc(") + std::to_string(need) + "): " + hipGetErrorString(e);
+            (void)hipGetLastError();
+            delete h;
+            return e == hipErrorOutOfMemory ? LBCM_ENOMEM : LBCM_EHIP;
+        }
+        h->owns_ws = true;
+    }
+    char *tail = h->ws + 2 * h->pair_bytes;
+    h->diag_partial = (double *)tail;
+    tail += align_up(kReduceBlocks * kDiagFields * sizeof(double));
+    h->diag_out = (double *)tail;
+    tail += align_up(kDiagFields * sizeof(double));
+    h->flag = (int *)tail;
+    *out = h;
+    return LBCM_OK;
+}
+
+int lbcm_init_device(lbcm_handle *h, const double *phi0, const double *rho0, const double *ux0, const double *uy0)
+{
+    if (!h) return LBCM_EINVAL;
+    if (!phi0) return fail(h, LBCM_EINVAL, "phi0 is NULL");
+    return dispatch(h, [&](auto *tag) { return do_init<std::remove_pointer_t<decltype(tag)>>(h, phi0, rho0, ux0, uy0); });
+}
+
+int lbcm_init(lbcm_handle *h, const double *phi0, const double *rho0, const double *ux0, const double *uy0)
+{
+    if (!h) return LBCM_EINVAL;
+    if (!phi0) return fail(h, LBCM_EINVAL, "phi0 is NULL");
+    // stage the host planes in pair 0 (overwritten only by the final un-stream of the init)
+    const size_t N = (size_t)h->p.nx * h->p.ny;
+    double *stage = (double *)h->ws;
+    const double *src[4] = {phi0, rho0, ux0, uy0};
+    const double *dev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 4; ++k) {
+        if (!src[k]) continue;
+        HIP_TRY(h, hipMemcpyAsync(stage + k * N, src[k], N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        dev[k] = stage + k * N;
+    }
+    int rc = lbcm_init_device(h, dev[0], dev[1], dev[2], dev[3]);
+    if (rc) return rc;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return LBCM_OK;
+}
+
+int lbcm_step(lbcm_handle *h, int64_t nsteps)
+{
+    if (!h) return LBCM_EINVAL;
+    if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_step before lbcm_init");
+    if (nsteps < 0) return fail(h, LBCM_EINVAL, "nsteps must be >= 0");
+    return dispatch(h, [&](auto *tag) { return launch_steps<std::remove_pointer_t<decltype(tag)>>(h, nsteps); });
+}
+
+int lbcm_fields_device(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy, double *p0)
+{
+    if (!h) return LBCM_EINVAL;
+    if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_fields before lbcm_init");
+    return dispatch(h, [&](auto *tag) { return do_fields<std::remove_pointer_t<decltype(tag)>>(h, phi, rho, ux, uy, p0); });
+}
+
+int lbcm_fields(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy, double *p0)
+{
+    if (!h) return LBCM_EINVAL;
+    if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_fields before lbcm_init");
+    // one plane at a time through the spare pair (>= 8 bytes per node for every precision)
+    const size_t N = (size_t)h->p.nx * h->p.ny;
+    double *stage = (double *)(h->ws + (size_t)(1 - h->cur) * h->pair_bytes);
+    double *dst[5] = {phi, rho, ux, uy, p0};
+    for (int k = 0; k < 5; ++k) {
+        if (!dst[k]) continue;
+        double *d[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        d[k] = stage;
+        int rc = lbcm_fields_device(h, d[0], d[1], d[2], d[3], d[4]);
+        if (rc) return rc;
+        HIP_TRY(h, hipMemcpyAsync(dst[k], stage, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    return LBCM_OK;
+}
+
+int lbcm_populations(lbcm_handle *h, double *f, double *g)
+{
+    if (!h) return LBCM_EINVAL;
+    if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_populations before lbcm_init");
+    const size_t N = (size_t)h->p.nx * h->p.ny;
+    double *stage = (double *)(h->ws + (size_t)(1 - h->cur) * h->pair_bytes);
+    for (int k = 0; k < 18; ++k) {
+        double *dst = k < 9 ? f : g;
+        if (!dst) continue;
+        int rc = dispatch(h, [&](auto *tag) { return do_population<std::remove_pointer_t<decltype(tag)>>(h, k, stage); });
+        if (rc) return rc;
+        HIP_TRY(h, hipMemcpyAsync(dst + (size_t)(k % 9) * N, stage, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    return LBCM_OK;
+}
+
+int lbcm_diag(lbcm_handle *h, lbcm_diagnostics *out)
+{
+    if (!h || !out) return fail(h, LBCM_EINVAL, "NULL argument");
+    if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_diag before lbcm_init");
+    int rc = dispatch(h, [&](auto *tag) { return do_diag<std::remove_pointer_t<decltype(tag)>>(h); });
+    if (rc) return rc;
+    double v[kDiagFields];
+    HIP_TRY(h, hipMemcpyAsync(v, h->diag_out, sizeof v, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out->sum_phi = v[0];
+    out->sum_abs_phi = v[1];
+    out->sum_rho = v[2];
+    out->sum_jx = v[3];
+    out->sum_jy = v[4];
+    out->max_u = v[5];
+    out->nonfinite = (int64_t)v[6];
+    out->step = h->step;
+    return LBCM_OK;
+}
+
+size_t lbcm_state_size(const lbcm_handle *h)
+{
+    return h ? 18 * (size_t)h->p.nx * h->p.ny * h->elem : 0;
+}
+
+int lbcm_get_state(lbcm_handle *h, void *host, size_t bytes)
+{
+    if (!h || !host) return fail(h, LBCM_EINVAL, "NULL argument");
+    if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_get_state before lbcm_init");
+    if (bytes != lbcm_state_size(h)) return fail(h, LBCM_EINVAL, "wrong state size");
+    HIP_TRY(h, hipMemcpyAsync(host, h->ws + (size_t)h->cur * h->pair_bytes, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return LBCM_OK;
+}
+
+int lbcm_set_state(lbcm_handle *h, const void *host, size_t bytes, int64_t step)
+{
+    if (!h || !host) return fail(h, LBCM_EINVAL, "NULL argument");
+    if (bytes != lbcm_state_size(h)) return fail(h, LBCM_EINVAL, "wrong state size");
+    if (step < 0) return fail(h, LBCM_EINVAL, "step must be >= 0");
+    HIP_TRY(h, hipMemcpyAsync(h->ws + (size_t)h->cur * h->pair_bytes, host, bytes, hipMemcpyHostToDevice, h->stream));
+    hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(1), 0, h->stream, h->flag);
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->ready = true;
+    h->step = step;
+    return LBCM_OK;
+}
+
+int lbcm_destroy(lbcm_handle *h)
+{
+    if (!h) return LBCM_OK;
+    int rc = LBCM_OK;
+    if (h->owns_ws && h->ws) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) rc = LBCM_EHIP;
+        if (hipFree(h->ws) != hipSuccess) rc = LBCM_EHIP;
+    }
+    delete h;
+    return rc;
+}
+
+const char *lbcm_last_error(const lbcm_handle *h)
+{
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every entry point
+that include/lbcm.h declares, sizes workspaces, and rejects bad parameters before touching a
+device."""
+import ctypes
+import subprocess
+
+import pytest
+
+from paper_1803_11345_amd import lbcm
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbcm.load()
+    names = lbcm.declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", lbcm.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(names) <= exported
+
+
+def test_library_has_no_oracle_dependency():
+    out = subprocess.run(["ldd", lbcm.LIB_PATH], capture_output=True, text=True).stdout
+    assert "oracle" not in out
+    nm = subprocess.run(["nm", "-D", lbcm.LIB_PATH], capture_output=True, text=True).stdout
+    assert "orc_" not in nm
+
+
+def test_struct_layout_matches_header():
+    # int32 x4, double x9, int32 x4, two pointers and a size_t
+    assert ctypes.sizeof(lbcm.lbcm_params) == 16 + 72 + 16 + 24
+    assert ctypes.sizeof(lbcm.lbcm_diagnostics) == 8 * 8
+
+
+@pytest.mark.parametrize("prec,elem", [("fp64", 8), ("fp32", 4)])
+def test_workspace_size(prec, elem):
+    nx, ny = 100, 37
+    ws = lbcm.lbcm_workspace_size(lbcm.make_params(nx, ny, precision=prec))
+    pops = 2 * 18 * nx * ny * elem
+    assert pops <= ws <= pops + 2 * 256 + 128 * 1024
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(nx=0, ny=4), "nx and ny"),
+    (dict(nx=4, ny=-1), "nx and ny"),
+    (dict(nx=4, ny=4, nu_l=0.0), "viscosities"),
+    (dict(nx=4, ny=4, nu_g=-1.0), "viscosities"),
+    (dict(nx=4, ny=4, mobility=0.0), "mobility"),
+    (dict(nx=4, ny=4, omega3=2.0), "omega3"),
+    (dict(nx=4, ny=4, bc_y=2), "bc_y"),
+    (dict(nx=4, ny=4, precision=7), "precision"),
+    (dict(nx=4, ny=4, k8_variant=3), "k8_variant"),
+    (dict(nx=4, ny=4, a=float("nan")), "finite"),
+    (dict(nx=70000, ny=70000, precision="fp32"), "too large"),
+])
+def test_bad_params_rejected_on_host(kw, frag):
+    nx, ny = kw.pop("nx"), kw.pop("ny")
+    p = lbcm.make_params(nx, ny, **kw)
+    assert lbcm.lbcm_workspace_size(p) == 0
+    with pytest.raises(lbcm.LbcmError) as e:
+        lbcm.lbcm_create(p)
+    assert e.value.code == lbcm.LBCM_EINVAL
+    assert frag in str(e.value)
+
+
+def test_small_workspace_rejected():
+    p = lbcm.make_params(8, 8)
+    need = lbcm.lbcm_workspace_size(p)
+    p.workspace = 256 * 1024
+    p.workspace_bytes = need - 1
+    with pytest.raises(lbcm.LbcmError, match="too small"):
+        lbcm.lbcm_create(p)
+
+
+def test_misaligned_workspace_rejected():
+    p = lbcm.make_params(8, 8)
+    p.workspace = 256 * 1024 + 8
+    p.workspace_bytes = 1 << 30
+    with pytest.raises(lbcm.LbcmError, match="aligned"):
+        lbcm.lbcm_create(p)
+
+
+def test_null_handle_calls_are_rejected():
+    lib = lbcm.load()
+    assert lib.lbcm_step(None, 1) == lbcm.LBCM_EINVAL
+    assert lib.lbcm_destroy(None) == lbcm.LBCM_OK
+    assert lib.lbcm_state_size(None) == 0

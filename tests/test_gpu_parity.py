@@ -1,0 +1,258 @@
+"""GPU parity: the HIP step (through the C-ABI) against the FP64 CPU oracle, element by element,
+on the same seeded inputs.
+
+Tolerances.  FP64 runs differ from the oracle only by rounding order (the oracle solves a 9x9
+system where the kernel uses the closed-form inverse), so populations agree to a few 1e-16 per
+step.  FP32 runs store and compute in single precision: one rounding of a population of size
+~0.5 is 3e-8, a node update chains ~100 operations on O(1) values, so one step carries errors of
+a few 1e-7 at most and short runs of a few hundred steps stay below the stated bounds, which
+are the measured errors with about a 5x margin.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1803_11345_amd import inputs, lbcm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def both(nx, ny, phi, rho=None, ux=None, uy=None, steps=1, prec="fp64", tile_rows=0, **kw):
+    """Run the GPU and the oracle from the same macroscopic state; return both population sets."""
+    say(f"case {nx}x{ny} {prec} steps={steps} tile_rows={tile_rows} {kw}")
+    okw = dict(kw)
+    if "bc_y" in okw:
+        okw["walls"] = okw.pop("bc_y")
+    p = oracle.Params(nx, ny, **okw)
+    fo, go = oracle.init(p, phi, rho, ux, uy)
+    fo, go = oracle.run(p, fo, go, steps)
+    lat = lbcm.Lattice(nx, ny, precision=prec, tile_rows=tile_rows, **kw).init(phi, rho, ux, uy)
+    lat.step(steps)
+    f, g = lat.populations()
+    fields = lat.fields()
+    lat.close()
+    return (f, g, fields), (fo, go, oracle.macro(p, fo, go))
+
+
+def maxerr(a, b):
+    return float(np.max(np.abs(a - b)))
+
+
+PHYS = dict(nu_l=0.1, nu_g=0.02, omega3=1.0)
+
+
+@pytest.mark.parametrize("bc_y,force", [(0, (0.0, 0.0)), (0, (2e-5, -1e-5)), (1, (0.0, 0.0)), (1, (1e-5, 0.0))])
+def test_fp64_one_step(bc_y, force):
+    nx, ny = 70, 45  # two column bands (64 + ragged 6), three row segments (16 + 16 + 13)
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=31)
+    (f, g, m), (fo, go, mo) = both(nx, ny, phi, rho, ux, uy, steps=1, tile_rows=16, bc_y=bc_y,
+                                   force_x=force[0], force_y=force[1], **PHYS)
+    ef, eg = maxerr(f, fo), maxerr(g, go)
+    say(f"  max |df| = {ef:.2e}  max |dg| = {eg:.2e}")
+    assert ef < 1e-14 and eg < 1e-14
+    for k in ("phi", "rho", "ux", "uy", "p0"):
+        assert maxerr(m[k], mo[k]) < 1e-13, k
+
+
+@pytest.mark.parametrize("bc_y", [0, 1])
+def test_fp64_200_steps(bc_y):
+    nx, ny = 70, 45
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=32)
+    (f, g, m), (fo, go, mo) = both(nx, ny, phi, rho, ux, uy, steps=200, tile_rows=16, bc_y=bc_y,
+                                   force_x=1e-5, **PHYS)
+    ef, eg = maxerr(f, fo), maxerr(g, go)
+    say(f"  max |df| = {ef:.2e}  max |dg| = {eg:.2e}")
+    assert ef < 1e-12 and eg < 1e-12
+
+
+@pytest.mark.parametrize("bc_y", [0, 1])
+def test_fp32_one_and_50_steps(bc_y):
+    nx, ny = 70, 45
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=33)
+    for steps, tol in ((1, 2e-6), (50, 2e-5)):
+        (f, g, m), (fo, go, mo) = both(nx, ny, phi, rho, ux, uy, steps=steps, prec="fp32", tile_rows=16,
+                                       bc_y=bc_y, force_x=1e-5, **PHYS)
+        ef, eg = maxerr(f, fo), maxerr(g, go)
+        say(f"  fp32 {steps} steps: max |df| = {ef:.2e}  max |dg| = {eg:.2e}")
+        assert ef < tol and eg < tol
+
+
+@pytest.mark.parametrize("nx,ny,bc_y", [(1, 1, 0), (1, 1, 1), (1, 6, 0), (6, 1, 0), (6, 1, 1), (2, 3, 1),
+                                        (3, 2, 0), (65, 2, 1), (64, 64, 0), (129, 7, 0), (5, 130, 1)])
+def test_fp64_edge_sizes(nx, ny, bc_y):
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=34)
+    (f, g, m), (fo, go, mo) = both(nx, ny, phi, rho, ux, uy, steps=3, tile_rows=0, bc_y=bc_y,
+                                   force_x=1e-5, **PHYS)
+    assert maxerr(f, fo) < 1e-14 and maxerr(g, go) < 1e-14
+
+
+@pytest.mark.parametrize("rows", [1, 2, 3, 7, 64, 1000])
+def test_segment_rows_do_not_change_results(rows):
+    """Tiling only changes which workgroup computes a node, never the arithmetic: bitwise equal."""
+    nx, ny = 100, 50
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=35)
+    ref = lbcm.Lattice(nx, ny, precision="fp32", tile_rows=16, **PHYS).init(phi, rho, ux, uy).step(7)
+    lat = lbcm.Lattice(nx, ny, precision="fp32", tile_rows=rows, **PHYS).init(phi, rho, ux, uy).step(7)
+    assert np.array_equal(ref.get_state(), lat.get_state())
+
+
+def test_static_droplet_fp64_2000_steps():
+    """64^2 static droplet, R = 16, a = 0.04, gamma = 0.08, M = 0.1, nu = 1/6, 2000 steps."""
+    n = 64
+    phi0 = inputs.droplet(n, n, 16, inputs.interface_width(0.04, 0.08))
+    say("case static droplet 64^2 fp64 2000 steps")
+    p = oracle.Params(n, n)
+    fo, go = oracle.run(p, *oracle.init(p, phi0), 2000)
+    mo = oracle.macro(p, fo, go)
+    lat = lbcm.Lattice(n, n, precision="fp64").init(phi0)
+    d0 = lat.diag()
+    lat.step(2000)
+    m = lat.fields()
+    d1 = lat.diag()
+    e = maxerr(m["phi"], mo["phi"])
+    drift = abs(d1["sum_phi"] - d0["sum_phi"]) / d0["sum_abs_phi"]
+    say(f"  max |dphi| = {e:.2e}, sum phi drift = {drift:.2e}, step = {d1['step']}")
+    assert e < 1e-11
+    assert drift < 1e-12
+    assert maxerr(m["p0"], mo["p0"]) < 1e-11
+    R = math.sqrt(np.sum((1 + m["phi"]) / 2) / math.pi)
+    dp = m["p0"][32, 32] - m["p0"][0, 0]
+    assert abs(dp * R / math.sqrt(8 * 0.08 * 0.04 / 9) - 1) < 0.10
+
+
+def test_static_droplet_fp32_2000_steps():
+    n = 64
+    phi0 = inputs.droplet(n, n, 16, inputs.interface_width(0.04, 0.08))
+    say("case static droplet 64^2 fp32 2000 steps")
+    p = oracle.Params(n, n)
+    mo = oracle.macro(p, *oracle.run(p, *oracle.init(p, phi0), 2000))
+    lat = lbcm.Lattice(n, n, precision="fp32").init(phi0)
+    d0 = lat.diag()
+    m = lat.step(2000).fields()
+    d1 = lat.diag()
+    e = np.linalg.norm(m["phi"] - mo["phi"]) / np.linalg.norm(mo["phi"])
+    drift = abs(d1["sum_phi"] - d0["sum_phi"]) / d0["sum_abs_phi"]
+    say(f"  phi rel L2 = {e:.2e}, sum phi drift = {drift:.2e}")
+    assert e < 1e-5
+    assert drift < 1e-5
+
+
+@pytest.mark.parametrize("ratio", [1, 10, 100, 1000])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-3)])
+def test_layered_poiseuille_4x256(ratio, prec, tol):
+    """4 x 256 channel, walls, force 1e-6, phi = +1 below / -1 above (tanh), nu1 = 0.1,
+    nu2 = ratio * nu1: velocity profile after 2000 steps from rest vs the oracle (relative L2)."""
+    nx, ny = 4, 256
+    W = inputs.interface_width(0.04, 0.08)
+    phi0 = inputs.layered(nx, ny, W)
+    kw = dict(bc_y=1, nu_l=0.1, nu_g=0.1 * ratio, force_x=1e-6)
+    (f, g, m), (fo, go, mo) = both(nx, ny, phi0, steps=2000, prec=prec, **kw)
+    e = np.linalg.norm(m["ux"] - mo["ux"]) / np.linalg.norm(mo["ux"])
+    say(f"  ux rel L2 = {e:.2e}  max |dphi| = {maxerr(m['phi'], mo['phi']):.2e}")
+    assert e < tol
+
+
+def _window(full_phi, y0, x0, h, w, steps, **kw):
+    """Oracle run on a periodic patch around a window; the window is exact when the margin
+    exceeds the 2-node-per-step reach of the step plus the 1-node reach of the initialisation."""
+    ny, nx = full_phi.shape
+    m = 2 * steps + 2
+    ys = np.arange(y0 - m, y0 + h + m) % ny
+    xs = np.arange(x0 - m, x0 + w + m) % nx
+    patch = full_phi[np.ix_(ys, xs)]
+    p = oracle.Params(w + 2 * m, h + 2 * m, **kw)
+    fo, go = oracle.run(p, *oracle.init(p, patch), steps)
+    return fo[:, m:m + h, m:m + w], go[:, m:m + h, m:m + w]
+
+
+def test_spinodal_4096_fp32_sampled_windows():
+    """4096^2 periodic spinodal (phi0 uniform in [-0.05, 0.05], SplitMix64 seed 1, a = 0.04,
+    gamma = 0.08, M = 0.1, nu = 0.05) in the benchmark's launch configuration: after 10 steps,
+    windows (including ones that wrap around the periodic edges) match the oracle."""
+    n, steps = 4096, 10
+    phi0 = inputs.spinodal(n, n, seed=1)
+    say("case spinodal 4096^2 fp32 10 steps")
+    lat = lbcm.Lattice(n, n, precision="fp32", nu_l=0.05, nu_g=0.05).init(phi0)
+    lat.step(steps)
+    f, g = lat.populations()
+    d = lat.diag()
+    lat.close()
+    assert d["nonfinite"] == 0
+    worst = 0.0
+    for (y0, x0) in [(0, 0), (4096 - 16, 4096 - 16), (1000, 63), (2047, 4000), (3333, 1234)]:
+        h = w = 32
+        fo, go = _window(phi0, y0, x0, h, w, steps, nu_l=0.05, nu_g=0.05)
+        ys = np.arange(y0, y0 + h) % n
+        xs = np.arange(x0, x0 + w) % n
+        fw = f[:, ys][:, :, xs]
+        gw = g[:, ys][:, :, xs]
+        e = max(maxerr(fw, fo), maxerr(gw, go))
+        worst = max(worst, e)
+    say(f"  worst window |GPU - oracle| = {worst:.2e}")
+    assert worst < 2e-6
+
+
+def test_checkpoint_resume_bitwise():
+    nx, ny = 66, 33
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=36)
+    a = lbcm.Lattice(nx, ny, precision="fp32", **PHYS).init(phi, rho, ux, uy).step(5)
+    snap = a.get_state()
+    a.step(5)
+    b = lbcm.Lattice(nx, ny, precision="fp32", **PHYS)
+    b.set_state(snap, step=5)
+    b.step(5)
+    assert np.array_equal(a.get_state(), b.get_state())
+    assert b.diag()["step"] == 10
+
+
+def test_errors_and_divergence_flag():
+    lat = lbcm.Lattice(16, 16, precision="fp32", check_every=1)
+    with pytest.raises(lbcm.LbcmError) as e:
+        lat.step(1)
+    assert e.value.code == lbcm.LBCM_ESTATE
+    phi = np.zeros((16, 16))
+    phi[5, 7] = np.nan
+    lat.init(phi)
+    with pytest.raises(lbcm.LbcmError) as e:
+        lat.step(3)
+    assert e.value.code == lbcm.LBCM_EDIVERGED
+    assert lat.diag()["nonfinite"] > 0
+    with pytest.raises(lbcm.LbcmError):
+        lat.step(-1)
+    lat.close()
+
+
+def test_torch_stream_and_device_io():
+    import torch
+
+    nx, ny = 40, 24
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=37)
+    s = torch.cuda.Stream()
+    ref = lbcm.Lattice(nx, ny, precision="fp64", **PHYS).init(phi, rho, ux, uy).step(4)
+    lat = lbcm.Lattice(nx, ny, precision="fp64", stream=s, **PHYS)
+    with torch.cuda.stream(s):
+        t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (phi, rho, ux, uy)]
+        lbcm.lbcm_init_device(lat.h, *t)
+        lat.step(4)
+        out = [torch.empty((ny, nx), dtype=torch.float64, device="cuda") for _ in range(5)]
+        lbcm.lbcm_fields_device(lat.h, *out)
+    s.synchronize()
+    m = ref.fields()
+    for k, o in zip(("phi", "rho", "ux", "uy", "p0"), out):
+        assert np.array_equal(o.cpu().numpy(), m[k]), k
