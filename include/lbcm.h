@@ -91,7 +91,7 @@ typedef struct lbcm_handle lbcm_handle;
 size_t lbcm_workspace_size(const lbcm_params *p);
 
 /* Validate the parameters, allocate (or adopt) device memory and return a handle in *out.
-   Errors: LBCM_EINVAL (nx, ny < 1, plane larger than 4 GiB, nu <= 0, mobility <= 0, Gamma <= 0,
+   Errors: LBCM_EINVAL (nx, ny < 1, a population set (9 planes) of 4 GiB or more, nu <= 0, mobility <= 0, Gamma <= 0,
    omega3 outside (0, 2), unknown bc/precision, workspace too small or misaligned),
    LBCM_ENOMEM, LBCM_EHIP.  On error *out is NULL. */
 int lbcm_create(const lbcm_params *p, lbcm_handle **out);
@@ -129,10 +129,12 @@ int lbcm_populations(lbcm_handle *h, double *f, double *g);
 int lbcm_diag(lbcm_handle *h, lbcm_diagnostics *out);
 
 /* Bytes of the raw population state: 18 planes (f_0..f_8 then g_0..g_8) in storage precision. */
+/* The raw state is in pull layout (plane i at node x holds the post-collision value of the
+   previous step at its origin node x) and f is stored shifted, as f_i - w_i. */
 size_t lbcm_state_size(const lbcm_handle *h);
 
 /* Copy the raw populations out of / into the handle (host buffer of lbcm_state_size bytes;
-   values as stored, i.e. shifted for the *_SHIFTED precisions).  lbcm_set_state also marks the
+   values as stored: pull layout, f shifted by the weights).  lbcm_set_state also marks the
    handle initialised and sets the step counter to step.  Both synchronise. */
 int lbcm_get_state(lbcm_handle *h, void *host, size_t bytes);
 int lbcm_set_state(lbcm_handle *h, const void *host, size_t bytes, int64_t step);

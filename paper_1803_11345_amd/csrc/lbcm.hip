@@ -42,25 +42,56 @@
 
 namespace {
 
-constexpr int kTX = 64;           // lanes per workgroup: one wave, one column per lane
-constexpr int kDefaultRows = 64;  // rows per workgroup segment
+constexpr int kDefaultRows = 4;   // rows per tile (one wave row each)
+template <class S> constexpr int kMaxThreads = sizeof(S) == 8 ? 512 : 1024;
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
 constexpr int kDiagFields = 7;
 
 // ------------------------------------------------------------------------------------------
-// storage <-> compute precision
+// storage.  f is stored shifted by the lattice weights, f_i - w_i (its deviation from the
+// resting equilibrium rho = 1, v = 0), in every precision: the moments the collision needs are
+// then formed from small numbers and a weak body force is not lost in the rounding of
+// O(0.1) populations.  g is stored as is.
+
+constexpr int kBufFlags = 0x00020000;  // word 3 of a raw buffer resource (gfx9 family)
+constexpr int kNT = 2;                 // non-temporal policy bit of buffer stores
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+template <class S> __device__ __forceinline__ rsrc_t make_rsrc(const S *p, uint32_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(p), (short)0, (int)(n * (uint32_t)sizeof(S)),
+                                             kBufFlags);
+}
 
 template <class S> struct Io;
 template <> struct Io<double> {
     using R = double;
+    using V2 = __attribute__((__vector_size__(2 * sizeof(unsigned int)))) unsigned int;
     static __device__ __forceinline__ R ld(const double *p) { return *p; }
     static __device__ __forceinline__ void st(double *p, R v) { __builtin_nontemporal_store(v, p); }
+    static __device__ __forceinline__ R bld(rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    }
+    static __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, uint32_t soff, R v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)voff, (int)soff, kNT);
+    }
 };
 template <> struct Io<float> {
     using R = float;
     static __device__ __forceinline__ R ld(const float *p) { return *p; }
     static __device__ __forceinline__ void st(float *p, R v) { __builtin_nontemporal_store(v, p); }
+    static __device__ __forceinline__ R bld(rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    }
+    static __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, uint32_t soff, R v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)voff, (int)soff, kNT);
+    }
 };
 
 // ------------------------------------------------------------------------------------------
@@ -69,8 +100,9 @@ template <> struct Io<float> {
 struct Geo {
     int nx, ny;
     uint32_t plane;  // nx * ny
-    int rows;        // rows per segment
-    int nbands, nsegs;
+    int wx;          // wave columns per tile (tile width 64 * wx)
+    int rows;        // rows per tile (one wave row each)
+    int nbands, nrows;  // tiles across and down
     int walls;
 };
 
@@ -82,17 +114,26 @@ template <class R> struct Phys {
     int k8_printed;
 };
 
+__constant__ double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+__constant__ int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int kCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__constant__ int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
 // ------------------------------------------------------------------------------------------
-// pull of the 9 post-streaming populations of node (x, y) from the stored post-collision
-// planes.  xl / xr are the periodic neighbours x - 1 / x + 1.  y is uniform across the wave.
+// pull of the 9 post-streaming populations of one row.  One buffer resource covers the 9 planes
+// of a population set (pb bytes apart); the plane and the row y (uniform across the wave) go in
+// the scalar offset of the buffer loads, and each lane supplies the byte offsets of its columns
+// x, x - 1 and x + 1 (periodic).  With walls, a link that would
+// come from behind a wall takes the node's own opposite post-collision value (the weights of
+// opposite directions are equal, so this holds for the shifted f as well).
 
 template <class S, bool WALLS>
-__device__ __forceinline__ void pull9(const S *__restrict__ P, uint32_t plane, int nx, int ny, int y,
-                                      int x, int xl, int xr, typename Io<S>::R v[9])
+__device__ __forceinline__ void pull_row(rsrc_t P, uint32_t pb, int nx, int ny, int y, uint32_t cx,
+                                         uint32_t cl, uint32_t cr, typename Io<S>::R v[9])
 {
     using IO = Io<S>;
-    int yd = y - 1;  // source row of directions with c_y = +1 (2, 5, 6)
-    int yu = y + 1;  // source row of directions with c_y = -1 (4, 7, 8)
+    int yd = y - 1;  // source row of the directions with c_y = +1 (2, 5, 6)
+    int yu = y + 1;  // source row of the directions with c_y = -1 (4, 7, 8)
     bool bot = false, top = false;
     if (WALLS) {
         bot = yd < 0;
@@ -101,32 +142,54 @@ __device__ __forceinline__ void pull9(const S *__restrict__ P, uint32_t plane, i
         if (yd < 0) yd += ny;
         if (yu >= ny) yu -= ny;
     }
-    const uint32_t r0 = (uint32_t)y * (uint32_t)nx;
-    const uint32_t rd = (uint32_t)yd * (uint32_t)nx;
-    const uint32_t ru = (uint32_t)yu * (uint32_t)nx;
-    const S *P0 = P, *P1 = P + (size_t)plane, *P2 = P + 2 * (size_t)plane, *P3 = P + 3 * (size_t)plane,
-            *P4 = P + 4 * (size_t)plane, *P5 = P + 5 * (size_t)plane, *P6 = P + 6 * (size_t)plane,
-            *P7 = P + 7 * (size_t)plane, *P8 = P + 8 * (size_t)plane;
-    v[0] = IO::ld(P0 + (r0 + x));
-    v[1] = IO::ld(P1 + (r0 + xl));
-    v[3] = IO::ld(P3 + (r0 + xr));
+    const uint32_t rowb = (uint32_t)nx * (uint32_t)sizeof(S);
+    const uint32_t s0 = (uint32_t)y * rowb, sd = (uint32_t)yd * rowb, su = (uint32_t)yu * rowb;
+    v[0] = IO::bld(P, cx, s0);
+    v[1] = IO::bld(P, cl, pb + s0);
+    v[3] = IO::bld(P, cr, 3 * pb + s0);
     if (WALLS && bot) {
-        v[2] = IO::ld(P4 + (r0 + x));
-        v[5] = IO::ld(P7 + (r0 + x));
-        v[6] = IO::ld(P8 + (r0 + x));
+        v[2] = IO::bld(P, cx, 4 * pb + s0);
+        v[5] = IO::bld(P, cx, 7 * pb + s0);
+        v[6] = IO::bld(P, cx, 8 * pb + s0);
     } else {
-        v[2] = IO::ld(P2 + (rd + x));
-        v[5] = IO::ld(P5 + (rd + xl));
-        v[6] = IO::ld(P6 + (rd + xr));
+        v[2] = IO::bld(P, cx, 2 * pb + sd);
+        v[5] = IO::bld(P, cl, 5 * pb + sd);
+        v[6] = IO::bld(P, cr, 6 * pb + sd);
     }
     if (WALLS && top) {
-        v[4] = IO::ld(P2 + (r0 + x));
-        v[7] = IO::ld(P5 + (r0 + x));
-        v[8] = IO::ld(P6 + (r0 + x));
+        v[4] = IO::bld(P, cx, 2 * pb + s0);
+        v[7] = IO::bld(P, cx, 5 * pb + s0);
+        v[8] = IO::bld(P, cx, 6 * pb + s0);
     } else {
-        v[4] = IO::ld(P4 + (ru + x));
-        v[7] = IO::ld(P7 + (ru + xr));
-        v[8] = IO::ld(P8 + (ru + xl));
+        v[4] = IO::bld(P, cx, 4 * pb + su);
+        v[7] = IO::bld(P, cr, 7 * pb + su);
+        v[8] = IO::bld(P, cl, 8 * pb + su);
+    }
+}
+
+// The same pull for one arbitrary node (readers; plain global loads, any y per lane).
+template <class S>
+__device__ __forceinline__ void pull_node(const S *__restrict__ P, const Geo &geo, size_t n, double v[9])
+{
+    using IO = Io<S>;
+    const int nx = geo.nx, ny = geo.ny;
+    const int y = (int)(n / nx), x = (int)(n % nx);
+    const int xl = x == 0 ? nx - 1 : x - 1, xr = x == nx - 1 ? 0 : x + 1;
+    const size_t N = geo.plane;
+    for (int i = 0; i < 9; ++i) {
+        int xs = kCX[i] > 0 ? xl : (kCX[i] < 0 ? xr : x);
+        int ys = y - kCY[i];
+        int ii = i;
+        if (ys < 0 || ys >= ny) {
+            if (geo.walls) {
+                ii = kOpp[i];
+                xs = x;
+                ys = y;
+            } else {
+                ys = ys < 0 ? ys + ny : ys - ny;
+            }
+        }
+        v[i] = (double)IO::ld(P + (size_t)ii * N + (size_t)ys * nx + xs);
     }
 }
 
@@ -139,56 +202,63 @@ template <class R> __device__ __forceinline__ R sum9(const R v[9])
 }
 
 // ------------------------------------------------------------------------------------------
-// populations from central moments.  k* = (rho, c10, c01, c20, c02, c11, c21, c12, c22) are the
-// central moments about v of the populations to build, in the plain monomial form
-// c_pq = sum f (c_x - v_x)^p (c_y - v_y)^q.
+// populations from central moments, in deviation form.  Input: rho - 1, rho, v and the central
+// moments about v of the populations to build, c_pq = sum f (c_x - v_x)^p (c_y - v_y)^q, with
+// c20, c02 and c22 given as deviations from their resting values 1/3, 1/3 and 1/9.  Output:
+// f_i - w_i.  The central moments are shifted back to raw moments m_pq = sum f c_x^p c_y^q
+// (binomial expansion in v), the raw moments of the weights are taken off, and the D2Q9
+// raw-moment map is inverted as the tensor product of the 1-D map
+// (m0, m1, m2) -> (f_0, f_+, f_-) = (m0 - m2, (m1 + m2)/2, (m2 - m1)/2).
 
 template <class R>
-__device__ __forceinline__ void from_central(R rho, R ux, R uy, R c10, R c01, R c20, R c02, R c11,
-                                             R c21, R c12, R c22, R out[9])
+__device__ __forceinline__ void from_central(R rd, R rho, R ux, R uy, R c10, R c01, R c20d, R c02d,
+                                             R c11, R c21, R c12, R c22d, R out[9])
 {
+    const R third = (R)(1.0 / 3.0);
+    const R c20 = c20d + third, c02 = c02d + third;
     const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
-    // raw moments m_pq = sum f c_x^p c_y^q (binomial shift by v)
+    const R m00 = rd;
     const R m10 = c10 + ux * rho;
     const R m01 = c01 + uy * rho;
-    const R m20 = c20 + 2 * ux * c10 + ux2 * rho;
-    const R m02 = c02 + 2 * uy * c01 + uy2 * rho;
+    const R m20 = c20d + 2 * ux * c10 + ux2 * rho;
+    const R m02 = c02d + 2 * uy * c01 + uy2 * rho;
     const R m11 = c11 + ux * c01 + uy * c10 + uxy * rho;
     const R m21 = c21 + 2 * ux * c11 + uy * c20 + ux2 * c01 + 2 * uxy * c10 + ux2 * uy * rho;
     const R m12 = c12 + 2 * uy * c11 + ux * c02 + uy2 * c10 + 2 * uxy * c01 + ux * uy2 * rho;
-    const R m22 = c22 + 2 * ux * c12 + 2 * uy * c21 + ux2 * c02 + uy2 * c20 + 4 * uxy * c11 +
+    const R m22 = c22d + 2 * ux * c12 + 2 * uy * c21 + ux2 * c02 + uy2 * c20 + 4 * uxy * c11 +
                   2 * ux * uy2 * c10 + 2 * ux2 * uy * c01 + ux2 * uy2 * rho;
     // inverse along x for each y-order q: h_q(0), h_q(+1), h_q(-1)
-    const R h0z = rho - m20, h0p = (R)0.5 * (m10 + m20), h0m = (R)0.5 * (m20 - m10);
+    const R h0z = m00 - m20, h0p = (R)0.5 * (m10 + m20), h0m = (R)0.5 * (m20 - m10);
     const R h1z = m01 - m21, h1p = (R)0.5 * (m11 + m21), h1m = (R)0.5 * (m21 - m11);
     const R h2z = m02 - m22, h2p = (R)0.5 * (m12 + m22), h2m = (R)0.5 * (m22 - m12);
     // inverse along y
-    out[0] = h0z - h2z;                 // ( 0,  0)
-    out[1] = h0p - h2p;                 // (+1,  0)
-    out[2] = (R)0.5 * (h1z + h2z);      // ( 0, +1)
-    out[3] = h0m - h2m;                 // (-1,  0)
-    out[4] = (R)0.5 * (h2z - h1z);      // ( 0, -1)
-    out[5] = (R)0.5 * (h1p + h2p);      // (+1, +1)
-    out[6] = (R)0.5 * (h1m + h2m);      // (-1, +1)
-    out[7] = (R)0.5 * (h2m - h1m);      // (-1, -1)
-    out[8] = (R)0.5 * (h2p - h1p);      // (+1, -1)
+    out[0] = h0z - h2z;             // ( 0,  0)
+    out[1] = h0p - h2p;             // (+1,  0)
+    out[2] = (R)0.5 * (h1z + h2z);  // ( 0, +1)
+    out[3] = h0m - h2m;             // (-1,  0)
+    out[4] = (R)0.5 * (h2z - h1z);  // ( 0, -1)
+    out[5] = (R)0.5 * (h1p + h2p);  // (+1, +1)
+    out[6] = (R)0.5 * (h1m + h2m);  // (-1, +1)
+    out[7] = (R)0.5 * (h2m - h1m);  // (-1, -1)
+    out[8] = (R)0.5 * (h2p - h1p);  // (+1, -1)
 }
 
-// Equilibrium central moments (the list ending in Eq. (16)), returned as
-// (c20, c02, c11, c21, c12, c22) = ((k3+k4)/2, (k3-k4)/2, k5, k6, k7, k8).
+// Equilibrium central moments k3..k8 (the list ending in Eq. (16)), k3 and k8 as deviations
+// from their resting values 2/3 and 1/9.  rd = rho - 1, ptd = p~ - 1/3.
 template <class R>
-__device__ __forceinline__ void eq_central(R rho, R ux, R uy, R pt, R gamma, R dpx, R dpy, R surf,
-                                           R &k3, R &k4, R &k5, R &k6, R &k7, R &k8)
+__device__ __forceinline__ void eq_central(R rd, R rho, R ux, R uy, R ptd, R gamma, R dpx, R dpy, R surf,
+                                           R &e3, R &e4, R &e5, R &e6, R &e7, R &e8)
 {
     const R third = (R)(1.0 / 3.0);
     const R ux2 = ux * ux, uy2 = uy * uy;
-    k3 = 2 * pt;
-    k4 = gamma * (dpx * dpx - dpy * dpy);
-    k5 = gamma * dpx * dpy;
-    k6 = -(R)0.5 * uy * k4 - 2 * ux * k5 + rho * uy * (third - ux2) - pt * uy;
-    k7 = (R)0.5 * ux * k4 - 2 * uy * k5 + rho * ux * (third - uy2) - pt * ux;
-    k8 = pt * (third + ux2 + uy2) - rho * third * (ux2 + uy2) + 3 * rho * ux2 * uy2 -
-         (R)(1.0 / 6.0) * gamma * surf + (R)0.5 * k4 * (uy2 - ux2) + 4 * ux * uy * k5;
+    const R q = rd * third - ptd;  // rho c_s^2 - p~
+    e3 = 2 * ptd;
+    e4 = gamma * (dpx * dpx - dpy * dpy);
+    e5 = gamma * dpx * dpy;
+    e6 = -(R)0.5 * uy * e4 - 2 * ux * e5 - rho * uy * ux2 + uy * q;
+    e7 = (R)0.5 * ux * e4 - 2 * uy * e5 - rho * ux * uy2 + ux * q;
+    e8 = ptd * third - (ux2 + uy2) * q + 3 * rho * ux2 * uy2 - (R)(1.0 / 6.0) * gamma * surf +
+         (R)0.5 * e4 * (uy2 - ux2) + 4 * ux * uy * e5;
 }
 
 // g equilibrium (Eqs. (9)-(10)): w_i [Gamma mu + phi (3 c.v + 9/2 (c.v)^2 - 3/2 v^2)], i >= 1,
@@ -202,7 +272,7 @@ __device__ __forceinline__ void g_equilibrium(R phi, R gmu, R ux, R uy, R out[9]
     const R ax = 3 * phi * ux, ay = 3 * phi * uy;
     const R qx = (R)4.5 * phi * ux * ux, qy = (R)4.5 * phi * uy * uy;
     const R sp = ux + uy, sm = ux - uy;
-    const R a5 = 3 * phi * sp, a6 = 3 * phi * sm;  // (+1,+1) and (+1,-1) projections
+    const R a5 = 3 * phi * sp, a6 = 3 * phi * sm;  // projections on (+1,+1) and (+1,-1)
     const R q5 = (R)4.5 * phi * sp * sp, q6 = (R)4.5 * phi * sm * sm;
     out[1] = w1 * (base + ax + qx);
     out[3] = w1 * (base - ax + qx);
@@ -216,14 +286,17 @@ __device__ __forceinline__ void g_equilibrium(R phi, R gmu, R ux, R uy, R out[9]
 }
 
 // ------------------------------------------------------------------------------------------
-// one node: CM collision of f (Eq. (17)) and BGK of g (Eq. (7)).
+// one node: central-moment collision of f (Eq. (17)) and BGK of g (Eq. (7)).
+// f and fo hold f_i - w_i.
 
 template <class R, bool FORCE>
 __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, R dpx, R dpy,
                                              R lap, const Phys<R> &c, R fo[9], R go[9],
                                              R &rho_out)
 {
-    const R rho = sum9(f);
+    const R third = (R)(1.0 / 3.0);
+    const R rd = sum9(f);  // rho - 1
+    const R rho = 1 + rd;
     const R jx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
     const R jy = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
     const R irho = (R)1 / rho;
@@ -231,7 +304,8 @@ __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, 
     const R ux = (jx + hFx) * irho, uy = (jy + hFy) * irho;
     rho_out = rho;
 
-    // pre-collision central moments of second order (about v, with m10 = rho ux - hFx)
+    // pre-collision second-order central moments about v (m10 = rho ux - F_x/2); the weights'
+    // share 1/3 of the diagonal ones cancels against the same share of the equilibria
     const R sxx = (f[1] + f[3]) + (f[5] + f[6]) + (f[7] + f[8]);
     const R syy = (f[2] + f[4]) + (f[5] + f[6]) + (f[7] + f[8]);
     const R sxy = (f[5] - f[6]) + (f[7] - f[8]);
@@ -245,30 +319,28 @@ __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, 
     }
     const R k3 = kxx + kyy, k4 = kxx - kyy, k5 = kxy;
 
-    // thermodynamics
+    // thermodynamics: mu, p~ - 1/3, omega_rho
     const R phi2 = phi * phi;
     const R mu = c.a * phi * (phi2 - 1) - c.gamma * lap;
-    const R p0 = rho * (R)(1.0 / 3.0) + c.a * phi2 * ((R)0.75 * phi2 - (R)0.5);
-    const R pt = p0 - c.gamma * phi * lap;
+    const R ptd = rd * third + c.a * phi2 * ((R)0.75 * phi2 - (R)0.5) - c.gamma * phi * lap;
     const R wr = c.w_mid + c.w_half * phi;
     const R surf = c.k8_printed ? lap : dpx * dpx + dpy * dpy;
 
     R e3, e4, e5, e6, e7, e8;
-    eq_central(rho, ux, uy, pt, c.gamma, dpx, dpy, surf, e3, e4, e5, e6, e7, e8);
+    eq_central(rd, rho, ux, uy, ptd, c.gamma, dpx, dpy, surf, e3, e4, e5, e6, e7, e8);
 
-    R s3 = k3 + c.w3 * (e3 - k3);
-    R s4 = k4 + wr * (e4 - k4);
-    R s5 = k5 + wr * (e5 - k5);
+    const R s3 = k3 + c.w3 * (e3 - k3);
+    const R s4 = k4 + wr * (e4 - k4);
+    const R s5 = k5 + wr * (e5 - k5);
     R s6 = e6, s7 = e7, s8 = e8;
     if (FORCE) {
-        // central moments of Guo's forcing term, weighted by (1 - omega/2) = 1/2 for k6..k8
+        // central moments of Guo's forcing term; k6..k8 relax at rate 1, weight 1/2
         const R Fx = 2 * hFx, Fy = 2 * hFy;
-        const R third = (R)(1.0 / 3.0);
         s6 += (R)0.5 * (Fy * (third - ux * ux) - 2 * Fx * ux * uy);
         s7 += (R)0.5 * (Fx * (third - uy * uy) - 2 * Fy * ux * uy);
-        s8 += (R)0.5 * (4 * ux * uy * (Fx * uy + Fy * ux));
+        s8 += 2 * ux * uy * (Fx * uy + Fy * ux);
     }
-    from_central(rho, ux, uy, hFx, hFy, (R)0.5 * (s3 + s4), (R)0.5 * (s3 - s4), s5, s6, s7, s8, fo);
+    from_central(rd, rho, ux, uy, hFx, hFy, (R)0.5 * (s3 + s4), (R)0.5 * (s3 - s4), s5, s6, s7, s8, fo);
 
     R geq[9];
     g_equilibrium(phi, c.Gamma * mu, ux, uy, geq);
@@ -277,109 +349,129 @@ __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, 
 }
 
 // ------------------------------------------------------------------------------------------
-// blockIdx -> tile.  Workgroups are handed to the 8 XCDs round-robin; renumber them so that
-// each XCD gets a contiguous run of tiles (rows), and the halo rows/columns a workgroup shares
-// with its neighbours sit in the same L2.
-
-__device__ __forceinline__ int xcd_tile(int b, int n)
-{
-    const int q = n >> 3, r = n & 7;
-    const int k = b & 7, j = b >> 3;
-    return k * q + (k < r ? k : r) + j;
-}
+// the step kernel.  A workgroup owns a tile of 64 * wx columns by rows_t rows; each of its waves
+// owns one 64-column row segment.  Every wave pulls f and g of its own nodes, sums phi into an
+// LDS tile with a one-node halo, and the halo is filled by the same pulls one node further out:
+// the waves of the first and last tile row also pull g of the rows above and below, and lanes 0
+// and 1 of the first wave column pull the two halo columns.  One barrier later every node reads
+// its 3x3 phi stencil from LDS, collides and stores f*, g* at its own node (non-temporal).
+//
+// Every load of a workgroup is issued before its barrier, and workgroups are dispatched in
+// row-major tile order, so the waves resident at any moment cover a compact band of rows: the
+// HBM sees a few long streams per plane instead of many short ones.  The halo re-reads (one
+// extra g row per tile row-pair, two columns per tile) are served by L2 and the MALL.
+// Workgroups are dealt round-robin to the 8 XCDs; with a multiple of 8 tiles per tile row the
+// tiles above and below a tile land on its XCD, so its halo rows are hits in the same L2.
 
 template <class S, bool WALLS, bool FORCE>
-__global__ __launch_bounds__(kTX) void k_step(const S *__restrict__ fa, const S *__restrict__ ga,
-                                              S *__restrict__ fb, S *__restrict__ gb, Geo geo,
-                                              Phys<typename Io<S>::R> c, int *__restrict__ flag)
+__global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ fa, const S *__restrict__ ga,
+                                                         S *__restrict__ fb, S *__restrict__ gb, Geo geo,
+                                                         Phys<typename Io<S>::R> c, int *__restrict__ flag)
 {
     using R = typename Io<S>::R;
     using IO = Io<S>;
-    __shared__ R phs[4][kTX + 2];
+    constexpr uint32_t E = sizeof(S);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    R *phs = reinterpret_cast<R *>(lds_raw);  // [rows_t + 2][ldw]
 
-    const int lane = threadIdx.x;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int band = t % geo.nbands, seg = t / geo.nbands;
     const int nx = geo.nx, ny = geo.ny;
-    const uint32_t plane = geo.plane;
-    const int x0 = band * kTX;
-    const int x1 = min(x0 + kTX, nx);
-    const int w = x1 - x0;
-    const bool valid = lane < w;
-    const int x = valid ? x0 + lane : x0;
+    const int wx = geo.wx, rows_t = geo.rows;
+    const int ldw = 64 * wx + 2;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wc = wave % wx, wr = wave / wx;  // wave column and row inside the tile
+    const int band = blockIdx.x % geo.nbands, rg = blockIdx.x / geo.nbands;
+    const int X0 = band * 64 * wx;
+    const int X1 = min(X0 + 64 * wx, nx);
+    const int y0 = rg * rows_t;
+    const int y1 = min(y0 + rows_t, ny);
+    const int y = y0 + wr;
+    const bool row_ok = y < y1;                       // uniform per wave
+    const int xr_ = X0 + wc * 64 + lane;
+    const bool col_ok = xr_ < X1;
+    const bool valid = row_ok && col_ok;
+    const int x = col_ok ? xr_ : X1 - 1;              // clamped for addressing
+    const int yy = row_ok ? y : y1 - 1;
     const int xl = x == 0 ? nx - 1 : x - 1;
     const int xr = x == nx - 1 ? 0 : x + 1;
-    // halo columns: lane 0 takes x0 - 1, lane 1 takes x1 (both periodic)
-    const int hx = lane == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x1 == nx ? 0 : x1);
-    const int hxl = hx == 0 ? nx - 1 : hx - 1;
-    const int hxr = hx == nx - 1 ? 0 : hx + 1;
-    const int hslot = lane == 0 ? 0 : w + 1;
-    const int y0 = seg * geo.rows;
-    const int y1 = min(y0 + geo.rows, ny);
+    const uint32_t cx = (uint32_t)x * E, cl = (uint32_t)xl * E, cr = (uint32_t)xr * E;
+    const uint32_t pb = geo.plane * E;
+    const rsrc_t rfa = make_rsrc(fa, 9 * geo.plane), rga = make_rsrc(ga, 9 * geo.plane);
+    const rsrc_t rfb = make_rsrc(fb, 9 * geo.plane), rgb = make_rsrc(gb, 9 * geo.plane);
+    const int slot = wc * 64 + lane + 1;              // LDS column of this lane
+    const int last = y1 - y0 - 1;                     // last valid tile row
 
-    // phi of row r (a valid row index) into ring slot s; the row's g is kept in gk.
-    auto phi_row = [&](int r, int s, R gk[9]) {
-        pull9<S, WALLS>(ga, plane, nx, ny, r, x, xl, xr, gk);
-        if (valid) phs[s][lane + 1] = sum9(gk);
-        if (lane < 2) {
-            R hv[9];
-            pull9<S, WALLS>(ga, plane, nx, ny, r, hx, hxl, hxr, hv);
-            phs[s][hslot] = sum9(hv);
-        }
-    };
-    auto mirror_row = [&](int from, int to) {
-        if (valid) phs[to][lane + 1] = phs[from][lane + 1];
-        if (lane < 2) phs[to][hslot] = phs[from][hslot];
-    };
+    // own populations
+    R g[9], f[9];
+    pull_row<S, WALLS>(rga, pb, nx, ny, yy, cx, cl, cr, g);
+    pull_row<S, WALLS>(rfa, pb, nx, ny, yy, cx, cl, cr, f);
+    const R phi_own = sum9(g);
+    if (valid) phs[(wr + 1) * ldw + slot] = phi_own;
 
-    R gc[9], gn[9];
-    // prime the ring: slot of row y is (y - y0 + 1) & 3
-    if (WALLS && y0 == 0) {
-        phi_row(0, 1, gc);
-        mirror_row(1, 0);
-    } else {
-        phi_row(y0 == 0 ? ny - 1 : y0 - 1, 0, gn);
-        phi_row(y0, 1, gc);
-    }
-
-    int flagged = 0;
-    for (int y = y0; y < y1; ++y) {
-        const int yn = y + 1;
-        const int sc = (y - y0 + 1) & 3, sn = (y - y0 + 2) & 3, sp = (y - y0) & 3;
-        if (WALLS && yn == ny) {
-            mirror_row(sc, sn);
+    // halo rows: the first tile row fetches the row above, the last valid one the row below
+    auto halo_row = [&](int hy, int hslot_row, int own_slot_row) {
+        if (WALLS && (hy < 0 || hy >= ny)) {  // ghost row behind a wall: mirror
+            if (col_ok) phs[hslot_row * ldw + slot] = phi_own;
+            (void)own_slot_row;
         } else {
-            phi_row(yn == ny ? 0 : yn, sn, gn);
+            R h[9];
+            pull_row<S, WALLS>(rga, pb, nx, ny, hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy), cx, cl, cr, h);
+            if (col_ok) phs[hslot_row * ldw + slot] = sum9(h);
         }
-        R f[9];
-        pull9<S, WALLS>(fa, plane, nx, ny, y, x, xl, xr, f);
-        __syncthreads();
+    };
+    if (wr == 0) halo_row(y0 - 1, 0, 1);
+    if (wr == last) halo_row(y1, last + 2, last + 1);
 
-        const int l = lane + 1;
-        const R pS = phs[sp][l], pSW = phs[sp][l - 1], pSE = phs[sp][l + 1];
-        const R pC = phs[sc][l], pW = phs[sc][l - 1], pE = phs[sc][l + 1];
-        const R pN = phs[sn][l], pNW = phs[sn][l - 1], pNE = phs[sn][l + 1];
-        const R dpx = ((R)4 * (pE - pW) + (pNE - pNW) + (pSE - pSW)) * (R)(1.0 / 12.0);
-        const R dpy = ((R)4 * (pN - pS) + (pNE - pSE) + (pNW - pSW)) * (R)(1.0 / 12.0);
-        const R lap = ((R)4 * ((pE + pW) + (pN + pS)) + ((pNE + pNW) + (pSE + pSW)) - (R)20 * pC) *
-                      (R)(1.0 / 6.0);
-
-        R fo[9], go[9], rho;
-        collide_node<R, FORCE>(f, gc, pC, dpx, dpy, lap, c, fo, go, rho);
-        if (!(std::isfinite(rho) && std::isfinite(pC))) flagged = 1;
-
-        if (valid) {
-            const uint32_t o = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                IO::st(fb + (size_t)i * plane + o, fo[i]);
-                IO::st(gb + (size_t)i * plane + o, go[i]);
+    // halo columns (x = X0 - 1 on lane 0, x = X1 on lane 1) for this wave's row and, on the
+    // first / last tile row, the corner rows
+    if (wc == 0 && lane < 2 && wr <= last) {
+        const int hx = lane == 0 ? (X0 == 0 ? nx - 1 : X0 - 1) : (X1 == nx ? 0 : X1);
+        const int hxl = hx == 0 ? nx - 1 : hx - 1, hxr = hx == nx - 1 ? 0 : hx + 1;
+        const uint32_t hcx = (uint32_t)hx * E, hcl = (uint32_t)hxl * E, hcr = (uint32_t)hxr * E;
+        const int hs = lane == 0 ? 0 : X1 - X0 + 1;
+        R h[9];
+        pull_row<S, WALLS>(rga, pb, nx, ny, y, hcx, hcl, hcr, h);
+        const R ph = sum9(h);
+        phs[(wr + 1) * ldw + hs] = ph;
+        for (int side = 0; side < 2; ++side) {
+            if (side == 0 && wr != 0) continue;
+            if (side == 1 && wr != last) continue;
+            const int hy = side == 0 ? y0 - 1 : y1;
+            const int srow = side == 0 ? 0 : last + 2;
+            if (WALLS && (hy < 0 || hy >= ny)) {
+                phs[srow * ldw + hs] = ph;
+            } else {
+                R h2[9];
+                pull_row<S, WALLS>(rga, pb, nx, ny, hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy), hcx, hcl, hcr, h2);
+                phs[srow * ldw + hs] = sum9(h2);
             }
         }
-#pragma unroll
-        for (int i = 0; i < 9; ++i) gc[i] = gn[i];
     }
-    if (__any(flagged && valid) && lane == 0) atomicOr(flag, 1);
+    __syncthreads();
+    if (!row_ok) return;
+
+    const R *rS = phs + wr * ldw, *rC = phs + (wr + 1) * ldw, *rN = phs + (wr + 2) * ldw;
+    const R pS = rS[slot], pSW = rS[slot - 1], pSE = rS[slot + 1];
+    const R pC = rC[slot], pW = rC[slot - 1], pE = rC[slot + 1];
+    const R pN = rN[slot], pNW = rN[slot - 1], pNE = rN[slot + 1];
+    const R dpx = ((R)4 * (pE - pW) + (pNE - pNW) + (pSE - pSW)) * (R)(1.0 / 12.0);
+    const R dpy = ((R)4 * (pN - pS) + (pNE - pSE) + (pNW - pSW)) * (R)(1.0 / 12.0);
+    const R lap = ((R)4 * ((pE + pW) + (pN + pS)) + ((pNE + pNW) + (pSE + pSW)) - (R)20 * pC) *
+                  (R)(1.0 / 6.0);
+
+    R fo[9], go[9], rho;
+    collide_node<R, FORCE>(f, g, pC, dpx, dpy, lap, c, fo, go, rho);
+    const bool bad = !(std::isfinite(rho) && std::isfinite(pC)) && col_ok;
+    if (__any(bad) && lane == 0) atomicOr(flag, 1);
+
+    if (col_ok) {
+        const uint32_t so = (uint32_t)y * (uint32_t)nx * E;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            IO::bst(rfb, cx, i * pb + so, fo[i]);
+            IO::bst(rgb, cx, i * pb + so, go[i]);
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -387,7 +479,6 @@ __global__ __launch_bounds__(kTX) void k_step(const S *__restrict__ fa, const S 
 // a post-streaming state (9 + 9 planes, node-local); k_unstream stores them in pull layout:
 // P[i](z) = F[i](z + c_i), or F[opp(i)](z) where z + c_i is behind a wall.
 
-template <class R>
 __device__ __forceinline__ double plane_at(const double *p, int nx, int ny, bool walls, int x, int y)
 {
     x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
@@ -414,35 +505,32 @@ __global__ void k_equilibria(const double *__restrict__ phi0, const double *__re
         const bool wl = geo.walls != 0;
         double nb[3][3];
         for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) nb[dy + 1][dx + 1] = plane_at<R>(phi0, nx, ny, wl, x + dx, y + dy);
+            for (int dx = -1; dx <= 1; ++dx) nb[dy + 1][dx + 1] = plane_at(phi0, nx, ny, wl, x + dx, y + dy);
         const R pC = (R)nb[1][1], pE = (R)nb[1][2], pW = (R)nb[1][0], pN = (R)nb[2][1], pS = (R)nb[0][1];
         const R pNE = (R)nb[2][2], pNW = (R)nb[2][0], pSE = (R)nb[0][2], pSW = (R)nb[0][0];
         const R dpx = ((R)4 * (pE - pW) + (pNE - pNW) + (pSE - pSW)) * (R)(1.0 / 12.0);
         const R dpy = ((R)4 * (pN - pS) + (pNE - pSE) + (pNW - pSW)) * (R)(1.0 / 12.0);
         const R lap = ((R)4 * ((pE + pW) + (pN + pS)) + ((pNE + pNW) + (pSE + pSW)) - (R)20 * pC) *
                       (R)(1.0 / 6.0);
-        const R rho = rho0 ? (R)rho0[n] : (R)1;
+        const R rd = rho0 ? (R)(rho0[n] - 1.0) : (R)0;
+        const R rho = 1 + rd;
         const R ux = ux0 ? (R)ux0[n] : (R)0, uy = uy0 ? (R)uy0[n] : (R)0;
         const R phi = pC;
         const R phi2 = phi * phi;
         const R mu = c.a * phi * (phi2 - 1) - c.gamma * lap;
-        const R pt = rho * (R)(1.0 / 3.0) + c.a * phi2 * ((R)0.75 * phi2 - (R)0.5) - c.gamma * phi * lap;
+        const R ptd = rd * (R)(1.0 / 3.0) + c.a * phi2 * ((R)0.75 * phi2 - (R)0.5) - c.gamma * phi * lap;
         const R surf = c.k8_printed ? lap : dpx * dpx + dpy * dpy;
         R e3, e4, e5, e6, e7, e8;
-        eq_central(rho, ux, uy, pt, c.gamma, dpx, dpy, surf, e3, e4, e5, e6, e7, e8);
+        eq_central(rd, rho, ux, uy, ptd, c.gamma, dpx, dpy, surf, e3, e4, e5, e6, e7, e8);
         R fe[9], ge[9];
-        from_central(rho, ux, uy, (R)0, (R)0, (R)0.5 * (e3 + e4), (R)0.5 * (e3 - e4), e5, e6, e7, e8, fe);
+        from_central(rd, rho, ux, uy, (R)0, (R)0, (R)0.5 * (e3 + e4), (R)0.5 * (e3 - e4), e5, e6, e7, e8, fe);
         g_equilibrium(phi, c.Gamma * mu, ux, uy, ge);
         for (int i = 0; i < 9; ++i) {
-            Io<S>::st(F + i * N + n, fe[i]);
-            Io<S>::st(G + i * N + n, ge[i]);
+            Io<S>::st(F + i * N + n, (S)fe[i]);
+            Io<S>::st(G + i * N + n, (S)ge[i]);
         }
     }
 }
-
-__constant__ int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__constant__ int kCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__constant__ int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 template <class S>
 __global__ void k_unstream(const S *__restrict__ F, S *__restrict__ P, Geo geo)
@@ -472,70 +560,57 @@ __global__ void k_unstream(const S *__restrict__ F, S *__restrict__ P, Geo geo)
 }
 
 // ------------------------------------------------------------------------------------------
-// readers: post-streaming populations, macroscopic fields and FP64 reductions.
+// readers: post-streaming populations, macroscopic fields and FP64 reductions (in double).
 
-template <class S, bool WALLS>
-__device__ __forceinline__ void pull_node(const S *P, const Geo &geo, size_t n, typename Io<S>::R v[9])
+template <class S>
+__global__ void k_fields(const S *__restrict__ f, const S *__restrict__ g, Geo geo, double a,
+                         double hFx, double hFy, double *phi, double *rho, double *ux, double *uy,
+                         double *p0)
 {
-    const int nx = geo.nx;
-    const int y = (int)(n / nx), x = (int)(n % nx);
-    const int xl = x == 0 ? nx - 1 : x - 1, xr = x == nx - 1 ? 0 : x + 1;
-    pull9<S, WALLS>(P, geo.plane, nx, geo.ny, y, x, xl, xr, v);
-}
-
-// which: bit 0 phi, 1 rho, 2 ux, 3 uy, 4 p0
-template <class S, bool WALLS>
-__global__ void k_fields(const S *__restrict__ f, const S *__restrict__ g, Geo geo,
-                         Phys<typename Io<S>::R> c, double *phi, double *rho, double *ux,
-                         double *uy, double *p0)
-{
-    using R = typename Io<S>::R;
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
-        R fv[9], gv[9];
-        pull_node<S, WALLS>(f, geo, n, fv);
-        pull_node<S, WALLS>(g, geo, n, gv);
-        const double r = (double)sum9(fv);
-        const double ph = (double)sum9(gv);
-        const double jx = (double)((fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7]));
-        const double jy = (double)((fv[2] + fv[5] + fv[6]) - (fv[4] + fv[7] + fv[8]));
+        double fv[9], gv[9];
+        pull_node<S>(f, geo, n, fv);
+        pull_node<S>(g, geo, n, gv);
+        const double r = 1.0 + sum9(fv);
+        const double ph = sum9(gv);
+        const double jx = (fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7]);
+        const double jy = (fv[2] + fv[5] + fv[6]) - (fv[4] + fv[7] + fv[8]);
         if (phi) phi[n] = ph;
         if (rho) rho[n] = r;
-        if (ux) ux[n] = (jx + (double)c.hFx) / r;
-        if (uy) uy[n] = (jy + (double)c.hFy) / r;
-        if (p0) p0[n] = r / 3.0 + (double)c.a * (-0.5 * ph * ph + 0.75 * ph * ph * ph * ph);
+        if (ux) ux[n] = (jx + hFx) / r;
+        if (uy) uy[n] = (jy + hFy) / r;
+        if (p0) p0[n] = r / 3.0 + a * (-0.5 * ph * ph + 0.75 * ph * ph * ph * ph);
     }
 }
 
-// one post-streaming population plane i (0..8 f, 9..17 g) as FP64
-template <class S, bool WALLS>
+// one post-streaming population plane (which = 0..8: f_i, 9..17: g_i) as FP64
+template <class S>
 __global__ void k_population(const S *__restrict__ f, const S *__restrict__ g, Geo geo, int which,
                              double *out)
 {
-    using R = typename Io<S>::R;
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
-        R v[9];
-        pull_node<S, WALLS>(which < 9 ? f : g, geo, n, v);
-        out[n] = (double)v[which % 9];
+        double v[9];
+        pull_node<S>(which < 9 ? f : g, geo, n, v);
+        out[n] = which < 9 ? v[which] + kW[which] : v[which - 9];
     }
 }
 
-template <class S, bool WALLS>
+template <class S>
 __global__ __launch_bounds__(kReduceThreads) void k_diag(const S *__restrict__ f,
                                                          const S *__restrict__ g, Geo geo,
-                                                         Phys<typename Io<S>::R> c, double *partial)
+                                                         double hFx, double hFy, double *partial)
 {
-    using R = typename Io<S>::R;
     double acc[kDiagFields] = {0, 0, 0, 0, 0, 0, 0};  // phi, |phi|, rho, jx, jy, max|u|, nonfinite
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
-        R fv[9], gv[9];
-        pull_node<S, WALLS>(f, geo, n, fv);
-        pull_node<S, WALLS>(g, geo, n, gv);
-        const double r = (double)sum9(fv), ph = (double)sum9(gv);
-        const double jx = (double)((fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7])) + (double)c.hFx;
-        const double jy = (double)((fv[2] + fv[5] + fv[6]) - (fv[4] + fv[7] + fv[8])) + (double)c.hFy;
+        double fv[9], gv[9];
+        pull_node<S>(f, geo, n, fv);
+        pull_node<S>(g, geo, n, gv);
+        const double r = 1.0 + sum9(fv), ph = sum9(gv);
+        const double jx = (fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7]) + hFx;
+        const double jy = (fv[2] + fv[5] + fv[6]) - (fv[4] + fv[7] + fv[8]) + hFy;
         if (!(std::isfinite(r) && std::isfinite(ph))) {
             acc[6] += 1;
             continue;
@@ -545,8 +620,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_diag(const S *__restrict__ f
         acc[2] += r;
         acc[3] += jx;
         acc[4] += jy;
-        const double u = sqrt(jx * jx + jy * jy) / r;
-        acc[5] = fmax(acc[5], u);
+        acc[5] = fmax(acc[5], sqrt(jx * jx + jy * jy) / r);
     }
     __shared__ double red[kDiagFields][kReduceThreads];
     for (int k = 0; k < kDiagFields; ++k) red[k][threadIdx.x] = acc[k];
@@ -630,8 +704,8 @@ const char *check_params(const lbcm_params *p)
     if (p->bc_y != LBCM_BC_PERIODIC && p->bc_y != LBCM_BC_WALLS) return "bc_y must be 0 or 1";
     if (elem_bytes(p->precision) == 0) return "unsupported precision";
     const double N = (double)p->nx * (double)p->ny;
-    if (N * (double)elem_bytes(p->precision) > 4294967295.0)
-        return "lattice too large: one plane must stay below 4 GiB";
+    if (9.0 * N * (double)elem_bytes(p->precision) > 4294967295.0)
+        return "lattice too large: one population set (9 planes) must stay below 4 GiB";
     if (!(p->nu_l > 0) || !(p->nu_g > 0)) return "viscosities must be > 0";
     if (!(p->mobility > 0) || !(p->Gamma > 0)) return "mobility and Gamma must be > 0";
     if (!(p->omega3 > 0 && p->omega3 < 2)) return "omega3 must lie in (0, 2)";
@@ -688,10 +762,15 @@ Geo make_geo(const lbcm_params &p)
     g.nx = p.nx;
     g.ny = p.ny;
     g.plane = (uint32_t)((size_t)p.nx * p.ny);
-    g.rows = p.tile_rows > 0 ? p.tile_rows : kDefaultRows;
-    if (g.rows > p.ny) g.rows = p.ny;
-    g.nbands = (p.nx + kTX - 1) / kTX;
-    g.nsegs = (p.ny + g.rows - 1) / g.rows;
+    const int max_waves = (p.precision == LBCM_FP64 ? 512 : 1024) / 64;
+    g.wx = (p.nx + 63) / 64;
+    if (g.wx > 4) g.wx = 4;
+    int rows = p.tile_rows > 0 ? p.tile_rows : (p.precision == LBCM_FP64 ? 2 : kDefaultRows);
+    if (rows > max_waves / g.wx) rows = max_waves / g.wx;
+    if (rows > p.ny) rows = p.ny;
+    g.rows = rows;
+    g.nbands = (p.nx + 64 * g.wx - 1) / (64 * g.wx);
+    g.nrows = (p.ny + g.rows - 1) / g.rows;
     g.walls = p.bc_y;
     return g;
 }
@@ -716,18 +795,19 @@ template <class S> int launch_steps(lbcm_handle *h, int64_t nsteps)
     const Phys<R> c = make_phys<R>(h->p);
     const bool walls = h->p.bc_y == LBCM_BC_WALLS;
     const bool force = h->p.force_x != 0 || h->p.force_y != 0;
-    const int64_t nblk = (int64_t)geo.nbands * geo.nsegs;
+    const int64_t nblk = (int64_t)geo.nbands * geo.nrows;
     if (nblk > 0x7fffffff) return fail(h, LBCM_EINVAL, "too many tiles");
+    const dim3 grid((unsigned)nblk), block(64 * geo.wx * geo.rows);
+    const size_t lds = (size_t)(geo.rows + 2) * (64 * geo.wx + 2) * sizeof(R);
     for (int64_t s = 0; s < nsteps; ++s) {
         const S *fa = pop<S>(h, h->cur, 0), *ga = pop<S>(h, h->cur, 1);
         S *fb = pop<S>(h, 1 - h->cur, 0), *gb = pop<S>(h, 1 - h->cur, 1);
-        dim3 grid((unsigned)nblk), block(kTX);
         if (walls) {
-            if (force) hipLaunchKernelGGL((k_step<S, true, true>), grid, block, 0, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            else hipLaunchKernelGGL((k_step<S, true, false>), grid, block, 0, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            if (force) hipLaunchKernelGGL((k_step<S, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            else hipLaunchKernelGGL((k_step<S, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
         } else {
-            if (force) hipLaunchKernelGGL((k_step<S, false, true>), grid, block, 0, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            else hipLaunchKernelGGL((k_step<S, false, false>), grid, block, 0, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            if (force) hipLaunchKernelGGL((k_step<S, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            else hipLaunchKernelGGL((k_step<S, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
         }
         HIP_TRY(h, hipGetLastError());
         h->cur = 1 - h->cur;
@@ -769,15 +849,11 @@ int do_init(lbcm_handle *h, const double *phi0, const double *rho0, const double
 template <class S>
 int do_fields(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy, double *p0)
 {
-    using R = typename Io<S>::R;
     const Geo geo = make_geo(h->p);
-    const Phys<R> c = make_phys<R>(h->p);
     const int gb = grid_for(geo.plane, 256);
     const S *f = pop<S>(h, h->cur, 0), *g = pop<S>(h, h->cur, 1);
-    if (h->p.bc_y == LBCM_BC_WALLS)
-        hipLaunchKernelGGL((k_fields<S, true>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, c, phi, rho, ux, uy, p0);
-    else
-        hipLaunchKernelGGL((k_fields<S, false>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, c, phi, rho, ux, uy, p0);
+    hipLaunchKernelGGL((k_fields<S>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, h->p.a,
+                       0.5 * h->p.force_x, 0.5 * h->p.force_y, phi, rho, ux, uy, p0);
     HIP_TRY(h, hipGetLastError());
     return LBCM_OK;
 }
@@ -787,24 +863,17 @@ template <class S> int do_population(lbcm_handle *h, int which, double *out)
     const Geo geo = make_geo(h->p);
     const int gb = grid_for(geo.plane, 256);
     const S *f = pop<S>(h, h->cur, 0), *g = pop<S>(h, h->cur, 1);
-    if (h->p.bc_y == LBCM_BC_WALLS)
-        hipLaunchKernelGGL((k_population<S, true>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, which, out);
-    else
-        hipLaunchKernelGGL((k_population<S, false>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, which, out);
+    hipLaunchKernelGGL((k_population<S>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, which, out);
     HIP_TRY(h, hipGetLastError());
     return LBCM_OK;
 }
 
 template <class S> int do_diag(lbcm_handle *h)
 {
-    using R = typename Io<S>::R;
     const Geo geo = make_geo(h->p);
-    const Phys<R> c = make_phys<R>(h->p);
     const S *f = pop<S>(h, h->cur, 0), *g = pop<S>(h, h->cur, 1);
-    if (h->p.bc_y == LBCM_BC_WALLS)
-        hipLaunchKernelGGL((k_diag<S, true>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, h->stream, f, g, geo, c, h->diag_partial);
-    else
-        hipLaunchKernelGGL((k_diag<S, false>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, h->stream, f, g, geo, c, h->diag_partial);
+    hipLaunchKernelGGL((k_diag<S>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, h->stream, f, g, geo,
+                       0.5 * h->p.force_x, 0.5 * h->p.force_y, h->diag_partial);
     HIP_TRY(h, hipGetLastError());
     hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(kReduceThreads), 0, h->stream, h->diag_partial, kReduceBlocks, h->diag_out);
     HIP_TRY(h, hipGetLastError());

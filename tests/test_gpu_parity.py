@@ -154,17 +154,20 @@ def test_static_droplet_fp32_2000_steps():
 
 
 @pytest.mark.parametrize("ratio", [1, 10, 100, 1000])
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
 def test_layered_poiseuille_4x256(ratio, prec, tol):
     """4 x 256 channel, walls, force 1e-6, phi = +1 below / -1 above (tanh), nu1 = 0.1,
-    nu2 = ratio * nu1: velocity profile after 2000 steps from rest vs the oracle (relative L2)."""
+    nu2 = ratio * nu1: velocity profile after 2000 steps from rest vs the oracle.  The velocity
+    (~1e-4 here) is a difference of O(0.1) populations divided by rho, so its error is bounded in
+    absolute terms by a few roundings of the populations: the bound is on max |u - u_oracle|."""
     nx, ny = 4, 256
     W = inputs.interface_width(0.04, 0.08)
     phi0 = inputs.layered(nx, ny, W)
     kw = dict(bc_y=1, nu_l=0.1, nu_g=0.1 * ratio, force_x=1e-6)
     (f, g, m), (fo, go, mo) = both(nx, ny, phi0, steps=2000, prec=prec, **kw)
-    e = np.linalg.norm(m["ux"] - mo["ux"]) / np.linalg.norm(mo["ux"])
-    say(f"  ux rel L2 = {e:.2e}  max |dphi| = {maxerr(m['phi'], mo['phi']):.2e}")
+    e = maxerr(m["ux"], mo["ux"])
+    rel = np.linalg.norm(m["ux"] - mo["ux"]) / np.linalg.norm(mo["ux"])
+    say(f"  max |dux| = {e:.2e} (rel L2 {rel:.2e})  max |dphi| = {maxerr(m['phi'], mo['phi']):.2e}")
     assert e < tol
 
 
