@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--n", type=int, default=4096, help="lattice side")
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_LUP))
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--tile-wx", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps in the CPU sample (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a plain device copy")
     return ap.parse_args()
@@ -91,7 +92,7 @@ def main():
     torch.cuda.set_device(0)
     n = args.n
     phi0 = inputs.spinodal(n, n, seed=1)
-    lat = lbcm.Lattice(n, n, precision=args.precision, tile_rows=args.tile_rows, a=0.04, gamma=0.08,
+    lat = lbcm.Lattice(n, n, precision=args.precision, tile_rows=args.tile_rows, tile_wx=args.tile_wx, a=0.04, gamma=0.08,
                        mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05)
     lat.init(phi0)
     lat.step(args.warmup)

@@ -66,8 +66,9 @@ typedef struct lbcm_params {
     int32_t check_every; /* > 0: lbcm_step synchronises every check_every steps and at its end
                             and returns LBCM_EDIVERGED once a non-finite rho or phi was seen;
                             0: no check (lbcm_diag still reports it) */
-    int32_t tile_rows;   /* rows per workgroup of the step kernel, 0 = default */
-    int32_t reserved0;
+    int32_t tile_rows;   /* step-kernel tile height in rows (one wave per row), 0 = default */
+    int32_t tile_wx;     /* step-kernel tile width in waves of 64 columns, 0 = default;
+                            tile_wx * tile_rows is capped at 16 (FP32) or 8 (FP64) waves */
     void *stream;        /* hipStream_t to queue work on; NULL = null stream */
     void *workspace;     /* optional caller-owned device memory of lbcm_workspace_size() bytes,
                             256-byte aligned; NULL = the library allocates and frees it */

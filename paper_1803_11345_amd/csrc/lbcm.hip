@@ -42,7 +42,8 @@
 
 namespace {
 
-constexpr int kDefaultRows = 4;   // rows per tile (one wave row each)
+constexpr int kDefaultRows = 2;   // rows per tile (one wave row each)
+constexpr int kDefaultWx = 8;     // 64-column waves across a tile
 template <class S> constexpr int kMaxThreads = sizeof(S) == 8 ? 512 : 1024;
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
@@ -55,7 +56,18 @@ constexpr int kDiagFields = 7;
 // O(0.1) populations.  g is stored as is.
 
 constexpr int kBufFlags = 0x00020000;  // word 3 of a raw buffer resource (gfx9 family)
-constexpr int kNT = 2;                 // non-temporal policy bit of buffer stores
+#ifndef LBCM_F_LOAD_AUX
+#define LBCM_F_LOAD_AUX 0
+#endif
+#ifndef LBCM_G_LOAD_AUX
+#define LBCM_G_LOAD_AUX 0
+#endif
+#ifndef LBCM_STORE_AUX
+#define LBCM_STORE_AUX 2
+#endif
+constexpr int kFLoad = LBCM_F_LOAD_AUX;  // cache policy of the f pulls
+constexpr int kGLoad = LBCM_G_LOAD_AUX;  // cache policy of the g pulls (re-read as tile halos)
+constexpr int kNT = LBCM_STORE_AUX;      // cache policy of the stores (2 = non-temporal)
 
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
@@ -71,9 +83,9 @@ template <> struct Io<double> {
     using V2 = __attribute__((__vector_size__(2 * sizeof(unsigned int)))) unsigned int;
     static __device__ __forceinline__ R ld(const double *p) { return *p; }
     static __device__ __forceinline__ void st(double *p, R v) { __builtin_nontemporal_store(v, p); }
-    static __device__ __forceinline__ R bld(rsrc_t r, uint32_t voff, uint32_t soff)
+    template <int AUX> static __device__ __forceinline__ R bld(rsrc_t r, uint32_t voff, uint32_t soff)
     {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX));
     }
     static __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, uint32_t soff, R v)
     {
@@ -84,9 +96,9 @@ template <> struct Io<float> {
     using R = float;
     static __device__ __forceinline__ R ld(const float *p) { return *p; }
     static __device__ __forceinline__ void st(float *p, R v) { __builtin_nontemporal_store(v, p); }
-    static __device__ __forceinline__ R bld(rsrc_t r, uint32_t voff, uint32_t soff)
+    template <int AUX> static __device__ __forceinline__ R bld(rsrc_t r, uint32_t voff, uint32_t soff)
     {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
     }
     static __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, uint32_t soff, R v)
     {
@@ -127,7 +139,7 @@ __constant__ int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 // come from behind a wall takes the node's own opposite post-collision value (the weights of
 // opposite directions are equal, so this holds for the shifted f as well).
 
-template <class S, bool WALLS>
+template <class S, bool WALLS, int AUX>
 __device__ __forceinline__ void pull_row(rsrc_t P, uint32_t pb, int nx, int ny, int y, uint32_t cx,
                                          uint32_t cl, uint32_t cr, typename Io<S>::R v[9])
 {
@@ -144,26 +156,26 @@ __device__ __forceinline__ void pull_row(rsrc_t P, uint32_t pb, int nx, int ny, 
     }
     const uint32_t rowb = (uint32_t)nx * (uint32_t)sizeof(S);
     const uint32_t s0 = (uint32_t)y * rowb, sd = (uint32_t)yd * rowb, su = (uint32_t)yu * rowb;
-    v[0] = IO::bld(P, cx, s0);
-    v[1] = IO::bld(P, cl, pb + s0);
-    v[3] = IO::bld(P, cr, 3 * pb + s0);
+    v[0] = IO::template bld<AUX>(P, cx, s0);
+    v[1] = IO::template bld<AUX>(P, cl, pb + s0);
+    v[3] = IO::template bld<AUX>(P, cr, 3 * pb + s0);
     if (WALLS && bot) {
-        v[2] = IO::bld(P, cx, 4 * pb + s0);
-        v[5] = IO::bld(P, cx, 7 * pb + s0);
-        v[6] = IO::bld(P, cx, 8 * pb + s0);
+        v[2] = IO::template bld<AUX>(P, cx, 4 * pb + s0);
+        v[5] = IO::template bld<AUX>(P, cx, 7 * pb + s0);
+        v[6] = IO::template bld<AUX>(P, cx, 8 * pb + s0);
     } else {
-        v[2] = IO::bld(P, cx, 2 * pb + sd);
-        v[5] = IO::bld(P, cl, 5 * pb + sd);
-        v[6] = IO::bld(P, cr, 6 * pb + sd);
+        v[2] = IO::template bld<AUX>(P, cx, 2 * pb + sd);
+        v[5] = IO::template bld<AUX>(P, cl, 5 * pb + sd);
+        v[6] = IO::template bld<AUX>(P, cr, 6 * pb + sd);
     }
     if (WALLS && top) {
-        v[4] = IO::bld(P, cx, 2 * pb + s0);
-        v[7] = IO::bld(P, cx, 5 * pb + s0);
-        v[8] = IO::bld(P, cx, 6 * pb + s0);
+        v[4] = IO::template bld<AUX>(P, cx, 2 * pb + s0);
+        v[7] = IO::template bld<AUX>(P, cx, 5 * pb + s0);
+        v[8] = IO::template bld<AUX>(P, cx, 6 * pb + s0);
     } else {
-        v[4] = IO::bld(P, cx, 4 * pb + su);
-        v[7] = IO::bld(P, cr, 7 * pb + su);
-        v[8] = IO::bld(P, cl, 8 * pb + su);
+        v[4] = IO::template bld<AUX>(P, cx, 4 * pb + su);
+        v[7] = IO::template bld<AUX>(P, cr, 7 * pb + su);
+        v[8] = IO::template bld<AUX>(P, cl, 8 * pb + su);
     }
 }
 
@@ -289,6 +301,14 @@ __device__ __forceinline__ void g_equilibrium(R phi, R gmu, R ux, R uy, R out[9]
 // one node: central-moment collision of f (Eq. (17)) and BGK of g (Eq. (7)).
 // f and fo hold f_i - w_i.
 
+template <class R> struct Rcp;
+template <> struct Rcp<double> {
+    static __device__ __forceinline__ double of(double v) { return 1.0 / v; }
+};
+template <> struct Rcp<float> {
+    static __device__ __forceinline__ float of(float v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
+};
+
 template <class R, bool FORCE>
 __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, R dpx, R dpy,
                                              R lap, const Phys<R> &c, R fo[9], R go[9],
@@ -299,7 +319,7 @@ __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, 
     const R rho = 1 + rd;
     const R jx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
     const R jy = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
-    const R irho = (R)1 / rho;
+    const R irho = Rcp<R>::of(rho);
     const R hFx = FORCE ? c.hFx : (R)0, hFy = FORCE ? c.hFy : (R)0;
     const R ux = (jx + hFx) * irho, uy = (jy + hFy) * irho;
     rho_out = rho;
@@ -378,7 +398,8 @@ __global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ f
     const int wx = geo.wx, rows_t = geo.rows;
     const int ldw = 64 * wx + 2;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // wave index made explicitly uniform, so that the row offsets stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wc = wave % wx, wr = wave / wx;  // wave column and row inside the tile
     const int band = blockIdx.x % geo.nbands, rg = blockIdx.x / geo.nbands;
     const int X0 = band * 64 * wx;
@@ -401,10 +422,12 @@ __global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ f
     const int slot = wc * 64 + lane + 1;              // LDS column of this lane
     const int last = y1 - y0 - 1;                     // last valid tile row
 
-    // own populations
+    // own populations; the loads go out at raised wave priority so that the memory pipeline of
+    // the CU keeps being fed while other workgroups compute
+    __builtin_amdgcn_s_setprio(3);
     R g[9], f[9];
-    pull_row<S, WALLS>(rga, pb, nx, ny, yy, cx, cl, cr, g);
-    pull_row<S, WALLS>(rfa, pb, nx, ny, yy, cx, cl, cr, f);
+    pull_row<S, WALLS, kFLoad>(rfa, pb, nx, ny, yy, cx, cl, cr, f);
+    pull_row<S, WALLS, kGLoad>(rga, pb, nx, ny, yy, cx, cl, cr, g);
     const R phi_own = sum9(g);
     if (valid) phs[(wr + 1) * ldw + slot] = phi_own;
 
@@ -415,7 +438,7 @@ __global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ f
             (void)own_slot_row;
         } else {
             R h[9];
-            pull_row<S, WALLS>(rga, pb, nx, ny, hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy), cx, cl, cr, h);
+            pull_row<S, WALLS, kGLoad>(rga, pb, nx, ny, hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy), cx, cl, cr, h);
             if (col_ok) phs[hslot_row * ldw + slot] = sum9(h);
         }
     };
@@ -430,7 +453,7 @@ __global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ f
         const uint32_t hcx = (uint32_t)hx * E, hcl = (uint32_t)hxl * E, hcr = (uint32_t)hxr * E;
         const int hs = lane == 0 ? 0 : X1 - X0 + 1;
         R h[9];
-        pull_row<S, WALLS>(rga, pb, nx, ny, y, hcx, hcl, hcr, h);
+        pull_row<S, WALLS, kGLoad>(rga, pb, nx, ny, y, hcx, hcl, hcr, h);
         const R ph = sum9(h);
         phs[(wr + 1) * ldw + hs] = ph;
         for (int side = 0; side < 2; ++side) {
@@ -442,12 +465,13 @@ __global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ f
                 phs[srow * ldw + hs] = ph;
             } else {
                 R h2[9];
-                pull_row<S, WALLS>(rga, pb, nx, ny, hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy), hcx, hcl, hcr, h2);
+                pull_row<S, WALLS, kGLoad>(rga, pb, nx, ny, hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy), hcx, hcl, hcr, h2);
                 phs[srow * ldw + hs] = sum9(h2);
             }
         }
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
     if (!row_ok) return;
 
     const R *rS = phs + wr * ldw, *rC = phs + (wr + 1) * ldw, *rN = phs + (wr + 2) * ldw;
@@ -714,7 +738,7 @@ const char *check_params(const lbcm_params *p)
         return "a, gamma and the force must be finite";
     if (p->k8_variant != 0 && p->k8_variant != 1) return "k8_variant must be 0 or 1";
     if (p->check_every < 0) return "check_every must be >= 0";
-    if (p->tile_rows < 0) return "tile_rows must be >= 0";
+    if (p->tile_rows < 0 || p->tile_wx < 0) return "tile_rows and tile_wx must be >= 0";
     return nullptr;
 }
 
@@ -763,8 +787,10 @@ Geo make_geo(const lbcm_params &p)
     g.ny = p.ny;
     g.plane = (uint32_t)((size_t)p.nx * p.ny);
     const int max_waves = (p.precision == LBCM_FP64 ? 512 : 1024) / 64;
-    g.wx = (p.nx + 63) / 64;
-    if (g.wx > 4) g.wx = 4;
+    const int need = (p.nx + 63) / 64;
+    g.wx = p.tile_wx > 0 ? p.tile_wx : kDefaultWx;
+    if (g.wx > need) g.wx = need;
+    if (g.wx > max_waves) g.wx = max_waves;
     int rows = p.tile_rows > 0 ? p.tile_rows : (p.precision == LBCM_FP64 ? 2 : kDefaultRows);
     if (rows > max_waves / g.wx) rows = max_waves / g.wx;
     if (rows > p.ny) rows = p.ny;
