@@ -23,7 +23,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BASELINE_METRIC = "MLUPS & % of HBM peak (D2Q9 f+g); surrogate speedup at φ L2 err ≤1e-2"
-BYTES_PER_LUP = {"fp64": 288, "fp32": 144, "fp16s": 72, "bf16s": 72}
+# bytes moved per lattice update (read + write of both sets): FP64 / FP32 planes, or 16-bit f and
+# g_1..g_8 with g_0 kept in FP32
+BYTES_PER_LUP = {"fp64": 288, "fp32": 144, "fp16s": 76, "bf16s": 76}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f32 (f16 storage)", "bf16s": "f32 (bf16 storage)"}
 
 
@@ -38,6 +40,8 @@ def parse():
     ap.add_argument("--tile-wx", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps in the CPU sample (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a plain device copy")
+    ap.add_argument("--acc-steps", type=int, default=2000,
+                    help="steps of the reduced-precision accuracy comparison (0 = skip the report)")
     return ap.parse_args()
 
 
@@ -78,6 +82,56 @@ def copy_probe(nbytes: int = 1 << 31, reps: int = 20) -> float:
     return 2 * nbytes / sec / 1e9
 
 
+def make_lattice(lbcm, n, precision, args):
+    return lbcm.Lattice(n, n, precision=precision, tile_rows=args.tile_rows, tile_wx=args.tile_wx,
+                        a=0.04, gamma=0.08, mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05)
+
+
+def time_steps(lat, steps, warmup):
+    """Average step time (s) over `steps` launches between HIP events on the lattice's stream."""
+    import torch
+
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def precision_report(lbcm, phi0, n, args, fp32_sec):
+    """Reduced-precision storage against the plain FP32 step: throughput, speedup, and the phi
+    error against an FP64 run of the same workload after acc_steps steps."""
+    import numpy as np
+
+    phis, drift = {}, {}
+    for prec in ("fp64", "fp32", "fp16s", "bf16s"):
+        lat = make_lattice(lbcm, n, prec, args).init(phi0)
+        d0 = lat.diag()
+        lat.step(args.acc_steps)
+        phis[prec] = lat.fields()["phi"]
+        d1 = lat.diag()
+        drift[prec] = abs(d1["sum_phi"] - d0["sum_phi"]) / d0["sum_abs_phi"]
+        lat.close()
+    ref = phis["fp64"]
+    out = {"acc_steps": args.acc_steps, "reference": "fp64 GPU run, same initial state",
+           "fp64_sum_phi_drift": drift["fp64"],
+           "fp32": {"phi_rel_l2": float(np.linalg.norm(phis["fp32"] - ref) / np.linalg.norm(ref)),
+                    "sum_phi_drift": drift["fp32"]}}
+    for prec in ("fp16s", "bf16s"):
+        lat = make_lattice(lbcm, n, prec, args).init(phi0)
+        sec = time_steps(lat, args.steps, args.warmup)
+        lat.close()
+        out[prec] = {"value": round(n * n / sec / 1e6, 1), "unit": "MLUPS",
+                     "speedup_vs_fp32": round(fp32_sec / sec, 3),
+                     "hbm_gbs_alg": round(BYTES_PER_LUP[prec] * n * n / sec / 1e9, 1),
+                     "phi_rel_l2": float(np.linalg.norm(phis[prec] - ref) / np.linalg.norm(ref)),
+                     "sum_phi_drift": drift[prec]}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -92,21 +146,11 @@ def main():
     torch.cuda.set_device(0)
     n = args.n
     phi0 = inputs.spinodal(n, n, seed=1)
-    lat = lbcm.Lattice(n, n, precision=args.precision, tile_rows=args.tile_rows, tile_wx=args.tile_wx, a=0.04, gamma=0.08,
-                       mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05)
-    lat.init(phi0)
-    lat.step(args.warmup)
-    torch.cuda.synchronize()
-    stream = lat.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lat = make_lattice(lbcm, n, args.precision, args).init(phi0)
     wall0 = time.perf_counter()
-    e0.record(stream)
-    lat.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
+    sec_per_step = time_steps(lat, args.steps, args.warmup)
     wall = time.perf_counter() - wall0
-    ms = e0.elapsed_time(e1)
-    sec_per_step = ms / 1e3 / args.steps
+    ms = sec_per_step * 1e3 * args.steps
     nodes = n * n
     mlups = nodes / sec_per_step / 1e6
     d = lat.diag()
@@ -132,10 +176,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_step", "bytes_per_lup": BYTES_PER_LUP[args.precision]},
-        "wall_s_timed": round(wall, 3),
+        "wall_s_warmup_and_timed": round(wall, 3),
         "sum_phi_drift": abs(d["sum_phi"] - float(np.sum(phi0))) / float(np.sum(np.abs(phi0))),
     }
     lat.close()
+    if args.acc_steps > 0 and args.precision == "fp32":
+        out["reduced_precision"] = precision_report(lbcm, phi0, n, args, sec_per_step)
     if args.copy_probe:
         out["copy_probe_gbs"] = round(copy_probe(), 1)
     if args.cpu_steps > 0:

@@ -2,33 +2,32 @@
 // Cahn-Hilliard--Navier-Stokes equations (De Rosis, Saito, Kaneko, Abe, arXiv:1803.11345),
 // written for MI355X (gfx950, wave64).
 //
-// Data layout in HBM.  Each population set is 9 planes [i][y][x] (x fastest).  Two copies
-// ("pairs") of (f, g) live back to back in one workspace; a step reads pair `cur` and writes
-// pair 1 - cur.  Streaming is done by pulling: the stored value P[i](x) is the post-collision
-// population f*_i(x, t-1) at its origin node, and the post-streaming population of the paper,
-// f_i(x, t) = f*_i(x - c_i, t - 1) (Eqs. (4)-(5)), is read at x - c_i.  With walls, a link that
-// would come from outside is the same node's opposite post-collision value (half-way
-// bounce-back).  Every reader of the state (step, fields, diagnostics) pulls.
+// Data layout in HBM.  Each population set (f or g) is 9 planes [i][y][x] (x fastest), packed
+// back to back; two copies ("pairs") of (f, g) live in one workspace, a step reads pair `cur`
+// and writes pair 1 - cur.  Streaming is done by pulling: the stored value P[i](x) is the
+// post-collision population f*_i(x, t-1) at its origin node, and the post-streaming population
+// of the paper, f_i(x, t) = f*_i(x - c_i, t - 1) (Eqs. (4)-(5)), is read at x - c_i.  With
+// walls, a link that would come from outside is the same node's opposite post-collision value
+// (half-way bounce-back).  Every reader of the state (step, fields, diagnostics) pulls.
 //
-// The step kernel (k_step) is one fused pass per time step.  A workgroup is one wave of 64
-// lanes that owns a band of 64 columns and walks down a segment of rows.  For row y it
-//   1. pulls g of row y+1 and sums it into phi(y+1) (plus the two halo columns), kept in a
-//      4-row ring in LDS so that the 3x3 phi stencil of row y is available;
-//   2. pulls f of row y;
-//   3. evaluates grad phi and Lap phi (Eq. (12)), mu, p0, p~ and omega_rho;
-//   4. collides f in central moments (Eqs. (15)-(17)) and g with BGK (Eq. (7));
-//   5. stores f* and g* of row y at their own node (coalesced, non-temporal).
-// Each g value is pulled once per segment (+2 rows of priming), so HBM traffic stays near the
-// 36 values per node the step must move.
+// Storage modes.  f is always stored shifted by the lattice weights, f_i - w_i (its deviation
+// from the resting equilibrium rho = 1, v = 0), so that its moments are formed from small
+// numbers and a weak body force is not lost in the rounding of O(0.1) values.  g is stored as
+// is.  FP64 and FP32 store every plane in that type.  The 16-bit modes store the nine f planes
+// and g_1..g_8 (all small) as IEEE half or bfloat16 and keep g_0, which carries phi in [-1, 1],
+// in FP32; arithmetic is FP32 in every mode but FP64.
 //
-// The central-moment collision never forms the 9x9 matrix: the few pre-collision central
-// moments it needs (k3, k4, k5) come from raw moments, and the post-collision populations are
-// rebuilt by shifting the post-collision central moments back to raw moments (binomial
-// expansion in v) and inverting the raw-moment map of D2Q9, which factorises into the 1-D map
-// (m0, m1, m2) -> (f_0, f_+, f_-) = (m0 - m2, (m1 + m2)/2, (m2 - m1)/2) applied along x and y.
+// The step kernel (k_step) is one fused pass per time step over 2-D tiles; see its comment.
+//
+// The central-moment collision never forms the 9x9 matrix of the basis: the few pre-collision
+// central moments it needs (k3, k4, k5) come from raw moments, and the post-collision
+// populations are rebuilt by shifting the post-collision central moments back to raw moments
+// (binomial expansion in v) and inverting the raw-moment map of D2Q9, which factorises into the
+// 1-D map (m0, m1, m2) -> (f_0, f_+, f_-) = (m0 - m2, (m1 + m2)/2, (m2 - m1)/2) along x and y.
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -42,78 +41,137 @@
 
 namespace {
 
-constexpr int kDefaultRows = 2;   // rows per tile (one wave row each)
-constexpr int kDefaultWx = 8;     // 64-column waves across a tile
-template <class S> constexpr int kMaxThreads = sizeof(S) == 8 ? 512 : 1024;
+constexpr int kDefaultRows = 2;  // rows per tile (one wave row each)
+constexpr int kDefaultWx = 8;    // 64-column waves across a tile
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
 constexpr int kDiagFields = 7;
 
 // ------------------------------------------------------------------------------------------
-// storage.  f is stored shifted by the lattice weights, f_i - w_i (its deviation from the
-// resting equilibrium rho = 1, v = 0), in every precision: the moments the collision needs are
-// then formed from small numbers and a weak body force is not lost in the rounding of
-// O(0.1) populations.  g is stored as is.
+// raw buffer access
 
 constexpr int kBufFlags = 0x00020000;  // word 3 of a raw buffer resource (gfx9 family)
-#ifndef LBCM_F_LOAD_AUX
-#define LBCM_F_LOAD_AUX 0
-#endif
-#ifndef LBCM_G_LOAD_AUX
-#define LBCM_G_LOAD_AUX 0
-#endif
-#ifndef LBCM_STORE_AUX
-#define LBCM_STORE_AUX 2
-#endif
-constexpr int kFLoad = LBCM_F_LOAD_AUX;  // cache policy of the f pulls
-constexpr int kGLoad = LBCM_G_LOAD_AUX;  // cache policy of the g pulls (re-read as tile halos)
-constexpr int kNT = LBCM_STORE_AUX;      // cache policy of the stores (2 = non-temporal)
+constexpr int kLoadAux = 0;            // cache policy of the pulls (g rows are re-read as halos)
+constexpr int kStoreAux = 2;           // cache policy of the stores: non-temporal
 
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
-template <class S> __device__ __forceinline__ rsrc_t make_rsrc(const S *p, uint32_t n)
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(p), (short)0, (int)(n * (uint32_t)sizeof(S)),
-                                             kBufFlags);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kBufFlags);
 }
 
-template <class S> struct Io;
-template <> struct Io<double> {
-    using R = double;
+// One stored element type: load through a buffer resource into the compute type R, store R.
+template <class T> struct Elem;
+template <> struct Elem<double> {
     using V2 = __attribute__((__vector_size__(2 * sizeof(unsigned int)))) unsigned int;
-    static __device__ __forceinline__ R ld(const double *p) { return *p; }
-    static __device__ __forceinline__ void st(double *p, R v) { __builtin_nontemporal_store(v, p); }
-    template <int AUX> static __device__ __forceinline__ R bld(rsrc_t r, uint32_t voff, uint32_t soff)
+    template <class R> static __device__ __forceinline__ R ld(rsrc_t r, uint32_t v, uint32_t s)
     {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX));
+        return (R)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, kLoadAux));
     }
-    static __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, uint32_t soff, R v)
+    template <class R> static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, R x)
     {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)voff, (int)soff, kNT);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, (double)x), r, (int)v, (int)s, kStoreAux);
     }
 };
-template <> struct Io<float> {
-    using R = float;
-    static __device__ __forceinline__ R ld(const float *p) { return *p; }
-    static __device__ __forceinline__ void st(float *p, R v) { __builtin_nontemporal_store(v, p); }
-    template <int AUX> static __device__ __forceinline__ R bld(rsrc_t r, uint32_t voff, uint32_t soff)
+template <> struct Elem<float> {
+    template <class R> static __device__ __forceinline__ R ld(rsrc_t r, uint32_t v, uint32_t s)
     {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
+        return (R)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, kLoadAux));
     }
-    static __device__ __forceinline__ void bst(rsrc_t r, uint32_t voff, uint32_t soff, R v)
+    template <class R> static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, R x)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)voff, (int)soff, kNT);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)x), r, (int)v, (int)s, kStoreAux);
     }
 };
+template <> struct Elem<_Float16> {
+    template <class R> static __device__ __forceinline__ R ld(rsrc_t r, uint32_t v, uint32_t s)
+    {
+        return (R)(float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, kLoadAux));
+    }
+    template <class R> static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, R x)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)(float)x), r, (int)v, (int)s,
+                                              kStoreAux);
+    }
+};
+template <> struct Elem<__bf16> {
+    template <class R> static __device__ __forceinline__ R ld(rsrc_t r, uint32_t v, uint32_t s)
+    {
+        return (R)(float)__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, kLoadAux));
+    }
+    template <class R> static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, R x)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)(float)x), r, (int)v, (int)s,
+                                              kStoreAux);
+    }
+};
+
+// Storage modes: compute type R, type of the f planes, of g_0 and of g_1..g_8.
+struct ModeF64 { using R = double; using F = double; using G0 = double; using G = double; };
+struct ModeF32 { using R = float; using F = float; using G0 = float; using G = float; };
+struct ModeF16 { using R = float; using F = _Float16; using G0 = float; using G = _Float16; };
+struct ModeB16 { using R = float; using F = __bf16; using G0 = float; using G = __bf16; };
+
+// Byte offset of plane i in a set whose plane 0 has element type T0 and planes 1..8 type T.
+template <class T0, class T> __device__ __forceinline__ uint32_t plane_off(int i, uint32_t N)
+{
+    return i == 0 ? 0u : N * (uint32_t)sizeof(T0) + (uint32_t)(i - 1) * N * (uint32_t)sizeof(T);
+}
+template <class T0, class T> __device__ __forceinline__ uint32_t set_bytes(uint32_t N)
+{
+    return N * (uint32_t)sizeof(T0) + 8u * N * (uint32_t)sizeof(T);
+}
+
+// Runtime description of a set (for the readers and the initialisation, not on the hot path).
+enum : int { kKindF64 = 0, kKindF32 = 1, kKindF16 = 2, kKindB16 = 3 };
+struct SetView {
+    unsigned char *base;
+    uint32_t off[9];  // byte offset of each plane
+    int kind[9];      // element kind of each plane
+};
+
+__device__ __forceinline__ double view_ld(const SetView &v, int i, size_t n)
+{
+    const unsigned char *p = v.base + v.off[i];
+    switch (v.kind[i]) {
+    case kKindF64: return ((const double *)p)[n];
+    case kKindF32: return (double)((const float *)p)[n];
+    case kKindF16: return (double)(float)((const _Float16 *)p)[n];
+    default: return (double)(float)((const __bf16 *)p)[n];
+    }
+}
+
+__device__ __forceinline__ void view_st(const SetView &v, int i, size_t n, double x)
+{
+    unsigned char *p = v.base + v.off[i];
+    switch (v.kind[i]) {
+    case kKindF64: ((double *)p)[n] = x; break;
+    case kKindF32: ((float *)p)[n] = (float)x; break;
+    case kKindF16: ((_Float16 *)p)[n] = (_Float16)(float)x; break;
+    default: ((__bf16 *)p)[n] = (__bf16)(float)x; break;
+    }
+}
+
+__device__ __forceinline__ void view_copy(const SetView &src, int i, size_t ns, const SetView &dst, int j, size_t nd)
+{
+    const unsigned char *s = src.base + src.off[i];
+    unsigned char *d = dst.base + dst.off[j];
+    switch (src.kind[i]) {
+    case kKindF64: ((double *)d)[nd] = ((const double *)s)[ns]; break;
+    case kKindF32: ((float *)d)[nd] = ((const float *)s)[ns]; break;
+    default: ((unsigned short *)d)[nd] = ((const unsigned short *)s)[ns]; break;
+    }
+}
 
 // ------------------------------------------------------------------------------------------
 // parameters
 
 struct Geo {
     int nx, ny;
-    uint32_t plane;  // nx * ny
-    int wx;          // wave columns per tile (tile width 64 * wx)
-    int rows;        // rows per tile (one wave row each)
+    uint32_t plane;     // nx * ny
+    int wx;             // wave columns per tile (tile width 64 * wx)
+    int rows;           // rows per tile (one wave row each)
     int nbands, nrows;  // tiles across and down
     int walls;
 };
@@ -133,17 +191,17 @@ __constant__ int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 // ------------------------------------------------------------------------------------------
 // pull of the 9 post-streaming populations of one row.  One buffer resource covers the 9 planes
-// of a population set (pb bytes apart); the plane and the row y (uniform across the wave) go in
-// the scalar offset of the buffer loads, and each lane supplies the byte offsets of its columns
-// x, x - 1 and x + 1 (periodic).  With walls, a link that would
-// come from behind a wall takes the node's own opposite post-collision value (the weights of
-// opposite directions are equal, so this holds for the shifted f as well).
+// of a set; the plane offset and the row y (uniform across the wave) go in the scalar offset of
+// the buffer loads, and each lane supplies the element index of its columns x, x - 1 and x + 1
+// (periodic).  With walls, a link that would come from behind a wall takes the node's own
+// opposite post-collision value (the weights of opposite directions are equal, so this holds
+// for the shifted f as well; plane 0 never bounces, so g_0 keeps its own type).
 
-template <class S, bool WALLS, int AUX>
-__device__ __forceinline__ void pull_row(rsrc_t P, uint32_t pb, int nx, int ny, int y, uint32_t cx,
-                                         uint32_t cl, uint32_t cr, typename Io<S>::R v[9])
+template <class T0, class T, class R, bool WALLS>
+__device__ __forceinline__ void pull_row(rsrc_t P, uint32_t N, int nx, int ny, int y, uint32_t x,
+                                         uint32_t xl, uint32_t xr, R v[9])
 {
-    using IO = Io<S>;
+    constexpr uint32_t b0 = sizeof(T0), b = sizeof(T);
     int yd = y - 1;  // source row of the directions with c_y = +1 (2, 5, 6)
     int yu = y + 1;  // source row of the directions with c_y = -1 (4, 7, 8)
     bool bot = false, top = false;
@@ -154,40 +212,39 @@ __device__ __forceinline__ void pull_row(rsrc_t P, uint32_t pb, int nx, int ny, 
         if (yd < 0) yd += ny;
         if (yu >= ny) yu -= ny;
     }
-    const uint32_t rowb = (uint32_t)nx * (uint32_t)sizeof(S);
-    const uint32_t s0 = (uint32_t)y * rowb, sd = (uint32_t)yd * rowb, su = (uint32_t)yu * rowb;
-    v[0] = IO::template bld<AUX>(P, cx, s0);
-    v[1] = IO::template bld<AUX>(P, cl, pb + s0);
-    v[3] = IO::template bld<AUX>(P, cr, 3 * pb + s0);
+    const uint32_t rb = (uint32_t)nx * b;
+    const uint32_t s0 = (uint32_t)y * rb, sd = (uint32_t)yd * rb, su = (uint32_t)yu * rb;
+    const uint32_t cx = x * b, cl = xl * b, cr = xr * b;
+    auto po = [&](int i) { return plane_off<T0, T>(i, N); };
+    v[0] = Elem<T0>::template ld<R>(P, x * b0, (uint32_t)y * (uint32_t)nx * b0);
+    v[1] = Elem<T>::template ld<R>(P, cl, po(1) + s0);
+    v[3] = Elem<T>::template ld<R>(P, cr, po(3) + s0);
     if (WALLS && bot) {
-        v[2] = IO::template bld<AUX>(P, cx, 4 * pb + s0);
-        v[5] = IO::template bld<AUX>(P, cx, 7 * pb + s0);
-        v[6] = IO::template bld<AUX>(P, cx, 8 * pb + s0);
+        v[2] = Elem<T>::template ld<R>(P, cx, po(4) + s0);
+        v[5] = Elem<T>::template ld<R>(P, cx, po(7) + s0);
+        v[6] = Elem<T>::template ld<R>(P, cx, po(8) + s0);
     } else {
-        v[2] = IO::template bld<AUX>(P, cx, 2 * pb + sd);
-        v[5] = IO::template bld<AUX>(P, cl, 5 * pb + sd);
-        v[6] = IO::template bld<AUX>(P, cr, 6 * pb + sd);
+        v[2] = Elem<T>::template ld<R>(P, cx, po(2) + sd);
+        v[5] = Elem<T>::template ld<R>(P, cl, po(5) + sd);
+        v[6] = Elem<T>::template ld<R>(P, cr, po(6) + sd);
     }
     if (WALLS && top) {
-        v[4] = IO::template bld<AUX>(P, cx, 2 * pb + s0);
-        v[7] = IO::template bld<AUX>(P, cx, 5 * pb + s0);
-        v[8] = IO::template bld<AUX>(P, cx, 6 * pb + s0);
+        v[4] = Elem<T>::template ld<R>(P, cx, po(2) + s0);
+        v[7] = Elem<T>::template ld<R>(P, cx, po(5) + s0);
+        v[8] = Elem<T>::template ld<R>(P, cx, po(6) + s0);
     } else {
-        v[4] = IO::template bld<AUX>(P, cx, 4 * pb + su);
-        v[7] = IO::template bld<AUX>(P, cr, 7 * pb + su);
-        v[8] = IO::template bld<AUX>(P, cl, 8 * pb + su);
+        v[4] = Elem<T>::template ld<R>(P, cx, po(4) + su);
+        v[7] = Elem<T>::template ld<R>(P, cr, po(7) + su);
+        v[8] = Elem<T>::template ld<R>(P, cl, po(8) + su);
     }
 }
 
-// The same pull for one arbitrary node (readers; plain global loads, any y per lane).
-template <class S>
-__device__ __forceinline__ void pull_node(const S *__restrict__ P, const Geo &geo, size_t n, double v[9])
+// The same pull for one arbitrary node (readers; any y per lane), in double.
+__device__ __forceinline__ void pull_node(const SetView &P, const Geo &geo, size_t n, double v[9])
 {
-    using IO = Io<S>;
     const int nx = geo.nx, ny = geo.ny;
     const int y = (int)(n / nx), x = (int)(n % nx);
     const int xl = x == 0 ? nx - 1 : x - 1, xr = x == nx - 1 ? 0 : x + 1;
-    const size_t N = geo.plane;
     for (int i = 0; i < 9; ++i) {
         int xs = kCX[i] > 0 ? xl : (kCX[i] < 0 ? xr : x);
         int ys = y - kCY[i];
@@ -201,7 +258,7 @@ __device__ __forceinline__ void pull_node(const S *__restrict__ P, const Geo &ge
                 ys = ys < 0 ? ys + ny : ys - ny;
             }
         }
-        v[i] = (double)IO::ld(P + (size_t)ii * N + (size_t)ys * nx + xs);
+        v[i] = view_ld(P, ii, (size_t)ys * nx + xs);
     }
 }
 
@@ -219,8 +276,7 @@ template <class R> __device__ __forceinline__ R sum9(const R v[9])
 // c20, c02 and c22 given as deviations from their resting values 1/3, 1/3 and 1/9.  Output:
 // f_i - w_i.  The central moments are shifted back to raw moments m_pq = sum f c_x^p c_y^q
 // (binomial expansion in v), the raw moments of the weights are taken off, and the D2Q9
-// raw-moment map is inverted as the tensor product of the 1-D map
-// (m0, m1, m2) -> (f_0, f_+, f_-) = (m0 - m2, (m1 + m2)/2, (m2 - m1)/2).
+// raw-moment map is inverted as the tensor product of the 1-D map.
 
 template <class R>
 __device__ __forceinline__ void from_central(R rd, R rho, R ux, R uy, R c10, R c01, R c20d, R c02d,
@@ -297,10 +353,6 @@ __device__ __forceinline__ void g_equilibrium(R phi, R gmu, R ux, R uy, R out[9]
     out[0] = phi - (R)(5.0 / 9.0) * gmu - (R)(2.0 / 3.0) * phi * u2;
 }
 
-// ------------------------------------------------------------------------------------------
-// one node: central-moment collision of f (Eq. (17)) and BGK of g (Eq. (7)).
-// f and fo hold f_i - w_i.
-
 template <class R> struct Rcp;
 template <> struct Rcp<double> {
     static __device__ __forceinline__ double of(double v) { return 1.0 / v; }
@@ -308,6 +360,10 @@ template <> struct Rcp<double> {
 template <> struct Rcp<float> {
     static __device__ __forceinline__ float of(float v) { return __builtin_amdgcn_rcpf(v); }  // 1 ulp
 };
+
+// ------------------------------------------------------------------------------------------
+// one node: central-moment collision of f (Eq. (17)) and BGK of g (Eq. (7)).
+// f and fo hold f_i - w_i.
 
 template <class R, bool FORCE>
 __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, R dpx, R dpy,
@@ -369,32 +425,36 @@ __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, 
 }
 
 // ------------------------------------------------------------------------------------------
-// the step kernel.  A workgroup owns a tile of 64 * wx columns by rows_t rows; each of its waves
+// the step kernel.  A workgroup owns a tile of 64 * wx columns by `rows` rows; each of its waves
 // owns one 64-column row segment.  Every wave pulls f and g of its own nodes, sums phi into an
 // LDS tile with a one-node halo, and the halo is filled by the same pulls one node further out:
 // the waves of the first and last tile row also pull g of the rows above and below, and lanes 0
 // and 1 of the first wave column pull the two halo columns.  One barrier later every node reads
 // its 3x3 phi stencil from LDS, collides and stores f*, g* at its own node (non-temporal).
 //
-// Every load of a workgroup is issued before its barrier, and workgroups are dispatched in
-// row-major tile order, so the waves resident at any moment cover a compact band of rows: the
-// HBM sees a few long streams per plane instead of many short ones.  The halo re-reads (one
-// extra g row per tile row-pair, two columns per tile) are served by L2 and the MALL.
-// Workgroups are dealt round-robin to the 8 XCDs; with a multiple of 8 tiles per tile row the
-// tiles above and below a tile land on its XCD, so its halo rows are hits in the same L2.
+// Every load of a workgroup is issued before its barrier (at raised wave priority, f first), and
+// workgroups are dispatched in row-major tile order, so the waves resident at any moment cover a
+// compact band of rows: the HBM sees a few long streams per plane instead of many short ones.
+// The halo re-reads are served by L2 and the MALL.  With a multiple of 8 tiles per tile row the
+// tiles above and below a tile are dealt to its XCD, so its halo rows are hits in the same L2.
 
-template <class S, bool WALLS, bool FORCE>
-__global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ fa, const S *__restrict__ ga,
-                                                         S *__restrict__ fb, S *__restrict__ gb, Geo geo,
-                                                         Phys<typename Io<S>::R> c, int *__restrict__ flag)
+template <class M> constexpr int kMaxThreads = sizeof(typename M::R) == 8 ? 512 : 1024;
+
+template <class M, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(kMaxThreads<M>) void
+k_step(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ ga,
+       unsigned char *__restrict__ fb, unsigned char *__restrict__ gb, Geo geo,
+       Phys<typename M::R> c, int *__restrict__ flag)
 {
-    using R = typename Io<S>::R;
-    using IO = Io<S>;
-    constexpr uint32_t E = sizeof(S);
+    using R = typename M::R;
+    using F = typename M::F;
+    using G0 = typename M::G0;
+    using G = typename M::G;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    R *phs = reinterpret_cast<R *>(lds_raw);  // [rows_t + 2][ldw]
+    R *phs = reinterpret_cast<R *>(lds_raw);  // [rows + 2][ldw]
 
     const int nx = geo.nx, ny = geo.ny;
+    const uint32_t N = geo.plane;
     const int wx = geo.wx, rows_t = geo.rows;
     const int ldw = 64 * wx + 2;
     const int lane = threadIdx.x & 63;
@@ -407,53 +467,53 @@ __global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ f
     const int y0 = rg * rows_t;
     const int y1 = min(y0 + rows_t, ny);
     const int y = y0 + wr;
-    const bool row_ok = y < y1;                       // uniform per wave
+    const bool row_ok = y < y1;  // uniform per wave
     const int xr_ = X0 + wc * 64 + lane;
     const bool col_ok = xr_ < X1;
     const bool valid = row_ok && col_ok;
-    const int x = col_ok ? xr_ : X1 - 1;              // clamped for addressing
+    const int x = col_ok ? xr_ : X1 - 1;  // clamped for addressing
     const int yy = row_ok ? y : y1 - 1;
-    const int xl = x == 0 ? nx - 1 : x - 1;
-    const int xr = x == nx - 1 ? 0 : x + 1;
-    const uint32_t cx = (uint32_t)x * E, cl = (uint32_t)xl * E, cr = (uint32_t)xr * E;
-    const uint32_t pb = geo.plane * E;
-    const rsrc_t rfa = make_rsrc(fa, 9 * geo.plane), rga = make_rsrc(ga, 9 * geo.plane);
-    const rsrc_t rfb = make_rsrc(fb, 9 * geo.plane), rgb = make_rsrc(gb, 9 * geo.plane);
-    const int slot = wc * 64 + lane + 1;              // LDS column of this lane
-    const int last = y1 - y0 - 1;                     // last valid tile row
+    const uint32_t xl = x == 0 ? nx - 1 : x - 1;
+    const uint32_t xr = x == nx - 1 ? 0 : x + 1;
+    const rsrc_t rfa = make_rsrc(fa, set_bytes<F, F>(N));
+    const rsrc_t rga = make_rsrc(ga, set_bytes<G0, G>(N));
+    const rsrc_t rfb = make_rsrc(fb, set_bytes<F, F>(N));
+    const rsrc_t rgb = make_rsrc(gb, set_bytes<G0, G>(N));
+    const int slot = wc * 64 + lane + 1;  // LDS column of this lane
+    const int last = y1 - y0 - 1;         // last valid tile row
+    auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
 
     // own populations; the loads go out at raised wave priority so that the memory pipeline of
     // the CU keeps being fed while other workgroups compute
     __builtin_amdgcn_s_setprio(3);
     R g[9], f[9];
-    pull_row<S, WALLS, kFLoad>(rfa, pb, nx, ny, yy, cx, cl, cr, f);
-    pull_row<S, WALLS, kGLoad>(rga, pb, nx, ny, yy, cx, cl, cr, g);
+    pull_row<F, F, R, WALLS>(rfa, N, nx, ny, yy, (uint32_t)x, xl, xr, f);
+    pull_row<G0, G, R, WALLS>(rga, N, nx, ny, yy, (uint32_t)x, xl, xr, g);
     const R phi_own = sum9(g);
     if (valid) phs[(wr + 1) * ldw + slot] = phi_own;
 
-    // halo rows: the first tile row fetches the row above, the last valid one the row below
-    auto halo_row = [&](int hy, int hslot_row, int own_slot_row) {
-        if (WALLS && (hy < 0 || hy >= ny)) {  // ghost row behind a wall: mirror
-            if (col_ok) phs[hslot_row * ldw + slot] = phi_own;
-            (void)own_slot_row;
+    // halo rows: the first tile row fetches the row above, the last valid one the row below;
+    // behind a wall the ghost row mirrors the first / last row
+    auto halo_row = [&](int hy, int srow) {
+        if (WALLS && (hy < 0 || hy >= ny)) {
+            if (col_ok) phs[srow * ldw + slot] = phi_own;
         } else {
             R h[9];
-            pull_row<S, WALLS, kGLoad>(rga, pb, nx, ny, hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy), cx, cl, cr, h);
-            if (col_ok) phs[hslot_row * ldw + slot] = sum9(h);
+            pull_row<G0, G, R, WALLS>(rga, N, nx, ny, wrap_row(hy), (uint32_t)x, xl, xr, h);
+            if (col_ok) phs[srow * ldw + slot] = sum9(h);
         }
     };
-    if (wr == 0) halo_row(y0 - 1, 0, 1);
-    if (wr == last) halo_row(y1, last + 2, last + 1);
+    if (wr == 0) halo_row(y0 - 1, 0);
+    if (wr == last) halo_row(y1, last + 2);
 
     // halo columns (x = X0 - 1 on lane 0, x = X1 on lane 1) for this wave's row and, on the
     // first / last tile row, the corner rows
     if (wc == 0 && lane < 2 && wr <= last) {
-        const int hx = lane == 0 ? (X0 == 0 ? nx - 1 : X0 - 1) : (X1 == nx ? 0 : X1);
-        const int hxl = hx == 0 ? nx - 1 : hx - 1, hxr = hx == nx - 1 ? 0 : hx + 1;
-        const uint32_t hcx = (uint32_t)hx * E, hcl = (uint32_t)hxl * E, hcr = (uint32_t)hxr * E;
+        const uint32_t hx = lane == 0 ? (X0 == 0 ? nx - 1 : X0 - 1) : (X1 == nx ? 0 : X1);
+        const uint32_t hxl = hx == 0 ? nx - 1 : hx - 1, hxr = hx == (uint32_t)nx - 1 ? 0 : hx + 1;
         const int hs = lane == 0 ? 0 : X1 - X0 + 1;
         R h[9];
-        pull_row<S, WALLS, kGLoad>(rga, pb, nx, ny, y, hcx, hcl, hcr, h);
+        pull_row<G0, G, R, WALLS>(rga, N, nx, ny, y, hx, hxl, hxr, h);
         const R ph = sum9(h);
         phs[(wr + 1) * ldw + hs] = ph;
         for (int side = 0; side < 2; ++side) {
@@ -465,7 +525,7 @@ __global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ f
                 phs[srow * ldw + hs] = ph;
             } else {
                 R h2[9];
-                pull_row<S, WALLS, kGLoad>(rga, pb, nx, ny, hy < 0 ? hy + ny : (hy >= ny ? hy - ny : hy), hcx, hcl, hcr, h2);
+                pull_row<G0, G, R, WALLS>(rga, N, nx, ny, wrap_row(hy), hx, hxl, hxr, h2);
                 phs[srow * ldw + hs] = sum9(h2);
             }
         }
@@ -489,19 +549,21 @@ __global__ __launch_bounds__(kMaxThreads<S>) void k_step(const S *__restrict__ f
     if (__any(bad) && lane == 0) atomicOr(flag, 1);
 
     if (col_ok) {
-        const uint32_t so = (uint32_t)y * (uint32_t)nx * E;
+        const uint32_t ux_ = (uint32_t)x, uy_ = (uint32_t)y, unx = (uint32_t)nx;
+        constexpr uint32_t bf = sizeof(F), bg0 = sizeof(G0), bg = sizeof(G);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            IO::bst(rfb, cx, i * pb + so, fo[i]);
-            IO::bst(rgb, cx, i * pb + so, go[i]);
-        }
+        for (int i = 0; i < 9; ++i) Elem<F>::template st<R>(rfb, ux_ * bf, plane_off<F, F>(i, N) + uy_ * unx * bf, fo[i]);
+        Elem<G0>::template st<R>(rgb, ux_ * bg0, uy_ * unx * bg0, go[0]);
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+            Elem<G>::template st<R>(rgb, ux_ * bg, plane_off<G0, G>(i, N) + uy_ * unx * bg, go[i]);
     }
 }
 
 // ------------------------------------------------------------------------------------------
 // initialisation.  k_equilibria computes the equilibria of the given macroscopic planes into
-// a post-streaming state (9 + 9 planes, node-local); k_unstream stores them in pull layout:
-// P[i](z) = F[i](z + c_i), or F[opp(i)](z) where z + c_i is behind a wall.
+// a post-streaming state (9 + 9 planes, node-local, storage types); k_unstream stores them in
+// pull layout: P[i](z) = F[i](z + c_i), or F[opp(i)](z) where z + c_i is behind a wall.
 
 __device__ __forceinline__ double plane_at(const double *p, int nx, int ny, bool walls, int x, int y)
 {
@@ -514,13 +576,11 @@ __device__ __forceinline__ double plane_at(const double *p, int nx, int ny, bool
     return p[(size_t)y * nx + x];
 }
 
-template <class S>
+template <class R>
 __global__ void k_equilibria(const double *__restrict__ phi0, const double *__restrict__ rho0,
                              const double *__restrict__ ux0, const double *__restrict__ uy0,
-                             S *__restrict__ F, S *__restrict__ G, Geo geo,
-                             Phys<typename Io<S>::R> c)
+                             SetView F, SetView G, Geo geo, Phys<R> c)
 {
-    using R = typename Io<S>::R;
     const int nx = geo.nx, ny = geo.ny;
     const size_t N = geo.plane;
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
@@ -550,14 +610,13 @@ __global__ void k_equilibria(const double *__restrict__ phi0, const double *__re
         from_central(rd, rho, ux, uy, (R)0, (R)0, (R)0.5 * (e3 + e4), (R)0.5 * (e3 - e4), e5, e6, e7, e8, fe);
         g_equilibrium(phi, c.Gamma * mu, ux, uy, ge);
         for (int i = 0; i < 9; ++i) {
-            Io<S>::st(F + i * N + n, (S)fe[i]);
-            Io<S>::st(G + i * N + n, (S)ge[i]);
+            view_st(F, i, n, (double)fe[i]);
+            view_st(G, i, n, (double)ge[i]);
         }
     }
 }
 
-template <class S>
-__global__ void k_unstream(const S *__restrict__ F, S *__restrict__ P, Geo geo)
+__global__ void k_unstream(SetView F, SetView P, Geo geo)
 {
     const int nx = geo.nx, ny = geo.ny;
     const size_t N = geo.plane;
@@ -568,34 +627,34 @@ __global__ void k_unstream(const S *__restrict__ F, S *__restrict__ P, Geo geo)
         const int y = (int)(n / nx), x = (int)(n % nx);
         int xs = x + kCX[i], ys = y + kCY[i];
         xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-        size_t src;
+        int si = i;
+        size_t sn;
         if (ys < 0 || ys >= ny) {
             if (geo.walls) {
-                src = (size_t)kOpp[i] * N + n;
+                si = kOpp[i];
+                sn = n;
             } else {
                 ys = ys < 0 ? ys + ny : ys - ny;
-                src = (size_t)i * N + (size_t)ys * nx + xs;
+                sn = (size_t)ys * nx + xs;
             }
         } else {
-            src = (size_t)i * N + (size_t)ys * nx + xs;
+            sn = (size_t)ys * nx + xs;
         }
-        P[t] = F[src];
+        view_copy(F, si, sn, P, i, n);
     }
 }
 
 // ------------------------------------------------------------------------------------------
 // readers: post-streaming populations, macroscopic fields and FP64 reductions (in double).
 
-template <class S>
-__global__ void k_fields(const S *__restrict__ f, const S *__restrict__ g, Geo geo, double a,
-                         double hFx, double hFy, double *phi, double *rho, double *ux, double *uy,
-                         double *p0)
+__global__ void k_fields(SetView f, SetView g, Geo geo, double a, double hFx, double hFy, double *phi,
+                         double *rho, double *ux, double *uy, double *p0)
 {
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
         double fv[9], gv[9];
-        pull_node<S>(f, geo, n, fv);
-        pull_node<S>(g, geo, n, gv);
+        pull_node(f, geo, n, fv);
+        pull_node(g, geo, n, gv);
         const double r = 1.0 + sum9(fv);
         const double ph = sum9(gv);
         const double jx = (fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7]);
@@ -609,29 +668,25 @@ __global__ void k_fields(const S *__restrict__ f, const S *__restrict__ g, Geo g
 }
 
 // one post-streaming population plane (which = 0..8: f_i, 9..17: g_i) as FP64
-template <class S>
-__global__ void k_population(const S *__restrict__ f, const S *__restrict__ g, Geo geo, int which,
-                             double *out)
+__global__ void k_population(SetView f, SetView g, Geo geo, int which, double *out)
 {
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
         double v[9];
-        pull_node<S>(which < 9 ? f : g, geo, n, v);
+        pull_node(which < 9 ? f : g, geo, n, v);
         out[n] = which < 9 ? v[which] + kW[which] : v[which - 9];
     }
 }
 
-template <class S>
-__global__ __launch_bounds__(kReduceThreads) void k_diag(const S *__restrict__ f,
-                                                         const S *__restrict__ g, Geo geo,
-                                                         double hFx, double hFy, double *partial)
+__global__ __launch_bounds__(kReduceThreads) void k_diag(SetView f, SetView g, Geo geo, double hFx,
+                                                         double hFy, double *partial)
 {
     double acc[kDiagFields] = {0, 0, 0, 0, 0, 0, 0};  // phi, |phi|, rho, jx, jy, max|u|, nonfinite
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
         double fv[9], gv[9];
-        pull_node<S>(f, geo, n, fv);
-        pull_node<S>(g, geo, n, gv);
+        pull_node(f, geo, n, fv);
+        pull_node(g, geo, n, gv);
         const double r = 1.0 + sum9(fv), ph = sum9(gv);
         const double jx = (fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7]) + hFx;
         const double jy = (fv[2] + fv[5] + fv[6]) - (fv[4] + fv[7] + fv[8]) + hFy;
@@ -692,11 +747,12 @@ struct lbcm_handle {
     lbcm_params p{};
     hipStream_t stream = nullptr;
     int device = 0;
-    size_t elem = 0;         // bytes per stored value
-    size_t pair_bytes = 0;   // bytes of one (f, g) pair
-    char *ws = nullptr;      // workspace base
+    size_t fset = 0, gset = 0;  // bytes of the f and g sets
+    size_t fset_al = 0;         // f set bytes rounded up to the alignment (offset of the g set)
+    size_t pair_bytes = 0;      // bytes of one (f, g) pair
+    char *ws = nullptr;         // workspace base
     bool owns_ws = false;
-    int cur = 0;             // pair holding the current state
+    int cur = 0;                // pair holding the current state
     bool ready = false;
     int64_t step = 0;
     double *diag_partial = nullptr;
@@ -712,13 +768,29 @@ std::string g_create_error;
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
-size_t elem_bytes(int precision)
+// element kinds of the f planes, of g_0 and of g_1..g_8
+struct Kinds {
+    int f, g0, g;
+};
+bool kinds_of(int precision, Kinds &k)
 {
     switch (precision) {
-    case LBCM_FP64: return 8;
-    case LBCM_FP32: return 4;
-    default: return 0;
+    case LBCM_FP64: k = {kKindF64, kKindF64, kKindF64}; return true;
+    case LBCM_FP32: k = {kKindF32, kKindF32, kKindF32}; return true;
+    case LBCM_FP16_SHIFTED: k = {kKindF16, kKindF32, kKindF16}; return true;
+    case LBCM_BF16_SHIFTED: k = {kKindB16, kKindF32, kKindB16}; return true;
+    default: return false;
     }
+}
+size_t kind_bytes(int kind) { return kind == kKindF64 ? 8 : (kind == kKindF32 ? 4 : 2); }
+
+void set_sizes(const lbcm_params *p, size_t &fset, size_t &gset)
+{
+    Kinds k;
+    kinds_of(p->precision, k);
+    const size_t N = (size_t)p->nx * (size_t)p->ny;
+    fset = 9 * N * kind_bytes(k.f);
+    gset = N * kind_bytes(k.g0) + 8 * N * kind_bytes(k.g);
 }
 
 const char *check_params(const lbcm_params *p)
@@ -726,10 +798,11 @@ const char *check_params(const lbcm_params *p)
     if (!p) return "params is NULL";
     if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
     if (p->bc_y != LBCM_BC_PERIODIC && p->bc_y != LBCM_BC_WALLS) return "bc_y must be 0 or 1";
-    if (elem_bytes(p->precision) == 0) return "unsupported precision";
+    Kinds k;
+    if (!kinds_of(p->precision, k)) return "unsupported precision";
     const double N = (double)p->nx * (double)p->ny;
-    if (9.0 * N * (double)elem_bytes(p->precision) > 4294967295.0)
-        return "lattice too large: one population set (9 planes) must stay below 4 GiB";
+    const double per_node = std::max(9.0 * (double)kind_bytes(k.f), (double)kind_bytes(k.g0) + 8.0 * kind_bytes(k.g));
+    if (N * per_node > 4294967295.0) return "lattice too large: one population set (9 planes) must stay below 4 GiB";
     if (!(p->nu_l > 0) || !(p->nu_g > 0)) return "viscosities must be > 0";
     if (!(p->mobility > 0) || !(p->Gamma > 0)) return "mobility and Gamma must be > 0";
     if (!(p->omega3 > 0 && p->omega3 < 2)) return "omega3 must lie in (0, 2)";
@@ -744,10 +817,15 @@ const char *check_params(const lbcm_params *p)
 
 size_t pair_bytes_of(const lbcm_params *p)
 {
-    return align_up(18 * (size_t)p->nx * (size_t)p->ny * elem_bytes(p->precision));
+    size_t fs, gs;
+    set_sizes(p, fs, gs);
+    return align_up(fs) + align_up(gs);
 }
 
-size_t tail_bytes() { return align_up(kReduceBlocks * kDiagFields * sizeof(double)) + align_up(kDiagFields * sizeof(double)) + kAlign; }
+size_t tail_bytes()
+{
+    return align_up(kReduceBlocks * kDiagFields * sizeof(double)) + align_up(kDiagFields * sizeof(double)) + kAlign;
+}
 
 int fail(lbcm_handle *h, int code, const std::string &msg)
 {
@@ -791,7 +869,7 @@ Geo make_geo(const lbcm_params &p)
     g.wx = p.tile_wx > 0 ? p.tile_wx : kDefaultWx;
     if (g.wx > need) g.wx = need;
     if (g.wx > max_waves) g.wx = max_waves;
-    int rows = p.tile_rows > 0 ? p.tile_rows : (p.precision == LBCM_FP64 ? 2 : kDefaultRows);
+    int rows = p.tile_rows > 0 ? p.tile_rows : kDefaultRows;
     if (rows > max_waves / g.wx) rows = max_waves / g.wx;
     if (rows > p.ny) rows = p.ny;
     g.rows = rows;
@@ -801,9 +879,24 @@ Geo make_geo(const lbcm_params &p)
     return g;
 }
 
-template <class S> S *pop(lbcm_handle *h, int pair, int set)  // set 0 = f, 1 = g
+unsigned char *set_base(lbcm_handle *h, int pair, int set)  // set 0 = f, 1 = g
 {
-    return reinterpret_cast<S *>(h->ws + (size_t)pair * h->pair_bytes) + (size_t)set * 9 * h->p.nx * (size_t)h->p.ny;
+    return reinterpret_cast<unsigned char *>(h->ws + (size_t)pair * h->pair_bytes + (set ? h->fset_al : 0));
+}
+
+SetView view_of(lbcm_handle *h, int pair, int set)
+{
+    Kinds k;
+    kinds_of(h->p.precision, k);
+    const size_t N = (size_t)h->p.nx * h->p.ny;
+    SetView v;
+    v.base = set_base(h, pair, set);
+    const int k0 = set ? k.g0 : k.f, k1 = set ? k.g : k.f;
+    for (int i = 0; i < 9; ++i) {
+        v.kind[i] = i == 0 ? k0 : k1;
+        v.off[i] = (uint32_t)(i == 0 ? 0 : N * kind_bytes(k0) + (size_t)(i - 1) * N * kind_bytes(k1));
+    }
+    return v;
 }
 
 int grid_for(size_t n, int threads)
@@ -814,9 +907,9 @@ int grid_for(size_t n, int threads)
     return (int)b;
 }
 
-template <class S> int launch_steps(lbcm_handle *h, int64_t nsteps)
+template <class M> int launch_steps(lbcm_handle *h, int64_t nsteps)
 {
-    using R = typename Io<S>::R;
+    using R = typename M::R;
     const Geo geo = make_geo(h->p);
     const Phys<R> c = make_phys<R>(h->p);
     const bool walls = h->p.bc_y == LBCM_BC_WALLS;
@@ -826,14 +919,14 @@ template <class S> int launch_steps(lbcm_handle *h, int64_t nsteps)
     const dim3 grid((unsigned)nblk), block(64 * geo.wx * geo.rows);
     const size_t lds = (size_t)(geo.rows + 2) * (64 * geo.wx + 2) * sizeof(R);
     for (int64_t s = 0; s < nsteps; ++s) {
-        const S *fa = pop<S>(h, h->cur, 0), *ga = pop<S>(h, h->cur, 1);
-        S *fb = pop<S>(h, 1 - h->cur, 0), *gb = pop<S>(h, 1 - h->cur, 1);
+        const unsigned char *fa = set_base(h, h->cur, 0), *ga = set_base(h, h->cur, 1);
+        unsigned char *fb = set_base(h, 1 - h->cur, 0), *gb = set_base(h, 1 - h->cur, 1);
         if (walls) {
-            if (force) hipLaunchKernelGGL((k_step<S, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            else hipLaunchKernelGGL((k_step<S, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            if (force) hipLaunchKernelGGL((k_step<M, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            else hipLaunchKernelGGL((k_step<M, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
         } else {
-            if (force) hipLaunchKernelGGL((k_step<S, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            else hipLaunchKernelGGL((k_step<S, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            if (force) hipLaunchKernelGGL((k_step<M, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            else hipLaunchKernelGGL((k_step<M, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
         }
         HIP_TRY(h, hipGetLastError());
         h->cur = 1 - h->cur;
@@ -848,21 +941,21 @@ template <class S> int launch_steps(lbcm_handle *h, int64_t nsteps)
     return LBCM_OK;
 }
 
-template <class S>
+template <class M>
 int do_init(lbcm_handle *h, const double *phi0, const double *rho0, const double *ux0, const double *uy0)
 {
-    using R = typename Io<S>::R;
+    using R = typename M::R;
     const Geo geo = make_geo(h->p);
     const Phys<R> c = make_phys<R>(h->p);
     // equilibria into the spare pair, then un-stream into pair 0
-    S *F = pop<S>(h, 1, 0), *G = pop<S>(h, 1, 1);
+    const SetView F = view_of(h, 1, 0), G = view_of(h, 1, 1);
     const int gb = grid_for(geo.plane, 256);
-    hipLaunchKernelGGL((k_equilibria<S>), dim3(gb), dim3(256), 0, h->stream, phi0, rho0, ux0, uy0, F, G, geo, c);
+    hipLaunchKernelGGL((k_equilibria<R>), dim3(gb), dim3(256), 0, h->stream, phi0, rho0, ux0, uy0, F, G, geo, c);
     HIP_TRY(h, hipGetLastError());
     const int gu = grid_for(9 * (size_t)geo.plane, 256);
-    hipLaunchKernelGGL((k_unstream<S>), dim3(gu), dim3(256), 0, h->stream, F, pop<S>(h, 0, 0), geo);
+    hipLaunchKernelGGL(k_unstream, dim3(gu), dim3(256), 0, h->stream, F, view_of(h, 0, 0), geo);
     HIP_TRY(h, hipGetLastError());
-    hipLaunchKernelGGL((k_unstream<S>), dim3(gu), dim3(256), 0, h->stream, G, pop<S>(h, 0, 1), geo);
+    hipLaunchKernelGGL(k_unstream, dim3(gu), dim3(256), 0, h->stream, G, view_of(h, 0, 1), geo);
     HIP_TRY(h, hipGetLastError());
     hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(1), 0, h->stream, h->flag);
     HIP_TRY(h, hipGetLastError());
@@ -872,46 +965,46 @@ int do_init(lbcm_handle *h, const double *phi0, const double *rho0, const double
     return LBCM_OK;
 }
 
-template <class S>
 int do_fields(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy, double *p0)
 {
     const Geo geo = make_geo(h->p);
     const int gb = grid_for(geo.plane, 256);
-    const S *f = pop<S>(h, h->cur, 0), *g = pop<S>(h, h->cur, 1);
-    hipLaunchKernelGGL((k_fields<S>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, h->p.a,
-                       0.5 * h->p.force_x, 0.5 * h->p.force_y, phi, rho, ux, uy, p0);
+    hipLaunchKernelGGL(k_fields, dim3(gb), dim3(256), 0, h->stream, view_of(h, h->cur, 0), view_of(h, h->cur, 1), geo,
+                       h->p.a, 0.5 * h->p.force_x, 0.5 * h->p.force_y, phi, rho, ux, uy, p0);
     HIP_TRY(h, hipGetLastError());
     return LBCM_OK;
 }
 
-template <class S> int do_population(lbcm_handle *h, int which, double *out)
+int do_population(lbcm_handle *h, int which, double *out)
 {
     const Geo geo = make_geo(h->p);
     const int gb = grid_for(geo.plane, 256);
-    const S *f = pop<S>(h, h->cur, 0), *g = pop<S>(h, h->cur, 1);
-    hipLaunchKernelGGL((k_population<S>), dim3(gb), dim3(256), 0, h->stream, f, g, geo, which, out);
+    hipLaunchKernelGGL(k_population, dim3(gb), dim3(256), 0, h->stream, view_of(h, h->cur, 0), view_of(h, h->cur, 1),
+                       geo, which, out);
     HIP_TRY(h, hipGetLastError());
     return LBCM_OK;
 }
 
-template <class S> int do_diag(lbcm_handle *h)
+int do_diag(lbcm_handle *h)
 {
     const Geo geo = make_geo(h->p);
-    const S *f = pop<S>(h, h->cur, 0), *g = pop<S>(h, h->cur, 1);
-    hipLaunchKernelGGL((k_diag<S>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, h->stream, f, g, geo,
-                       0.5 * h->p.force_x, 0.5 * h->p.force_y, h->diag_partial);
+    hipLaunchKernelGGL(k_diag, dim3(kReduceBlocks), dim3(kReduceThreads), 0, h->stream, view_of(h, h->cur, 0),
+                       view_of(h, h->cur, 1), geo, 0.5 * h->p.force_x, 0.5 * h->p.force_y, h->diag_partial);
     HIP_TRY(h, hipGetLastError());
-    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(kReduceThreads), 0, h->stream, h->diag_partial, kReduceBlocks, h->diag_out);
+    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(kReduceThreads), 0, h->stream, h->diag_partial, kReduceBlocks,
+                       h->diag_out);
     HIP_TRY(h, hipGetLastError());
     return LBCM_OK;
 }
 
-// host-side dispatch on the storage precision
+// host-side dispatch on the storage mode
 template <class Fn> int dispatch(lbcm_handle *h, Fn &&fn)
 {
     switch (h->p.precision) {
-    case LBCM_FP64: return fn((double *)nullptr);
-    case LBCM_FP32: return fn((float *)nullptr);
+    case LBCM_FP64: return fn(ModeF64{});
+    case LBCM_FP32: return fn(ModeF32{});
+    case LBCM_FP16_SHIFTED: return fn(ModeF16{});
+    case LBCM_BF16_SHIFTED: return fn(ModeB16{});
     default: return fail(h, LBCM_EINVAL, "unsupported precision");
     }
 }
@@ -955,7 +1048,8 @@ int lbcm_create(const lbcm_params *p, lbcm_handle **out)
     }
     h->p = *p;
     h->stream = (hipStream_t)p->stream;
-    h->elem = elem_bytes(p->precision);
+    set_sizes(p, h->fset, h->gset);
+    h->fset_al = align_up(h->fset);
     h->pair_bytes = pair_bytes_of(p);
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
@@ -989,14 +1083,15 @@ int lbcm_init_device(lbcm_handle *h, const double *phi0, const double *rho0, con
 {
     if (!h) return LBCM_EINVAL;
     if (!phi0) return fail(h, LBCM_EINVAL, "phi0 is NULL");
-    return dispatch(h, [&](auto *tag) { return do_init<std::remove_pointer_t<decltype(tag)>>(h, phi0, rho0, ux0, uy0); });
+    return dispatch(h, [&](auto mode) { return do_init<decltype(mode)>(h, phi0, rho0, ux0, uy0); });
 }
 
 int lbcm_init(lbcm_handle *h, const double *phi0, const double *rho0, const double *ux0, const double *uy0)
 {
     if (!h) return LBCM_EINVAL;
     if (!phi0) return fail(h, LBCM_EINVAL, "phi0 is NULL");
-    // stage the host planes in pair 0 (overwritten only by the final un-stream of the init)
+    // stage the host planes in pair 0 (>= 36 bytes per node in every mode; overwritten only by
+    // the final un-stream of the initialisation)
     const size_t N = (size_t)h->p.nx * h->p.ny;
     double *stage = (double *)h->ws;
     const double *src[4] = {phi0, rho0, ux0, uy0};
@@ -1017,21 +1112,21 @@ int lbcm_step(lbcm_handle *h, int64_t nsteps)
     if (!h) return LBCM_EINVAL;
     if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_step before lbcm_init");
     if (nsteps < 0) return fail(h, LBCM_EINVAL, "nsteps must be >= 0");
-    return dispatch(h, [&](auto *tag) { return launch_steps<std::remove_pointer_t<decltype(tag)>>(h, nsteps); });
+    return dispatch(h, [&](auto mode) { return launch_steps<decltype(mode)>(h, nsteps); });
 }
 
 int lbcm_fields_device(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy, double *p0)
 {
     if (!h) return LBCM_EINVAL;
     if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_fields before lbcm_init");
-    return dispatch(h, [&](auto *tag) { return do_fields<std::remove_pointer_t<decltype(tag)>>(h, phi, rho, ux, uy, p0); });
+    return do_fields(h, phi, rho, ux, uy, p0);
 }
 
 int lbcm_fields(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy, double *p0)
 {
     if (!h) return LBCM_EINVAL;
     if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_fields before lbcm_init");
-    // one plane at a time through the spare pair (>= 8 bytes per node for every precision)
+    // one plane at a time through the spare pair (>= 8 bytes per node in every mode)
     const size_t N = (size_t)h->p.nx * h->p.ny;
     double *stage = (double *)(h->ws + (size_t)(1 - h->cur) * h->pair_bytes);
     double *dst[5] = {phi, rho, ux, uy, p0};
@@ -1039,7 +1134,7 @@ int lbcm_fields(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy
         if (!dst[k]) continue;
         double *d[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
         d[k] = stage;
-        int rc = lbcm_fields_device(h, d[0], d[1], d[2], d[3], d[4]);
+        int rc = do_fields(h, d[0], d[1], d[2], d[3], d[4]);
         if (rc) return rc;
         HIP_TRY(h, hipMemcpyAsync(dst[k], stage, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -1056,7 +1151,7 @@ int lbcm_populations(lbcm_handle *h, double *f, double *g)
     for (int k = 0; k < 18; ++k) {
         double *dst = k < 9 ? f : g;
         if (!dst) continue;
-        int rc = dispatch(h, [&](auto *tag) { return do_population<std::remove_pointer_t<decltype(tag)>>(h, k, stage); });
+        int rc = do_population(h, k, stage);
         if (rc) return rc;
         HIP_TRY(h, hipMemcpyAsync(dst + (size_t)(k % 9) * N, stage, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -1068,7 +1163,7 @@ int lbcm_diag(lbcm_handle *h, lbcm_diagnostics *out)
 {
     if (!h || !out) return fail(h, LBCM_EINVAL, "NULL argument");
     if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_diag before lbcm_init");
-    int rc = dispatch(h, [&](auto *tag) { return do_diag<std::remove_pointer_t<decltype(tag)>>(h); });
+    int rc = do_diag(h);
     if (rc) return rc;
     double v[kDiagFields];
     HIP_TRY(h, hipMemcpyAsync(v, h->diag_out, sizeof v, hipMemcpyDeviceToHost, h->stream));
@@ -1086,7 +1181,7 @@ int lbcm_diag(lbcm_handle *h, lbcm_diagnostics *out)
 
 size_t lbcm_state_size(const lbcm_handle *h)
 {
-    return h ? 18 * (size_t)h->p.nx * h->p.ny * h->elem : 0;
+    return h ? h->fset + h->gset : 0;
 }
 
 int lbcm_get_state(lbcm_handle *h, void *host, size_t bytes)
@@ -1094,7 +1189,8 @@ int lbcm_get_state(lbcm_handle *h, void *host, size_t bytes)
     if (!h || !host) return fail(h, LBCM_EINVAL, "NULL argument");
     if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_get_state before lbcm_init");
     if (bytes != lbcm_state_size(h)) return fail(h, LBCM_EINVAL, "wrong state size");
-    HIP_TRY(h, hipMemcpyAsync(host, h->ws + (size_t)h->cur * h->pair_bytes, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(host, set_base(h, h->cur, 0), h->fset, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync((char *)host + h->fset, set_base(h, h->cur, 1), h->gset, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return LBCM_OK;
 }
@@ -1104,7 +1200,9 @@ int lbcm_set_state(lbcm_handle *h, const void *host, size_t bytes, int64_t step)
     if (!h || !host) return fail(h, LBCM_EINVAL, "NULL argument");
     if (bytes != lbcm_state_size(h)) return fail(h, LBCM_EINVAL, "wrong state size");
     if (step < 0) return fail(h, LBCM_EINVAL, "step must be >= 0");
-    HIP_TRY(h, hipMemcpyAsync(h->ws + (size_t)h->cur * h->pair_bytes, host, bytes, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(set_base(h, h->cur, 0), host, h->fset, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(set_base(h, h->cur, 1), (const char *)host + h->fset, h->gset, hipMemcpyHostToDevice,
+                              h->stream));
     hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(1), 0, h->stream, h->flag);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipStreamSynchronize(h->stream));

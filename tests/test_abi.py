@@ -41,6 +41,15 @@ def test_workspace_size(prec, elem):
     assert pops <= ws <= pops + 2 * 256 + 128 * 1024
 
 
+@pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
+def test_workspace_size_16bit(prec):
+    nx, ny = 100, 37
+    N = nx * ny
+    ws = lbcm.lbcm_workspace_size(lbcm.make_params(nx, ny, precision=prec))
+    pops = 2 * (9 * N * 2 + N * 4 + 8 * N * 2)  # f in 16 bits, g_0 in FP32, g_1..8 in 16 bits
+    assert pops <= ws <= pops + 4 * 256 + 128 * 1024
+
+
 @pytest.mark.parametrize("kw,frag", [
     (dict(nx=0, ny=4), "nx and ny"),
     (dict(nx=4, ny=-1), "nx and ny"),

@@ -93,6 +93,39 @@ def test_fp32_one_and_50_steps(bc_y):
         assert ef < tol and eg < tol
 
 
+@pytest.mark.parametrize("prec,tol1,tol50", [("fp16s", 3e-5, 3e-4), ("bf16s", 3e-4, 3e-3)])
+@pytest.mark.parametrize("bc_y", [0, 1])
+def test_16bit_storage_one_and_50_steps(prec, tol1, tol50, bc_y):
+    """FP32 arithmetic with f_i - w_i and g_1..g_8 stored in 16 bits (g_0 in FP32).  A stored
+    f deviation of ~0.02 carries a half-ulp of 7.6e-6 in FP16 (6.1e-5 in BF16); the bounds are a
+    few such roundings per step, and about ten times that after 50 steps."""
+    nx, ny = 70, 45
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=38)
+    for steps, tol in ((1, tol1), (50, tol50)):
+        (f, g, m), (fo, go, mo) = both(nx, ny, phi, rho, ux, uy, steps=steps, prec=prec, tile_rows=2,
+                                       bc_y=bc_y, force_x=1e-5, **PHYS)
+        ef, eg = maxerr(f, fo), maxerr(g, go)
+        say(f"  {prec} {steps} steps: max |df| = {ef:.2e}  max |dg| = {eg:.2e}  max |dphi| = "
+            f"{maxerr(m['phi'], mo['phi']):.2e}")
+        assert ef < tol and eg < tol
+
+
+@pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
+def test_16bit_checkpoint_and_tiling(prec):
+    nx, ny = 130, 37
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=39)
+    a = lbcm.Lattice(nx, ny, precision=prec, tile_rows=2, **PHYS).init(phi, rho, ux, uy).step(4)
+    b = lbcm.Lattice(nx, ny, precision=prec, tile_rows=1, tile_wx=1, **PHYS).init(phi, rho, ux, uy).step(4)
+    sa = a.get_state()
+    assert sa.nbytes == 9 * nx * ny * 2 + nx * ny * 4 + 8 * nx * ny * 2
+    assert np.array_equal(sa, b.get_state())
+    a.step(3)
+    c = lbcm.Lattice(nx, ny, precision=prec, **PHYS)
+    c.set_state(sa, step=4)
+    c.step(3)
+    assert np.array_equal(a.get_state(), c.get_state())
+
+
 @pytest.mark.parametrize("nx,ny,bc_y", [(1, 1, 0), (1, 1, 1), (1, 6, 0), (6, 1, 0), (6, 1, 1), (2, 3, 1),
                                         (3, 2, 0), (65, 2, 1), (64, 64, 0), (129, 7, 0), (5, 130, 1)])
 def test_fp64_edge_sizes(nx, ny, bc_y):
