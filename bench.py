@@ -82,6 +82,21 @@ def copy_probe(nbytes: int = 1 << 31, reps: int = 20) -> float:
     return 2 * nbytes / sec / 1e9
 
 
+def measured_traffic(n, precision, args, sec_per_step):
+    """HBM traffic of the step kernel from the committed rocprofv3 counter record of this
+    workload, as GB/s at the live step time; None when no record exists, the tiles differ from
+    the defaults it was taken with, or the kernel source has changed since."""
+    from paper_1803_11345_amd import profile_summary
+
+    path = os.path.join(ROOT, "profiles", f"k_step_spinodal{n}_{precision}_traffic.json")
+    if args.tile_rows or args.tile_wx or not os.path.exists(path):
+        return None, None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != profile_summary.source_digest() or rec.get("nodes") != n * n:
+        return None, None
+    return rec["traffic_bytes_per_launch"] / sec_per_step / 1e9, rec["traffic_bytes_per_launch"]
+
+
 def make_lattice(lbcm, n, precision, args):
     return lbcm.Lattice(n, n, precision=precision, tile_rows=args.tile_rows, tile_wx=args.tile_wx,
                         a=0.04, gamma=0.08, mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05)
@@ -156,6 +171,7 @@ def main():
     d = lat.diag()
     assert d["nonfinite"] == 0, "non-finite state after the timed steps"
     achieved = BYTES_PER_LUP[args.precision] * nodes / sec_per_step / 1e9
+    traffic, traffic_bytes = measured_traffic(n, args.precision, args, sec_per_step)
     out = {
         "metric": BASELINE_METRIC,
         "value": round(mlups, 1),
@@ -174,7 +190,9 @@ def main():
                                f"{args.precision} populations",
                    "nx": n, "ny": n, "precision": args.precision, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic, 1),
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": "k_step", "bytes_per_lup": BYTES_PER_LUP[args.precision]},
         "wall_s_warmup_and_timed": round(wall, 3),
         "sum_phi_drift": abs(d["sum_phi"] - float(np.sum(phi0))) / float(np.sum(np.abs(phi0))),

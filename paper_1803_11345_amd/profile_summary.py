@@ -1,0 +1,116 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+  python -m paper_1803_11345_amd.profile_summary stats  <kernel_stats.csv> --command "..." --out X.md
+  python -m paper_1803_11345_amd.profile_summary traffic <fetch counter_collection.csv>
+         <write counter_collection.csv> --kernel k_step --copy-bytes 2147483648 --nodes N
+         --bytes-per-lup B --command "..." --out X.json
+
+``traffic`` calibrates the two TCC counters with the plain device copy that bench.py --copy-probe
+runs (a copy of --copy-bytes bytes reads and writes exactly that many bytes): each counter of the
+step kernel is scaled by (copy bytes / what the same counter reads for the copy).  The record
+carries the SHA-256 of the kernel source, so bench.py reports the traffic only while the kernel
+is the one that was measured.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import statistics
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "lbcm.hip")
+
+
+def source_digest() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def _short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
+    return name.split("(")[0] if not name.startswith("void ") else name[5:].split("(")[0]
+
+
+def stats_md(path: str, command: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    lines = ["# Kernel time (rocprofv3 --kernel-trace --stats)", "", "Command (from /tmp, TMPDIR=/tmp):", "",
+             "```", command, "```", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} % |")
+    return "\n".join(lines) + "\n"
+
+
+def _per_kernel(path: str, counter: str):
+    out = defaultdict(list)
+    grids = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        grids[r["Kernel_Name"]].append(int(r["Grid_Size"]))
+    return out, grids
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, nodes: int, bytes_per_lup: int,
+            command: str) -> dict:
+    res = {}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        vals, grids = _per_kernel(path, counter)
+        step = [v for k, v in vals.items() if kernel in k]
+        if not step:
+            raise SystemExit(f"no dispatch of {kernel} in {path}")
+        step_vals = step[0]
+        # the probe copy: the copy-kernel dispatches with the largest grid
+        copies = [(g, v) for k in vals if "copyBuffer" in k for g, v in zip(grids[k], vals[k])]
+        gmax = max(g for g, _ in copies)
+        copy_vals = [v for g, v in copies if g == gmax]
+        kib_copy = statistics.median(copy_vals)
+        scale = (copy_bytes / 1024.0) / kib_copy
+        kib = statistics.mean(step_vals)
+        res[key] = {"counter": counter, "step_kib_mean": kib, "step_dispatches": len(step_vals),
+                    "copy_kib_median": kib_copy, "copy_dispatches": len(copy_vals), "scale": scale,
+                    "bytes_per_launch": kib * 1024.0 * scale}
+    alg = nodes * bytes_per_lup
+    total = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
+    return {"kernel": kernel, "source_sha256": source_digest(), "command": command, "nodes": nodes,
+            "bytes_per_lup": bytes_per_lup, "algorithmic_bytes_per_launch": alg,
+            "traffic_bytes_per_launch": total, "traffic_over_algorithmic": total / alg,
+            "read_over_algorithmic": res["fetch"]["bytes_per_launch"] / (alg / 2),
+            "write_over_algorithmic": res["write"]["bytes_per_launch"] / (alg / 2), **res}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--command", required=True)
+    a.add_argument("--out", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_csv")
+    b.add_argument("write_csv")
+    b.add_argument("--kernel", default="k_step")
+    b.add_argument("--copy-bytes", type=int, default=1 << 31)
+    b.add_argument("--nodes", type=int, required=True)
+    b.add_argument("--bytes-per-lup", type=int, required=True)
+    b.add_argument("--command", required=True)
+    b.add_argument("--out", required=True)
+    args = ap.parse_args()
+    if args.what == "stats":
+        open(args.out, "w").write(stats_md(args.csv, args.command))
+    else:
+        rec = traffic(args.fetch_csv, args.write_csv, args.kernel, args.copy_bytes, args.nodes, args.bytes_per_lup,
+                      args.command)
+        json.dump(rec, open(args.out, "w"), indent=2)
+        print(json.dumps({k: rec[k] for k in ("traffic_bytes_per_launch", "traffic_over_algorithmic",
+                                               "read_over_algorithmic", "write_over_algorithmic")}))
+
+
+if __name__ == "__main__":
+    main()
