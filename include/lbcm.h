@@ -146,6 +146,60 @@ int lbcm_destroy(lbcm_handle *h);
 /* Message of the last error on h (or of the last failed lbcm_create when h is NULL). */
 const char *lbcm_last_error(const lbcm_handle *h);
 
+/* Pick the step kernel's tile shape by timing: every (tile_wx, tile_rows) split with tile_wx a
+   power of two up to the lattice width is run `trials` times (reading the current populations
+   and writing the spare copy, so the state does not change), and the fastest is kept in the
+   handle.  Needs lbcm_init first.  Synchronises. */
+int lbcm_autotune(lbcm_handle *h, int trials);
+
+/* Tile shape the step kernel uses (after clamping to the lattice). */
+int lbcm_tile_shape(const lbcm_handle *h, int32_t *wx, int32_t *rows);
+
+/* ---------------------------------------------------------------------------------------------
+   Ensembles: many independent lattices (boxes) of any sizes, boundaries, forces and viscosities,
+   advanced together by one launch per time step that covers every tile of every box.  Each box
+   is an ordinary handle (lbcm_batch_box) whose memory lives in the batch: initialise it with
+   lbcm_init, read it with lbcm_fields / lbcm_diag / lbcm_populations.  All boxes share the
+   precision and the stream (a NULL stream gets a stream of the batch, needed for graph capture).
+   Not thread-safe; lbcm_step on a box handle advances that box alone (the batch notices). */
+typedef struct lbcm_batch lbcm_batch;
+
+/* nboxes parameter sets (workspace fields ignored).  Errors: LBCM_EINVAL (any box invalid,
+   mixed precision or stream), LBCM_ENOMEM, LBCM_EHIP. */
+int lbcm_batch_create(const lbcm_params *boxes, int32_t nboxes, lbcm_batch **out);
+
+/* Handle of box i (owned by the batch; do not destroy it), NULL if i is out of range. */
+lbcm_handle *lbcm_batch_box(lbcm_batch *b, int32_t i);
+
+/* Advance every box by nsteps with one kernel launch per step (every box must be initialised).
+   With graphs enabled (the default) pairs of steps are replayed from a captured hipGraph.
+   Asynchronous. */
+int lbcm_batch_step(lbcm_batch *b, int64_t nsteps);
+
+/* The same steps as single-box launches, box after box (the baseline the batched launch is
+   measured against). */
+int lbcm_batch_step_looped(lbcm_batch *b, int64_t nsteps);
+
+/* Autotuner: for each box size, the fastest tile split of a workgroup of 8 or 16 waves (timed
+   on that box), then the workgroup size and the tile order (box order or largest boxes first)
+   of the batched launch by timing whole launches.  Timing runs read the current populations and
+   write the spare copies, so no state changes.  Synchronises. */
+int lbcm_batch_autotune(lbcm_batch *b, int32_t trials);
+
+/* Enable (1, default) or disable (0) hipGraph replay in lbcm_batch_step. */
+int lbcm_batch_set_graph(lbcm_batch *b, int32_t enable);
+
+/* Current launch configuration: waves per workgroup, tile order, number of tiles, and per box
+   the tile shape (arrays of nboxes entries; any pointer may be NULL). */
+int lbcm_batch_info(const lbcm_batch *b, int32_t *waves, int32_t *order, int32_t *ntiles, int32_t *wx,
+                    int32_t *rows);
+
+/* Free the batch, its boxes and its memory. */
+int lbcm_batch_destroy(lbcm_batch *b);
+
+/* Message of the last error on b (or of the last failed lbcm_batch_create when b is NULL). */
+const char *lbcm_batch_last_error(const lbcm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,6 +36,7 @@
 #include <new>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "lbcm.h"
 
@@ -440,18 +441,18 @@ __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, 
 
 template <class M> constexpr int kMaxThreads = sizeof(typename M::R) == 8 ? 512 : 1024;
 
+// One tile (band, rg) of one lattice; called by the single-lattice and the batched kernels with
+// the workgroup's LDS.  All threads of the workgroup must call it (it contains the barrier).
 template <class M, bool WALLS, bool FORCE>
-__global__ __launch_bounds__(kMaxThreads<M>) void
-k_step(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ ga,
-       unsigned char *__restrict__ fb, unsigned char *__restrict__ gb, Geo geo,
-       Phys<typename M::R> c, int *__restrict__ flag)
+__device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ ga,
+                                          unsigned char *__restrict__ fb, unsigned char *__restrict__ gb,
+                                          const Geo &geo, const Phys<typename M::R> &c, int *__restrict__ flag,
+                                          int band, int rg, typename M::R *phs)
 {
     using R = typename M::R;
     using F = typename M::F;
     using G0 = typename M::G0;
     using G = typename M::G;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    R *phs = reinterpret_cast<R *>(lds_raw);  // [rows + 2][ldw]
 
     const int nx = geo.nx, ny = geo.ny;
     const uint32_t N = geo.plane;
@@ -461,7 +462,6 @@ k_step(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ g
     // wave index made explicitly uniform, so that the row offsets stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wc = wave % wx, wr = wave / wx;  // wave column and row inside the tile
-    const int band = blockIdx.x % geo.nbands, rg = blockIdx.x / geo.nbands;
     const int X0 = band * 64 * wx;
     const int X1 = min(X0 + 64 * wx, nx);
     const int y0 = rg * rows_t;
@@ -557,6 +557,55 @@ k_step(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ g
 #pragma unroll
         for (int i = 1; i < 9; ++i)
             Elem<G>::template st<R>(rgb, ux_ * bg, plane_off<G0, G>(i, N) + uy_ * unx * bg, go[i]);
+    }
+}
+
+template <class M, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(kMaxThreads<M>) void
+k_step(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ ga,
+       unsigned char *__restrict__ fb, unsigned char *__restrict__ gb, Geo geo,
+       Phys<typename M::R> c, int *__restrict__ flag)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int band = blockIdx.x % geo.nbands, rg = blockIdx.x / geo.nbands;
+    step_tile<M, WALLS, FORCE>(fa, ga, fb, gb, geo, c, flag, band, rg, reinterpret_cast<typename M::R *>(lds_raw));
+}
+
+// ------------------------------------------------------------------------------------------
+// batched step: every tile of every box of an ensemble in one launch.  The tiles of box b are
+// the flat grid indices [first_tile, first_tile + nbands * nrows) in the box's row-major order;
+// tile_box maps a grid index to its box.  Each box has its own size, tile shape (within the
+// launch's workgroup size), boundaries, force and physics.
+
+template <class R> struct BoxDesc {
+    Geo geo;
+    Phys<R> c;
+    const unsigned char *set[2][2];  // [pair][f or g]
+    int first_tile;
+    int walls, force;
+};
+
+template <class M>
+__global__ __launch_bounds__(kMaxThreads<M>) void k_step_batch(const BoxDesc<typename M::R> *__restrict__ boxes,
+                                                               const int *__restrict__ tile_box, int cur,
+                                                               int *__restrict__ flag)
+{
+    using R = typename M::R;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    R *phs = reinterpret_cast<R *>(lds_raw);
+    const int b = tile_box[blockIdx.x];
+    const BoxDesc<R> &d = boxes[b];
+    const int t = (int)blockIdx.x - d.first_tile;
+    const int band = t % d.geo.nbands, rg = t / d.geo.nbands;
+    const unsigned char *fa = d.set[cur][0], *ga = d.set[cur][1];
+    unsigned char *fb = const_cast<unsigned char *>(d.set[1 - cur][0]);
+    unsigned char *gb = const_cast<unsigned char *>(d.set[1 - cur][1]);
+    if (d.walls) {
+        if (d.force) step_tile<M, true, true>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
+        else step_tile<M, true, false>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
+    } else {
+        if (d.force) step_tile<M, false, true>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
+        else step_tile<M, false, false>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
     }
 }
 
@@ -941,6 +990,68 @@ template <class M> int launch_steps(lbcm_handle *h, int64_t nsteps)
     return LBCM_OK;
 }
 
+// Time `trials` launches of the step kernel with tile shape (wx, rows) that read the current
+// pair and write the spare one (the state is left as it was).  Returns ms per launch, < 0 on error.
+template <class M> float time_tiles(lbcm_handle *h, int wx, int rows, int trials)
+{
+    using R = typename M::R;
+    lbcm_params q = h->p;
+    q.tile_wx = wx;
+    q.tile_rows = rows;
+    const Geo geo = make_geo(q);
+    const Phys<R> c = make_phys<R>(q);
+    const bool walls = q.bc_y == LBCM_BC_WALLS, force = q.force_x != 0 || q.force_y != 0;
+    const dim3 grid((unsigned)(geo.nbands * geo.nrows)), block(64 * geo.wx * geo.rows);
+    const size_t lds = (size_t)(geo.rows + 2) * (64 * geo.wx + 2) * sizeof(R);
+    const unsigned char *fa = set_base(h, h->cur, 0), *ga = set_base(h, h->cur, 1);
+    unsigned char *fb = set_base(h, 1 - h->cur, 0), *gb = set_base(h, 1 - h->cur, 1);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1;
+    }
+    float ms = -1;
+    for (int pass = 0; pass < 2; ++pass) {  // pass 0 warms up
+        if (pass == 1 && hipEventRecord(e0, h->stream) != hipSuccess) break;
+        for (int s = 0; s < (pass ? trials : 1); ++s) {
+            if (walls) {
+                if (force) hipLaunchKernelGGL((k_step<M, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+                else hipLaunchKernelGGL((k_step<M, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            } else {
+                if (force) hipLaunchKernelGGL((k_step<M, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+                else hipLaunchKernelGGL((k_step<M, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            }
+        }
+        if (hipGetLastError() != hipSuccess) break;
+        if (pass == 1 && hipEventRecord(e1, h->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+            hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            ms /= (float)trials;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
+
+int max_waves_of(int precision) { return precision == LBCM_FP64 ? 8 : 16; }
+
+// Candidate tile shapes (wx, rows) for a lattice: wx a power of two up to the lattice width,
+// wx * rows == waves (or every split up to waves when waves == 0).
+std::vector<std::pair<int, int>> tile_candidates(const lbcm_params &p, int waves)
+{
+    std::vector<std::pair<int, int>> out;
+    const int need = (p.nx + 63) / 64, mw = max_waves_of(p.precision);
+    for (int wx = 1; wx <= mw; wx *= 2) {
+        if (wx > need && wx > 1) break;
+        for (int rows = 1; wx * rows <= mw; rows *= 2) {
+            if (rows > p.ny && rows > 1) break;
+            if (waves == 0 || wx * rows == waves) out.push_back({wx, rows});
+        }
+    }
+    if (out.empty()) out.push_back({1, 1});
+    return out;
+}
+
 template <class M>
 int do_init(lbcm_handle *h, const double *phi0, const double *rho0, const double *ux0, const double *uy0)
 {
@@ -1006,6 +1117,266 @@ template <class Fn> int dispatch(lbcm_handle *h, Fn &&fn)
     case LBCM_FP16_SHIFTED: return fn(ModeF16{});
     case LBCM_BF16_SHIFTED: return fn(ModeB16{});
     default: return fail(h, LBCM_EINVAL, "unsupported precision");
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// ensembles
+
+struct lbcm_batch {
+    int n = 0;
+    int precision = 0;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    char *arena = nullptr;
+    std::vector<lbcm_handle *> box;
+    std::vector<int> wx, rows;     // tile shape of each box in the batched launch
+    int waves = 16;                // waves per workgroup of the batched launch
+    int order = 1;                 // 0: tiles in box order, 1: largest boxes first
+    void *d_desc = nullptr;        // BoxDesc table
+    int *d_tile_box = nullptr;     // grid index -> box
+    int *flag = nullptr;
+    int ntiles = 0;
+    size_t lds = 0;
+    std::vector<int> base_cur;     // pair that was current in each box when the table was built
+    int phase = 0;                 // steps taken since the table was built, mod 2
+    bool use_graph = true;
+    bool graph_ok = false;
+    hipGraphExec_t gexec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int bfail(lbcm_batch *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIP_TRY(b, call)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return bfail(b, LBCM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+void drop_graph(lbcm_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->graph_ok = false;
+}
+
+// (Re)build the descriptor and tile tables from the current state of every box.
+template <class M> int build_tables(lbcm_batch *b)
+{
+    using R = typename M::R;
+    std::vector<int> idx(b->n);
+    for (int i = 0; i < b->n; ++i) idx[i] = i;
+    if (b->order == 1)
+        std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) {
+            return (size_t)b->box[u]->p.nx * b->box[u]->p.ny > (size_t)b->box[v]->p.nx * b->box[v]->p.ny;
+        });
+    std::vector<BoxDesc<R>> desc(b->n);
+    std::vector<int> tile_box;
+    size_t lds = 0;
+    b->base_cur.assign(b->n, 0);
+    for (int i : idx) {
+        lbcm_handle *h = b->box[i];
+        if (!h->ready) return bfail(b, LBCM_ESTATE, "box " + std::to_string(i) + " is not initialised");
+        lbcm_params q = h->p;
+        q.tile_wx = b->wx[i];
+        q.tile_rows = b->rows[i];
+        BoxDesc<R> &d = desc[i];
+        d.geo = make_geo(q);
+        if (d.geo.wx * d.geo.rows > b->waves) return bfail(b, LBCM_EINVAL, "tile larger than the workgroup");
+        d.c = make_phys<R>(q);
+        b->base_cur[i] = h->cur;
+        for (int k = 0; k < 2; ++k) {
+            d.set[k][0] = set_base(h, h->cur ^ k, 0);
+            d.set[k][1] = set_base(h, h->cur ^ k, 1);
+        }
+        d.walls = q.bc_y == LBCM_BC_WALLS;
+        d.force = q.force_x != 0 || q.force_y != 0;
+        d.first_tile = (int)tile_box.size();
+        const size_t nt = (size_t)d.geo.nbands * d.geo.nrows;
+        if (tile_box.size() + nt > 0x7fffffff) return bfail(b, LBCM_EINVAL, "too many tiles");
+        tile_box.insert(tile_box.end(), nt, i);
+        lds = std::max(lds, (size_t)(d.geo.rows + 2) * (64 * d.geo.wx + 2) * sizeof(R));
+    }
+    drop_graph(b);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_tile_box) (void)hipFree(b->d_tile_box);
+    b->d_desc = nullptr;
+    b->d_tile_box = nullptr;
+    BHIP_TRY(b, hipMalloc(&b->d_desc, desc.size() * sizeof(BoxDesc<R>)));
+    BHIP_TRY(b, hipMalloc((void **)&b->d_tile_box, tile_box.size() * sizeof(int)));
+    BHIP_TRY(b, hipMemcpyAsync(b->d_desc, desc.data(), desc.size() * sizeof(BoxDesc<R>), hipMemcpyHostToDevice, b->stream));
+    BHIP_TRY(b, hipMemcpyAsync(b->d_tile_box, tile_box.data(), tile_box.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    b->ntiles = (int)tile_box.size();
+    b->lds = lds;
+    b->phase = 0;
+    return LBCM_OK;
+}
+
+bool tables_stale(lbcm_batch *b)
+{
+    if (!b->d_desc) return true;
+    for (int i = 0; i < b->n; ++i)
+        if (b->box[i]->cur != (b->base_cur[i] ^ b->phase)) return true;
+    return false;
+}
+
+template <class M> void launch_batch(lbcm_batch *b, int phase)
+{
+    hipLaunchKernelGGL((k_step_batch<M>), dim3(b->ntiles), dim3(64 * b->waves), b->lds, b->stream,
+                       (const BoxDesc<typename M::R> *)b->d_desc, b->d_tile_box, phase, b->flag);
+}
+
+void advance_boxes(lbcm_batch *b, int64_t steps)
+{
+    for (lbcm_handle *h : b->box) {
+        h->cur ^= (int)(steps & 1);
+        h->step += steps;
+    }
+    b->phase ^= (int)(steps & 1);
+}
+
+template <class M> int batch_steps(lbcm_batch *b, int64_t nsteps)
+{
+    if (tables_stale(b)) {
+        int rc = build_tables<M>(b);
+        if (rc) return rc;
+    }
+    int64_t s = 0;
+    if (b->phase == 1 && s < nsteps) {  // get to an even phase for the two-step graph
+        launch_batch<M>(b, 1);
+        BHIP_TRY(b, hipGetLastError());
+        advance_boxes(b, 1);
+        ++s;
+    }
+    if (b->use_graph && nsteps - s >= 2) {
+        if (!b->graph_ok) {
+            hipGraph_t g = nullptr;
+            BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            launch_batch<M>(b, 0);
+            launch_batch<M>(b, 1);
+            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            if (e != hipSuccess) return bfail(b, LBCM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return bfail(b, LBCM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            b->graph_ok = true;
+        }
+        for (; s + 2 <= nsteps; s += 2) {
+            BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream));
+            advance_boxes(b, 2);
+        }
+    }
+    for (; s < nsteps; ++s) {
+        launch_batch<M>(b, b->phase);
+        BHIP_TRY(b, hipGetLastError());
+        advance_boxes(b, 1);
+    }
+    return LBCM_OK;
+}
+
+// ms per batched launch that reads the current pairs and writes the spare ones (state unchanged)
+template <class M> float time_batch(lbcm_batch *b, int trials)
+{
+    if (tables_stale(b) && build_tables<M>(b) != LBCM_OK) return -1;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1;
+    }
+    float ms = -1;
+    launch_batch<M>(b, b->phase);
+    if (hipEventRecord(e0, b->stream) == hipSuccess) {
+        for (int t = 0; t < trials; ++t) launch_batch<M>(b, b->phase);
+        if (hipGetLastError() == hipSuccess && hipEventRecord(e1, b->stream) == hipSuccess &&
+            hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            ms /= (float)trials;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
+
+template <class M> int batch_autotune(lbcm_batch *b, int trials)
+{
+    // per box size and per workgroup size: the fastest tile split of that many waves
+    const int mw = max_waves_of(b->precision);
+    float best_ms = -1;
+    std::vector<int> best_wx, best_rows;
+    int best_waves = 0, best_order = 0;
+    for (int waves = mw / 2; waves <= mw; waves *= 2) {
+        std::vector<int> wx(b->n, 1), rows(b->n, 1);
+        std::vector<std::pair<std::pair<int, int>, std::pair<int, int>>> memo;  // (nx, ny) -> (wx, rows)
+        for (int i = 0; i < b->n; ++i) {
+            lbcm_handle *h = b->box[i];
+            auto key = std::make_pair(h->p.nx, h->p.ny);
+            auto it = std::find_if(memo.begin(), memo.end(), [&](auto &m) { return m.first == key; });
+            if (it == memo.end()) {
+                float bms = -1;
+                std::pair<int, int> bc{1, waves};
+                for (auto cand : tile_candidates(h->p, waves)) {
+                    const float ms = time_tiles<M>(h, cand.first, cand.second, trials);
+                    if (ms < 0) return bfail(b, LBCM_EHIP, "timing a tile shape failed");
+                    if (bms < 0 || ms < bms) {
+                        bms = ms;
+                        bc = cand;
+                    }
+                }
+                memo.push_back({key, bc});
+                it = memo.end() - 1;
+            }
+            wx[i] = it->second.first;
+            rows[i] = it->second.second;
+        }
+        for (int order = 0; order < 2; ++order) {
+            b->wx = wx;
+            b->rows = rows;
+            b->waves = waves;
+            b->order = order;
+            int rc = build_tables<M>(b);
+            if (rc) return rc;
+            const float ms = time_batch<M>(b, trials);
+            if (ms < 0) return bfail(b, LBCM_EHIP, "timing the batched launch failed");
+            if (best_ms < 0 || ms < best_ms) {
+                best_ms = ms;
+                best_wx = wx;
+                best_rows = rows;
+                best_waves = waves;
+                best_order = order;
+            }
+        }
+    }
+    b->wx = best_wx;
+    b->rows = best_rows;
+    b->waves = best_waves;
+    b->order = best_order;
+    // the looped single-box launches use the same per-box shapes
+    for (int i = 0; i < b->n; ++i) {
+        b->box[i]->p.tile_wx = b->wx[i];
+        b->box[i]->p.tile_rows = b->rows[i];
+    }
+    return build_tables<M>(b);
+}
+
+template <class Fn> int bdispatch(lbcm_batch *b, Fn &&fn)
+{
+    switch (b->precision) {
+    case LBCM_FP64: return fn(ModeF64{});
+    case LBCM_FP32: return fn(ModeF32{});
+    case LBCM_FP16_SHIFTED: return fn(ModeF16{});
+    case LBCM_BF16_SHIFTED: return fn(ModeB16{});
+    default: return bfail(b, LBCM_EINVAL, "unsupported precision");
     }
 }
 
@@ -1226,6 +1597,185 @@ int lbcm_destroy(lbcm_handle *h)
 const char *lbcm_last_error(const lbcm_handle *h)
 {
     return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int lbcm_autotune(lbcm_handle *h, int trials)
+{
+    if (!h) return LBCM_EINVAL;
+    if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_autotune before lbcm_init");
+    if (trials < 1) return fail(h, LBCM_EINVAL, "trials must be >= 1");
+    return dispatch(h, [&](auto mode) -> int {
+        using M = decltype(mode);
+        float best = -1;
+        std::pair<int, int> bc{h->p.tile_wx, h->p.tile_rows};
+        for (auto cand : tile_candidates(h->p, 0)) {
+            const float ms = time_tiles<M>(h, cand.first, cand.second, trials);
+            if (ms < 0) return fail(h, LBCM_EHIP, "timing a tile shape failed");
+            if (best < 0 || ms < best) {
+                best = ms;
+                bc = cand;
+            }
+        }
+        h->p.tile_wx = bc.first;
+        h->p.tile_rows = bc.second;
+        return LBCM_OK;
+    });
+}
+
+int lbcm_tile_shape(const lbcm_handle *h, int32_t *wx, int32_t *rows)
+{
+    if (!h || !wx || !rows) return LBCM_EINVAL;
+    const Geo g = make_geo(h->p);
+    *wx = g.wx;
+    *rows = g.rows;
+    return LBCM_OK;
+}
+
+int lbcm_batch_create(const lbcm_params *boxes, int32_t nboxes, lbcm_batch **out)
+{
+    if (!out) return LBCM_EINVAL;
+    *out = nullptr;
+    if (!boxes || nboxes < 1) {
+        g_create_error = "need at least one box";
+        return LBCM_EINVAL;
+    }
+    for (int i = 0; i < nboxes; ++i) {
+        if (const char *m = check_params(&boxes[i])) {
+            g_create_error = "box " + std::to_string(i) + ": " + m;
+            return LBCM_EINVAL;
+        }
+        if (boxes[i].precision != boxes[0].precision || boxes[i].stream != boxes[0].stream) {
+            g_create_error = "every box of a batch must have the same precision and stream";
+            return LBCM_EINVAL;
+        }
+    }
+    lbcm_batch *b = new (std::nothrow) lbcm_batch();
+    if (!b) {
+        g_create_error = "out of host memory";
+        return LBCM_ENOMEM;
+    }
+    b->n = nboxes;
+    b->precision = boxes[0].precision;
+    b->waves = max_waves_of(b->precision);
+    b->stream = (hipStream_t)boxes[0].stream;
+    auto bail = [&](int code, const std::string &m) {
+        g_create_error = m;
+        lbcm_batch_destroy(b);
+        return code;
+    };
+    if (!b->stream) {  // graph capture needs a stream of its own
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(LBCM_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        b->owns_stream = true;
+    }
+    std::vector<size_t> off(nboxes);
+    size_t total = 0;
+    for (int i = 0; i < nboxes; ++i) {
+        off[i] = total;
+        total += align_up(lbcm_workspace_size(&boxes[i]));
+    }
+    const size_t flag_off = total;
+    total += kAlign;
+    hipError_t e = hipMalloc((void **)&b->arena, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(e == hipErrorOutOfMemory ? LBCM_ENOMEM : LBCM_EHIP, std::string("hipMalloc(") + std::to_string(total) + "): " + hipGetErrorString(e));
+    }
+    b->flag = (int *)(b->arena + flag_off);
+    e = hipMemsetAsync(b->flag, 0, sizeof(int), b->stream);
+    if (e != hipSuccess) return bail(LBCM_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+    b->box.resize(nboxes, nullptr);
+    b->wx.resize(nboxes);
+    b->rows.resize(nboxes);
+    for (int i = 0; i < nboxes; ++i) {
+        lbcm_params q = boxes[i];
+        q.stream = b->stream;
+        q.workspace = b->arena + off[i];
+        q.workspace_bytes = align_up(lbcm_workspace_size(&boxes[i]));
+        int rc = lbcm_create(&q, &b->box[i]);
+        if (rc) return bail(rc, "box " + std::to_string(i) + ": " + g_create_error);
+        // default tile: as wide as the box allows, the rest of the workgroup in rows
+        const Geo g = make_geo(q);
+        b->wx[i] = g.wx;
+        b->rows[i] = std::max(1, b->waves / g.wx);
+    }
+    *out = b;
+    return LBCM_OK;
+}
+
+lbcm_handle *lbcm_batch_box(lbcm_batch *b, int32_t i)
+{
+    return (b && i >= 0 && i < b->n) ? b->box[i] : nullptr;
+}
+
+int lbcm_batch_set_graph(lbcm_batch *b, int32_t enable)
+{
+    if (!b) return LBCM_EINVAL;
+    b->use_graph = enable != 0;
+    if (!b->use_graph) drop_graph(b);
+    return LBCM_OK;
+}
+
+int lbcm_batch_autotune(lbcm_batch *b, int32_t trials)
+{
+    if (!b) return LBCM_EINVAL;
+    if (trials < 1) return bfail(b, LBCM_EINVAL, "trials must be >= 1");
+    for (int i = 0; i < b->n; ++i)
+        if (!b->box[i]->ready) return bfail(b, LBCM_ESTATE, "box " + std::to_string(i) + " is not initialised");
+    return bdispatch(b, [&](auto mode) { return batch_autotune<decltype(mode)>(b, trials); });
+}
+
+int lbcm_batch_step(lbcm_batch *b, int64_t nsteps)
+{
+    if (!b) return LBCM_EINVAL;
+    if (nsteps < 0) return bfail(b, LBCM_EINVAL, "nsteps must be >= 0");
+    return bdispatch(b, [&](auto mode) { return batch_steps<decltype(mode)>(b, nsteps); });
+}
+
+int lbcm_batch_step_looped(lbcm_batch *b, int64_t nsteps)
+{
+    if (!b) return LBCM_EINVAL;
+    if (nsteps < 0) return bfail(b, LBCM_EINVAL, "nsteps must be >= 0");
+    for (int64_t s = 0; s < nsteps; ++s)
+        for (int i = 0; i < b->n; ++i) {
+            int rc = lbcm_step(b->box[i], 1);
+            if (rc) return bfail(b, rc, "box " + std::to_string(i) + ": " + b->box[i]->err);
+        }
+    return LBCM_OK;
+}
+
+int lbcm_batch_info(const lbcm_batch *b, int32_t *waves, int32_t *order, int32_t *ntiles, int32_t *wx, int32_t *rows)
+{
+    if (!b) return LBCM_EINVAL;
+    if (waves) *waves = b->waves;
+    if (order) *order = b->order;
+    if (ntiles) *ntiles = b->ntiles;
+    for (int i = 0; i < b->n; ++i) {
+        if (wx) wx[i] = b->wx[i];
+        if (rows) rows[i] = b->rows[i];
+    }
+    return LBCM_OK;
+}
+
+int lbcm_batch_destroy(lbcm_batch *b)
+{
+    if (!b) return LBCM_OK;
+    int rc = LBCM_OK;
+    if (b->stream && hipStreamSynchronize(b->stream) != hipSuccess) rc = LBCM_EHIP;
+    drop_graph(b);
+    for (lbcm_handle *h : b->box)
+        if (h && lbcm_destroy(h) != LBCM_OK) rc = LBCM_EHIP;
+    if (b->d_desc && hipFree(b->d_desc) != hipSuccess) rc = LBCM_EHIP;
+    if (b->d_tile_box && hipFree(b->d_tile_box) != hipSuccess) rc = LBCM_EHIP;
+    if (b->arena && hipFree(b->arena) != hipSuccess) rc = LBCM_EHIP;
+    if (b->owns_stream && hipStreamDestroy(b->stream) != hipSuccess) rc = LBCM_EHIP;
+    delete b;
+    return rc;
+}
+
+const char *lbcm_batch_last_error(const lbcm_batch *b)
+{
+    return b ? b->err.c_str() : g_create_error.c_str();
 }
 
 }  // extern "C"

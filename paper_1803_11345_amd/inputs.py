@@ -100,3 +100,29 @@ def smooth_state(nx: int, ny: int, seed: int, u_amp: float = 0.05, rho_amp: floa
     ux = u_amp * field(2)
     uy = u_amp * field(3)
     return phi, rho, ux, uy
+
+
+def ensemble(count: int, seed: int = 7, sides=(64, 128, 256, 512, 1024), a: float = 0.04,
+             gamma: float = 0.04, nu1: float = 0.1, force: float = 1e-6):
+    """A seeded ensemble of independent square boxes: side uniform over ``sides``; each box a
+    static droplet (periodic, R uniform in [0.15, 0.35] * side, nu_l = nu1, nu_g = nu1 / ratio) or
+    a layered channel (walls in y, body force along x, phi = +1 below with nu1 and -1 above with
+    ratio * nu1), with the viscosity ratio log-uniform in [1, 1000].  The default a = gamma = 0.04
+    are the free-energy constants of the paper's high-contrast bubble runs.  Returns a list of
+    (params, phi0) with params a dict of lattice parameters."""
+    u = uniform(seed, 4 * count).reshape(count, 4)
+    W = interface_width(a, gamma)
+    out = []
+    for k in range(count):
+        side = int(sides[min(int(u[k, 0] * len(sides)), len(sides) - 1)])
+        ratio = 10.0 ** (3.0 * u[k, 2])
+        if u[k, 1] < 0.5:
+            radius = (0.15 + 0.2 * u[k, 3]) * side
+            params = dict(nx=side, ny=side, bc_y=0, a=a, gamma=gamma, nu_l=nu1, nu_g=nu1 / ratio)
+            phi0 = droplet(side, side, radius, W)
+        else:
+            params = dict(nx=side, ny=side, bc_y=1, a=a, gamma=gamma, nu_l=nu1, nu_g=nu1 * ratio,
+                          force_x=force)
+            phi0 = layered(side, side, W)
+        out.append((params, phi0))
+    return out

@@ -97,6 +97,21 @@ def load():
     lib.lbcm_destroy.argtypes = [_H]
     lib.lbcm_last_error.argtypes = [_H]
     lib.lbcm_last_error.restype = ctypes.c_char_p
+    I32 = ctypes.c_int32
+    PI = ctypes.POINTER(ctypes.c_int32)
+    lib.lbcm_autotune.argtypes = [_H, ctypes.c_int]
+    lib.lbcm_tile_shape.argtypes = [_H, PI, PI]
+    lib.lbcm_batch_create.argtypes = [P, I32, ctypes.POINTER(_H)]
+    lib.lbcm_batch_box.argtypes = [_H, I32]
+    lib.lbcm_batch_box.restype = _H
+    lib.lbcm_batch_step.argtypes = [_H, ctypes.c_int64]
+    lib.lbcm_batch_step_looped.argtypes = [_H, ctypes.c_int64]
+    lib.lbcm_batch_autotune.argtypes = [_H, I32]
+    lib.lbcm_batch_set_graph.argtypes = [_H, I32]
+    lib.lbcm_batch_info.argtypes = [_H, PI, PI, PI, PI, PI]
+    lib.lbcm_batch_destroy.argtypes = [_H]
+    lib.lbcm_batch_last_error.argtypes = [_H]
+    lib.lbcm_batch_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -104,7 +119,8 @@ def load():
 def declared_functions() -> list[str]:
     """Names of the entry points declared in include/lbcm.h."""
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*)\s*\**\s*(lbcm_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*|lbcm_handle \*)\s*\**\s*(lbcm_\w+)\s*\(",
+                                 text, re.M)))
 
 
 def _check(h, rc):
@@ -196,27 +212,78 @@ def lbcm_last_error(h) -> str:
     return m.decode() if m else ""
 
 
-# ---------------------------------------------------------------- convenience wrapper
+def lbcm_autotune(h, trials: int = 5):
+    return _check(h, load().lbcm_autotune(h, int(trials)))
 
-class Lattice:
-    """One lattice on the current CUDA device.  The workspace is a torch uint8 tensor and work
-    is queued on ``stream`` (default: torch's current stream)."""
 
-    def __init__(self, nx, ny, *, stream=None, own_workspace=True, **kw):
-        import torch
+def lbcm_tile_shape(h):
+    wx, rows = ctypes.c_int32(), ctypes.c_int32()
+    _check(h, load().lbcm_tile_shape(h, ctypes.byref(wx), ctypes.byref(rows)))
+    return wx.value, rows.value
 
-        self.nx, self.ny = nx, ny
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.params = make_params(nx, ny, stream=self.stream.cuda_stream, **kw)
-        self.workspace = None
-        if own_workspace:
-            nbytes = lbcm_workspace_size(self.params)
-            if nbytes == 0:
-                raise LbcmError(LBCM_EINVAL, "invalid parameters")
-            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-            self.params.workspace = self.workspace.data_ptr()
-            self.params.workspace_bytes = nbytes
-        self.h = lbcm_create(self.params)
+
+def _bcheck(b, rc):
+    if rc != LBCM_OK:
+        raise LbcmError(rc, lbcm_batch_last_error(b))
+    return rc
+
+
+def lbcm_batch_create(params_list):
+    arr = (lbcm_params * len(params_list))(*params_list)
+    b = _H()
+    rc = load().lbcm_batch_create(arr, len(params_list), ctypes.byref(b))
+    if rc != LBCM_OK:
+        raise LbcmError(rc, lbcm_batch_last_error(None))
+    return b
+
+
+def lbcm_batch_box(b, i: int):
+    h = load().lbcm_batch_box(b, int(i))
+    if not h:
+        raise IndexError(i)
+    return _H(h)
+
+
+def lbcm_batch_step(b, nsteps: int = 1):
+    return _bcheck(b, load().lbcm_batch_step(b, int(nsteps)))
+
+
+def lbcm_batch_step_looped(b, nsteps: int = 1):
+    return _bcheck(b, load().lbcm_batch_step_looped(b, int(nsteps)))
+
+
+def lbcm_batch_autotune(b, trials: int = 5):
+    return _bcheck(b, load().lbcm_batch_autotune(b, int(trials)))
+
+
+def lbcm_batch_set_graph(b, enable: bool):
+    return _bcheck(b, load().lbcm_batch_set_graph(b, int(bool(enable))))
+
+
+def lbcm_batch_info(b, nboxes: int) -> dict:
+    waves, order, ntiles = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    wx = (ctypes.c_int32 * nboxes)()
+    rows = (ctypes.c_int32 * nboxes)()
+    _bcheck(b, load().lbcm_batch_info(b, ctypes.byref(waves), ctypes.byref(order), ctypes.byref(ntiles), wx, rows))
+    return {"waves": waves.value, "order": order.value, "ntiles": ntiles.value, "wx": list(wx), "rows": list(rows)}
+
+
+def lbcm_batch_destroy(b):
+    return _bcheck(None, load().lbcm_batch_destroy(b))
+
+
+def lbcm_batch_last_error(b) -> str:
+    m = load().lbcm_batch_last_error(b)
+    return m.decode() if m else ""
+
+
+# ---------------------------------------------------------------- convenience wrappers
+
+class _View:
+    """Host-side operations on one lattice handle (own or inside a batch)."""
+
+    h = None
+    nx = ny = 0
 
     def init(self, phi0, rho0=None, ux0=None, uy0=None):
         arr = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (phi0, rho0, ux0, uy0)]
@@ -251,6 +318,88 @@ class Lattice:
 
     def set_state(self, buf, step=0):
         lbcm_set_state(self.h, np.ascontiguousarray(buf, dtype=np.uint8), step)
+
+    def autotune(self, trials=5):
+        lbcm_autotune(self.h, trials)
+        return lbcm_tile_shape(self.h)
+
+    def tile_shape(self):
+        return lbcm_tile_shape(self.h)
+
+
+class Batch:
+    """An ensemble of boxes advanced by one launch per step.  ``boxes`` is a list of dicts of
+    make_params keywords (nx, ny and any physics); precision and stream are shared."""
+
+    class Box(_View):
+        def __init__(self, h, nx, ny):
+            self.h, self.nx, self.ny = h, nx, ny
+
+    def __init__(self, boxes, *, precision="fp32", stream=None):
+        import torch
+
+        # a stream of its own (the null stream cannot be captured into a graph)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        plist = [make_params(precision=precision, stream=self.stream.cuda_stream, **kw) for kw in boxes]
+        self.b = lbcm_batch_create(plist)
+        self.boxes = [Batch.Box(lbcm_batch_box(self.b, i), p.nx, p.ny) for i, p in enumerate(plist)]
+
+    def __len__(self):
+        return len(self.boxes)
+
+    def __getitem__(self, i):
+        return self.boxes[i]
+
+    def step(self, n=1):
+        lbcm_batch_step(self.b, n)
+        return self
+
+    def step_looped(self, n=1):
+        lbcm_batch_step_looped(self.b, n)
+        return self
+
+    def autotune(self, trials=5):
+        lbcm_batch_autotune(self.b, trials)
+        return self.info()
+
+    def set_graph(self, enable):
+        lbcm_batch_set_graph(self.b, enable)
+
+    def info(self):
+        return lbcm_batch_info(self.b, len(self.boxes))
+
+    def close(self):
+        if self.b is not None:
+            lbcm_batch_destroy(self.b)
+            self.b = None
+            self.boxes = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Lattice(_View):
+    """One lattice on the current CUDA device.  The workspace is a torch uint8 tensor and work
+    is queued on ``stream`` (default: torch's current stream)."""
+
+    def __init__(self, nx, ny, *, stream=None, own_workspace=True, **kw):
+        import torch
+
+        self.nx, self.ny = nx, ny
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.params = make_params(nx, ny, stream=self.stream.cuda_stream, **kw)
+        self.workspace = None
+        if own_workspace:
+            nbytes = lbcm_workspace_size(self.params)
+            if nbytes == 0:
+                raise LbcmError(LBCM_EINVAL, "invalid parameters")
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            self.params.workspace = self.workspace.data_ptr()
+            self.params.workspace_bytes = nbytes
+        self.h = lbcm_create(self.params)
 
     def close(self):
         if self.h is not None:

@@ -1,0 +1,138 @@
+"""GPU tests of the ensemble path: one launch per step over every tile of every box.  The
+per-node arithmetic does not depend on the tile a node falls in, so every box of a batch must
+match, bit for bit, the same box stepped as a single lattice (which the parity tests tie to the
+oracle)."""
+import numpy as np
+import pytest
+
+from paper_1803_11345_amd import inputs, lbcm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+BOXES = [
+    dict(nx=64, ny=64, nu_l=0.1, nu_g=0.01),
+    dict(nx=100, ny=37, bc_y=1, nu_l=0.1, nu_g=1.0, force_x=1e-5),
+    dict(nx=33, ny=17, nu_l=0.1, nu_g=0.05, force_y=2e-5),
+    dict(nx=130, ny=65, bc_y=1, nu_l=0.05, nu_g=0.5),
+    dict(nx=1, ny=1),
+    dict(nx=200, ny=3, nu_l=0.1, nu_g=0.1),
+    dict(nx=257, ny=129, nu_l=0.1, nu_g=0.002),
+]
+
+
+def _states(seed):
+    return [inputs.smooth_state(b["nx"], b["ny"], seed=seed + k) for k, b in enumerate(BOXES)]
+
+
+def _singles(prec, steps, seed):
+    out = []
+    for b, st in zip(BOXES, _states(seed)):
+        lat = lbcm.Lattice(precision=prec, **b).init(*st).step(steps)
+        out.append(lat.get_state())
+        lat.close()
+    return out
+
+
+def _batch(prec, seed):
+    bt = lbcm.Batch(BOXES, precision=prec)
+    for box, st in zip(bt, _states(seed)):
+        box.init(*st)
+    return bt
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s", "fp64"])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_matches_single_lattices(prec, graph):
+    say(f"case batch {prec} graph={graph}")
+    ref = _singles(prec, 7, 50)
+    bt = _batch(prec, 50)
+    bt.set_graph(graph)
+    bt.step(3).step(4)  # odd first call: phase handling around the two-step graph
+    for k, box in enumerate(bt):
+        assert np.array_equal(box.get_state(), ref[k]), k
+        assert box.diag()["step"] == 7
+    bt.close()
+
+
+def test_batch_looped_equals_batched():
+    a = _batch("fp32", 60)
+    b = _batch("fp32", 60)
+    a.step(5)
+    b.step_looped(5)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.get_state(), y.get_state())
+    a.close()
+    b.close()
+
+
+def test_batch_autotune_keeps_state_and_results():
+    bt = _batch("fp32", 70)
+    before = [box.get_state() for box in bt]
+    info = bt.autotune(trials=2)
+    say(f"  autotuned: {info}")
+    assert info["waves"] in (8, 16) and info["order"] in (0, 1)
+    for b, w, r in zip(BOXES, info["wx"], info["rows"]):
+        # a full workgroup unless the box is smaller than the tile
+        assert w * r == info["waves"] or (w * 64 >= b["nx"] and r >= b["ny"]) or r * w < info["waves"] and r >= b["ny"]
+    for box, st in zip(bt, before):
+        assert np.array_equal(box.get_state(), st)
+    bt.step(6)
+    ref = _singles("fp32", 6, 70)
+    for k, box in enumerate(bt):
+        assert np.array_equal(box.get_state(), ref[k]), k
+    bt.close()
+
+
+def test_box_stepped_alone_then_batch():
+    bt = _batch("fp32", 80)
+    bt[0].step(1)
+    bt.step(4)
+    ref = _singles("fp32", 4, 80)
+    ref0 = _singles("fp32", 5, 80)[0]
+    assert np.array_equal(bt[0].get_state(), ref0)
+    for k in range(1, len(BOXES)):
+        assert np.array_equal(bt[k].get_state(), ref[k]), k
+    bt.close()
+
+
+def test_graph_replays_match_eager():
+    """Several graph replays with eager work (diagnostics, host reads) in between, each checked
+    against a batch stepped without graphs."""
+    g = _batch("fp32", 90)
+    e = _batch("fp32", 90)
+    e.set_graph(False)
+    for rep in range(4):
+        g.step(2)
+        e.step(2)
+        for x, y in zip(g, e):
+            x.diag()
+            assert np.array_equal(x.get_state(), y.get_state()), rep
+    g.close()
+    e.close()
+
+
+def test_ensemble_generator_runs_finite():
+    spec = inputs.ensemble(12, seed=3, sides=(64, 128))
+    bt = lbcm.Batch([p for p, _ in spec], precision="fp16s")
+    for box, (_, phi0) in zip(bt, spec):
+        box.init(phi0)
+    bt.autotune(trials=2)
+    bt.step(200)
+    for box in bt:
+        assert box.diag()["nonfinite"] == 0
+    bt.close()
