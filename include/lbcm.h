@@ -44,9 +44,9 @@ enum { LBCM_BC_PERIODIC = 0, LBCM_BC_WALLS = 1 };
 /* Storage precision of the populations.  FP64 computes in double; the others compute in float. */
 enum {
     LBCM_FP64 = 0,
-    LBCM_FP32 = 1,
-    LBCM_FP16_SHIFTED = 2, /* f_i - w_i and g_i - w_i phi_ref... stored as IEEE half */
-    LBCM_BF16_SHIFTED = 3  /* same offsets, stored as bfloat16 */
+    LBCM_FP32 = 1,         /* f_i - w_i and g_i in float */
+    LBCM_FP16_SHIFTED = 2, /* f_i - w_i and g_1..g_8 stored as IEEE half, g_0 as float */
+    LBCM_BF16_SHIFTED = 3  /* the same planes stored as bfloat16, g_0 as float */
 };
 
 typedef struct lbcm_params {
@@ -151,6 +151,10 @@ const char *lbcm_last_error(const lbcm_handle *h);
    and writing the spare copy, so the state does not change), and the fastest is kept in the
    handle.  Needs lbcm_init first.  Synchronises. */
 int lbcm_autotune(lbcm_handle *h, int trials);
+
+/* Copy of the parameters the handle was created with into *out (stream: the handle's stream;
+   workspace: as given at creation, NULL when the library allocated it). */
+int lbcm_info(const lbcm_handle *h, lbcm_params *out);
 
 /* Tile shape the step kernel uses (after clamping to the lattice). */
 int lbcm_tile_shape(const lbcm_handle *h, int32_t *wx, int32_t *rows);

@@ -1,0 +1,112 @@
+/*
+ * lbcm_net — learned surrogate for the lattice Boltzmann step of lbcm.h: a stack of 3x3
+ * convolutions with circular padding that maps the macroscopic state (phi, v_x, v_y) of periodic
+ * boxes to the state K lattice steps later, as state + network(state).  Forward and backward
+ * passes run on the MFMA units (BF16 operands, FP32 accumulation); master parameters, gradients
+ * and the Adam moments are FP32.  This is not part of the paper's method: it is trained on
+ * trajectories of the method and checked against it (see lbcm_step).
+ *
+ * Conventions
+ *   - A network is created for a fixed batch of B samples of H x W pixels; B * H * W must be a
+ *     multiple of 32.  Layer 0 maps 3 -> C channels, layers 1..L-2 map C -> C (ReLU after every
+ *     layer but the last), layer L-1 maps C -> 3; C is 32 or 64.
+ *   - State tensors on the device are FP32 [B][H][W][3] (phi, v_x / u_scale, v_y / u_scale).
+ *   - The parameter vector (FP32, lbcm_net_param_count entries) holds, layer after layer, the
+ *     weights W[t][ci][co] (t = 3 (dy + 1) + (dx + 1) is the tap reading the input at (y + dy,
+ *     x + dx); ci, co the real channel counts) and then the biases b[co'], where co' runs over the
+ *     padded output channels (C, or 32 for the last layer; the entries past 3 must be 0).
+ *   - Return codes and ownership as in lbcm.h (LBCM_OK, LBCM_EINVAL, LBCM_ENOMEM, LBCM_EHIP).
+ *     Work is queued on the stream given at creation; calls that return host data synchronise.
+ */
+#ifndef LBCM_NET_H
+#define LBCM_NET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbcm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbcm_net lbcm_net;
+
+/* Allocate a network and its buffers (parameters zero).  stream: hipStream_t or NULL. */
+int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channels, int32_t layers, void *stream,
+                    lbcm_net **out);
+
+size_t lbcm_net_param_count(const lbcm_net *n);
+
+/* Copy the FP32 parameter vector in (resets the Adam moments) or out.  Synchronise. */
+int lbcm_net_set_params(lbcm_net *n, const float *host, size_t count);
+int lbcm_net_get_params(lbcm_net *n, float *host, size_t count);
+
+/* Forward pass on a device state [B][H][W][3]; out (device, same shape, may be NULL) receives
+   state + network(state).  The activations are kept for lbcm_net_backward. */
+int lbcm_net_forward(lbcm_net *n, const float *in, float *out);
+
+/* Forward pass from device FP64 planes [B][H][W] of phi, v_x, v_y (v divided by u_scale on the
+   way in and multiplied back on the way out) into device FP64 planes. */
+int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, double u_scale,
+                            double *phi_out, double *ux_out, double *uy_out);
+
+/* Device FP64 planes -> a device state tensor [B][H][W][3] (v divided by u_scale). */
+int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, double u_scale,
+                               float *state);
+
+/* Gradient of the loss mean((out - target)^2) over pixels and the 3 channels, after a forward
+   pass, into the internal FP32 gradient vector (same layout as the parameters).  *loss (host,
+   may be NULL) receives the loss (then the call synchronises). */
+int lbcm_net_backward(lbcm_net *n, const float *target, float *loss);
+
+/* Copy the gradient vector of the last lbcm_net_backward to the host.  Synchronises. */
+int lbcm_net_get_grads(lbcm_net *n, float *host, size_t count);
+
+/* One Adam update of the parameters with the current gradients (t = 1, 2, ... the step count). */
+int lbcm_net_adam(lbcm_net *n, float lr, float beta1, float beta2, float eps, int64_t t);
+
+int lbcm_net_destroy(lbcm_net *n);
+const char *lbcm_net_last_error(const lbcm_net *n);
+
+/* ---- hybrid driver ------------------------------------------------------------------------
+   Advances a periodic lattice in windows of J * K lattice steps.  A window reads (phi, v) of the
+   lattice, makes J - 1 surrogate jumps of K steps, and does the J-th jump both ways: with the
+   surrogate and with K lattice Boltzmann steps from equilibrium populations of the same state
+   (density 1).  The check error is ||phi_net - phi_LB|| / ||phi_LB|| (L2 over the box).  At or
+   below the threshold the window ends in the lattice Boltzmann result.  Above it the window is
+   redone with J * K lattice Boltzmann steps from equilibrium populations of its starting fields,
+   and the next window runs the plain step too.  The lattice and the network must share a stream;
+   the network is built for one box (batch 1) of the lattice's size. */
+
+typedef struct lbcm_hybrid lbcm_hybrid;
+
+typedef struct lbcm_hybrid_stats {
+    int64_t steps;         /* lattice steps of simulated time advanced */
+    int64_t jumps;         /* accepted surrogate jumps (not counting the checked jumps) */
+    int64_t lb_steps_run;  /* lattice Boltzmann steps executed (checks, redone and plain windows) */
+    int64_t checks;        /* checks made */
+    int64_t failed_checks; /* checks above the threshold */
+    double last_error;     /* error of the last check */
+    double max_error;      /* largest check error so far */
+} lbcm_hybrid_stats;
+
+/* lattice: a periodic lattice after lbcm_init; net: the trained network (batch 1, same ny x nx);
+   steps_per_jump K >= 1 (what the network was trained for); jumps_per_check J >= 1; u_scale > 0:
+   velocity scale of the network's state; threshold >= 0: largest accepted check error.  The
+   driver borrows both handles (they must outlive it). */
+int lbcm_hybrid_create(lbcm_handle *lattice, lbcm_net *net, int32_t steps_per_jump, int32_t jumps_per_check,
+                       double u_scale, double threshold, lbcm_hybrid **out);
+
+/* Advance by `windows` windows (each J * K lattice steps; synchronises once per window). */
+int lbcm_hybrid_advance(lbcm_hybrid *h, int64_t windows);
+
+int lbcm_hybrid_get_stats(const lbcm_hybrid *h, lbcm_hybrid_stats *out);
+int lbcm_hybrid_destroy(lbcm_hybrid *h);
+const char *lbcm_hybrid_last_error(const lbcm_hybrid *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBCM_NET_H */

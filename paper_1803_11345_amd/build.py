@@ -1,4 +1,4 @@
-"""Build step of the gfx950 library: hipcc -> paper_1803_11345_amd/liblbcm.so."""
+"""Build step of the gfx950 library: hipcc (lbcm.hip + surrogate.hip) -> paper_1803_11345_amd/liblbcm.so."""
 from __future__ import annotations
 
 import os
@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "lbcm.hip")
+SRCS = [os.path.join(HERE, "csrc", "lbcm.hip"), os.path.join(HERE, "csrc", "surrogate.hip")]
 LIB = os.path.join(HERE, "liblbcm.so")
 
 HIPCC_FLAGS = [
@@ -25,7 +25,7 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     """Compile liblbcm.so for gfx950 (always recompiles)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"), SRC, "-o", tmp]
+    cmd = [hipcc, *HIPCC_FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"), *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

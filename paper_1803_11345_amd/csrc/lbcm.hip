@@ -1622,6 +1622,14 @@ int lbcm_autotune(lbcm_handle *h, int trials)
     });
 }
 
+int lbcm_info(const lbcm_handle *h, lbcm_params *out)
+{
+    if (!h || !out) return LBCM_EINVAL;
+    *out = h->p;
+    out->stream = h->stream;
+    return LBCM_OK;
+}
+
 int lbcm_tile_shape(const lbcm_handle *h, int32_t *wx, int32_t *rows)
 {
     if (!h || !wx || !rows) return LBCM_EINVAL;

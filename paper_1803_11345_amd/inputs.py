@@ -126,3 +126,35 @@ def ensemble(count: int, seed: int = 7, sides=(64, 128, 256, 512, 1024), a: floa
             phi0 = layered(side, side, W)
         out.append((params, phi0))
     return out
+
+
+def two_droplets(nx: int, ny: int, r1: float, r2: float, gap: float, width: float) -> np.ndarray:
+    """Two droplets side by side along x, centred in the box, whose surfaces are ``gap`` nodes
+    apart: phi = tanh((r1 - d1) / W) + tanh((r2 - d2) / W) + 1 (+1 inside either, -1 outside)."""
+    span = 2 * r1 + gap + 2 * r2
+    x0 = nx / 2.0 - span / 2.0
+    c1, c2 = x0 + r1, x0 + 2 * r1 + gap + r2
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    d1 = np.hypot(x - c1, y - ny / 2.0)
+    d2 = np.hypot(x - c2, y - ny / 2.0)
+    return np.tanh((r1 - d1) / width) + np.tanh((r2 - d2) / width) + 1.0
+
+
+def coalescence_cases(count: int, seed: int = 11, rmin: float = 20.0, rmax: float = 40.0, gmin: float = 2.0,
+                      gmax: float = 6.0):
+    """``count`` (r1, r2, gap) triples: radii uniform in [rmin, rmax], gap uniform in [gmin, gmax]."""
+    u = uniform(seed, 3 * count).reshape(count, 3)
+    return [(rmin + (rmax - rmin) * a, rmin + (rmax - rmin) * b, gmin + (gmax - gmin) * c) for a, b, c in u]
+
+
+def he_uniform(seed: int, shapes):
+    """Seeded initial network parameters: for each (fan_in, count, zero) entry, ``count`` values
+    uniform in +-sqrt(6 / fan_in) (He et al., ICCV 2015, uniform form), or zeros when ``zero``."""
+    out = []
+    for k, (fan_in, count, zero) in enumerate(shapes):
+        if zero:
+            out.append(np.zeros(count))
+        else:
+            lim = math.sqrt(6.0 / fan_in)
+            out.append(uniform(seed * 1000 + k, count, -lim, lim))
+    return np.concatenate(out) if out else np.zeros(0)

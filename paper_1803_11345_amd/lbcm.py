@@ -17,6 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbcm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lbcm.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(HERE), "include", "lbcm_net.h")]
 
 LBCM_OK, LBCM_EINVAL, LBCM_ENOMEM, LBCM_EHIP, LBCM_EDIVERGED, LBCM_ESTATE = 0, -1, -2, -3, -4, -5
 LBCM_BC_PERIODIC, LBCM_BC_WALLS = 0, 1
@@ -101,6 +102,7 @@ def load():
     PI = ctypes.POINTER(ctypes.c_int32)
     lib.lbcm_autotune.argtypes = [_H, ctypes.c_int]
     lib.lbcm_tile_shape.argtypes = [_H, PI, PI]
+    lib.lbcm_info.argtypes = [_H, P]
     lib.lbcm_batch_create.argtypes = [P, I32, ctypes.POINTER(_H)]
     lib.lbcm_batch_box.argtypes = [_H, I32]
     lib.lbcm_batch_box.restype = _H
@@ -117,8 +119,8 @@ def load():
 
 
 def declared_functions() -> list[str]:
-    """Names of the entry points declared in include/lbcm.h."""
-    text = open(HEADER).read()
+    """Names of the entry points declared in include/lbcm.h and include/lbcm_net.h."""
+    text = "\n".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*|lbcm_handle \*)\s*\**\s*(lbcm_\w+)\s*\(",
                                  text, re.M)))
 
@@ -214,6 +216,12 @@ def lbcm_last_error(h) -> str:
 
 def lbcm_autotune(h, trials: int = 5):
     return _check(h, load().lbcm_autotune(h, int(trials)))
+
+
+def lbcm_info(h) -> lbcm_params:
+    p = lbcm_params()
+    _check(h, load().lbcm_info(h, ctypes.byref(p)))
+    return p
 
 
 def lbcm_tile_shape(h):

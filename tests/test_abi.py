@@ -4,6 +4,8 @@ device."""
 import ctypes
 import subprocess
 
+import numpy as np
+
 import pytest
 
 from paper_1803_11345_amd import lbcm
@@ -95,3 +97,43 @@ def test_null_handle_calls_are_rejected():
     assert lib.lbcm_step(None, 1) == lbcm.LBCM_EINVAL
     assert lib.lbcm_destroy(None) == lbcm.LBCM_OK
     assert lib.lbcm_state_size(None) == 0
+
+
+def test_bad_network_shapes_rejected_on_host():
+    from paper_1803_11345_amd import net
+
+    lib = net.load()
+    h = ctypes.c_void_p()
+    assert lib.lbcm_net_create(1, 5, 5, 64, 6, None, ctypes.byref(h)) == lbcm.LBCM_EINVAL  # 25 pixels
+    assert b"multiple of 32" in lib.lbcm_net_last_error(None)
+    assert lib.lbcm_net_create(1, 8, 8, 48, 6, None, ctypes.byref(h)) == lbcm.LBCM_EINVAL
+    assert lib.lbcm_net_create(1, 8, 8, 64, 1, None, ctypes.byref(h)) == lbcm.LBCM_EINVAL
+    assert lib.lbcm_net_create(0, 8, 8, 64, 6, None, ctypes.byref(h)) == lbcm.LBCM_EINVAL
+    assert h.value is None
+    assert lib.lbcm_net_forward(None, None, None) == lbcm.LBCM_EINVAL
+    assert lib.lbcm_net_destroy(None) == lbcm.LBCM_OK
+    assert lib.lbcm_net_param_count(None) == 0
+
+
+def test_hybrid_requires_handles():
+    from paper_1803_11345_amd import net
+
+    lib = net.load()
+    h = ctypes.c_void_p()
+    assert lib.lbcm_hybrid_create(None, None, 16, 8, 1.0, 1e-2, ctypes.byref(h)) == lbcm.LBCM_EINVAL
+    assert b"required" in lib.lbcm_hybrid_last_error(None)
+    assert lib.lbcm_hybrid_advance(None, 1) == lbcm.LBCM_EINVAL
+    assert lib.lbcm_hybrid_destroy(None) == lbcm.LBCM_OK
+    assert lib.lbcm_info(None, None) == lbcm.LBCM_EINVAL
+
+
+def test_network_parameter_layout_matches_oracle():
+    from oracle import convnet
+    from paper_1803_11345_amd import net
+
+    assert net.layer_shapes(64, 6) == convnet.layer_shapes(64, 6)
+    p = net.initial_params(64, 6, seed=1)
+    assert p.shape == (convnet.param_count(64, 6),) and p.dtype == np.float32
+    # the last layer (weights and bias) starts at zero: the initial network is the identity
+    ci, co, nb = convnet.layer_shapes(64, 6)[-1]
+    assert np.all(p[-(9 * ci * co + nb):] == 0) and np.abs(p).max() > 0
