@@ -1,14 +1,15 @@
 /*
  * lbcm_net — learned surrogate for the lattice Boltzmann step of lbcm.h: a stack of 3x3
  * convolutions with circular padding that maps the macroscopic state (phi, v_x, v_y) of periodic
- * boxes to the state K lattice steps later, as state + network(state).  Forward and backward
- * passes run on the MFMA units (BF16 operands, FP32 accumulation); master parameters, gradients
- * and the Adam moments are FP32.  This is not part of the paper's method: it is trained on
- * trajectories of the method and checked against it (see lbcm_step).
+ * boxes to the state K lattice steps later, as state + alpha * network(state) with a fixed
+ * per-channel output scale alpha.  The first layer runs in FP32 on the vector ALU; the others
+ * run on the MFMA units (BF16 activations and weights, FP32 accumulation); master parameters,
+ * gradients and the Adam moments are FP32.  This is not part of the paper's method: it is
+ * trained on trajectories of the method and checked against it (see lbcm_step).
  *
  * Conventions
- *   - A network is created for a fixed batch of B samples of H x W pixels; B * H * W must be a
- *     multiple of 32.  Layer 0 maps 3 -> C channels, layers 1..L-2 map C -> C (ReLU after every
+ *   - A network is created for a fixed batch of B samples of H x W pixels (B * H * W <= 2^26).
+ *     Layer 0 maps 3 -> C channels, layers 1..L-2 map C -> C (ReLU after every
  *     layer but the last), layer L-1 maps C -> 3; C is 32 or 64.
  *   - State tensors on the device are FP32 [B][H][W][3] (phi, v_x / u_scale, v_y / u_scale).
  *   - The parameter vector (FP32, lbcm_net_param_count entries) holds, layer after layer, the
@@ -38,12 +39,16 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
 
 size_t lbcm_net_param_count(const lbcm_net *n);
 
+/* Output scale alpha[0..2] (host, each finite and > 0; default 1): out = state + alpha * z and
+   the loss is mean(((out - target) / alpha)^2).  Takes effect at the next call. */
+int lbcm_net_set_output_scale(lbcm_net *n, const float *alpha);
+
 /* Copy the FP32 parameter vector in (resets the Adam moments) or out.  Synchronise. */
 int lbcm_net_set_params(lbcm_net *n, const float *host, size_t count);
 int lbcm_net_get_params(lbcm_net *n, float *host, size_t count);
 
 /* Forward pass on a device state [B][H][W][3]; out (device, same shape, may be NULL) receives
-   state + network(state).  The activations are kept for lbcm_net_backward. */
+   state + alpha * network(state).  The activations are kept for lbcm_net_backward. */
 int lbcm_net_forward(lbcm_net *n, const float *in, float *out);
 
 /* Forward pass from device FP64 planes [B][H][W] of phi, v_x, v_y (v divided by u_scale on the
@@ -55,9 +60,9 @@ int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, co
 int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, double u_scale,
                                float *state);
 
-/* Gradient of the loss mean((out - target)^2) over pixels and the 3 channels, after a forward
-   pass, into the internal FP32 gradient vector (same layout as the parameters).  *loss (host,
-   may be NULL) receives the loss (then the call synchronises). */
+/* Gradient of the loss mean(((out - target) / alpha)^2) over pixels and the 3 channels, after a
+   forward pass, into the internal FP32 gradient vector (same layout as the parameters).  *loss
+   (host, may be NULL) receives the loss (then the call synchronises). */
 int lbcm_net_backward(lbcm_net *n, const float *target, float *loss);
 
 /* Copy the gradient vector of the last lbcm_net_backward to the host.  Synchronises. */

@@ -10,8 +10,9 @@ trained on trajectories of the method.  Its definition, written out here in plai
   tap t = 0..8 reads the input at (y + dy_t, x + dx_t) with dy_t = t // 3 - 1, dx_t = t % 3 - 1,
   indices taken modulo the box (circular padding);
   layer l:  z_l[p] = b_l + sum_t a_l[p + d_t] @ W_l[t]       (W_l[t] of shape [c_in, c_out])
-  a_0 = s,  a_{l+1} = max(z_l, 0) for l < L - 1,  out = s + z_{L-1};
-  loss = mean over pixels and the 3 channels of (out - target)^2.
+  a_0 = s,  a_{l+1} = max(z_l, 0) for l < L - 1,  out = s + alpha * z_{L-1};
+  loss = mean over pixels and the 3 channels of ((out - target) / alpha)^2,
+with alpha a fixed per-channel output scale (the typical size of the state's change).
 
 Layer 0 maps 3 -> C channels, the hidden layers C -> C and the last C -> 3.  The flat parameter
 vector holds, layer after layer, W_l[t][ci][co] and then the bias padded to the kernels' output
@@ -19,9 +20,9 @@ width (C for hidden layers, 32 for the last; the padding entries carry no meanin
 gradient).
 
 With ``emulate_bf16`` the oracle rounds to bfloat16 (round to nearest even) exactly the operands
-that the MFMA kernels hold in bfloat16: the convolution input, the weights, each hidden
-activation, the gradient of the output and each hidden gradient.  Everything else (biases, the
-residual add, sums) stays FP64.
+that the MFMA kernels hold in bfloat16: the weights of layers 1 .. L-1, each hidden activation,
+the gradient of the output and each hidden gradient.  The first layer (state and weights) and
+everything else (biases, the residual add, sums) stay FP64, as the kernels keep them in FP32.
 
 Adam follows Kingma and Ba, "Adam: A method for stochastic optimization" (ICLR 2015), Algorithm 1,
 with the bias corrections applied to the moments.
@@ -100,31 +101,32 @@ def conv(a: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
     return z
 
 
-def forward(params, state, C: int, L: int, emulate_bf16: bool = False):
+def forward(params, state, C: int, L: int, emulate_bf16: bool = False, alpha=(1.0, 1.0, 1.0)):
     """Returns (out, cache); cache holds what ``backward`` needs."""
     rnd = bf16 if emulate_bf16 else (lambda v: v)
     s = np.asarray(state, dtype=np.float64)
-    layers = [(rnd(W), b) for W, b in unpack(params, C, L)]
-    acts = [rnd(s)]
+    alpha = np.asarray(alpha, dtype=np.float64)
+    layers = [(W if l == 0 else rnd(W), b) for l, (W, b) in enumerate(unpack(params, C, L))]
+    acts = [s]
     z = None
     for l, (W, b) in enumerate(layers):
         z = conv(acts[l], W, b)
         if l < L - 1:
             acts.append(rnd(np.maximum(z, 0.0)))
-    out = s + z
-    return out, {"acts": acts, "layers": layers, "out": out, "emulate": emulate_bf16}
+    out = s + alpha * z
+    return out, {"acts": acts, "layers": layers, "out": out, "emulate": emulate_bf16, "alpha": alpha}
 
 
-def loss(out, target) -> float:
-    return float(np.mean((np.asarray(out) - np.asarray(target)) ** 2))
+def loss(out, target, alpha=(1.0, 1.0, 1.0)) -> float:
+    return float(np.mean(((np.asarray(out) - np.asarray(target)) / np.asarray(alpha, dtype=np.float64)) ** 2))
 
 
 def backward(cache, target, C: int, L: int):
     """Gradient of ``loss`` with respect to the flat parameter vector, and the loss."""
     rnd = bf16 if cache["emulate"] else (lambda v: v)
-    out, acts, layers = cache["out"], cache["acts"], cache["layers"]
+    out, acts, layers, alpha = cache["out"], cache["acts"], cache["layers"], cache["alpha"]
     target = np.asarray(target, dtype=np.float64)
-    g = rnd(2.0 * (out - target) / out.size)  # d loss / d z_{L-1}
+    g = rnd(2.0 * (out - target) / alpha / out.size)  # d loss / d z_{L-1}
     grads = [None] * L
     for l in range(L - 1, -1, -1):
         a = acts[l]
@@ -139,7 +141,7 @@ def backward(cache, target, C: int, L: int):
         for t, (dy, dx) in enumerate(taps()):
             da += shifted(g, -dy, -dx) @ W[t].T
         g = rnd(da * (a > 0))
-    return pack(grads, C, L), loss(out, target)
+    return pack(grads, C, L), loss(out, target, alpha)
 
 
 def adam(params, grads, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):

@@ -1,20 +1,22 @@
 // Learned surrogate of the lattice Boltzmann step: a stack of 3x3 convolutions (circular
 // padding, periodic boxes) that maps the macroscopic state (phi, v_x, v_y) to the state K steps
-// later, trained on trajectories of the LB solver.  Forward and backward passes are implicit GEMMs
-// on the MFMA units of gfx950 (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation).
+// later, trained on trajectories of the LB solver.
 //
-// Tensors.  Activations are NHWC in BF16 with the channel count padded to a multiple of 32 (the K
-// step of one MFMA); the three state channels are padded to 32 on input and 16 on output.  Master
-// weights are FP32, W[l][t][ci][co] with t = 3 (dy + 1) + (dx + 1) the tap at (dy, dx); each
-// iteration packs them to BF16 twice: Wf[t][co][ci] for the forward pass (the MFMA B operand wants
-// 8 consecutive input channels per lane) and Wb[t][ci][co] = W[8 - t][ci][co] for the input
-// gradient: tap t of the mirrored pack sits at d_t = -d_{8-t}, so running the forward kernel on dZ
-// with it gives sum_t dZ[p - d_t] W[t].
+// Network.  z_l[p] = b_l + sum_t a_l[p + d_t] W_l[t] with tap t = 3 (dy + 1) + (dx + 1) at
+// d_t = (dy, dx); a_0 = state, a_{l+1} = relu(z_l), out = state + alpha * z_{L-1} (alpha: a fixed
+// per-channel output scale).  Loss: mean over pixels and channels of ((out - target) / alpha)^2.
 //
-// One convolution layer computes Y[p][co] = b[co] + sum_t sum_ci X[p + d_t][ci] W[t][ci][co] for
-// every pixel p of every sample; its input gradient dX[p][ci] = sum_t sum_co dZ[p - d_t][co]
-// W[t][ci][co] is the same kernel on the mirrored pack; its weight gradient
-// dW[t][ci][co] = sum_p X[p + d_t][ci] dZ[p][co] is a GEMM whose K dimension runs over pixels.
+// Precision and units.  Layer 0 (3 real input channels, 27 products per output) runs on the
+// vector ALU in FP32 with FP32 state and weights, so the state enters at full precision.  Layers
+// 1 .. L-1 are implicit GEMMs on the MFMA units (v_mfma_f32_16x16x32_bf16: BF16 activations and
+// weights, FP32 accumulation); their weights are packed to BF16 from the FP32 masters after every
+// update.  Activations are NHWC BF16 [P][C]; the last layer's 3 outputs are padded to 32.
+//
+// Packs.  Wf[t][co][ci] feeds the forward pass (the MFMA B operand takes 8 consecutive K = input
+// channels per lane).  Wb[t][ci][co] = W[8 - t][ci][co] feeds the input gradient: tap t of the
+// mirrored pack sits at d_t = -d_{8-t}, so the forward kernel run on dZ with it gives
+// dX[p] = sum_t dZ[p - d_t] W[t]^T.  The weight gradient dW[t] = sum_p X[p + d_t]^T dZ[p] is a GEMM
+// whose K dimension runs over pixels.
 
 #include <hip/hip_runtime.h>
 
@@ -28,131 +30,475 @@
 
 #include "lbcm_net.h"
 
+// dynamic LDS of the convolution kernels (external linkage: an array declared in the anonymous
+// namespace would be a zero-sized object of this file)
+extern __shared__ __align__(16) __bf16 lbcm_conv_lds[];
+
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int u32x4;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+typedef __attribute__((__vector_size__(2 * sizeof(unsigned int)))) unsigned int u32x2;
 
-constexpr int kStateC = 3;      // phi, v_x, v_y
-constexpr int kInC = 32;        // padded input channels of the first layer
-constexpr int kOutC = 32;       // padded output channels of the last layer (a K step of the input gradient)
-constexpr int kConvThreads = 256;
-constexpr int kPixPerWave = 32;  // two 16-row MFMA tiles
-constexpr int kDwPix = 64;       // pixels staged per iteration of the weight-gradient kernel
-constexpr int kDwChunk = 4096;   // pixels reduced by one weight-gradient workgroup
+constexpr int kStateC = 3;        // phi, v_x, v_y
+constexpr int kOutC = 32;         // padded output channels of the last layer (a K step of its input gradient)
+constexpr int kThreads = 256;     // four waves
+constexpr int kTileH = 8;         // conv tile: 8 rows x 32 columns of one sample
+constexpr int kTileW = 32;
+constexpr int kPatchH = kTileH + 2, kPatchW = kTileW + 2;
+constexpr int kDwPix = 64;        // pixels staged per iteration of the weight-gradient kernel
+constexpr int kDwChunk = 4096;    // pixels reduced by one weight-gradient workgroup
 
 __device__ __forceinline__ int tap_dy(int t) { return t / 3 - 1; }
 __device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
+
+__device__ __forceinline__ int wrap(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
 
 // pixel index of p shifted by (dy, dx) inside its sample (circular)
 __device__ __forceinline__ uint32_t shift_pix(uint32_t p, int dy, int dx, int H, int W)
 {
     const uint32_t hw = (uint32_t)H * W;
     const uint32_t n = p / hw, r = p - n * hw;
-    int y = (int)(r / W) + dy, x = (int)(r % W) + dx;
-    y = y < 0 ? y + H : (y >= H ? y - H : y);
-    x = x < 0 ? x + W : (x >= W ? x - W : x);
+    const int y = wrap((int)(r / W) + dy, H), x = wrap((int)(r % W) + dx, W);
     return n * hw + (uint32_t)y * W + (uint32_t)x;
 }
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16 *p) { return __builtin_bit_cast(bf16x8, *(const u32x4 *)p); }
 
-// ------------------------------------------------------------------------------------------
-// convolution (forward, or input gradient with the mirrored pack).
-// Each wave computes 32 pixels x Cout output channels (Cout <= 64: up to 4 N-tiles of 16).
-// mode 0: out = bf16(act(bias + conv)); mode 1: out_f32[p][c] = resid[p][c] + bias + conv for
-// c < kStateC (the last layer).  relu: 1 applies max(0, .).  mask (may be NULL): the result is
-// multiplied by [mask > 0] (the ReLU derivative of the layer input, for the input gradient).
-
-template <int NT>
-__global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict__ X, int cin, const __bf16 *__restrict__ Wp,
-                                                       const float *__restrict__ bias, int cout, int sign, int relu,
-                                                       const __bf16 *__restrict__ mask, int mode, __bf16 *__restrict__ Y,
-                                                       const float *__restrict__ resid, float *__restrict__ Yf,
-                                                       uint32_t P, int H, int W)
+// wrap v into [0, n) for v in [-1, n + 40] (the rows and columns a tile and its halo touch)
+__device__ __forceinline__ int wrap_near(int v, int n)
 {
-    const int lane = threadIdx.x & 63;
-    const uint32_t wave = blockIdx.x * (kConvThreads / 64) + (threadIdx.x >> 6);
-    const uint32_t m0 = wave * kPixPerWave;
-    if (m0 >= P) return;  // P is a multiple of 32 (checked on the host)
-    const int r = lane & 15, q = lane >> 4;  // row / column inside a tile, K group
-    f32x4 acc[2][NT];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
-    for (int t = 0; t < 9; ++t) {
-        const int dy = sign * tap_dy(t), dx = sign * tap_dx(t);
-        const uint32_t pa = shift_pix(m0 + r, dy, dx, H, W), pb = shift_pix(m0 + 16 + r, dy, dx, H, W);
-        const __bf16 *Wt = Wp + (size_t)t * cout * cin;
-        for (int kc = 0; kc < cin; kc += 32) {
-            const int k = kc + 8 * q;
-            const bf16x8 a0 = ld8(X + (size_t)pa * cin + k);
-            const bf16x8 a1 = ld8(X + (size_t)pb * cin + k);
+    if (v < 0) v += n;
+    if (v >= n) {
+        v -= n;
+        if (v >= n) v %= n;
+    }
+    return v;
+}
+
+// tile index -> (sample, first row, first column) of an 8 x 32 tile
+struct TileCoord {
+    int n, y0, x0;
+};
+__device__ __forceinline__ TileCoord tile_coord(int tile, int H, int W)
+{
+    const int tx = (W + kTileW - 1) / kTileW, ty = (H + kTileH - 1) / kTileH;
+    const int n = tile / (tx * ty), rem = tile % (tx * ty);
+    return {n, (rem / tx) * kTileH, (rem % tx) * kTileW};
+}
+
+// stage the FP32 state patch (tile plus circular halo) of one tile in LDS: sp[(py * 34 + px) * 3 + c]
+__device__ __forceinline__ void stage_state(const float *__restrict__ s, TileCoord tc, int H, int W, float *sp)
+{
+    constexpr int NV = kPatchH * kPatchW * kStateC, NI = (NV + kThreads - 1) / kThreads;
+    float v[NI];
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const bf16x8 b = ld8(Wt + (size_t)(16 * j + r) * cin + k);
-                acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[0][j], 0, 0, 0);
-                acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[1][j], 0, 0, 0);
-            }
+    for (int i = 0; i < NI; ++i) {
+        const int k = threadIdx.x + i * kThreads;
+        if (k < NV) {
+            const int px = k / kStateC, c = k % kStateC;
+            const int gy = wrap_near(tc.y0 - 1 + px / kPatchW, H), gx = wrap_near(tc.x0 - 1 + px % kPatchW, W);
+            v[i] = s[(((size_t)tc.n * H + gy) * W + gx) * kStateC + c];
         }
     }
-    // D layout: lane holds rows 4q..4q+3 of column r of each 16x16 tile
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int c = 16 * j + r;
-            const float bc = bias ? bias[c] : 0.f;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t p = m0 + 16 * i + 4 * q + e;
-                float v = acc[i][j][e] + bc;
-                if (mode == 1) {
-                    if (c < kStateC) Yf[(size_t)p * kStateC + c] = resid[(size_t)p * kStateC + c] + v;
-                } else {
-                    if (mask && !((float)mask[(size_t)p * cout + c] > 0.f)) v = 0.f;
-                    if (relu) v = fmaxf(v, 0.f);
-                    Y[(size_t)p * cout + c] = (__bf16)v;
-                }
-            }
-        }
+    for (int i = 0; i < NI; ++i) {
+        const int k = threadIdx.x + i * kThreads;
+        if (k < NV) sp[k] = v[i];
+    }
 }
 
 // ------------------------------------------------------------------------------------------
-// weight gradient: partial[chunk][t][ci][co] = sum over the chunk's pixels p of
-// X[p + d_t][ci] dZ[p][co].  A workgroup (4 waves) owns one tap and one chunk of pixels; it stages
-// 64 pixels of X (shifted) and dZ in LDS with 16-byte loads, then each wave accumulates its share
-// of the (ci, co) 16x16 tiles with MFMAs whose K dimension is the pixels.
+// layer 0 on the vector ALU over 8 x 32 tiles: Y[p][co] = bf16(relu(b[co] + sum_{t, ci}
+// s[p + d_t][ci] W0[t][ci][co])), one tile per workgroup.  The state patch and the 27 x C weights
+// are staged in LDS.  Wave
+// w of the 8 computes output channels [C/8 w, C/8 (w + 1)) and each lane 4 pixels of the tile,
+// so that every weight read (a wave-uniform LDS broadcast) feeds 4 FMAs.
 
-__global__ __launch_bounds__(kConvThreads) void k_conv_dw(const __bf16 *__restrict__ X, int cin, const __bf16 *__restrict__ dZ,
-                                                          int cout, uint32_t P, int H, int W, float *__restrict__ partial)
+constexpr int kFirstThreads = 512;
+
+template <int C>
+__global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict__ s, const float *__restrict__ W0,
+                                                         const float *__restrict__ b0, int H, int W,
+                                                         __bf16 *__restrict__ Y)
 {
-    __shared__ __align__(16) __bf16 sx[kDwPix * 64];
-    __shared__ __align__(16) __bf16 sz[kDwPix * 64];
+    constexpr int CW = C / 8;  // channels per wave
+    __shared__ float sp[kPatchH * kPatchW * kStateC];
+    __shared__ __align__(16) float sw[28 * C];  // rows 0..26: W0[3 t + ci][co]; row 27: bias
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c0 = CW * wave;
+    const int base = (((lane >> 5) + 1) * kPatchW + (lane & 31) + 1) * kStateC;  // patch index of pixel `lane`
+    for (int k = threadIdx.x; k < 28 * C; k += kFirstThreads) sw[k] = k < 27 * C ? W0[k] : b0[k - 27 * C];
+    const TileCoord tc = tile_coord(blockIdx.x, H, W);
+    {
+        constexpr int NV = kPatchH * kPatchW * kStateC, NI = (NV + kFirstThreads - 1) / kFirstThreads;
+        float v[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kFirstThreads;
+            if (k < NV) {
+                const int px = k / kStateC, c = k % kStateC;
+                const int gy = wrap_near(tc.y0 - 1 + px / kPatchW, H), gx = wrap_near(tc.x0 - 1 + px % kPatchW, W);
+                v[i] = s[(((size_t)tc.n * H + gy) * W + gx) * kStateC + c];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kFirstThreads;
+            if (k < NV) sp[k] = v[i];
+        }
+    }
+    __syncthreads();
+    float acc[4][CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+        const float b = sw[27 * C + c0 + j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k][j] = b;
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+#pragma unroll
+        for (int ci = 0; ci < kStateC; ++ci) {
+            float x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)  // pixel lane + 64 k sits 2 k rows below pixel lane
+                x[k] = sp[base + ((2 * k + tap_dy(t)) * kPatchW + tap_dx(t)) * kStateC + ci];
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+                const float w = sw[(3 * t + ci) * C + c0 + j];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k][j] = fmaf(x[k], w, acc[k][j]);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep each tap's weight reads next to its FMAs
+    }
+    // materialise the sums here: otherwise the FMAs are sunk into the per-pixel store branches
+    // below, and every LDS read ahead of them stays live at once
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) asm volatile("" : "+v"(acc[k][j]));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int pix = lane + 64 * k, y = tc.y0 + pix / kTileW, xg = tc.x0 + pix % kTileW;
+        if (y >= H || xg >= W) continue;
+        __bf16 *out = Y + (((size_t)tc.n * H + y) * W + xg) * C + c0;
+        if constexpr (CW % 8 == 0) {
+#pragma unroll
+            for (int j = 0; j < CW; j += 8) {
+                bf16x8 v;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = (__bf16)fmaxf(acc[k][j + e], 0.f);
+                *(u32x4 *)(out + j) = __builtin_bit_cast(u32x4, v);
+            }
+        } else {
+            static_assert(CW == 4, "4 or a multiple of 8 channels per wave");
+            bf16x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (__bf16)fmaxf(acc[k][e], 0.f);
+            *(u32x2 *)out = __builtin_bit_cast(u32x2, v);
+        }
+    }
+}
+
+// layer 0 gradients, one 8 x 32 tile per workgroup: partial[tile][r][co] for r = 3 t + ci
+// (r < 27: sum_p s[p + d_t][ci] dZ[p][co]) and r = 27 (sum_p dZ[p][co], the bias).  The state
+// patch and the tile's dZ are staged in LDS; thread (g, co) accumulates rows r = g, g + G, ...
+// with G = kThreads / C.
+template <int C>
+__global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__ s, const __bf16 *__restrict__ dz, int H,
+                                                       int W, float *__restrict__ partial)
+{
+    constexpr int G = kThreads / C, R = (28 + G - 1) / G;
+    __shared__ float sp[kPatchH * kPatchW * kStateC];
+    __shared__ __align__(16) __bf16 sd[kTileH * kTileW * C];
+    const TileCoord tc = tile_coord(blockIdx.x, H, W);
+    stage_state(s, tc, H, W, sp);
+    constexpr int NV = kTileH * kTileW * C / 8;
+#pragma unroll
+    for (int k = threadIdx.x; k < NV; k += kThreads) {
+        const int px = k / (C / 8), ch = (k % (C / 8)) * 8;
+        const int y = tc.y0 + px / kTileW, xg = tc.x0 + px % kTileW;
+        u32x4 v = {0, 0, 0, 0};  // pixels past the box edge contribute nothing
+        if (y < H && xg < W) v = *(const u32x4 *)(dz + (((size_t)tc.n * H + y) * W + xg) * C + ch);
+        *(u32x4 *)(sd + px * C + ch) = v;
+    }
+    __syncthreads();
+    const int co = threadIdx.x % C, g = threadIdx.x / C;
+    float acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.f;
+    for (int px = 0; px < kTileH * kTileW; ++px) {
+        const float d = (float)sd[px * C + co];
+        const int ly = px / kTileW, lx = px % kTileW;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = g + k * G;
+            if (r < 27) {
+                const int t = r / 3;
+                acc[k] = fmaf(sp[((ly + 1 + tap_dy(t)) * kPatchW + lx + 1 + tap_dx(t)) * kStateC + r % 3], d, acc[k]);
+            } else if (r == 27) {
+                acc[k] += d;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = g + k * G;
+        if (r < 28) partial[((size_t)blockIdx.x * 28 + r) * C + co] = acc[k];
+    }
+}
+
+// out[j] = sum over rows i of partial[i * ld + j] for j < ncols, one workgroup per column, in a
+// fixed tree order (deterministic)
+__global__ __launch_bounds__(256) void k_sum_rows(const float *__restrict__ partial, int nrows, int ld, int ncols,
+                                                  float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const int j = blockIdx.x;
+    if (j >= ncols) return;
+    float a = 0;
+    for (int i = threadIdx.x; i < nrows; i += 256) a += partial[(size_t)i * ld + j];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// ------------------------------------------------------------------------------------------
+// MFMA convolution over 8 x 32 pixel tiles of one sample (layers 1 .. L-1 forward, and the input
+// gradient with the mirrored pack).
+//
+// The workgroup (8 waves) stages the layer's weights once and the 10 x 34 input patch (tile plus
+// circular halo) of each tile in dynamic LDS, with row strides padded by 16 bytes so that the 16
+// rows of a fragment fall in distinct banks; a thread issues all its global loads of a patch
+// before storing any, and the next tile's during the current tile's MFMAs.  Wave (mg, ng) computes
+// output channels [16 ng, 16 ng + 16) for the tile rows of row group mg (COUT / 16 channel groups
+// times 8 / (COUT / 16) row groups).  It keeps its weight fragments (9 taps x CIN / 32 K-steps) in
+// registers for the whole launch, as the MFMA A operand, and takes 16 pixels as the B operand, so
+// that each lane ends with 4 consecutive output channels of one pixel (one 8-byte store).
+// Tiles past the grid are taken in a grid-stride loop.  Dynamic LDS: ConvLds<CIN, COUT>::bytes.
+//
+// MODE 0: Y = bf16(relu(bias + conv));  MODE 2: Y = bf16(conv * [mask > 0]) (the input gradient
+// times the ReLU derivative of the layer input);  MODE 1: Yf[p][c] = resid[p][c] + alpha_c (bias
+// + conv) for c < 3 (the last layer, FP32).
+
+constexpr int kConvThreads = 512;
+
+struct OutArgs {
+    const float *bias;
+    const __bf16 *mask;
+    __bf16 *Y;
+    const float *resid;
+    float *Yf;
+    float alpha0, alpha1, alpha2;
+};
+
+template <int CIN>
+struct Patch {
+    static constexpr int PS = CIN + 8;  // LDS pixel stride (bf16)
+    static constexpr int NV = kPatchH * kPatchW * (CIN / 8), NI = (NV + kConvThreads - 1) / kConvThreads;
+    u32x4 v[NI];
+
+    __device__ __forceinline__ void load(const __bf16 *__restrict__ X, TileCoord tc, int H, int W)
+    {
+        const __bf16 *Xn = X + (size_t)tc.n * H * W * CIN;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kConvThreads;
+            if (k < NV) {
+                const int px = k / (CIN / 8), ch = (k % (CIN / 8)) * 8;
+                const int gy = wrap_near(tc.y0 - 1 + px / kPatchW, H), gx = wrap_near(tc.x0 - 1 + px % kPatchW, W);
+                v[i] = *(const u32x4 *)(Xn + ((size_t)gy * W + gx) * CIN + ch);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(__bf16 *patch) const
+    {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kConvThreads;
+            if (k < NV) *(u32x4 *)(patch + (k / (CIN / 8)) * PS + (k % (CIN / 8)) * 8) = v[i];
+        }
+    }
+};
+
+template <int CIN, int COUT>
+struct ConvLds {
+    static constexpr int PS = Patch<CIN>::PS;        // patch pixel stride (bf16)
+    static constexpr int WS = CIN + 8;               // weight row stride (bf16), padded like the patch
+    static constexpr int patch_elems = kPatchH * kPatchW * PS;
+    static constexpr int weight_elems = 9 * COUT * WS;
+    static constexpr size_t bytes = (size_t)(patch_elems + weight_elems) * sizeof(__bf16);
+};
+
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wp, OutArgs o,
+                                                       int ntiles, int H, int W)
+{
+    using Lds = ConvLds<CIN, COUT>;
+    constexpr int PS = Lds::PS, WS = Lds::WS;
+    static_assert(PS == Patch<CIN>::PS, "patch stride");
+    constexpr int KS = CIN / 32;      // K-steps per tap
+    constexpr int NG = COUT / 16;     // channel groups (one 16-channel tile each)
+    constexpr int MG = 8 / NG;        // row groups
+    constexpr int RW = kTileH / MG;   // tile rows per wave
+    constexpr int MT = 2 * RW;        // pixel tiles (16 pixels) per wave
+    __bf16 *patch = lbcm_conv_lds, *wl = lbcm_conv_lds + Lds::patch_elems;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int mg = wave % MG, ng = wave / MG;
+    const int r = lane & 15, q = lane >> 4;
+    const int cbase = 16 * ng;
+
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    // the layer's weights Wp[t][co][ci] go to LDS once per workgroup (coalesced 16-byte loads),
+    // then each wave takes its fragments from there
+    {
+        constexpr int NV = 9 * COUT * CIN / 8, NI = (NV + kConvThreads - 1) / kConvThreads;
+        u32x4 v[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kConvThreads;
+            if (k < NV) v[i] = *(const u32x4 *)(Wp + (size_t)k * 8);
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kConvThreads;
+            if (k < NV) *(u32x4 *)(wl + (k / (CIN / 8)) * WS + (k % (CIN / 8)) * 8) = v[i];
+        }
+    }
+    Patch<CIN> pre;
+    pre.load(X, tile_coord(tile, H, W), H, W);
+    __syncthreads();
+    // A fragments: lane (r, q) holds W[t][co = cbase + r][ci = 32 ks + 8 q .. + 8]
+    bf16x8 wa[9][KS];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) wa[t][ks] = ld8(wl + (t * COUT + cbase + r) * WS + 32 * ks + 8 * q);
+    // this lane's output channels: cbase + 4 q + e
+    float bias[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bias[e] = (MODE != 2) ? o.bias[cbase + 4 * q + e] : 0.f;
+
+    for (; tile < ntiles; tile += gridDim.x) {
+        const TileCoord tc = tile_coord(tile, H, W);
+        __syncthreads();  // the previous tile's readers are done
+        pre.store(patch);
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) pre.load(X, tile_coord(tile + gridDim.x, H, W), H, W);
+        f32x4 acc[MT];
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi) acc[mi] = f32x4{0, 0, 0, 0};
+        // input-stationary order: each pixel fragment of the wave's RW + 2 patch rows is read from
+        // LDS once and applied to every output row (tap dy) that uses it.  Stage s covers patch
+        // row s / 2 and column half s % 2 (3 horizontal taps x KS fragments); the fragments of
+        // stage s + 1 are read before the MFMAs of stage s, in a second register buffer.
+        constexpr int NS = 2 * (RW + 2);
+        bf16x8 fr[2][3][KS];
+        auto load_stage = [&](int st, bf16x8 (&f)[3][KS]) {
+            const int py = st >> 1, half = st & 1;
+#pragma unroll
+            for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+                    f[dxi][ks] = ld8(patch + ((RW * mg + py) * kPatchW + 16 * half + r + dxi) * PS + 32 * ks + 8 * q);
+        };
+        load_stage(0, fr[0]);
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            if (st + 1 < NS) load_stage(st + 1, fr[(st + 1) & 1]);
+            const int py = st >> 1, half = st & 1;
+#pragma unroll
+            for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                    for (int rho = 0; rho < RW; ++rho) {
+                        const int dyi = py - rho;  // tap row index dy + 1
+                        if (dyi < 0 || dyi > 2) continue;
+                        acc[2 * rho + half] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 * dyi + dxi][ks], fr[st & 1][dxi][ks],
+                                                                                      acc[2 * rho + half], 0, 0, 0);
+                    }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // D[co][pixel]: lane (r, q) holds channels cbase + 4 q .. + 3 of pixel r of each tile
+        const int c0 = cbase + 4 * q;
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi) {
+            const int yy = tc.y0 + RW * mg + (mi >> 1), xx = tc.x0 + 16 * (mi & 1) + r;
+            if (yy >= H || xx >= W) continue;
+            const size_t p = ((size_t)tc.n * H + yy) * W + xx;
+            if (MODE == 1) {
+                if (c0 == 0) {  // channels 0 .. 2 live in the q = 0 lanes of the first channel group
+                    o.Yf[p * kStateC + 0] = o.resid[p * kStateC + 0] + o.alpha0 * (acc[mi][0] + bias[0]);
+                    o.Yf[p * kStateC + 1] = o.resid[p * kStateC + 1] + o.alpha1 * (acc[mi][1] + bias[1]);
+                    o.Yf[p * kStateC + 2] = o.resid[p * kStateC + 2] + o.alpha2 * (acc[mi][2] + bias[2]);
+                }
+            } else {
+                bf16x4 m4 = {};
+                if (MODE == 2) m4 = __builtin_bit_cast(bf16x4, *(const u32x2 *)(o.mask + p * COUT + c0));
+                bf16x4 v4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float v = acc[mi][e] + bias[e];
+                    v4[e] = (__bf16)(MODE == 2 ? (((float)m4[e] > 0.f) ? v : 0.f) : fmaxf(v, 0.f));
+                }
+                *(u32x2 *)(o.Y + p * COUT + c0) = __builtin_bit_cast(u32x2, v4);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// weight gradient of layers 1 .. L-1: partial[chunk][t][ci][co] = sum over the chunk's pixels p
+// of X[p + d_t][ci] dZ[p][co].  A workgroup owns one tap and one chunk; it stages 64 pixels of X
+// (shifted) and dZ in LDS with 16-byte loads (pixel stride padded by 16 bytes), then each wave
+// accumulates its share of the (ci, co) 16 x 16 tiles with MFMAs whose K dimension is the pixels.
+
+__global__ __launch_bounds__(kThreads) void k_conv_dw(const __bf16 *__restrict__ X, int cin, const __bf16 *__restrict__ dZ,
+                                                      int cout, uint32_t P, int H, int W, float *__restrict__ partial)
+{
+    constexpr int PS = 64 + 8;
+    __shared__ __align__(16) __bf16 sx[kDwPix * PS];
+    __shared__ __align__(16) __bf16 sz[kDwPix * PS];
     const int t = blockIdx.y;
     const uint32_t chunk = blockIdx.x;
     const uint32_t p_begin = chunk * kDwChunk, p_end = min(P, p_begin + kDwChunk);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const int mt = cin / 16, nt = cout / 16, ntiles = mt * nt;  // <= 16 tiles, 4 per wave
+    const int nt = cout / 16, ntiles = (cin / 16) * nt;  // <= 16 tiles, 4 per wave
     f32x4 acc[4];
     for (int i = 0; i < 4; ++i) acc[i] = f32x4{0, 0, 0, 0};
     const int dy = tap_dy(t), dx = tap_dx(t);
     for (uint32_t p0 = p_begin; p0 < p_end; p0 += kDwPix) {
-        // stage: 64 pixels x cin of X shifted, 64 x cout of dZ; 8 bf16 per thread per load
-        for (int v = threadIdx.x; v < kDwPix * cin / 8; v += kConvThreads) {
+        for (int v = threadIdx.x; v < kDwPix * cin / 8; v += kThreads) {
             const int px = v / (cin / 8), ch = (v % (cin / 8)) * 8;
             const uint32_t p = p0 + px;
             u32x4 val = {0, 0, 0, 0};
             if (p < p_end) val = *(const u32x4 *)(X + (size_t)shift_pix(p, dy, dx, H, W) * cin + ch);
-            *(u32x4 *)(sx + px * cin + ch) = val;
+            *(u32x4 *)(sx + px * PS + ch) = val;
         }
-        for (int v = threadIdx.x; v < kDwPix * cout / 8; v += kConvThreads) {
+        for (int v = threadIdx.x; v < kDwPix * cout / 8; v += kThreads) {
             const int px = v / (cout / 8), ch = (v % (cout / 8)) * 8;
             const uint32_t p = p0 + px;
             u32x4 val = {0, 0, 0, 0};
             if (p < p_end) val = *(const u32x4 *)(dZ + (size_t)p * cout + ch);
-            *(u32x4 *)(sz + px * cout + ch) = val;
+            *(u32x4 *)(sz + px * PS + ch) = val;
         }
         __syncthreads();
         for (int s = 0; s < 4; ++s) {
@@ -165,8 +511,8 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_dw(const __bf16 *__restri
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int px = kk + 8 * q + e;
-                    a[e] = sx[px * cin + 16 * mi + r];  // A[ci][pixel]
-                    b[e] = sz[px * cout + 16 * ni + r]; // B[pixel][co]
+                    a[e] = sx[px * PS + 16 * mi + r];  // A[ci][pixel]
+                    b[e] = sz[px * PS + 16 * ni + r];  // B[pixel][co]
                 }
                 acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[s], 0, 0, 0);
             }
@@ -196,7 +542,7 @@ __global__ void k_dw_reduce(const float *__restrict__ partial, int nchunks, int 
     }
 }
 
-// bias gradient db[co] = sum_p dZ[p][co]: per-block partial sums, then a fixed-order sum
+// bias gradient db[co] = sum_p dZ[p][co]: per-block partial sums (then k_sum_rows)
 __global__ __launch_bounds__(256) void k_db_partial(const __bf16 *__restrict__ dZ, int cout, uint32_t P,
                                                     float *__restrict__ partial)
 {
@@ -215,34 +561,30 @@ __global__ __launch_bounds__(256) void k_db_partial(const __bf16 *__restrict__ d
     }
 }
 
-__global__ void k_db_reduce(const float *__restrict__ partial, int nblocks, int cout_r, float *__restrict__ db)
-{
-    const int c = threadIdx.x;
-    if (c >= cout_r) return;
-    float s = 0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * 64 + c];
-    db[c] = s;
-}
-
 // ------------------------------------------------------------------------------------------
-// loss: mean over pixels and the three state channels of (pred - target)^2; the gradient of the
-// last layer's output is 2 (pred - target) / (3 P), stored padded to kOutC channels.
+// loss: mean over pixels and the three state channels of ((pred - target) / alpha_c)^2; the
+// gradient of the last layer's pre-scale output is 2 (pred - target) / (alpha_c 3 P), stored padded
+// to kOutC channels.
 __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ pred, const float *__restrict__ target, uint32_t P,
-                                              __bf16 *__restrict__ dZ, float *__restrict__ partial)
+                                              float ia0, float ia1, float ia2, __bf16 *__restrict__ dZ,
+                                              float *__restrict__ partial)
 {
     __shared__ float red[256];
     const float scale = 2.0f / (3.0f * (float)P);
+    const float ia[3] = {ia0, ia1, ia2};
     float s = 0;
     for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < P; p += gridDim.x * 256u) {
-        for (int c = 0; c < kOutC; ++c) {
-            float g = 0;
-            if (c < kStateC) {
-                const float d = pred[(size_t)p * kStateC + c] - target[(size_t)p * kStateC + c];
-                s += d * d;
-                g = scale * d;
-            }
-            dZ[(size_t)p * kOutC + c] = (__bf16)g;
+        bf16x8 g[kOutC / 8];
+#pragma unroll
+        for (int c = 0; c < kOutC; ++c) g[c / 8][c % 8] = (__bf16)0.f;
+#pragma unroll
+        for (int c = 0; c < kStateC; ++c) {
+            const float d = (pred[(size_t)p * kStateC + c] - target[(size_t)p * kStateC + c]) * ia[c];
+            s += d * d;
+            g[0][c] = (__bf16)(scale * d);
         }
+#pragma unroll
+        for (int k = 0; k < kOutC / 8; ++k) *(u32x4 *)(dZ + (size_t)p * kOutC + 8 * k) = __builtin_bit_cast(u32x4, g[k]);
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -287,13 +629,6 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
         v[i] = vi;
         p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     }
-}
-
-// FP32 state [P][3] -> BF16 [P][kInC] (zero padded)
-__global__ void k_in_pack(const float *__restrict__ s, uint32_t P, __bf16 *__restrict__ x)
-{
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
-        for (int c = 0; c < kInC; ++c) x[(size_t)p * kInC + c] = (__bf16)(c < kStateC ? s[(size_t)p * kStateC + c] : 0.f);
 }
 
 // state planes (FP64, [B][H][W] each) -> FP32 [P][3] with the velocity divided by u_scale, and back
@@ -354,15 +689,18 @@ struct lbcm_net {
     int batch = 0, H = 0, W = 0, C = 0, L = 0;
     uint32_t P = 0;
     hipStream_t stream = nullptr;
+    int ntiles = 0;                             // 8 x 32 tiles over the batch
+    int conv_grid = 0;                          // workgroups of a conv launch (grid-stride over tiles)
     std::vector<int> cin_r, cout_r, cin, cout;  // real and padded channel counts per layer
     std::vector<size_t> w_off, b_off;           // offsets of each layer in the parameter vector
     size_t nparams = 0;
+    float alpha[3] = {1.f, 1.f, 1.f};           // output scale per state channel
     float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
-    std::vector<__bf16 *> Wf, Wb;
-    std::vector<__bf16 *> act;                  // act[0] = packed input, act[l + 1] = output of layer l (l < L - 1)
-    __bf16 *dz_a = nullptr, *dz_b = nullptr;    // gradient ping-pong buffers (P x C)
-    float *resid = nullptr, *out = nullptr;     // FP32 [P][3]
-    float *dw_partial = nullptr, *db_partial = nullptr, *loss_partial = nullptr;
+    std::vector<__bf16 *> Wf, Wb;               // BF16 packs of layers 1 .. L-1
+    std::vector<__bf16 *> act;                  // act[l] = input of layer l >= 1 (relu output of layer l - 1)
+    __bf16 *dz_a = nullptr, *dz_b = nullptr;    // gradient ping-pong buffers (P x 64)
+    float *resid = nullptr, *out = nullptr;     // FP32 [P][3]: input state, output state
+    float *dw_partial = nullptr, *db_partial = nullptr, *loss_partial = nullptr, *first_partial = nullptr;
     int loss_blocks = 0;
     bool packed = false;
     std::string err;
@@ -391,24 +729,37 @@ int grid_of(size_t n, int threads)
     return (int)std::max<size_t>(1, std::min<size_t>(b, 65535));
 }
 
-int launch_conv(lbcm_net *n, const __bf16 *X, int cin, const __bf16 *Wp, const float *bias, int cout, int sign, int relu,
-                const __bf16 *mask, int mode, __bf16 *Y, const float *resid, float *Yf)
+template <int CI, int CO, int MO>
+int launch_conv_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wp, const OutArgs &o)
 {
-    const uint32_t waves = n->P / kPixPerWave;
-    const dim3 grid((waves + kConvThreads / 64 - 1) / (kConvThreads / 64)), block(kConvThreads);
-    switch (cout / 16) {
-    case 1: hipLaunchKernelGGL(k_conv<1>, grid, block, 0, n->stream, X, cin, Wp, bias, cout, sign, relu, mask, mode, Y, resid, Yf, n->P, n->H, n->W); break;
-    case 2: hipLaunchKernelGGL(k_conv<2>, grid, block, 0, n->stream, X, cin, Wp, bias, cout, sign, relu, mask, mode, Y, resid, Yf, n->P, n->H, n->W); break;
-    case 4: hipLaunchKernelGGL(k_conv<4>, grid, block, 0, n->stream, X, cin, Wp, bias, cout, sign, relu, mask, mode, Y, resid, Yf, n->P, n->H, n->W); break;
-    default: return nfail(n, LBCM_EINVAL, "unsupported channel count");
+    constexpr size_t bytes = ConvLds<CI, CO>::bytes;
+    static bool attr = false;  // beyond 64 KiB of dynamic LDS must be allowed explicitly, once
+    if (!attr) {
+        NHIP(n, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv<CI, CO, MO>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        attr = true;
     }
+    hipLaunchKernelGGL((k_conv<CI, CO, MO>), dim3(n->conv_grid), dim3(kConvThreads), bytes, n->stream, X, Wp, o, n->ntiles,
+                       n->H, n->W);
     NHIP(n, hipGetLastError());
     return LBCM_OK;
 }
 
+int launch_conv(lbcm_net *n, const __bf16 *X, int cin, const __bf16 *Wp, int cout, int mode, const OutArgs &o)
+{
+    if (cin == 64 && cout == 64 && mode == 0) return launch_conv_t<64, 64, 0>(n, X, Wp, o);
+    if (cin == 64 && cout == 64 && mode == 2) return launch_conv_t<64, 64, 2>(n, X, Wp, o);
+    if (cin == 64 && cout == 32 && mode == 1) return launch_conv_t<64, 32, 1>(n, X, Wp, o);
+    if (cin == 32 && cout == 64 && mode == 2) return launch_conv_t<32, 64, 2>(n, X, Wp, o);
+    if (cin == 32 && cout == 32 && mode == 0) return launch_conv_t<32, 32, 0>(n, X, Wp, o);
+    if (cin == 32 && cout == 32 && mode == 1) return launch_conv_t<32, 32, 1>(n, X, Wp, o);
+    if (cin == 32 && cout == 32 && mode == 2) return launch_conv_t<32, 32, 2>(n, X, Wp, o);
+    return nfail(n, LBCM_EINVAL, "unsupported channel counts");
+}
+
 int pack_all(lbcm_net *n)
 {
-    for (int l = 0; l < n->L; ++l) {
+    for (int l = 1; l < n->L; ++l) {
         hipLaunchKernelGGL(k_pack, dim3(grid_of(9 * (size_t)n->cin[l] * n->cout[l], 256)), dim3(256), 0, n->stream,
                            n->params + n->w_off[l], n->cin_r[l], n->cout_r[l], n->cin[l], n->cout[l], n->Wf[l], n->Wb[l]);
         NHIP(n, hipGetLastError());
@@ -424,12 +775,25 @@ int forward(lbcm_net *n)
         int rc = pack_all(n);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_in_pack, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, n->resid, n->P, n->act[0]);
+    const dim3 g1(n->ntiles), b1(kFirstThreads);
+    if (n->C == 64)
+        hipLaunchKernelGGL(k_first<64>, g1, b1, 0, n->stream, n->resid, n->params + n->w_off[0], n->params + n->b_off[0], n->H,
+                           n->W, n->act[1]);
+    else
+        hipLaunchKernelGGL(k_first<32>, g1, b1, 0, n->stream, n->resid, n->params + n->w_off[0], n->params + n->b_off[0], n->H,
+                           n->W, n->act[1]);
     NHIP(n, hipGetLastError());
-    for (int l = 0; l < n->L; ++l) {
+    for (int l = 1; l < n->L; ++l) {
         const bool last = l == n->L - 1;
-        int rc = launch_conv(n, n->act[l], n->cin[l], n->Wf[l], n->params + n->b_off[l], n->cout[l], 1, last ? 0 : 1, nullptr,
-                             last ? 1 : 0, last ? nullptr : n->act[l + 1], n->resid, n->out);
+        OutArgs o{};
+        o.bias = n->params + n->b_off[l];
+        o.Y = last ? nullptr : n->act[l + 1];
+        o.resid = n->resid;
+        o.Yf = n->out;
+        o.alpha0 = n->alpha[0];
+        o.alpha1 = n->alpha[1];
+        o.alpha2 = n->alpha[2];
+        int rc = launch_conv(n, n->act[l], n->cin[l], n->Wf[l], n->cout[l], last ? 1 : 0, o);
         if (rc) return rc;
     }
     return LBCM_OK;
@@ -445,8 +809,8 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
     if (!out) return LBCM_EINVAL;
     *out = nullptr;
     const size_t P = (size_t)batch * height * width;
-    if (batch < 1 || height < 1 || width < 1 || P % kPixPerWave || P > 0xffffffffull / 64) {
-        g_net_error = "batch * height * width must be a positive multiple of 32 (and below 2^26)";
+    if (batch < 1 || height < 1 || width < 1 || P > (1ull << 26)) {
+        g_net_error = "batch, height and width must be >= 1 with batch * height * width <= 2^26";
         return LBCM_EINVAL;
     }
     if (channels != 32 && channels != 64) {
@@ -466,15 +830,19 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
     n->L = layers;
     n->P = (uint32_t)P;
     n->stream = (hipStream_t)stream;
+    const size_t ntiles = (size_t)batch * ((height + kTileH - 1) / kTileH) * ((width + kTileW - 1) / kTileW);
+    n->ntiles = (int)ntiles;
+    // one resident workgroup per CU (LDS and two waves per SIMD); more tiles are taken in turn
+    n->conv_grid = (int)std::min<size_t>(ntiles, 256);
     for (int l = 0; l < layers; ++l) {
         n->cin_r.push_back(l == 0 ? kStateC : channels);
         n->cout_r.push_back(l == layers - 1 ? kStateC : channels);
-        n->cin.push_back(l == 0 ? kInC : channels);
+        n->cin.push_back(l == 0 ? kStateC : channels);
         n->cout.push_back(l == layers - 1 ? kOutC : channels);
         n->w_off.push_back(n->nparams);
         n->nparams += 9 * (size_t)n->cin_r[l] * n->cout_r[l];
         n->b_off.push_back(n->nparams);
-        n->nparams += n->cout_r[l] + (n->cout[l] - n->cout_r[l]);  // bias padded to cout (zeros)
+        n->nparams += n->cout[l];  // bias padded to the kernel's output width (zeros past cout_r)
     }
     auto bail = [&](const std::string &m) {
         g_net_error = m;
@@ -491,12 +859,11 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
         return bail("hipMemsetAsync failed");
     n->Wf.assign(layers, nullptr);
     n->Wb.assign(layers, nullptr);
-    for (int l = 0; l < layers; ++l) {
+    for (int l = 1; l < layers; ++l) {
         const size_t wb = 9 * (size_t)n->cin[l] * n->cout[l] * sizeof(__bf16);
         if (!dmalloc((void **)&n->Wf[l], wb) || !dmalloc((void **)&n->Wb[l], wb)) return bail("out of device memory (packs)");
     }
     n->act.assign(layers, nullptr);
-    if (!dmalloc((void **)&n->act[0], P * kInC * sizeof(__bf16))) return bail("out of device memory (input)");
     for (int l = 1; l < layers; ++l)
         if (!dmalloc((void **)&n->act[l], P * channels * sizeof(__bf16))) return bail("out of device memory (activations)");
     if (!dmalloc((void **)&n->dz_a, P * 64 * sizeof(__bf16)) || !dmalloc((void **)&n->dz_b, P * 64 * sizeof(__bf16)))
@@ -506,6 +873,8 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
     const size_t nchunks = (P + kDwChunk - 1) / kDwChunk;
     if (!dmalloc((void **)&n->dw_partial, nchunks * 9 * 64 * 64 * sizeof(float))) return bail("out of device memory (dW)");
     if (!dmalloc((void **)&n->db_partial, ((P + 1023) / 1024) * 64 * sizeof(float))) return bail("out of device memory (db)");
+    if (!dmalloc((void **)&n->first_partial, ntiles * 28 * channels * sizeof(float)))
+        return bail("out of device memory (first layer)");
     n->loss_blocks = grid_of(P, 256) > 1024 ? 1024 : grid_of(P, 256);
     if (!dmalloc((void **)&n->loss_partial, n->loss_blocks * sizeof(float))) return bail("out of device memory (loss)");
     *out = n;
@@ -513,6 +882,15 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
 }
 
 size_t lbcm_net_param_count(const lbcm_net *n) { return n ? n->nparams : 0; }
+
+int lbcm_net_set_output_scale(lbcm_net *n, const float *alpha)
+{
+    if (!n || !alpha) return LBCM_EINVAL;
+    for (int c = 0; c < kStateC; ++c)
+        if (!(alpha[c] > 0.f) || !std::isfinite(alpha[c])) return nfail(n, LBCM_EINVAL, "output scales must be finite and > 0");
+    for (int c = 0; c < kStateC; ++c) n->alpha[c] = alpha[c];
+    return LBCM_OK;
+}
 
 int lbcm_net_set_params(lbcm_net *n, const float *host, size_t count)
 {
@@ -584,29 +962,44 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
     if (!n || !target) return LBCM_EINVAL;
     const uint32_t P = n->P;
     const int L = n->L;
-    hipLaunchKernelGGL(k_loss, dim3(n->loss_blocks), dim3(256), 0, n->stream, n->out, target, P, n->dz_a, n->loss_partial);
+    hipLaunchKernelGGL(k_loss, dim3(n->loss_blocks), dim3(256), 0, n->stream, n->out, target, P, 1.f / n->alpha[0],
+                       1.f / n->alpha[1], 1.f / n->alpha[2], n->dz_a, n->loss_partial);
     NHIP(n, hipGetLastError());
     __bf16 *dz = n->dz_a, *dn = n->dz_b;
     const int nchunks = (int)((P + kDwChunk - 1) / kDwChunk);
     const int dbb = (int)((P + 1023) / 1024);
-    for (int l = L - 1; l >= 0; --l) {
+    for (int l = L - 1; l >= 1; --l) {
         // weight and bias gradients of layer l from its input act[l] and dz (gradient of its output)
-        hipLaunchKernelGGL(k_conv_dw, dim3(nchunks, 9), dim3(kConvThreads), 0, n->stream, n->act[l], n->cin[l], dz, n->cout[l],
-                           P, n->H, n->W, n->dw_partial);
+        hipLaunchKernelGGL(k_conv_dw, dim3(nchunks, 9), dim3(kThreads), 0, n->stream, n->act[l], n->cin[l], dz, n->cout[l], P,
+                           n->H, n->W, n->dw_partial);
         NHIP(n, hipGetLastError());
         hipLaunchKernelGGL(k_dw_reduce, dim3(grid_of(9 * (size_t)n->cin_r[l] * n->cout_r[l], 256)), dim3(256), 0, n->stream,
                            n->dw_partial, nchunks, n->cin[l], n->cout[l], n->cin_r[l], n->cout_r[l], n->grads + n->w_off[l]);
         NHIP(n, hipGetLastError());
         hipLaunchKernelGGL(k_db_partial, dim3(dbb), dim3(256), 0, n->stream, dz, n->cout[l], P, n->db_partial);
         NHIP(n, hipGetLastError());
-        hipLaunchKernelGGL(k_db_reduce, dim3(1), dim3(64), 0, n->stream, n->db_partial, dbb, n->cout[l], n->grads + n->b_off[l]);
+        hipLaunchKernelGGL(k_sum_rows, dim3(n->cout[l]), dim3(256), 0, n->stream, n->db_partial, dbb, 64, n->cout[l],
+                           n->grads + n->b_off[l]);
         NHIP(n, hipGetLastError());
-        if (l == 0) break;
-        // gradient of the layer input, times the ReLU derivative of that input (act[l] > 0)
-        int rc = launch_conv(n, dz, n->cout[l], n->Wb[l], nullptr, n->cin[l], 1, 0, n->act[l], 0, dn, nullptr, nullptr);
+        // gradient of the layer input times the ReLU derivative of that input (act[l] > 0)
+        OutArgs o{};
+        o.mask = n->act[l];
+        o.Y = dn;
+        int rc = launch_conv(n, dz, n->cout[l], n->Wb[l], n->cin[l], 2, o);
         if (rc) return rc;
         std::swap(dz, dn);
     }
+    // layer 0 on the vector ALU, per tile: its 27 x C weights and C biases are contiguous in the vector
+    if (n->C == 64)
+        hipLaunchKernelGGL(k_first_dw<64>, dim3(n->ntiles), dim3(kThreads), 0, n->stream, n->resid, dz, n->H, n->W,
+                           n->first_partial);
+    else
+        hipLaunchKernelGGL(k_first_dw<32>, dim3(n->ntiles), dim3(kThreads), 0, n->stream, n->resid, dz, n->H, n->W,
+                           n->first_partial);
+    NHIP(n, hipGetLastError());
+    hipLaunchKernelGGL(k_sum_rows, dim3(28 * n->C), dim3(256), 0, n->stream, n->first_partial, n->ntiles, 28 * n->C, 28 * n->C,
+                       n->grads + n->w_off[0]);
+    NHIP(n, hipGetLastError());
     if (loss) {
         std::vector<float> part(n->loss_blocks);
         NHIP(n, hipMemcpyAsync(part.data(), n->loss_partial, part.size() * sizeof(float), hipMemcpyDeviceToHost, n->stream));
@@ -648,6 +1041,7 @@ int lbcm_net_destroy(lbcm_net *n)
     f(n->out);
     f(n->dw_partial);
     f(n->db_partial);
+    f(n->first_partial);
     f(n->loss_partial);
     delete n;
     return LBCM_OK;
@@ -706,7 +1100,9 @@ int phi_error(lbcm_hybrid *h, const double *x, const double *ref, double *out)
         d2 += part[2 * i];
         r2 += part[2 * i + 1];
     }
-    *out = r2 > 0 ? std::sqrt(d2 / r2) : (d2 > 0 ? INFINITY : 0.0);
+    // a non-finite state on either side counts as an infinite error (rejected)
+    if (!std::isfinite(d2) || !std::isfinite(r2)) *out = INFINITY;
+    else *out = r2 > 0 ? std::sqrt(d2 / r2) : (d2 > 0 ? INFINITY : 0.0);
     return LBCM_OK;
 }
 

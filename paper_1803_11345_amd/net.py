@@ -34,6 +34,7 @@ def load():
     lib.lbcm_net_create.argtypes = [I32, I32, I32, I32, I32, _V, ctypes.POINTER(_H)]
     lib.lbcm_net_param_count.argtypes = [_H]
     lib.lbcm_net_param_count.restype = ctypes.c_size_t
+    lib.lbcm_net_set_output_scale.argtypes = [_H, _F]
     lib.lbcm_net_set_params.argtypes = [_H, _F, ctypes.c_size_t]
     lib.lbcm_net_get_params.argtypes = [_H, _F, ctypes.c_size_t]
     lib.lbcm_net_get_grads.argtypes = [_H, _F, ctypes.c_size_t]
@@ -95,6 +96,13 @@ def lbcm_net_create(batch, height, width, channels, layers, stream):
 
 def lbcm_net_param_count(n) -> int:
     return load().lbcm_net_param_count(n)
+
+
+def lbcm_net_set_output_scale(n, alpha):
+    a = np.ascontiguousarray(alpha, dtype=np.float32)
+    if a.shape != (3,):
+        raise ValueError("expected 3 output scales")
+    _nchk(n, load().lbcm_net_set_output_scale(n, a.ctypes.data_as(_F)))
 
 
 def lbcm_net_set_params(n, params):
@@ -215,10 +223,15 @@ class Surrogate:
         self.h = lbcm_net_create(batch, height, width, channels, layers, self.stream.cuda_stream)
         self.nparams = lbcm_net_param_count(self.h)
         self.t = 0
+        self.alpha = (1.0, 1.0, 1.0)
 
     def set_params(self, p):
         lbcm_net_set_params(self.h, p)
         self.t = 0
+
+    def set_output_scale(self, alpha):
+        lbcm_net_set_output_scale(self.h, alpha)
+        self.alpha = tuple(float(a) for a in alpha)
 
     def params(self):
         return lbcm_net_get_params(self.h)

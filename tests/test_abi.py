@@ -104,8 +104,8 @@ def test_bad_network_shapes_rejected_on_host():
 
     lib = net.load()
     h = ctypes.c_void_p()
-    assert lib.lbcm_net_create(1, 5, 5, 64, 6, None, ctypes.byref(h)) == lbcm.LBCM_EINVAL  # 25 pixels
-    assert b"multiple of 32" in lib.lbcm_net_last_error(None)
+    assert lib.lbcm_net_create(1 << 10, 256, 512, 64, 6, None, ctypes.byref(h)) == lbcm.LBCM_EINVAL  # 2^27 pixels
+    assert b"2^26" in lib.lbcm_net_last_error(None)
     assert lib.lbcm_net_create(1, 8, 8, 48, 6, None, ctypes.byref(h)) == lbcm.LBCM_EINVAL
     assert lib.lbcm_net_create(1, 8, 8, 64, 1, None, ctypes.byref(h)) == lbcm.LBCM_EINVAL
     assert lib.lbcm_net_create(0, 8, 8, 64, 6, None, ctypes.byref(h)) == lbcm.LBCM_EINVAL

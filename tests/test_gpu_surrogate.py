@@ -11,18 +11,19 @@ from paper_1803_11345_amd import inputs, lbcm, net
 
 pytestmark = pytest.mark.gpu
 
-# Tolerances.  Both sides round the same operands to bfloat16 and differ only by the FP32
-# accumulation order of the kernels and by the activations whose FP32 and FP64 values fall on
-# opposite sides of a bfloat16 rounding boundary (those then differ by one bfloat16 ulp, 2^-8
-# relative).  Shallow networks (L <= 4) see almost no such flips: the two agree to ~1e-7, and
-# 1e-5 is the bar.  In the 6-layer, 64-channel network a flip in an early layer moves later
-# sums by more than the FP32 noise and so causes further flips; the measured difference is
-# 2e-4 .. 6e-4 (output) and up to 2e-3 (first-layer weight gradient).  A hard bound is the sum of
-# both sides' rounding errors, L * 2^-8 ~ 2.3e-2 for L = 6 at unit layer gain; the deep bar is set
-# below it, at about 5x the measured values.  A wrong tap, channel or layout gives O(1).
+# Tolerances on random data.  Both sides round the same operands to bfloat16; they differ by
+# FP32 versus FP64 rounding of the sums (relative ~1e-7 .. 1e-6) and by the activations whose two
+# values fall on opposite sides of a bfloat16 rounding boundary: those differ by one bfloat16 ulp
+# (2^-8 relative).  A relative perturbation d of a layer's sums flips a fraction ~d / 2^-8 of its
+# activations, which perturbs the layer output by ~2^-8 sqrt(d / 2^-8); iterating from d ~ 1e-6
+# gives ~6e-5 after one rounded layer, ~5e-4 after two, ~1.4e-3 after three, tending to 2^-8.
+# With two layers (one rounded activation) the bar is 1e-4; deeper networks get 1e-2 for the
+# output and 4e-2 for the gradients, whose dZ roundings add a second cascade (bound ~2 L 2^-8;
+# measured up to 1.2e-2 for the first layer of six).  A wrong tap, channel or layout gives O(1).
+# Exactness itself is pinned by the integer-data tests below.
 def tolerances(L):
-    """(output rel L2, gradient rel L2, loss rel) for a network of L layers."""
-    return (1e-5, 1e-5, 1e-6) if L <= 4 else (3e-3, 1e-2, 1e-4)
+    """(output rel L2, gradient rel L2, loss rel) for a network of L layers on random data."""
+    return (1e-4, 1e-4, 1e-6) if L <= 2 else (1e-2, 4e-2, 1e-4)
 
 
 def _note(msg):
@@ -51,14 +52,20 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-SHAPES = [  # B, H, W, C, L: several waves, waves straddling rows and samples, both widths
+SHAPES = [  # B, H, W, C, L: full and partial 8 x 32 tiles, several tiles and samples, both widths
     (2, 16, 24, 64, 6),
     (1, 12, 8, 32, 3),
     (2, 3, 16, 64, 2),
     (3, 5, 32, 32, 4),
     (1, 33, 32, 64, 6),
     (1, 8, 16, 64, 3),
+    (2, 17, 70, 64, 3),
+    (1, 1, 32, 32, 2),
+    (1, 2, 48, 64, 4),
 ]
+
+
+ALPHA = (0.25, 2.0, 0.5)
 
 
 @pytest.mark.parametrize("B,H,W,C,L", SHAPES)
@@ -70,13 +77,117 @@ def test_forward_matches_oracle(B, H, W, C, L):
     s = _state(B, H, W, seed=7 + H)
     m = net.Surrogate(B, H, W, channels=C, layers=L)
     m.set_params(p)
+    m.set_output_scale(ALPHA)
     out = torch.empty(B, H, W, 3, dtype=torch.float32, device="cuda")
     m.forward(torch.from_numpy(s).cuda(), out)
     got = out.cpu().numpy().astype(np.float64)
-    ref, _ = cn.forward(p.astype(np.float64), s.astype(np.float64), C, L, emulate_bf16=True)
+    ref, _ = cn.forward(p.astype(np.float64), s.astype(np.float64), C, L, emulate_bf16=True, alpha=ALPHA)
     r = _rel(got - s, ref - s)
     _note(f"  residual rel L2 {r:.3e}")
     assert r < tolerances(L)[0]
+    m.close()
+
+
+def _integer_case(B, H, W, C, L, seed):
+    """Integer state in [-2, 2], integer biases in [-1, 1], layer-0 weights in {-1, 0, 1} and later
+    weights in {-1, 0, 1} with 1 in 64 nonzero."""
+    u = inputs.uniform(seed, B * H * W * 3).reshape(B, H, W, 3)
+    s = np.floor(5 * u) - 2
+    parts = []
+    for l, (ci, co, nb) in enumerate(cn.layer_shapes(C, L)):
+        w = inputs.uniform(seed * 100 + 2 * l, 9 * ci * co)
+        if l == 0:
+            w = np.floor(3 * w) - 1
+        else:
+            w = np.where(w < 1 / 128, -1.0, np.where(w > 1 - 1 / 128, 1.0, 0.0))
+        b = np.zeros(nb)
+        b[:co] = np.floor(3 * inputs.uniform(seed * 100 + 2 * l + 1, co)) - 1
+        parts += [w, b]
+    return np.concatenate(parts), s
+
+
+def _exactness_bound(p, s, C, L):
+    """Largest sum of |products| + |bias| over all outputs of all layers (integers): below 2^24
+    every partial sum is an exactly representable integer, in any order."""
+    worst, a = 0.0, s
+    for l, (Wl, bl) in enumerate(cn.unpack(p, C, L)):
+        worst = max(worst, cn.conv(np.abs(a), np.abs(Wl if l == 0 else cn.bf16(Wl)), np.abs(bl)).max())
+        z = cn.conv(a, Wl, bl)
+        a = cn.bf16(np.maximum(z, 0.0))
+    return worst
+
+
+@pytest.mark.parametrize("B,H,W,C,L", SHAPES)
+def test_forward_bit_exact_on_integer_data(B, H, W, C, L):
+    """On integer data both sides compute every sum exactly and round the same exact values to
+    bfloat16, so the outputs agree bit for bit."""
+    import torch
+
+    _note(f"integer forward B={B} H={H} W={W} C={C} L={L}")
+    p, s = _integer_case(B, H, W, C, L, seed=B + 3 * H + W + L)
+    assert _exactness_bound(p, s, C, L) < 2 ** 24
+    m = net.Surrogate(B, H, W, channels=C, layers=L)
+    m.set_params(p.astype(np.float32))
+    m.set_output_scale(ALPHA)
+    out = torch.empty(B, H, W, 3, dtype=torch.float32, device="cuda")
+    m.forward(torch.from_numpy(s.astype(np.float32)).cuda(), out)
+    ref, _ = cn.forward(p, s, C, L, emulate_bf16=True, alpha=ALPHA)
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.abs(ref - s).max() > 0
+    assert np.array_equal(got, ref), np.abs(got - ref).max()
+    m.close()
+
+
+def _backward_exactness(p, s, target, C, L):
+    """On integer data: the number of output-gradient values within 1e-6 (relative) of a bfloat16
+    rounding midpoint (where FP32 and FP64 could round apart), and the largest ratio of
+    sum |g| |W| to the grain of g over the input-gradient sums (below 2^24 they are exact)."""
+    out, cache = cn.forward(p, s, C, L, emulate_bf16=True, alpha=ALPHA)
+    v = 2.0 * (out - target) / np.asarray(ALPHA) / out.size
+    ambiguous = int(np.sum(cn.bf16(v * (1 - 1e-6)) != cn.bf16(v * (1 + 1e-6))))
+    g, worst = cn.bf16(v), 0.0
+    for l in range(L - 1, 0, -1):
+        W = cache["layers"][l][0]
+        nz = np.abs(g[g != 0])
+        if nz.size == 0:
+            break
+        grain = 2.0 ** (np.floor(np.log2(nz.min())) - 7)
+        S = sum(cn.shifted(np.abs(g), -dy, -dx) @ np.abs(W[t]).T for t, (dy, dx) in enumerate(cn.taps()))
+        worst = max(worst, S.max() / grain)
+        da = sum(cn.shifted(g, -dy, -dx) @ W[t].T for t, (dy, dx) in enumerate(cn.taps()))
+        g = cn.bf16(da * (cache["acts"][l] > 0))
+    return ambiguous, worst
+
+
+@pytest.mark.parametrize("B,H,W,C,L", SHAPES)
+def test_backward_on_integer_data(B, H, W, C, L):
+    """Integer data (see above) and an integer target: both sides hold the same bfloat16 output
+    gradient and compute the input gradients exactly, so the weight and bias gradients differ
+    only by FP32 accumulation."""
+    import torch
+
+    _note(f"integer backward B={B} H={H} W={W} C={C} L={L}")
+    p, s = _integer_case(B, H, W, C, L, seed=B + 3 * H + W + L)
+    tgt = s + np.floor(3 * inputs.uniform(99 + W, s.size)).reshape(s.shape) - 1
+    amb, worst = _backward_exactness(p, s, tgt, C, L)
+    assert amb == 0 and worst < 2 ** 24, (amb, worst)
+    m = net.Surrogate(B, H, W, channels=C, layers=L)
+    m.set_params(p.astype(np.float32))
+    m.set_output_scale(ALPHA)
+    m.forward(torch.from_numpy(s.astype(np.float32)).cuda())
+    loss = m.backward(torch.from_numpy(tgt.astype(np.float32)).cuda())
+    g = m.grads().astype(np.float64)
+    _, cache = cn.forward(p, s, C, L, emulate_bf16=True, alpha=ALPHA)
+    gref, lref = cn.backward(cache, tgt, C, L)
+    assert abs(loss - lref) <= 1e-6 * lref
+    o = 0
+    for l, (ci, co, nb) in enumerate(cn.layer_shapes(C, L)):
+        nw = 9 * ci * co
+        rw = _rel(g[o:o + nw], gref[o:o + nw])
+        rb = _rel(g[o + nw:o + nw + co], gref[o + nw:o + nw + co])
+        _note(f"  layer {l}: dW rel L2 {rw:.3e}, db rel L2 {rb:.3e}")
+        assert rw < 1e-5 and rb < 1e-5, l
+        o += nw + nb
     m.close()
 
 
@@ -90,10 +201,11 @@ def test_backward_matches_oracle(B, H, W, C, L):
     tgt = (s + _state(B, H, W, seed=27 + W, amp=0.3)).astype(np.float32)
     m = net.Surrogate(B, H, W, channels=C, layers=L)
     m.set_params(p)
+    m.set_output_scale(ALPHA)
     m.forward(torch.from_numpy(s).cuda())
     loss = m.backward(torch.from_numpy(tgt).cuda())
     g = m.grads().astype(np.float64)
-    out, cache = cn.forward(p.astype(np.float64), s.astype(np.float64), C, L, emulate_bf16=True)
+    out, cache = cn.forward(p.astype(np.float64), s.astype(np.float64), C, L, emulate_bf16=True, alpha=ALPHA)
     gref, lref = cn.backward(cache, tgt.astype(np.float64), C, L)
     _, gtol, ltol = tolerances(L)
     assert abs(loss - lref) <= ltol * lref
@@ -128,6 +240,38 @@ def test_full_size_forward_matches_oracle():
     _note(f"  residual rel L2 {r:.3e}")
     assert r < tolerances(L)[0]
     m.close()
+
+
+def test_training_steps_follow_the_oracle():
+    """Five Adam iterations (forward, backward, update) of the kernels against the same
+    iterations of the oracle, each started from the device parameters."""
+    import torch
+
+    _note("training parity")
+    B, H, W, C, L = 2, 8, 32, 32, 3
+    p = _params(C, L, seed=61, last_scale=0.2)
+    m = net.Surrogate(B, H, W, channels=C, layers=L)
+    m.set_params(p)
+    m.set_output_scale(ALPHA)
+    mm, vv = np.zeros(p.size), np.zeros(p.size)
+    losses = []
+    for t in range(1, 6):
+        s = _state(B, H, W, seed=70 + t)
+        tgt = (s + _state(B, H, W, seed=80 + t, amp=0.2) * np.array(ALPHA)).astype(np.float32)
+        pr = m.params().astype(np.float64)
+        m.forward(torch.from_numpy(s).cuda())
+        loss = m.backward(torch.from_numpy(tgt).cuda())
+        m.adam(3e-3, 0.9, 0.999, 1e-8)
+        _, cache = cn.forward(pr, s.astype(np.float64), C, L, emulate_bf16=True, alpha=ALPHA)
+        g, lref = cn.backward(cache, tgt.astype(np.float64), C, L)
+        assert abs(loss - lref) <= 1e-6 * lref
+        pref, mm, vv = cn.adam(pr, g, mm, vv, t, 3e-3, 0.9, 0.999, 1e-8)
+        got = m.params().astype(np.float64)
+        # Adam moves each parameter by about lr; compare the step taken
+        step_rel = np.linalg.norm((got - pr) - (pref - pr)) / np.linalg.norm(pref - pr)
+        _note(f"  iter {t}: loss {loss:.5e} step rel L2 {step_rel:.2e}")
+        assert step_rel < 1e-4
+        losses.append(loss)
 
 
 def test_adam_matches_oracle():

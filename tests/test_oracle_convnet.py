@@ -85,14 +85,15 @@ def test_forward_commutes_with_circular_shifts():
     assert np.allclose(out2, np.roll(out, (2, -3), axis=(1, 2)), rtol=0, atol=1e-13)
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("alpha", [(1.0, 1.0, 1.0), (0.01, 0.3, 2.0)])
+def test_gradient_matches_central_differences(alpha):
     C, L = 4, 3
     p = _params(61, C, L)
     s = _rand(62, (2, 5, 6, 3))
-    target = s + _rand(63, s.shape, -0.2, 0.2)
-    out, cache = cn.forward(p, s, C, L)
+    target = s + _rand(63, s.shape, -0.2, 0.2) * np.asarray(alpha)
+    out, cache = cn.forward(p, s, C, L, alpha=alpha)
     g, l0 = cn.backward(cache, target, C, L)
-    assert abs(l0 - cn.loss(out, target)) < 1e-15
+    assert abs(l0 - cn.loss(out, target, alpha)) < 1e-15
     # 40 random entries, plus every real bias entry and the first weight of every layer
     idx = list((inputs.splitmix64(64, 40) % np.uint64(p.size)).astype(np.int64))
     o = 0
@@ -104,7 +105,8 @@ def test_gradient_matches_central_differences():
         pp, pm = p.copy(), p.copy()
         pp[i] += h
         pm[i] -= h
-        fd = (cn.loss(cn.forward(pp, s, C, L)[0], target) - cn.loss(cn.forward(pm, s, C, L)[0], target)) / (2 * h)
+        fd = (cn.loss(cn.forward(pp, s, C, L, alpha=alpha)[0], target, alpha)
+              - cn.loss(cn.forward(pm, s, C, L, alpha=alpha)[0], target, alpha)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])) + 1e-10, (i, fd, g[i])
     # bias padding entries of the last layer have zero gradient
     assert np.all(g[-(cn.LAST_BIAS_PAD - 3):] == 0)
@@ -121,6 +123,15 @@ def test_gradient_of_every_layer_is_exercised():
     for ci, co, nb in cn.layer_shapes(C, L):
         assert np.abs(g[o:o + 9 * ci * co]).max() > 0
         o += 9 * ci * co + nb
+
+
+def test_output_scale_multiplies_the_residual():
+    C, L = 5, 3
+    p = _params(75, C, L)
+    s = _rand(76, (1, 6, 7, 3))
+    a, _ = cn.forward(p, s, C, L)
+    b, _ = cn.forward(p, s, C, L, alpha=(2.0, -1.0, 0.5))
+    assert np.allclose(b - s, (a - s) * np.array([2.0, -1.0, 0.5]), rtol=0, atol=1e-14)
 
 
 def test_emulated_bf16_forward_stays_close_to_fp64():
