@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--ens-boxes", type=int, default=512, help="boxes of the ensemble leg (0 = skip it)")
     ap.add_argument("--ens-steps", type=int, default=5000, help="batched steps of the ensemble leg")
     ap.add_argument("--ens-looped-steps", type=int, default=40, help="looped steps timed for comparison")
+    ap.add_argument("--sur-iters", type=int, default=2000, help="training iterations of the surrogate leg (0 = skip it)")
+    ap.add_argument("--sur-windows", type=int, default=40, help="hybrid windows (8 jumps of 16 steps) timed per case")
     return ap.parse_args()
 
 
@@ -193,6 +195,59 @@ def ensemble_report(lbcm, args) -> dict:
             "nonfinite_nodes": int(nonfinite)}
 
 
+def surrogate_report(lbcm, args) -> dict:
+    """Learned surrogate on 256 x 256 periodic boxes: record LB trajectories (spinodal
+    decomposition and two-droplet coalescence), train the 6-layer 64-channel network on the GPU
+    with the library's kernels, then compare one jump with persistence on held-out runs and time
+    the hybrid (surrogate jumps of K = 16 steps, a lattice check of the last of every 8 jumps,
+    fallback above a phi error of 1e-2) against the plain FP32 step on the same box."""
+    import numpy as np
+    import torch
+
+    from paper_1803_11345_amd import inputs
+    from paper_1803_11345_amd import train as T
+
+    n, K = 256, 16
+    cases = inputs.coalescence_cases(12, seed=11)
+    model, info = T.fit(n, K, T.dataset_runs(n, (101, 102, 103, 104), cases[:8]), 400, iters=args.sur_iters)
+    m1 = T.single_box(model)
+    model.close()
+    us, rs = info["u_scale"], info["rho_scale"]
+    # one jump against persistence on held-out runs
+    frames, pairs = T.build_dataset(n, K, T.dataset_runs(n, (105,), cases[8:9]), 400)
+    gains = {}
+    for name, sl in (("spinodal", slice(10, 399)), ("coalescence", slice(409, 798))):
+        e = T.jump_errors(m1, frames, pairs[sl], us, rs)
+        gains[name] = {k: {"mean": float(v.mean()), "max": float(v.max())} for k, v in e.items()}
+    # time of one jump (FP64 planes in and out, as the hybrid runs it)
+    outs = [torch.empty(n, n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    ins = [frames[c, 0] for c in range(4)]
+    for _ in range(5):
+        m1.forward_planes(*ins, us, rs, *outs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(100):
+        m1.forward_planes(*ins, us, rs, *outs)
+    e1.record()
+    torch.cuda.synchronize()
+    jump_us = e0.elapsed_time(e1) * 1e3 / 100
+    del frames, ins
+    torch.cuda.empty_cache()
+    # padded MFMA work of one jump: layers 1..L-2 are 64 -> 64, the last 64 -> 32 (4 real)
+    flops = 2 * n * n * 9 * 64 * (4 * 64 + 32)
+    hybrid = {}
+    for name, phi0 in (("spinodal", T.spinodal_phi(n, 106)), ("coalescence", T.coalescence_phi(n, cases[9]))):
+        hybrid[name] = T.hybrid_vs_lb(m1, phi0, us, rs, args.sur_windows)
+    m1.close()
+    return {"box": f"{n}x{n} periodic", "network": "3x3 conv x6, 64 channels, first layer FP32 VALU, "
+            "others BF16 MFMA with FP32 accumulation", "steps_per_jump": K, "jumps_per_check": 8,
+            "threshold_phi_rel_l2": 1e-2, "threshold_velocity_rel_l2": 0.25, "train": info, "one_jump_rel_l2": gains,
+            "jump_us": round(jump_us, 2), "jump_mfma_tflops": round(flops / jump_us / 1e6, 1),
+            "hybrid": hybrid,
+            "speedup_vs_lb": round(float(np.mean([h["speedup"] for h in hybrid.values()])), 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -248,6 +303,8 @@ def main():
         out["reduced_precision"] = precision_report(lbcm, phi0, n, args, sec_per_step)
     if args.ens_boxes > 0 and args.precision == "fp32":
         out["ensemble"] = ensemble_report(lbcm, args)
+    if args.sur_iters > 0 and args.precision == "fp32":
+        out["surrogate"] = surrogate_report(lbcm, args)
     if args.copy_probe:
         out["copy_probe_gbs"] = round(copy_probe(), 1)
     if args.cpu_steps > 0:

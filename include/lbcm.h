@@ -152,6 +152,16 @@ const char *lbcm_last_error(const lbcm_handle *h);
    handle.  Needs lbcm_init first.  Synchronises. */
 int lbcm_autotune(lbcm_handle *h, int trials);
 
+/* Device-to-device copy of src's populations into dst (same nx, ny and precision; other physics
+   may differ); dst's step counter becomes `step` and its divergence flag is cleared.  Queued on
+   dst's stream (after synchronising src's stream if they differ).  Errors: LBCM_EINVAL,
+   LBCM_ESTATE (src before lbcm_init), LBCM_EHIP. */
+int lbcm_copy_state(lbcm_handle *dst, const lbcm_handle *src, int64_t step);
+
+/* Steps taken since lbcm_init (or the step given to lbcm_set_state / lbcm_copy_state); -1 for
+   a NULL handle. */
+int64_t lbcm_step_count(const lbcm_handle *h);
+
 /* Copy of the parameters the handle was created with into *out (stream: the handle's stream;
    workspace: as given at creation, NULL when the library allocated it). */
 int lbcm_info(const lbcm_handle *h, lbcm_params *out);

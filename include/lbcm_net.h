@@ -1,21 +1,23 @@
 /*
  * lbcm_net — learned surrogate for the lattice Boltzmann step of lbcm.h: a stack of 3x3
- * convolutions with circular padding that maps the macroscopic state (phi, v_x, v_y) of periodic
- * boxes to the state K lattice steps later, as state + alpha * network(state) with a fixed
- * per-channel output scale alpha.  The first layer runs in FP32 on the vector ALU; the others
+ * convolutions with circular padding that maps the macroscopic state (phi, v_x, v_y, rho) of
+ * periodic boxes to the state K lattice steps later, as state + alpha * network(state) with a
+ * fixed per-channel output scale alpha.  The density carries the pressure field, without which
+ * the velocity K steps on is not determined by the state.  The first layer runs in FP32 on the vector ALU; the others
  * run on the MFMA units (BF16 activations and weights, FP32 accumulation); master parameters,
  * gradients and the Adam moments are FP32.  This is not part of the paper's method: it is
  * trained on trajectories of the method and checked against it (see lbcm_step).
  *
  * Conventions
  *   - A network is created for a fixed batch of B samples of H x W pixels (B * H * W <= 2^26).
- *     Layer 0 maps 3 -> C channels, layers 1..L-2 map C -> C (ReLU after every
- *     layer but the last), layer L-1 maps C -> 3; C is 32 or 64.
- *   - State tensors on the device are FP32 [B][H][W][3] (phi, v_x / u_scale, v_y / u_scale).
+ *     Layer 0 maps 4 -> C channels, layers 1..L-2 map C -> C (ReLU after every
+ *     layer but the last), layer L-1 maps C -> 4; C is 32 or 64.
+ *   - State tensors on the device are FP32 [B][H][W][4]: (phi, v_x / u_scale, v_y / u_scale,
+ *     (rho - 1) / rho_scale).
  *   - The parameter vector (FP32, lbcm_net_param_count entries) holds, layer after layer, the
  *     weights W[t][ci][co] (t = 3 (dy + 1) + (dx + 1) is the tap reading the input at (y + dy,
  *     x + dx); ci, co the real channel counts) and then the biases b[co'], where co' runs over the
- *     padded output channels (C, or 32 for the last layer; the entries past 3 must be 0).
+ *     padded output channels (C, or 32 for the last layer; the entries past 4 must be 0).
  *   - Return codes and ownership as in lbcm.h (LBCM_OK, LBCM_EINVAL, LBCM_ENOMEM, LBCM_EHIP).
  *     Work is queued on the stream given at creation; calls that return host data synchronise.
  */
@@ -39,7 +41,7 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
 
 size_t lbcm_net_param_count(const lbcm_net *n);
 
-/* Output scale alpha[0..2] (host, each finite and > 0; default 1): out = state + alpha * z and
+/* Output scale alpha[0..3] (host, each finite and > 0; default 1): out = state + alpha * z and
    the loss is mean(((out - target) / alpha)^2).  Takes effect at the next call. */
 int lbcm_net_set_output_scale(lbcm_net *n, const float *alpha);
 
@@ -47,20 +49,21 @@ int lbcm_net_set_output_scale(lbcm_net *n, const float *alpha);
 int lbcm_net_set_params(lbcm_net *n, const float *host, size_t count);
 int lbcm_net_get_params(lbcm_net *n, float *host, size_t count);
 
-/* Forward pass on a device state [B][H][W][3]; out (device, same shape, may be NULL) receives
+/* Forward pass on a device state [B][H][W][4]; out (device, same shape, may be NULL) receives
    state + alpha * network(state).  The activations are kept for lbcm_net_backward. */
 int lbcm_net_forward(lbcm_net *n, const float *in, float *out);
 
-/* Forward pass from device FP64 planes [B][H][W] of phi, v_x, v_y (v divided by u_scale on the
-   way in and multiplied back on the way out) into device FP64 planes. */
-int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, double u_scale,
-                            double *phi_out, double *ux_out, double *uy_out);
+/* Forward pass from device FP64 planes [B][H][W] of phi, v_x, v_y, rho (scaled on the way in as
+   in the state tensor, and back on the way out) into device FP64 planes. */
+int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, const double *rho,
+                            double u_scale, double rho_scale, double *phi_out, double *ux_out, double *uy_out,
+                            double *rho_out);
 
-/* Device FP64 planes -> a device state tensor [B][H][W][3] (v divided by u_scale). */
-int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, double u_scale,
-                               float *state);
+/* Device FP64 planes -> a device state tensor [B][H][W][4]. */
+int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, const double *rho,
+                               double u_scale, double rho_scale, float *state);
 
-/* Gradient of the loss mean(((out - target) / alpha)^2) over pixels and the 3 channels, after a
+/* Gradient of the loss mean(((out - target) / alpha)^2) over pixels and the 4 channels, after a
    forward pass, into the internal FP32 gradient vector (same layout as the parameters).  *loss
    (host, may be NULL) receives the loss (then the call synchronises). */
 int lbcm_net_backward(lbcm_net *n, const float *target, float *loss);
@@ -75,14 +78,17 @@ int lbcm_net_destroy(lbcm_net *n);
 const char *lbcm_net_last_error(const lbcm_net *n);
 
 /* ---- hybrid driver ------------------------------------------------------------------------
-   Advances a periodic lattice in windows of J * K lattice steps.  A window reads (phi, v) of the
-   lattice, makes J - 1 surrogate jumps of K steps, and does the J-th jump both ways: with the
-   surrogate and with K lattice Boltzmann steps from equilibrium populations of the same state
-   (density 1).  The check error is ||phi_net - phi_LB|| / ||phi_LB|| (L2 over the box).  At or
-   below the threshold the window ends in the lattice Boltzmann result.  Above it the window is
-   redone with J * K lattice Boltzmann steps from equilibrium populations of its starting fields,
-   and the next window runs the plain step too.  The lattice and the network must share a stream;
-   the network is built for one box (batch 1) of the lattice's size. */
+   Advances a periodic lattice in windows of J * K lattice steps.  A window reads (phi, v, rho)
+   of the lattice, makes J - 1 surrogate jumps of K steps, and does the J-th jump both ways: with
+   the surrogate, and with K lattice Boltzmann steps on a private scratch lattice from
+   equilibrium populations of the same state.  The check error is ||phi_net - phi_LB|| /
+   ||phi_LB|| (L2 over the box), the velocity error ||v_net - v_LB|| / ||v_LB||.  When the first
+   is at or below the threshold (and the second at or below the velocity threshold, if that is
+   > 0) the scratch state is copied into the lattice: the window ends in the lattice Boltzmann
+   result.  Otherwise the lattice, which still holds the window's starting populations, runs the
+   window with the plain step, and after k failed checks in a row the next min(2^(k-1), 16)
+   windows too.  The lattice and the network must share a stream; the network is built for one
+   box (batch 1) of the lattice's size. */
 
 typedef struct lbcm_hybrid lbcm_hybrid;
 
@@ -94,14 +100,20 @@ typedef struct lbcm_hybrid_stats {
     int64_t failed_checks; /* checks above the threshold */
     double last_error;     /* error of the last check */
     double max_error;      /* largest check error so far */
+    double last_velocity_error;          /* ||v_net - v_LB|| / ||v_LB|| of the last check */
+    double max_accepted_error;           /* largest check error of an accepted window */
+    double max_accepted_velocity_error;  /* largest velocity error of an accepted window */
 } lbcm_hybrid_stats;
 
 /* lattice: a periodic lattice after lbcm_init; net: the trained network (batch 1, same ny x nx);
-   steps_per_jump K >= 1 (what the network was trained for); jumps_per_check J >= 1; u_scale > 0:
-   velocity scale of the network's state; threshold >= 0: largest accepted check error.  The
-   driver borrows both handles (they must outlive it). */
+   steps_per_jump K >= 1 (what the network was trained for); jumps_per_check J >= 1; u_scale,
+   rho_scale > 0: velocity and density scales of the network's state; threshold >= 0: largest
+   accepted check error; velocity_threshold: largest accepted velocity error (<= 0: not checked).  The
+   driver borrows both handles (they must outlive it) and allocates its scratch lattice and
+   planes. */
 int lbcm_hybrid_create(lbcm_handle *lattice, lbcm_net *net, int32_t steps_per_jump, int32_t jumps_per_check,
-                       double u_scale, double threshold, lbcm_hybrid **out);
+                       double u_scale, double rho_scale, double threshold, double velocity_threshold,
+                       lbcm_hybrid **out);
 
 /* Advance by `windows` windows (each J * K lattice steps; synchronises once per window). */
 int lbcm_hybrid_advance(lbcm_hybrid *h, int64_t windows);

@@ -6,15 +6,16 @@ this module; the product path never imports it.  It shares no code with the HIP 
 The network is not part of the paper's method: it is a learned shortcut over K steps of it,
 trained on trajectories of the method.  Its definition, written out here in plain numpy:
 
-  state s of shape [B, H, W, 3] (phi, v_x / u_scale, v_y / u_scale) on periodic boxes;
+  state s of shape [B, H, W, 4] (phi, v_x / u_scale, v_y / u_scale, (rho - 1) / rho_scale) on
+  periodic boxes;
   tap t = 0..8 reads the input at (y + dy_t, x + dx_t) with dy_t = t // 3 - 1, dx_t = t % 3 - 1,
   indices taken modulo the box (circular padding);
   layer l:  z_l[p] = b_l + sum_t a_l[p + d_t] @ W_l[t]       (W_l[t] of shape [c_in, c_out])
   a_0 = s,  a_{l+1} = max(z_l, 0) for l < L - 1,  out = s + alpha * z_{L-1};
-  loss = mean over pixels and the 3 channels of ((out - target) / alpha)^2,
+  loss = mean over pixels and the 4 channels of ((out - target) / alpha)^2,
 with alpha a fixed per-channel output scale (the typical size of the state's change).
 
-Layer 0 maps 3 -> C channels, the hidden layers C -> C and the last C -> 3.  The flat parameter
+Layer 0 maps 4 -> C channels, the hidden layers C -> C and the last C -> 4.  The flat parameter
 vector holds, layer after layer, W_l[t][ci][co] and then the bias padded to the kernels' output
 width (C for hidden layers, 32 for the last; the padding entries carry no meaning and get zero
 gradient).
@@ -31,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-STATE_C = 3
+STATE_C = 4
 LAST_BIAS_PAD = 32
 
 
@@ -101,7 +102,7 @@ def conv(a: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
     return z
 
 
-def forward(params, state, C: int, L: int, emulate_bf16: bool = False, alpha=(1.0, 1.0, 1.0)):
+def forward(params, state, C: int, L: int, emulate_bf16: bool = False, alpha=(1.0,) * STATE_C):
     """Returns (out, cache); cache holds what ``backward`` needs."""
     rnd = bf16 if emulate_bf16 else (lambda v: v)
     s = np.asarray(state, dtype=np.float64)
@@ -117,7 +118,7 @@ def forward(params, state, C: int, L: int, emulate_bf16: bool = False, alpha=(1.
     return out, {"acts": acts, "layers": layers, "out": out, "emulate": emulate_bf16, "alpha": alpha}
 
 
-def loss(out, target, alpha=(1.0, 1.0, 1.0)) -> float:
+def loss(out, target, alpha=(1.0,) * STATE_C) -> float:
     return float(np.mean(((np.asarray(out) - np.asarray(target)) / np.asarray(alpha, dtype=np.float64)) ** 2))
 
 

@@ -1582,6 +1582,28 @@ int lbcm_set_state(lbcm_handle *h, const void *host, size_t bytes, int64_t step)
     return LBCM_OK;
 }
 
+int lbcm_copy_state(lbcm_handle *dst, const lbcm_handle *src, int64_t step)
+{
+    if (!dst || !src) return fail(dst, LBCM_EINVAL, "NULL argument");
+    if (!src->ready) return fail(dst, LBCM_ESTATE, "lbcm_copy_state from a lattice before lbcm_init");
+    if (step < 0) return fail(dst, LBCM_EINVAL, "step must be >= 0");
+    if (dst->p.nx != src->p.nx || dst->p.ny != src->p.ny || dst->p.precision != src->p.precision ||
+        dst->fset != src->fset || dst->gset != src->gset)
+        return fail(dst, LBCM_EINVAL, "lattices differ in size or precision");
+    if (dst->stream != src->stream) HIP_TRY(dst, hipStreamSynchronize(src->stream));
+    HIP_TRY(dst, hipMemcpyAsync(set_base(dst, dst->cur, 0), set_base(const_cast<lbcm_handle *>(src), src->cur, 0), dst->fset,
+                                hipMemcpyDeviceToDevice, dst->stream));
+    HIP_TRY(dst, hipMemcpyAsync(set_base(dst, dst->cur, 1), set_base(const_cast<lbcm_handle *>(src), src->cur, 1), dst->gset,
+                                hipMemcpyDeviceToDevice, dst->stream));
+    hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(1), 0, dst->stream, dst->flag);
+    HIP_TRY(dst, hipGetLastError());
+    dst->ready = true;
+    dst->step = step;
+    return LBCM_OK;
+}
+
+int64_t lbcm_step_count(const lbcm_handle *h) { return h ? h->step : -1; }
+
 int lbcm_destroy(lbcm_handle *h)
 {
     if (!h) return LBCM_OK;

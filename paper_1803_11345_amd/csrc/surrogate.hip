@@ -1,16 +1,17 @@
 // Learned surrogate of the lattice Boltzmann step: a stack of 3x3 convolutions (circular
 // padding, periodic boxes) that maps the macroscopic state (phi, v_x, v_y) to the state K steps
-// later, trained on trajectories of the LB solver.
+// later, trained on trajectories of the LB solver.  The state also carries the density, which
+// holds the pressure field: without it the velocity K steps on is not determined by the state.
 //
 // Network.  z_l[p] = b_l + sum_t a_l[p + d_t] W_l[t] with tap t = 3 (dy + 1) + (dx + 1) at
 // d_t = (dy, dx); a_0 = state, a_{l+1} = relu(z_l), out = state + alpha * z_{L-1} (alpha: a fixed
 // per-channel output scale).  Loss: mean over pixels and channels of ((out - target) / alpha)^2.
 //
-// Precision and units.  Layer 0 (3 real input channels, 27 products per output) runs on the
+// Precision and units.  Layer 0 (4 real input channels, 36 products per output) runs on the
 // vector ALU in FP32 with FP32 state and weights, so the state enters at full precision.  Layers
 // 1 .. L-1 are implicit GEMMs on the MFMA units (v_mfma_f32_16x16x32_bf16: BF16 activations and
 // weights, FP32 accumulation); their weights are packed to BF16 from the FP32 masters after every
-// update.  Activations are NHWC BF16 [P][C]; the last layer's 3 outputs are padded to 32.
+// update.  Activations are NHWC BF16 [P][C]; the last layer's 4 outputs are padded to 32.
 //
 // Packs.  Wf[t][co][ci] feeds the forward pass (the MFMA B operand takes 8 consecutive K = input
 // channels per lane).  Wb[t][ci][co] = W[8 - t][ci][co] feeds the input gradient: tap t of the
@@ -42,7 +43,8 @@ typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(2 * sizeof(unsigned int)))) unsigned int u32x2;
 
-constexpr int kStateC = 3;        // phi, v_x, v_y
+constexpr int kStateC = 4;        // phi, v_x, v_y, rho (channel order of the state)
+constexpr int kFirstRows = 9 * kStateC + 1;  // layer-0 weight rows (tap, channel) and the bias row
 constexpr int kOutC = 32;         // padded output channels of the last layer (a K step of its input gradient)
 constexpr int kThreads = 256;     // four waves
 constexpr int kTileH = 8;         // conv tile: 8 rows x 32 columns of one sample
@@ -93,7 +95,7 @@ __device__ __forceinline__ TileCoord tile_coord(int tile, int H, int W)
     return {n, (rem / tx) * kTileH, (rem % tx) * kTileW};
 }
 
-// stage the FP32 state patch (tile plus circular halo) of one tile in LDS: sp[(py * 34 + px) * 3 + c]
+// stage the FP32 state patch (tile plus circular halo) of one tile in LDS: sp[(py * 34 + px) * kStateC + c]
 __device__ __forceinline__ void stage_state(const float *__restrict__ s, TileCoord tc, int H, int W, float *sp)
 {
     constexpr int NV = kPatchH * kPatchW * kStateC, NI = (NV + kThreads - 1) / kThreads;
@@ -116,7 +118,7 @@ __device__ __forceinline__ void stage_state(const float *__restrict__ s, TileCoo
 
 // ------------------------------------------------------------------------------------------
 // layer 0 on the vector ALU over 8 x 32 tiles: Y[p][co] = bf16(relu(b[co] + sum_{t, ci}
-// s[p + d_t][ci] W0[t][ci][co])), one tile per workgroup.  The state patch and the 27 x C weights
+// s[p + d_t][ci] W0[t][ci][co])), one tile per workgroup.  The state patch and the 36 x C weights
 // are staged in LDS.  Wave
 // w of the 8 computes output channels [C/8 w, C/8 (w + 1)) and each lane 4 pixels of the tile,
 // so that every weight read (a wave-uniform LDS broadcast) feeds 4 FMAs.
@@ -130,12 +132,13 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
 {
     constexpr int CW = C / 8;  // channels per wave
     __shared__ float sp[kPatchH * kPatchW * kStateC];
-    __shared__ __align__(16) float sw[28 * C];  // rows 0..26: W0[3 t + ci][co]; row 27: bias
+    __shared__ __align__(16) float sw[kFirstRows * C];  // rows kStateC t + ci: W0[t][ci][co]; last row: bias
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c0 = CW * wave;
     const int base = (((lane >> 5) + 1) * kPatchW + (lane & 31) + 1) * kStateC;  // patch index of pixel `lane`
-    for (int k = threadIdx.x; k < 28 * C; k += kFirstThreads) sw[k] = k < 27 * C ? W0[k] : b0[k - 27 * C];
+    for (int k = threadIdx.x; k < kFirstRows * C; k += kFirstThreads)
+        sw[k] = k < (kFirstRows - 1) * C ? W0[k] : b0[k - (kFirstRows - 1) * C];
     const TileCoord tc = tile_coord(blockIdx.x, H, W);
     {
         constexpr int NV = kPatchH * kPatchW * kStateC, NI = (NV + kFirstThreads - 1) / kFirstThreads;
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
     float acc[4][CW];
 #pragma unroll
     for (int j = 0; j < CW; ++j) {
-        const float b = sw[27 * C + c0 + j];
+        const float b = sw[(kFirstRows - 1) * C + c0 + j];
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[k][j] = b;
     }
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
                 x[k] = sp[base + ((2 * k + tap_dy(t)) * kPatchW + tap_dx(t)) * kStateC + ci];
 #pragma unroll
             for (int j = 0; j < CW; ++j) {
-                const float w = sw[(3 * t + ci) * C + c0 + j];
+                const float w = sw[(kStateC * t + ci) * C + c0 + j];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) acc[k][j] = fmaf(x[k], w, acc[k][j]);
             }
@@ -209,15 +212,15 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
     }
 }
 
-// layer 0 gradients, one 8 x 32 tile per workgroup: partial[tile][r][co] for r = 3 t + ci
-// (r < 27: sum_p s[p + d_t][ci] dZ[p][co]) and r = 27 (sum_p dZ[p][co], the bias).  The state
+// layer 0 gradients, one 8 x 32 tile per workgroup: partial[tile][r][co] for r = kStateC t + ci
+// (r < 36: sum_p s[p + d_t][ci] dZ[p][co]) and r = 36 (sum_p dZ[p][co], the bias).  The state
 // patch and the tile's dZ are staged in LDS; thread (g, co) accumulates rows r = g, g + G, ...
 // with G = kThreads / C.
 template <int C>
 __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__ s, const __bf16 *__restrict__ dz, int H,
                                                        int W, float *__restrict__ partial)
 {
-    constexpr int G = kThreads / C, R = (28 + G - 1) / G;
+    constexpr int G = kThreads / C, R = (kFirstRows + G - 1) / G;
     __shared__ float sp[kPatchH * kPatchW * kStateC];
     __shared__ __align__(16) __bf16 sd[kTileH * kTileW * C];
     const TileCoord tc = tile_coord(blockIdx.x, H, W);
@@ -242,10 +245,10 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int r = g + k * G;
-            if (r < 27) {
-                const int t = r / 3;
-                acc[k] = fmaf(sp[((ly + 1 + tap_dy(t)) * kPatchW + lx + 1 + tap_dx(t)) * kStateC + r % 3], d, acc[k]);
-            } else if (r == 27) {
+            if (r < kFirstRows - 1) {
+                const int t = r / kStateC;
+                acc[k] = fmaf(sp[((ly + 1 + tap_dy(t)) * kPatchW + lx + 1 + tap_dx(t)) * kStateC + r % kStateC], d, acc[k]);
+            } else if (r == kFirstRows - 1) {
                 acc[k] += d;
             }
         }
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int r = g + k * G;
-        if (r < 28) partial[((size_t)blockIdx.x * 28 + r) * C + co] = acc[k];
+        if (r < kFirstRows) partial[((size_t)blockIdx.x * kFirstRows + r) * C + co] = acc[k];
     }
 }
 
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(256) void k_sum_rows(const float *__restrict__ part
 //
 // MODE 0: Y = bf16(relu(bias + conv));  MODE 2: Y = bf16(conv * [mask > 0]) (the input gradient
 // times the ReLU derivative of the layer input);  MODE 1: Yf[p][c] = resid[p][c] + alpha_c (bias
-// + conv) for c < 3 (the last layer, FP32).
+// + conv) for c < kStateC (the last layer, FP32).
 
 constexpr int kConvThreads = 512;
 
@@ -302,7 +305,7 @@ struct OutArgs {
     __bf16 *Y;
     const float *resid;
     float *Yf;
-    float alpha0, alpha1, alpha2;
+    float alpha0, alpha1, alpha2, alpha3;
 };
 
 template <int CIN>
@@ -444,10 +447,15 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
             if (yy >= H || xx >= W) continue;
             const size_t p = ((size_t)tc.n * H + yy) * W + xx;
             if (MODE == 1) {
-                if (c0 == 0) {  // channels 0 .. 2 live in the q = 0 lanes of the first channel group
-                    o.Yf[p * kStateC + 0] = o.resid[p * kStateC + 0] + o.alpha0 * (acc[mi][0] + bias[0]);
-                    o.Yf[p * kStateC + 1] = o.resid[p * kStateC + 1] + o.alpha1 * (acc[mi][1] + bias[1]);
-                    o.Yf[p * kStateC + 2] = o.resid[p * kStateC + 2] + o.alpha2 * (acc[mi][2] + bias[2]);
+                if (c0 == 0) {  // the 4 state channels are those of the q = 0 lanes of the first channel group
+                    static_assert(kStateC == 4, "one lane holds the four state channels of a pixel");
+                    const f32x4 rs = *(const f32x4 *)(o.resid + p * kStateC);
+                    f32x4 v;
+                    v[0] = rs[0] + o.alpha0 * (acc[mi][0] + bias[0]);
+                    v[1] = rs[1] + o.alpha1 * (acc[mi][1] + bias[1]);
+                    v[2] = rs[2] + o.alpha2 * (acc[mi][2] + bias[2]);
+                    v[3] = rs[3] + o.alpha3 * (acc[mi][3] + bias[3]);
+                    *(f32x4 *)(o.Yf + p * kStateC) = v;
                 }
             } else {
                 bf16x4 m4 = {};
@@ -562,16 +570,16 @@ __global__ __launch_bounds__(256) void k_db_partial(const __bf16 *__restrict__ d
 }
 
 // ------------------------------------------------------------------------------------------
-// loss: mean over pixels and the three state channels of ((pred - target) / alpha_c)^2; the
-// gradient of the last layer's pre-scale output is 2 (pred - target) / (alpha_c 3 P), stored padded
-// to kOutC channels.
+// loss: mean over pixels and the kStateC state channels of ((pred - target) / alpha_c)^2; the
+// gradient of the last layer's pre-scale output is 2 (pred - target) / (alpha_c kStateC P), stored
+// padded to kOutC channels.
 __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ pred, const float *__restrict__ target, uint32_t P,
-                                              float ia0, float ia1, float ia2, __bf16 *__restrict__ dZ,
+                                              float ia0, float ia1, float ia2, float ia3, __bf16 *__restrict__ dZ,
                                               float *__restrict__ partial)
 {
     __shared__ float red[256];
-    const float scale = 2.0f / (3.0f * (float)P);
-    const float ia[3] = {ia0, ia1, ia2};
+    const float scale = 2.0f / ((float)kStateC * (float)P);
+    const float ia[kStateC] = {ia0, ia1, ia2, ia3};
     float s = 0;
     for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < P; p += gridDim.x * 256u) {
         bf16x8 g[kOutC / 8];
@@ -631,53 +639,62 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
     }
 }
 
-// state planes (FP64, [B][H][W] each) -> FP32 [P][3] with the velocity divided by u_scale, and back
+// state planes (FP64, [B][H][W] each) -> FP32 [P][4] = (phi, v_x / u_scale, v_y / u_scale,
+// (rho - 1) / rho_scale), and back
 __global__ void k_from_planes(const double *__restrict__ phi, const double *__restrict__ ux, const double *__restrict__ uy,
-                              float inv_u, uint32_t P, float *__restrict__ s)
+                              const double *__restrict__ rho, float inv_u, float inv_r, uint32_t P, float *__restrict__ s)
 {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
-        s[(size_t)p * 3 + 0] = (float)phi[p];
-        s[(size_t)p * 3 + 1] = (float)ux[p] * inv_u;
-        s[(size_t)p * 3 + 2] = (float)uy[p] * inv_u;
+        f32x4 v;
+        v[0] = (float)phi[p];
+        v[1] = (float)ux[p] * inv_u;
+        v[2] = (float)uy[p] * inv_u;
+        v[3] = (float)(rho[p] - 1.0) * inv_r;
+        *(f32x4 *)(s + (size_t)p * kStateC) = v;
     }
 }
 
-__global__ void k_to_planes(const float *__restrict__ s, double u_scale, uint32_t P, double *__restrict__ phi,
-                            double *__restrict__ ux, double *__restrict__ uy)
+__global__ void k_to_planes(const float *__restrict__ s, double u_scale, double r_scale, uint32_t P, double *__restrict__ phi,
+                            double *__restrict__ ux, double *__restrict__ uy, double *__restrict__ rho)
 {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
-        phi[p] = s[(size_t)p * 3 + 0];
-        ux[p] = s[(size_t)p * 3 + 1] * u_scale;
-        uy[p] = s[(size_t)p * 3 + 2] * u_scale;
+        const f32x4 v = *(const f32x4 *)(s + (size_t)p * kStateC);
+        phi[p] = v[0];
+        ux[p] = v[1] * u_scale;
+        uy[p] = v[2] * u_scale;
+        rho[p] = 1.0 + v[3] * r_scale;
     }
 }
 
-// partial sums of (a - b)^2 and b^2 over P points, one pair per block (FP64)
-constexpr int kErrBlocks = 256;
+// partial sums, one set per block (FP64), of the check: (phi_a - phi_b)^2, phi_b^2,
+// |v_a - v_b|^2 and |v_b|^2 over P points; a and b hold (phi, v_x, v_y) planes
+constexpr int kErrBlocks = 256, kErrSums = 4;
 __global__ __launch_bounds__(256) void k_err_partial(const double *__restrict__ a, const double *__restrict__ b, uint32_t P,
                                                      double *__restrict__ partial)
 {
-    __shared__ double r0[256], r1[256];
-    double d2 = 0, b2 = 0;
+    __shared__ double red[kErrSums][256];
+    double acc[kErrSums] = {0, 0, 0, 0};
     for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < P; p += gridDim.x * 256u) {
         const double d = a[p] - b[p];
-        d2 += d * d;
-        b2 += b[p] * b[p];
-    }
-    r0[threadIdx.x] = d2;
-    r1[threadIdx.x] = b2;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if ((int)threadIdx.x < k) {
-            r0[threadIdx.x] += r0[threadIdx.x + k];
-            r1[threadIdx.x] += r1[threadIdx.x + k];
+        acc[0] += d * d;
+        acc[1] += b[p] * b[p];
+#pragma unroll
+        for (int c = 1; c < 3; ++c) {
+            const double bv = b[(size_t)c * P + p], dv = a[(size_t)c * P + p] - bv;
+            acc[2] += dv * dv;
+            acc[3] += bv * bv;
         }
+    }
+#pragma unroll
+    for (int k = 0; k < kErrSums; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < kErrSums; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        partial[2 * blockIdx.x] = r0[0];
-        partial[2 * blockIdx.x + 1] = r1[0];
-    }
+    if (threadIdx.x < kErrSums) partial[blockIdx.x * kErrSums + threadIdx.x] = red[threadIdx.x][0];
 }
 
 }  // namespace
@@ -694,12 +711,12 @@ struct lbcm_net {
     std::vector<int> cin_r, cout_r, cin, cout;  // real and padded channel counts per layer
     std::vector<size_t> w_off, b_off;           // offsets of each layer in the parameter vector
     size_t nparams = 0;
-    float alpha[3] = {1.f, 1.f, 1.f};           // output scale per state channel
+    float alpha[kStateC] = {1.f, 1.f, 1.f, 1.f};  // output scale per state channel
     float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     std::vector<__bf16 *> Wf, Wb;               // BF16 packs of layers 1 .. L-1
     std::vector<__bf16 *> act;                  // act[l] = input of layer l >= 1 (relu output of layer l - 1)
     __bf16 *dz_a = nullptr, *dz_b = nullptr;    // gradient ping-pong buffers (P x 64)
-    float *resid = nullptr, *out = nullptr;     // FP32 [P][3]: input state, output state
+    float *resid = nullptr, *out = nullptr;     // FP32 [P][kStateC]: input state, output state
     float *dw_partial = nullptr, *db_partial = nullptr, *loss_partial = nullptr, *first_partial = nullptr;
     int loss_blocks = 0;
     bool packed = false;
@@ -768,7 +785,7 @@ int pack_all(lbcm_net *n)
     return LBCM_OK;
 }
 
-// forward from the FP32 state in n->resid ([P][3]); result in n->out
+// forward from the FP32 state in n->resid ([P][kStateC]); result in n->out
 int forward(lbcm_net *n)
 {
     if (!n->packed) {
@@ -793,6 +810,7 @@ int forward(lbcm_net *n)
         o.alpha0 = n->alpha[0];
         o.alpha1 = n->alpha[1];
         o.alpha2 = n->alpha[2];
+        o.alpha3 = n->alpha[3];
         int rc = launch_conv(n, n->act[l], n->cin[l], n->Wf[l], n->cout[l], last ? 1 : 0, o);
         if (rc) return rc;
     }
@@ -873,7 +891,7 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
     const size_t nchunks = (P + kDwChunk - 1) / kDwChunk;
     if (!dmalloc((void **)&n->dw_partial, nchunks * 9 * 64 * 64 * sizeof(float))) return bail("out of device memory (dW)");
     if (!dmalloc((void **)&n->db_partial, ((P + 1023) / 1024) * 64 * sizeof(float))) return bail("out of device memory (db)");
-    if (!dmalloc((void **)&n->first_partial, ntiles * 28 * channels * sizeof(float)))
+    if (!dmalloc((void **)&n->first_partial, ntiles * kFirstRows * channels * sizeof(float)))
         return bail("out of device memory (first layer)");
     n->loss_blocks = grid_of(P, 256) > 1024 ? 1024 : grid_of(P, 256);
     if (!dmalloc((void **)&n->loss_partial, n->loss_blocks * sizeof(float))) return bail("out of device memory (loss)");
@@ -932,27 +950,28 @@ int lbcm_net_forward(lbcm_net *n, const float *in, float *out)
     return LBCM_OK;
 }
 
-int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, double u_scale,
-                            double *phi_out, double *ux_out, double *uy_out)
+int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, const double *rho, double u_scale,
+                            double rho_scale, double *phi_out, double *ux_out, double *uy_out, double *rho_out)
 {
-    if (!n || !phi || !ux || !uy || !phi_out || !ux_out || !uy_out || !(u_scale > 0)) return LBCM_EINVAL;
-    hipLaunchKernelGGL(k_from_planes, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, phi, ux, uy, (float)(1.0 / u_scale),
-                       n->P, n->resid);
+    if (!n || !phi || !ux || !uy || !rho || !phi_out || !ux_out || !uy_out || !rho_out || !(u_scale > 0) || !(rho_scale > 0))
+        return LBCM_EINVAL;
+    hipLaunchKernelGGL(k_from_planes, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, phi, ux, uy, rho, (float)(1.0 / u_scale),
+                       (float)(1.0 / rho_scale), n->P, n->resid);
     NHIP(n, hipGetLastError());
     int rc = forward(n);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_to_planes, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, n->out, u_scale, n->P, phi_out,
-                       ux_out, uy_out);
+    hipLaunchKernelGGL(k_to_planes, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, n->out, u_scale, rho_scale, n->P, phi_out,
+                       ux_out, uy_out, rho_out);
     NHIP(n, hipGetLastError());
     return LBCM_OK;
 }
 
-int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, double u_scale,
-                               float *state)
+int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, const double *rho,
+                               double u_scale, double rho_scale, float *state)
 {
-    if (!n || !phi || !ux || !uy || !state || !(u_scale > 0)) return LBCM_EINVAL;
-    hipLaunchKernelGGL(k_from_planes, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, phi, ux, uy, (float)(1.0 / u_scale),
-                       n->P, state);
+    if (!n || !phi || !ux || !uy || !rho || !state || !(u_scale > 0) || !(rho_scale > 0)) return LBCM_EINVAL;
+    hipLaunchKernelGGL(k_from_planes, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, phi, ux, uy, rho, (float)(1.0 / u_scale),
+                       (float)(1.0 / rho_scale), n->P, state);
     NHIP(n, hipGetLastError());
     return LBCM_OK;
 }
@@ -963,7 +982,7 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
     const uint32_t P = n->P;
     const int L = n->L;
     hipLaunchKernelGGL(k_loss, dim3(n->loss_blocks), dim3(256), 0, n->stream, n->out, target, P, 1.f / n->alpha[0],
-                       1.f / n->alpha[1], 1.f / n->alpha[2], n->dz_a, n->loss_partial);
+                       1.f / n->alpha[1], 1.f / n->alpha[2], 1.f / n->alpha[3], n->dz_a, n->loss_partial);
     NHIP(n, hipGetLastError());
     __bf16 *dz = n->dz_a, *dn = n->dz_b;
     const int nchunks = (int)((P + kDwChunk - 1) / kDwChunk);
@@ -989,7 +1008,7 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
         if (rc) return rc;
         std::swap(dz, dn);
     }
-    // layer 0 on the vector ALU, per tile: its 27 x C weights and C biases are contiguous in the vector
+    // layer 0 on the vector ALU, per tile: its 36 x C weights and C biases are contiguous in the vector
     if (n->C == 64)
         hipLaunchKernelGGL(k_first_dw<64>, dim3(n->ntiles), dim3(kThreads), 0, n->stream, n->resid, dz, n->H, n->W,
                            n->first_partial);
@@ -997,8 +1016,8 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
         hipLaunchKernelGGL(k_first_dw<32>, dim3(n->ntiles), dim3(kThreads), 0, n->stream, n->resid, dz, n->H, n->W,
                            n->first_partial);
     NHIP(n, hipGetLastError());
-    hipLaunchKernelGGL(k_sum_rows, dim3(28 * n->C), dim3(256), 0, n->stream, n->first_partial, n->ntiles, 28 * n->C, 28 * n->C,
-                       n->grads + n->w_off[0]);
+    hipLaunchKernelGGL(k_sum_rows, dim3(kFirstRows * n->C), dim3(256), 0, n->stream, n->first_partial, n->ntiles,
+                       kFirstRows * n->C, kFirstRows * n->C, n->grads + n->w_off[0]);
     NHIP(n, hipGetLastError());
     if (loss) {
         std::vector<float> part(n->loss_blocks);
@@ -1006,7 +1025,7 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
         NHIP(n, hipStreamSynchronize(n->stream));
         double s = 0;
         for (float v : part) s += v;
-        *loss = (float)(s / (3.0 * P));
+        *loss = (float)(s / ((double)kStateC * P));
     }
     return LBCM_OK;
 }
@@ -1055,14 +1074,17 @@ const char *lbcm_net_last_error(const lbcm_net *n) { return n ? n->err.c_str() :
 // hybrid driver: surrogate jumps checked against the lattice Boltzmann step
 
 struct lbcm_hybrid {
-    lbcm_handle *lat = nullptr;
+    lbcm_handle *lat = nullptr;      // the caller's lattice: holds the state between windows
+    lbcm_handle *scratch = nullptr;  // private lattice of the same size for the checks
     lbcm_net *net = nullptr;
     int K = 0, J = 0;
-    double u_scale = 1, threshold = 0;
+    double u_scale = 1, rho_scale = 1, threshold = 0, vthreshold = 0;
     uint32_t P = 0;
-    double *start = nullptr, *a = nullptr, *b = nullptr, *lbphi = nullptr;  // 3 planes each (lbphi: 1)
+    double *start = nullptr, *a = nullptr, *b = nullptr;  // (phi, v_x, v_y, rho) planes
+    double *lb = nullptr;                                 // the check's lattice Boltzmann (phi, v_x, v_y)
     double *err_partial = nullptr;
-    bool cooldown = false;
+    int64_t cooldown = 0;  // plain windows still to run after failed checks
+    int streak = 0;        // consecutive failed checks
     lbcm_hybrid_stats st{};
     std::string err;
 };
@@ -1077,33 +1099,39 @@ int hfail(lbcm_hybrid *h, int code, const std::string &m)
     return code;
 }
 
-#define HCALL(h, call, what)                                                                   \
-    do {                                                                                       \
-        int rc_ = (call);                                                                      \
-        if (rc_ != LBCM_OK) return hfail(h, rc_, std::string(what) + ": " + lbcm_last_error(h->lat) + lbcm_net_last_error(h->net)); \
+#define HCALL(h, call, what, errfn, obj)                                                      \
+    do {                                                                                      \
+        int rc_ = (call);                                                                     \
+        if (rc_ != LBCM_OK) return hfail(h, rc_, std::string(what) + ": " + errfn(obj));     \
     } while (0)
+#define HLAT(h, call, what) HCALL(h, call, what, lbcm_last_error, h->lat)
+#define HSCR(h, call, what) HCALL(h, call, what, lbcm_last_error, h->scratch)
+#define HNET(h, call, what) HCALL(h, call, what, lbcm_net_last_error, h->net)
 
 double *plane(double *base, uint32_t P, int k) { return base + (size_t)k * P; }
 
-// relative L2 difference of two device planes: ||x - ref|| / ||ref|| (FP64, synchronises)
-int phi_error(lbcm_hybrid *h, const double *x, const double *ref, double *out)
+// the four check sums of k_err_partial, read back (synchronises)
+int check_sums(lbcm_hybrid *h, const double *x, const double *ref, double (&sum)[kErrSums])
 {
     hipStream_t s = h->net->stream;
     hipLaunchKernelGGL(k_err_partial, dim3(kErrBlocks), dim3(256), 0, s, x, ref, h->P, h->err_partial);
     if (hipGetLastError() != hipSuccess) return hfail(h, LBCM_EHIP, "k_err_partial launch failed");
-    double part[2 * kErrBlocks];
+    double part[kErrSums * kErrBlocks];
     if (hipMemcpyAsync(part, h->err_partial, sizeof(part), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return hfail(h, LBCM_EHIP, "reading the error sums failed");
-    double d2 = 0, r2 = 0;
-    for (int i = 0; i < kErrBlocks; ++i) {
-        d2 += part[2 * i];
-        r2 += part[2 * i + 1];
-    }
-    // a non-finite state on either side counts as an infinite error (rejected)
-    if (!std::isfinite(d2) || !std::isfinite(r2)) *out = INFINITY;
-    else *out = r2 > 0 ? std::sqrt(d2 / r2) : (d2 > 0 ? INFINITY : 0.0);
+    for (int k = 0; k < kErrSums; ++k) sum[k] = 0;
+    for (int i = 0; i < kErrBlocks; ++i)
+        for (int k = 0; k < kErrSums; ++k) sum[k] += part[i * kErrSums + k];
     return LBCM_OK;
+}
+
+// relative L2 difference ||x - ref|| / ||ref||; a non-finite state on either side counts as an
+// infinite error (rejected)
+double rel_l2(double d2, double r2)
+{
+    if (!std::isfinite(d2) || !std::isfinite(r2)) return INFINITY;
+    return r2 > 0 ? std::sqrt(d2 / r2) : (d2 > 0 ? INFINITY : 0.0);
 }
 
 // one window of J * K lattice steps
@@ -1111,49 +1139,58 @@ int hybrid_window(lbcm_hybrid *h)
 {
     const uint32_t P = h->P;
     const int64_t span = (int64_t)h->J * h->K;
-    if (h->cooldown) {  // plain lattice Boltzmann window after a failed check
-        HCALL(h, lbcm_step(h->lat, span), "lbcm_step");
+    if (h->cooldown > 0) {  // plain lattice Boltzmann window after failed checks
+        HLAT(h, lbcm_step(h->lat, span), "lbcm_step");
         h->st.lb_steps_run += span;
         h->st.steps += span;
-        h->cooldown = false;
+        h->cooldown -= 1;
         return LBCM_OK;
     }
     double *x = h->a, *y = h->b;
-    HCALL(h, lbcm_fields_device(h->lat, plane(h->start, P, 0), nullptr, plane(h->start, P, 1), plane(h->start, P, 2), nullptr),
-          "lbcm_fields_device");
-    const double *cur = h->start;
+    auto pl = [&](double *base, int k) { return plane(base, P, k); };
+    HLAT(h, lbcm_fields_device(h->lat, pl(h->start, 0), pl(h->start, 3), pl(h->start, 1), pl(h->start, 2), nullptr),
+         "lbcm_fields_device");
+    double *cur = h->start;
+    auto jump = [&](double *in, double *outp) {
+        return lbcm_net_forward_planes(h->net, pl(in, 0), pl(in, 1), pl(in, 2), pl(in, 3), h->u_scale, h->rho_scale, pl(outp, 0),
+                                       pl(outp, 1), pl(outp, 2), pl(outp, 3));
+    };
     for (int j = 0; j < h->J - 1; ++j) {  // J - 1 surrogate jumps
-        HCALL(h, lbcm_net_forward_planes(h->net, plane((double *)cur, P, 0), plane((double *)cur, P, 1), plane((double *)cur, P, 2),
-                                         h->u_scale, plane(y, P, 0), plane(y, P, 1), plane(y, P, 2)),
-              "lbcm_net_forward_planes");
+        HNET(h, jump(cur, y), "lbcm_net_forward_planes");
         cur = y;
         std::swap(x, y);
     }
-    // the last jump of the window by both: the surrogate into y, the lattice from the same state
-    HCALL(h, lbcm_net_forward_planes(h->net, plane((double *)cur, P, 0), plane((double *)cur, P, 1), plane((double *)cur, P, 2),
-                                     h->u_scale, plane(y, P, 0), plane(y, P, 1), plane(y, P, 2)),
-          "lbcm_net_forward_planes");
-    HCALL(h, lbcm_init_device(h->lat, plane((double *)cur, P, 0), nullptr, plane((double *)cur, P, 1), plane((double *)cur, P, 2)),
-          "lbcm_init_device");
-    HCALL(h, lbcm_step(h->lat, h->K), "lbcm_step");
-    HCALL(h, lbcm_fields_device(h->lat, h->lbphi, nullptr, nullptr, nullptr, nullptr), "lbcm_fields_device");
-    double e = 0;
-    int rc = phi_error(h, plane(y, P, 0), h->lbphi, &e);
+    // the last jump of the window both ways: the surrogate into y, K lattice steps on the scratch
+    // lattice from equilibrium populations of the same state
+    HNET(h, jump(cur, y), "lbcm_net_forward_planes");
+    HSCR(h, lbcm_init_device(h->scratch, pl(cur, 0), pl(cur, 3), pl(cur, 1), pl(cur, 2)), "lbcm_init_device");
+    HSCR(h, lbcm_step(h->scratch, h->K), "lbcm_step");
+    HSCR(h, lbcm_fields_device(h->scratch, pl(h->lb, 0), nullptr, pl(h->lb, 1), pl(h->lb, 2), nullptr), "lbcm_fields_device");
+    double sum[kErrSums];
+    int rc = check_sums(h, y, h->lb, sum);
     if (rc) return rc;
+    const double e = rel_l2(sum[0], sum[1]), ev = rel_l2(sum[2], sum[3]);
     h->st.checks += 1;
     h->st.last_error = e;
     h->st.max_error = std::max(h->st.max_error, e);
-    if (!(e <= h->threshold)) {
-        // rejected: redo the window with the lattice Boltzmann step from its starting fields
+    h->st.last_velocity_error = ev;
+    const bool ok = e <= h->threshold && (h->vthreshold <= 0 || ev <= h->vthreshold);
+    if (!ok) {
+        // rejected: the caller's lattice still holds the window's starting populations; run the
+        // window with the plain step from there, then 2^(k-1) more plain windows (at most 16)
+        // after k failures in a row
         h->st.failed_checks += 1;
-        HCALL(h, lbcm_init_device(h->lat, plane(h->start, P, 0), nullptr, plane(h->start, P, 1), plane(h->start, P, 2)),
-              "lbcm_init_device");
-        HCALL(h, lbcm_step(h->lat, span), "lbcm_step");
+        HLAT(h, lbcm_step(h->lat, span), "lbcm_step");
         h->st.lb_steps_run += h->K + span;
-        h->cooldown = true;
+        h->streak = std::min(h->streak + 1, 5);
+        h->cooldown = (int64_t)1 << (h->streak - 1);
     } else {
+        HLAT(h, lbcm_copy_state(h->lat, h->scratch, lbcm_step_count(h->lat) + span), "lbcm_copy_state");
         h->st.jumps += h->J - 1;
         h->st.lb_steps_run += h->K;
+        h->st.max_accepted_error = std::max(h->st.max_accepted_error, e);
+        h->st.max_accepted_velocity_error = std::max(h->st.max_accepted_velocity_error, ev);
+        h->streak = 0;
     }
     h->st.steps += span;
     return LBCM_OK;
@@ -1164,7 +1201,7 @@ int hybrid_window(lbcm_hybrid *h)
 extern "C" {
 
 int lbcm_hybrid_create(lbcm_handle *lattice, lbcm_net *net, int32_t steps_per_jump, int32_t jumps_per_check, double u_scale,
-                       double threshold, lbcm_hybrid **out)
+                       double rho_scale, double threshold, double velocity_threshold, lbcm_hybrid **out)
 {
     if (!out) return LBCM_EINVAL;
     *out = nullptr;
@@ -1173,8 +1210,9 @@ int lbcm_hybrid_create(lbcm_handle *lattice, lbcm_net *net, int32_t steps_per_ju
         g_hybrid_error = "lattice and network are required";
         return LBCM_EINVAL;
     }
-    if (steps_per_jump < 1 || jumps_per_check < 1 || !(u_scale > 0) || !(threshold >= 0)) {
-        g_hybrid_error = "steps_per_jump and jumps_per_check must be >= 1, u_scale > 0, threshold >= 0";
+    if (steps_per_jump < 1 || jumps_per_check < 1 || !(u_scale > 0) || !(rho_scale > 0) || !(threshold >= 0) ||
+        std::isnan(velocity_threshold)) {
+        g_hybrid_error = "steps_per_jump and jumps_per_check must be >= 1, u_scale and rho_scale > 0, threshold >= 0";
         return LBCM_EINVAL;
     }
     if (p.bc_y != LBCM_BC_PERIODIC || net->batch != 1 || net->H != p.ny || net->W != p.nx) {
@@ -1192,12 +1230,23 @@ int lbcm_hybrid_create(lbcm_handle *lattice, lbcm_net *net, int32_t steps_per_ju
     h->K = steps_per_jump;
     h->J = jumps_per_check;
     h->u_scale = u_scale;
+    h->rho_scale = rho_scale;
     h->threshold = threshold;
+    h->vthreshold = velocity_threshold;
     h->P = net->P;
+    lbcm_params ps = p;  // the scratch lattice: same size, physics and stream; its own memory
+    ps.workspace = nullptr;
+    ps.workspace_bytes = 0;
+    ps.check_every = 0;
+    if (lbcm_create(&ps, &h->scratch) != LBCM_OK) {
+        g_hybrid_error = std::string("scratch lattice: ") + lbcm_last_error(nullptr);
+        delete h;
+        return LBCM_ENOMEM;
+    }
     const size_t pb = (size_t)h->P * sizeof(double);
-    if (hipMalloc((void **)&h->start, 3 * pb) != hipSuccess || hipMalloc((void **)&h->a, 3 * pb) != hipSuccess ||
-        hipMalloc((void **)&h->b, 3 * pb) != hipSuccess || hipMalloc((void **)&h->lbphi, pb) != hipSuccess ||
-        hipMalloc((void **)&h->err_partial, 2 * kErrBlocks * sizeof(double)) != hipSuccess) {
+    if (hipMalloc((void **)&h->start, 4 * pb) != hipSuccess || hipMalloc((void **)&h->a, 4 * pb) != hipSuccess ||
+        hipMalloc((void **)&h->b, 4 * pb) != hipSuccess || hipMalloc((void **)&h->lb, 3 * pb) != hipSuccess ||
+        hipMalloc((void **)&h->err_partial, kErrSums * kErrBlocks * sizeof(double)) != hipSuccess) {
         g_hybrid_error = "out of device memory";
         lbcm_hybrid_destroy(h);
         return LBCM_ENOMEM;
@@ -1228,8 +1277,9 @@ int lbcm_hybrid_destroy(lbcm_hybrid *h)
     if (!h) return LBCM_OK;
     if (h->net && h->net->stream) (void)hipStreamSynchronize(h->net->stream);
     else (void)hipDeviceSynchronize();
-    for (void *q : {(void *)h->start, (void *)h->a, (void *)h->b, (void *)h->lbphi, (void *)h->err_partial})
+    for (void *q : {(void *)h->start, (void *)h->a, (void *)h->b, (void *)h->lb, (void *)h->err_partial})
         if (q) (void)hipFree(q);
+    if (h->scratch) lbcm_destroy(h->scratch);
     delete h;
     return LBCM_OK;
 }

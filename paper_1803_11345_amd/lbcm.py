@@ -103,6 +103,9 @@ def load():
     lib.lbcm_autotune.argtypes = [_H, ctypes.c_int]
     lib.lbcm_tile_shape.argtypes = [_H, PI, PI]
     lib.lbcm_info.argtypes = [_H, P]
+    lib.lbcm_copy_state.argtypes = [_H, _H, ctypes.c_int64]
+    lib.lbcm_step_count.argtypes = [_H]
+    lib.lbcm_step_count.restype = ctypes.c_int64
     lib.lbcm_batch_create.argtypes = [P, I32, ctypes.POINTER(_H)]
     lib.lbcm_batch_box.argtypes = [_H, I32]
     lib.lbcm_batch_box.restype = _H
@@ -121,7 +124,7 @@ def load():
 def declared_functions() -> list[str]:
     """Names of the entry points declared in include/lbcm.h and include/lbcm_net.h."""
     text = "\n".join(open(h).read() for h in HEADERS)
-    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*|lbcm_handle \*)\s*\**\s*(lbcm_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int|size_t|const char \*|lbcm_handle \*)\s*\**\s*(lbcm_\w+)\s*\(",
                                  text, re.M)))
 
 
@@ -222,6 +225,14 @@ def lbcm_info(h) -> lbcm_params:
     p = lbcm_params()
     _check(h, load().lbcm_info(h, ctypes.byref(p)))
     return p
+
+
+def lbcm_copy_state(dst, src, step: int):
+    _check(dst, load().lbcm_copy_state(dst, src, step))
+
+
+def lbcm_step_count(h) -> int:
+    return load().lbcm_step_count(h)
 
 
 def lbcm_tile_shape(h):

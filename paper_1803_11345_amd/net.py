@@ -22,7 +22,8 @@ _bound = False
 class lbcm_hybrid_stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("jumps", ctypes.c_int64), ("lb_steps_run", ctypes.c_int64),
                 ("checks", ctypes.c_int64), ("failed_checks", ctypes.c_int64), ("last_error", ctypes.c_double),
-                ("max_error", ctypes.c_double)]
+                ("max_error", ctypes.c_double), ("last_velocity_error", ctypes.c_double),
+                ("max_accepted_error", ctypes.c_double), ("max_accepted_velocity_error", ctypes.c_double)]
 
 
 def load():
@@ -39,14 +40,14 @@ def load():
     lib.lbcm_net_get_params.argtypes = [_H, _F, ctypes.c_size_t]
     lib.lbcm_net_get_grads.argtypes = [_H, _F, ctypes.c_size_t]
     lib.lbcm_net_forward.argtypes = [_H, _V, _V]
-    lib.lbcm_net_forward_planes.argtypes = [_H, _V, _V, _V, D, _V, _V, _V]
-    lib.lbcm_net_state_from_planes.argtypes = [_H, _V, _V, _V, D, _V]
+    lib.lbcm_net_forward_planes.argtypes = [_H, _V, _V, _V, _V, D, D, _V, _V, _V, _V]
+    lib.lbcm_net_state_from_planes.argtypes = [_H, _V, _V, _V, _V, D, D, _V]
     lib.lbcm_net_backward.argtypes = [_H, _V, _F]
     lib.lbcm_net_adam.argtypes = [_H, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int64]
     lib.lbcm_net_destroy.argtypes = [_H]
     lib.lbcm_net_last_error.argtypes = [_H]
     lib.lbcm_net_last_error.restype = ctypes.c_char_p
-    lib.lbcm_hybrid_create.argtypes = [_H, _H, I32, I32, D, D, ctypes.POINTER(_H)]
+    lib.lbcm_hybrid_create.argtypes = [_H, _H, I32, I32, D, D, D, D, ctypes.POINTER(_H)]
     lib.lbcm_hybrid_advance.argtypes = [_H, ctypes.c_int64]
     lib.lbcm_hybrid_get_stats.argtypes = [_H, ctypes.POINTER(lbcm_hybrid_stats)]
     lib.lbcm_hybrid_destroy.argtypes = [_H]
@@ -98,10 +99,13 @@ def lbcm_net_param_count(n) -> int:
     return load().lbcm_net_param_count(n)
 
 
+STATE_C = 4  # (phi, v_x, v_y, rho)
+
+
 def lbcm_net_set_output_scale(n, alpha):
     a = np.ascontiguousarray(alpha, dtype=np.float32)
-    if a.shape != (3,):
-        raise ValueError("expected 3 output scales")
+    if a.shape != (STATE_C,):
+        raise ValueError(f"expected {STATE_C} output scales")
     _nchk(n, load().lbcm_net_set_output_scale(n, a.ctypes.data_as(_F)))
 
 
@@ -128,20 +132,20 @@ def lbcm_net_forward(n, state, out=None):
     _nchk(n, load().lbcm_net_forward(n, _dev(state, torch.float32), None if out is None else _dev(out, torch.float32)))
 
 
-def lbcm_net_forward_planes(n, phi, ux, uy, u_scale, phi_out, ux_out, uy_out):
+def lbcm_net_forward_planes(n, phi, ux, uy, rho, u_scale, rho_scale, phi_out, ux_out, uy_out, rho_out):
     import torch
 
     d = torch.float64
-    _nchk(n, load().lbcm_net_forward_planes(n, _dev(phi, d), _dev(ux, d), _dev(uy, d), u_scale, _dev(phi_out, d),
-                                            _dev(ux_out, d), _dev(uy_out, d)))
+    _nchk(n, load().lbcm_net_forward_planes(n, _dev(phi, d), _dev(ux, d), _dev(uy, d), _dev(rho, d), u_scale, rho_scale,
+                                            _dev(phi_out, d), _dev(ux_out, d), _dev(uy_out, d), _dev(rho_out, d)))
 
 
-def lbcm_net_state_from_planes(n, phi, ux, uy, u_scale, state):
+def lbcm_net_state_from_planes(n, phi, ux, uy, rho, u_scale, rho_scale, state):
     import torch
 
     d = torch.float64
-    _nchk(n, load().lbcm_net_state_from_planes(n, _dev(phi, d), _dev(ux, d), _dev(uy, d), u_scale,
-                                               _dev(state, torch.float32)))
+    _nchk(n, load().lbcm_net_state_from_planes(n, _dev(phi, d), _dev(ux, d), _dev(uy, d), _dev(rho, d), u_scale,
+                                               rho_scale, _dev(state, torch.float32)))
 
 
 def lbcm_net_backward(n, target, want_loss=True):
@@ -164,9 +168,11 @@ def lbcm_net_last_error(n) -> str:
     return _msg(load().lbcm_net_last_error(n))
 
 
-def lbcm_hybrid_create(lattice, net, steps_per_jump, jumps_per_check, u_scale, threshold):
+def lbcm_hybrid_create(lattice, net, steps_per_jump, jumps_per_check, u_scale, rho_scale, threshold,
+                       velocity_threshold=0.0):
     h = _H()
-    rc = load().lbcm_hybrid_create(lattice, net, steps_per_jump, jumps_per_check, u_scale, threshold, ctypes.byref(h))
+    rc = load().lbcm_hybrid_create(lattice, net, steps_per_jump, jumps_per_check, u_scale, rho_scale, threshold,
+                                   velocity_threshold, ctypes.byref(h))
     _hchk(None, rc)
     return h
 
@@ -195,8 +201,8 @@ def layer_shapes(channels: int, layers: int):
     """(c_in, c_out, bias entries) of each layer in the parameter vector."""
     out = []
     for l in range(layers):
-        cin = 3 if l == 0 else channels
-        cout = 3 if l == layers - 1 else channels
+        cin = STATE_C if l == 0 else channels
+        cout = STATE_C if l == layers - 1 else channels
         out.append((cin, cout, 32 if l == layers - 1 else channels))
     return out
 
@@ -223,7 +229,7 @@ class Surrogate:
         self.h = lbcm_net_create(batch, height, width, channels, layers, self.stream.cuda_stream)
         self.nparams = lbcm_net_param_count(self.h)
         self.t = 0
-        self.alpha = (1.0, 1.0, 1.0)
+        self.alpha = (1.0,) * STATE_C
 
     def set_params(self, p):
         lbcm_net_set_params(self.h, p)
@@ -243,11 +249,11 @@ class Surrogate:
         lbcm_net_forward(self.h, state, out)
         return out
 
-    def forward_planes(self, phi, ux, uy, u_scale, phi_out, ux_out, uy_out):
-        lbcm_net_forward_planes(self.h, phi, ux, uy, u_scale, phi_out, ux_out, uy_out)
+    def forward_planes(self, phi, ux, uy, rho, u_scale, rho_scale, phi_out, ux_out, uy_out, rho_out):
+        lbcm_net_forward_planes(self.h, phi, ux, uy, rho, u_scale, rho_scale, phi_out, ux_out, uy_out, rho_out)
 
-    def state_from_planes(self, phi, ux, uy, u_scale, state):
-        lbcm_net_state_from_planes(self.h, phi, ux, uy, u_scale, state)
+    def state_from_planes(self, phi, ux, uy, rho, u_scale, rho_scale, state):
+        lbcm_net_state_from_planes(self.h, phi, ux, uy, rho, u_scale, rho_scale, state)
 
     def backward(self, target, want_loss=True):
         return lbcm_net_backward(self.h, target, want_loss)
@@ -272,10 +278,12 @@ class Hybrid:
     """Surrogate jumps on a periodic lattice with a lattice Boltzmann check every
     ``jumps_per_check`` jumps (see lbcm_hybrid_create)."""
 
-    def __init__(self, lattice, net: Surrogate, *, steps_per_jump=16, jumps_per_check=8, u_scale=1.0, threshold=1e-2):
+    def __init__(self, lattice, net: Surrogate, *, steps_per_jump=16, jumps_per_check=8, u_scale=1.0, rho_scale=1.0,
+                 threshold=1e-2, velocity_threshold=0.0):
         self.lattice, self.net = lattice, net
         self.span = steps_per_jump * jumps_per_check
-        self.h = lbcm_hybrid_create(lattice.h, net.h, steps_per_jump, jumps_per_check, u_scale, threshold)
+        self.h = lbcm_hybrid_create(lattice.h, net.h, steps_per_jump, jumps_per_check, u_scale, rho_scale, threshold,
+                                    velocity_threshold)
 
     def advance(self, windows=1):
         lbcm_hybrid_advance(self.h, windows)

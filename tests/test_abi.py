@@ -120,7 +120,7 @@ def test_hybrid_requires_handles():
 
     lib = net.load()
     h = ctypes.c_void_p()
-    assert lib.lbcm_hybrid_create(None, None, 16, 8, 1.0, 1e-2, ctypes.byref(h)) == lbcm.LBCM_EINVAL
+    assert lib.lbcm_hybrid_create(None, None, 16, 8, 1.0, 1.0, 1e-2, 0.0, ctypes.byref(h)) == lbcm.LBCM_EINVAL
     assert b"required" in lib.lbcm_hybrid_last_error(None)
     assert lib.lbcm_hybrid_advance(None, 1) == lbcm.LBCM_EINVAL
     assert lib.lbcm_hybrid_destroy(None) == lbcm.LBCM_OK

