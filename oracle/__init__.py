@@ -49,6 +49,9 @@ class Params:
     omega3: float = 1.0
     force_x: float = 0.0
     force_y: float = 0.0
+    wall_ux_bottom: float = 0.0
+    wall_ux_top: float = 0.0
+    wall_gradient: float = 0.0
     k8_printed: int = 0
     collision: int = 0
     nthreads: int = 0
@@ -60,6 +63,7 @@ class _CParams(ctypes.Structure):
         ("a", ctypes.c_double), ("gamma", ctypes.c_double), ("mobility", ctypes.c_double),
         ("Gamma", ctypes.c_double), ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double),
         ("omega3", ctypes.c_double), ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
+        ("wall_ux_bottom", ctypes.c_double), ("wall_ux_top", ctypes.c_double), ("wall_gradient", ctypes.c_double),
         ("k8_printed", ctypes.c_int), ("collision", ctypes.c_int), ("nthreads", ctypes.c_int),
     ]
 

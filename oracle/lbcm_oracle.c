@@ -32,8 +32,14 @@
  *   - omega_3 (bulk) is not given; it is a parameter (default 1).
  *   - a body force F (not in the paper) enters with Guo's half-step: v = (sum f c + F/2)/rho,
  *     and the central moments R = Tbar^T F^Guo are added with weight (1 - omega_i/2).
- *   - walls (bc 1): half-way bounce-back of both f and g at y = -1/2 and y = ny - 1/2,
- *     with phi mirrored into the ghost rows (zero normal gradient).
+ *   - walls (bc 1): half-way bounce-back of both f and g at y = -1/2 and y = ny - 1/2.  The
+ *     ghost row behind a wall holds phi of the first (last) row minus the wall gradient
+ *     d_perp phi_w of the contact-angle test (taken along the normal into the fluid, one node
+ *     spacing across the wall; 0 gives the mirrored, zero-gradient row).
+ *   - moving walls (the shear test): a wall moving along x with speed U returns a link j with
+ *     the momentum correction 2 w_j s (c_j . U) / c_s^2 of the half-way bounce-back, s = 1 (the
+ *     reference density) for f and s = phi of the node for g, so that the wall drags phi as the
+ *     fluid does.
  *   - initial populations are the equilibria of the initial (phi, rho, v).
  *
  * Layout of every population array: P[i][y][x], i = 0..8, x fastest, planes of nx*ny values.
@@ -52,6 +58,8 @@ typedef struct {
     double nu_g;      /* viscosity where phi = -1 */
     double omega3;    /* bulk-viscosity rate of k3 */
     double force_x, force_y;
+    double wall_ux_bottom, wall_ux_top; /* x velocities of the walls (walls = 1) */
+    double wall_gradient;             /* d_perp phi_w at both walls, along the inward normal */
     int k8_printed;   /* 1: k8 equilibrium with the printed gamma*Lap(phi) term */
     int collision;    /* 0: central moments (the method); 1: central moments with every rate
                          equal to omega_rho; 2: double BGK (Eq. (6)) */
@@ -104,18 +112,19 @@ int orc_check(const orc_params *p)
     if (!p || p->nx < 1 || p->ny < 1) return -1;
     if (p->walls != 0 && p->walls != 1) return -1;
     if (!(p->nu_l > 0) || !(p->nu_g > 0) || !(p->mobility > 0) || !(p->Gamma > 0)) return -1;
+    if (!isfinite(p->wall_ux_bottom) || !isfinite(p->wall_ux_top) || !isfinite(p->wall_gradient)) return -1;
     if (p->collision < 0 || p->collision > 2) return -1;
     return 0;
 }
 
 /* phi at (x, y) where x may be any integer (periodic) and y may be -1 or ny with walls
-   (mirrored ghost row) or any integer when periodic. */
+   (ghost row: the first / last row minus the wall gradient) or any integer when periodic. */
 static double phi_at(const orc_params *p, const double *phi, int x, int y)
 {
     x = wrap(x, p->nx);
     if (p->walls) {
-        if (y < 0) y = 0;
-        if (y >= p->ny) y = p->ny - 1;
+        if (y < 0) return phi[x] - p->wall_gradient;
+        if (y >= p->ny) return phi[(size_t)(p->ny - 1) * p->nx + x] - p->wall_gradient;
     } else {
         y = wrap(y, p->ny);
     }
@@ -370,6 +379,30 @@ static void stream_push(const orc_params *p, const double *star, double *out)
             }
 }
 
+/* Moving walls: the links that returned from a wall at this step gain 2 w_j s (c_j . U) / c_s^2
+   (U the wall's x velocity; s = 1 for f, phi = sum of the node's g for g). */
+static void wall_motion(const orc_params *p, double *out, int is_g)
+{
+    if (!p->walls || (p->wall_ux_bottom == 0 && p->wall_ux_top == 0)) return;
+    const int nx = p->nx, ny = p->ny;
+    const size_t N = (size_t)nx * ny;
+    for (int x = 0; x < nx; ++x) {
+        for (int side = 0; side < 2; ++side) {
+            const int y = side == 0 ? 0 : ny - 1;
+            const double U = side == 0 ? p->wall_ux_bottom : p->wall_ux_top;
+            const int cy = side == 0 ? 1 : -1; /* links coming back from the wall */
+            const size_t n = (size_t)y * nx + x;
+            double s = 1.0;
+            if (is_g) {
+                s = 0;
+                for (int i = 0; i < 9; ++i) s += out[(size_t)i * N + n];
+            }
+            for (int j = 0; j < 9; ++j)
+                if (CY[j] == cy) out[(size_t)j * N + n] += 2.0 * W[j] * s * CX[j] * U / CS2;
+        }
+    }
+}
+
 /* Initial populations: equilibria of (phi0, rho0, u0).  NULL rho0/ux0/uy0 mean 1, 0, 0.
    Velocity passed in is the physical v (with a force the same v is used in f^eq). */
 int orc_init(const orc_params *p, const double *phi0, const double *rho0, const double *ux0,
@@ -456,9 +489,11 @@ int orc_step(const orc_params *p, const double *f, const double *g, double *f_ou
                 gs[(size_t)i * N + n] = go[i];
             }
         }
-    /* 6. streaming. */
+    /* 6. streaming, and the momentum the moving walls give back. */
     stream_push(p, fs, f_out);
     stream_push(p, gs, g_out);
+    wall_motion(p, f_out, 0);
+    wall_motion(p, g_out, 1);
     free(phi);
     free(dx);
     free(dy);

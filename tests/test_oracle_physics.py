@@ -7,6 +7,8 @@ Measured oracle errors (stated bounds are these with margin):
   shear-wave decay vs. nu k^2:                                    < 0.3 %
   spinodal linear growth vs. M k^2 (a - gamma k^2):               < 0.4 %
   flat tanh interface after 2000 steps:                           max |phi - tanh| = 0.015
+  Couette flow between walls moving at -U and +U:                 1e-15 U (exact)
+  wetting wall profile vs. the shifted tanh, W = 2 / 4:           1.2e-3 / 3.4e-4
 """
 import json
 import math
@@ -198,3 +200,76 @@ def test_stability_cm_vs_double_bgk(orc):
             out[coll] = float(np.max(np.hypot(m["ux"], m["uy"])))
     assert not np.isfinite(out[2]) or out[2] > 0.1
     assert np.isfinite(out[0]) and out[0] < 1e-2
+
+
+def test_couette_between_moving_walls(orc):
+    """Walls moving at -U (bottom) and +U (top): the steady flow is the linear profile through
+    the wall velocities at the wall positions y = -1/2 and y = L - 1/2, which half-way
+    bounce-back with the moving-wall term reproduces exactly."""
+    L, U, nu = 16, 1e-3, 1 / 6
+    p = orc.Params(4, L, walls=1, nu_l=nu, nu_g=nu, wall_ux_bottom=-U, wall_ux_top=U, nthreads=1)
+    f, g = orc.init(p, np.ones((L, 4)))
+    f, g = orc.run(p, f, g, 20000)
+    m = orc.macro(p, f, g)
+    ua = -U + 2 * U * (np.arange(L) + 0.5) / L
+    assert np.max(np.abs(m["ux"] - ua[:, None])) < 1e-12 * U * 1e3
+    assert np.max(np.abs(m["uy"])) < 1e-13
+    assert np.max(np.abs(m["phi"] - 1)) < 1e-13
+
+
+def _wetting_run(orc, W, hW=0.36, L=64, steps=30000):
+    """Flat channel in the phi = +1 phase with the wall gradient h = hW / W at both walls,
+    started from the closed-form profile; returns (phi after the run, the profile).  The width
+    W = sqrt(2 gamma / a) is set through a at gamma = 0.08."""
+    gamma = 0.08
+    a = 2 * gamma / (W * W)
+    h = hW / W
+    d0 = W * math.atanh(math.sqrt(1 - hW))
+    y = np.arange(L) + 0.5  # distance from the bottom wall at y = -1/2
+    prof = np.tanh((y + d0) / W) * np.tanh((L - y + d0) / W)
+    p = orc.Params(2, L, walls=1, a=a, gamma=gamma, wall_gradient=h, nthreads=1)
+    f, g = orc.init(p, np.repeat(prof[:, None], 2, axis=1))
+    f, g = orc.run(p, f, g, steps)
+    return orc.macro(p, f, g)["phi"][:, 0], prof
+
+
+def test_wetting_wall_profile(orc):
+    """Near a wall with wall gradient h (along the normal into the fluid) the equilibrium of the
+    phi = +1 phase is the tanh profile shifted so that its slope at the wall is h:
+    phi = tanh((d + d0) / W) with 1 - tanh(d0 / W)^2 = h W, d the distance from the wall.  The
+    discrete steady state must approach it as the interface width grows (error ~ 1 / W^2)."""
+    e = {}
+    for W in (2.0, 4.0):
+        phi, prof = _wetting_run(orc, W)
+        e[W] = np.max(np.abs(phi - prof))
+        assert phi[0] < 0.95 and abs(phi[32] - 1) < 2e-3  # depleted at the wall, bulk phase inside
+    assert e[2.0] < 5e-3, e
+    assert e[4.0] < 0.4 * e[2.0], e
+
+
+def test_wall_gradient_sign_decides_the_wall_value(orc):
+    """phi grows away from the wall when the wall gradient is positive and falls when it is
+    negative: a positive gradient depletes the phi = +1 phase at the wall, a negative one
+    raises the phi = -1 phase there."""
+    L = 32
+    for phase, h in ((1.0, 0.1), (-1.0, -0.1)):
+        p = orc.Params(2, L, walls=1, a=0.04, gamma=0.08, wall_gradient=h, nthreads=1)
+        f, g = orc.init(p, np.full((L, 2), phase))
+        f, g = orc.run(p, f, g, 20000)
+        phi = orc.macro(p, f, g)["phi"][:, 0]
+        assert np.sign(phi[L // 2] - phi[0]) == np.sign(h) and abs(phi[L // 2] - phi[0]) > 0.01
+        assert np.sign(phi[L // 2] - phi[-1]) == np.sign(h)
+
+
+def test_moving_wetting_walls_conserve_phi(orc):
+    """With moving walls and a wall gradient, sum phi is still conserved to round-off (the
+    moving-wall terms of g cancel at every node; the ghost rows only enter the stencil)."""
+    nx, ny = 32, 24
+    W = inputs.interface_width(0.04, 0.08)
+    phi0 = inputs.droplet(nx, ny, 7, W, cx=16, cy=6)
+    p = orc.Params(nx, ny, walls=1, wall_ux_bottom=-2e-3, wall_ux_top=3e-3, wall_gradient=0.05, nthreads=1)
+    f, g = orc.init(p, phi0)
+    s0 = orc.macro(p, f, g)["phi"].sum()
+    f, g = orc.run(p, f, g, 400)
+    s1 = orc.macro(p, f, g)["phi"].sum()
+    assert abs(s1 - s0) <= 1e-12 * np.abs(phi0).sum()
