@@ -52,8 +52,9 @@ enum {
 typedef struct lbcm_params {
     int32_t nx, ny;      /* lattice size, >= 1 each */
     int32_t bc_y;        /* LBCM_BC_PERIODIC, or LBCM_BC_WALLS: half-way bounce-back walls at
-                            y = -1/2 and y = ny - 1/2 for both f and g, phi mirrored into the
-                            ghost rows (zero normal gradient); x is always periodic */
+                            y = -1/2 and y = ny - 1/2 for both f and g (moving along x at the
+                            wall velocities below), phi in the ghost rows from the wall
+                            gradient; x is always periodic */
     int32_t precision;   /* LBCM_FP64 or LBCM_FP32 (others: see the enum) */
     double a, gamma;     /* free-energy constants: mu = a(-phi + phi^3) - gamma Lap(phi) */
     double mobility;     /* M = (1/omega_phi - 1/2) Gamma c_s^2 */
@@ -61,6 +62,11 @@ typedef struct lbcm_params {
     double nu_l, nu_g;   /* kinematic viscosities at phi = +1 and phi = -1 */
     double omega3;       /* relaxation rate of k3 (bulk viscosity), in (0, 2); 1 recommended */
     double force_x, force_y; /* uniform body force (Guo half-step; 0 = the paper's scheme) */
+    double wall_vx_bottom;   /* x velocity of the wall at y = -1/2 (bc_y = LBCM_BC_WALLS; shear test) */
+    double wall_vx_top;      /* x velocity of the wall at y = ny - 1/2 */
+    double wall_gradient;    /* d_perp phi_w of the contact-angle test at both walls, along the
+                                normal into the fluid: the ghost row behind a wall holds the first
+                                (last) row's phi minus this value (0: zero normal gradient) */
     int32_t k8_variant;  /* 0: k8 equilibrium from its definition (-gamma |grad phi|^2 / 6);
                             1: the printed -gamma Lap(phi) / 6 of Eq. (16) */
     int32_t check_every; /* > 0: lbcm_step synchronises every check_every steps and at its end

@@ -175,13 +175,33 @@ struct Geo {
     int rows;           // rows per tile (one wave row each)
     int nbands, nrows;  // tiles across and down
     int walls;
+    double ub6, ut6;    // x velocities of the bottom and top walls, divided by 6
+    double wgrad;       // wall gradient of phi along the inward normal
 };
+
+// Moving walls: a link that comes back from a wall moving along x with speed U gains
+// 2 w_j s (c_j . U) / c_s^2 = s c_jx U / 6 (the diagonal links 5, 6 at the bottom, 7, 8 at the
+// top; s = 1 for f, the node's phi for g).  Applied wherever populations are pulled.
+template <class R>
+__device__ __forceinline__ void wall_motion(R v[9], R s, bool bot, bool top, R ub6, R ut6)
+{
+    if (bot) {
+        v[5] += s * ub6;
+        v[6] -= s * ub6;
+    }
+    if (top) {
+        v[7] -= s * ut6;
+        v[8] += s * ut6;
+    }
+}
 
 template <class R> struct Phys {
     R a, gamma, Gamma;
     R w_mid, w_half;  // omega_rho = w_mid + w_half * phi
     R w3, wphi;
     R hFx, hFy;       // half of the body force
+    R ub6, ut6;       // wall x velocities / 6
+    R wgrad;          // wall gradient of phi (inward normal)
     int k8_printed;
 };
 
@@ -241,7 +261,7 @@ __device__ __forceinline__ void pull_row(rsrc_t P, uint32_t N, int nx, int ny, i
 }
 
 // The same pull for one arbitrary node (readers; any y per lane), in double.
-__device__ __forceinline__ void pull_node(const SetView &P, const Geo &geo, size_t n, double v[9])
+__device__ __forceinline__ void pull_node(const SetView &P, const Geo &geo, size_t n, double v[9], bool is_g)
 {
     const int nx = geo.nx, ny = geo.ny;
     const int y = (int)(n / nx), x = (int)(n % nx);
@@ -260,6 +280,14 @@ __device__ __forceinline__ void pull_node(const SetView &P, const Geo &geo, size
             }
         }
         v[i] = view_ld(P, ii, (size_t)ys * nx + xs);
+    }
+    if (geo.walls) {
+        double s = 1.0;
+        if (is_g) {
+            s = 0;
+            for (int i = 0; i < 9; ++i) s += v[i];
+        }
+        wall_motion(v, s, y == 0, y == ny - 1, geo.ub6, geo.ut6);
     }
 }
 
@@ -489,14 +517,19 @@ __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, 
     R g[9], f[9];
     pull_row<F, F, R, WALLS>(rfa, N, nx, ny, yy, (uint32_t)x, xl, xr, f);
     pull_row<G0, G, R, WALLS>(rga, N, nx, ny, yy, (uint32_t)x, xl, xr, g);
-    const R phi_own = sum9(g);
+    const R phi_own = sum9(g);  // the wall corrections of g cancel in the sum
+    if (WALLS) {
+        const bool bot = yy == 0, top = yy == ny - 1;
+        wall_motion(f, (R)1, bot, top, c.ub6, c.ut6);
+        wall_motion(g, phi_own, bot, top, c.ub6, c.ut6);
+    }
     if (valid) phs[(wr + 1) * ldw + slot] = phi_own;
 
     // halo rows: the first tile row fetches the row above, the last valid one the row below;
-    // behind a wall the ghost row mirrors the first / last row
+    // behind a wall the ghost row holds the first / last row's phi minus the wall gradient
     auto halo_row = [&](int hy, int srow) {
         if (WALLS && (hy < 0 || hy >= ny)) {
-            if (col_ok) phs[srow * ldw + slot] = phi_own;
+            if (col_ok) phs[srow * ldw + slot] = phi_own - c.wgrad;
         } else {
             R h[9];
             pull_row<G0, G, R, WALLS>(rga, N, nx, ny, wrap_row(hy), (uint32_t)x, xl, xr, h);
@@ -522,7 +555,7 @@ __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, 
             const int hy = side == 0 ? y0 - 1 : y1;
             const int srow = side == 0 ? 0 : last + 2;
             if (WALLS && (hy < 0 || hy >= ny)) {
-                phs[srow * ldw + hs] = ph;
+                phs[srow * ldw + hs] = ph - c.wgrad;
             } else {
                 R h2[9];
                 pull_row<G0, G, R, WALLS>(rga, N, nx, ny, wrap_row(hy), hx, hxl, hxr, h2);
@@ -614,11 +647,12 @@ __global__ __launch_bounds__(kMaxThreads<M>) void k_step_batch(const BoxDesc<typ
 // a post-streaming state (9 + 9 planes, node-local, storage types); k_unstream stores them in
 // pull layout: P[i](z) = F[i](z + c_i), or F[opp(i)](z) where z + c_i is behind a wall.
 
-__device__ __forceinline__ double plane_at(const double *p, int nx, int ny, bool walls, int x, int y)
+__device__ __forceinline__ double plane_at(const double *p, int nx, int ny, bool walls, double wgrad, int x, int y)
 {
     x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
     if (walls) {
-        y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        if (y < 0) return p[x] - wgrad;
+        if (y >= ny) return p[(size_t)(ny - 1) * nx + x] - wgrad;
     } else {
         y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
     }
@@ -638,7 +672,7 @@ __global__ void k_equilibria(const double *__restrict__ phi0, const double *__re
         const bool wl = geo.walls != 0;
         double nb[3][3];
         for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) nb[dy + 1][dx + 1] = plane_at(phi0, nx, ny, wl, x + dx, y + dy);
+            for (int dx = -1; dx <= 1; ++dx) nb[dy + 1][dx + 1] = plane_at(phi0, nx, ny, wl, geo.wgrad, x + dx, y + dy);
         const R pC = (R)nb[1][1], pE = (R)nb[1][2], pW = (R)nb[1][0], pN = (R)nb[2][1], pS = (R)nb[0][1];
         const R pNE = (R)nb[2][2], pNW = (R)nb[2][0], pSE = (R)nb[0][2], pSW = (R)nb[0][0];
         const R dpx = ((R)4 * (pE - pW) + (pNE - pNW) + (pSE - pSW)) * (R)(1.0 / 12.0);
@@ -665,7 +699,7 @@ __global__ void k_equilibria(const double *__restrict__ phi0, const double *__re
     }
 }
 
-__global__ void k_unstream(SetView F, SetView P, Geo geo)
+__global__ void k_unstream(SetView F, SetView P, Geo geo, bool is_g)
 {
     const int nx = geo.nx, ny = geo.ny;
     const size_t N = geo.plane;
@@ -676,20 +710,24 @@ __global__ void k_unstream(SetView F, SetView P, Geo geo)
         const int y = (int)(n / nx), x = (int)(n % nx);
         int xs = x + kCX[i], ys = y + kCY[i];
         xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-        int si = i;
-        size_t sn;
         if (ys < 0 || ys >= ny) {
             if (geo.walls) {
-                si = kOpp[i];
-                sn = n;
-            } else {
-                ys = ys < 0 ? ys + ny : ys - ny;
-                sn = (size_t)ys * nx + xs;
+                // the pull returns this value in direction opp(i) with the moving-wall term
+                // added: store it without that term
+                double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                const int j = kOpp[i];
+                double s = 1.0;
+                if (is_g) {
+                    s = 0;
+                    for (int k = 0; k < 9; ++k) s += view_ld(F, k, n);
+                }
+                wall_motion(v, s, y == 0 && ys < 0, y == ny - 1 && ys >= ny, geo.ub6, geo.ut6);
+                view_st(P, i, n, view_ld(F, j, n) - v[j]);
+                continue;
             }
-        } else {
-            sn = (size_t)ys * nx + xs;
+            ys = ys < 0 ? ys + ny : ys - ny;
         }
-        view_copy(F, si, sn, P, i, n);
+        view_copy(F, i, (size_t)ys * nx + xs, P, i, n);
     }
 }
 
@@ -702,8 +740,8 @@ __global__ void k_fields(SetView f, SetView g, Geo geo, double a, double hFx, do
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
         double fv[9], gv[9];
-        pull_node(f, geo, n, fv);
-        pull_node(g, geo, n, gv);
+        pull_node(f, geo, n, fv, false);
+        pull_node(g, geo, n, gv, true);
         const double r = 1.0 + sum9(fv);
         const double ph = sum9(gv);
         const double jx = (fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7]);
@@ -722,7 +760,7 @@ __global__ void k_population(SetView f, SetView g, Geo geo, int which, double *o
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
         double v[9];
-        pull_node(which < 9 ? f : g, geo, n, v);
+        pull_node(which < 9 ? f : g, geo, n, v, which >= 9);
         out[n] = which < 9 ? v[which] + kW[which] : v[which - 9];
     }
 }
@@ -734,8 +772,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_diag(SetView f, SetView g, G
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
         double fv[9], gv[9];
-        pull_node(f, geo, n, fv);
-        pull_node(g, geo, n, gv);
+        pull_node(f, geo, n, fv, false);
+        pull_node(g, geo, n, gv, true);
         const double r = 1.0 + sum9(fv), ph = sum9(gv);
         const double jx = (fv[1] + fv[5] + fv[8]) - (fv[3] + fv[6] + fv[7]) + hFx;
         const double jy = (fv[2] + fv[5] + fv[6]) - (fv[4] + fv[7] + fv[8]) + hFy;
@@ -858,6 +896,8 @@ const char *check_params(const lbcm_params *p)
     if (!std::isfinite(p->a) || !std::isfinite(p->gamma) || !std::isfinite(p->force_x) ||
         !std::isfinite(p->force_y))
         return "a, gamma and the force must be finite";
+    if (!std::isfinite(p->wall_vx_bottom) || !std::isfinite(p->wall_vx_top) || !std::isfinite(p->wall_gradient))
+        return "the wall velocities and the wall gradient must be finite";
     if (p->k8_variant != 0 && p->k8_variant != 1) return "k8_variant must be 0 or 1";
     if (p->check_every < 0) return "check_every must be >= 0";
     if (p->tile_rows < 0 || p->tile_wx < 0) return "tile_rows and tile_wx must be >= 0";
@@ -903,6 +943,9 @@ template <class R> Phys<R> make_phys(const lbcm_params &p)
     c.wphi = (R)(1.0 / (p.mobility / (p.Gamma * cs2) + 0.5));
     c.hFx = (R)(0.5 * p.force_x);
     c.hFy = (R)(0.5 * p.force_y);
+    c.ub6 = (R)(p.wall_vx_bottom / 6.0);
+    c.ut6 = (R)(p.wall_vx_top / 6.0);
+    c.wgrad = (R)p.wall_gradient;
     c.k8_printed = p.k8_variant;
     return c;
 }
@@ -925,6 +968,9 @@ Geo make_geo(const lbcm_params &p)
     g.nbands = (p.nx + 64 * g.wx - 1) / (64 * g.wx);
     g.nrows = (p.ny + g.rows - 1) / g.rows;
     g.walls = p.bc_y;
+    g.ub6 = p.wall_vx_bottom / 6.0;
+    g.ut6 = p.wall_vx_top / 6.0;
+    g.wgrad = p.wall_gradient;
     return g;
 }
 
@@ -1064,9 +1110,9 @@ int do_init(lbcm_handle *h, const double *phi0, const double *rho0, const double
     hipLaunchKernelGGL((k_equilibria<R>), dim3(gb), dim3(256), 0, h->stream, phi0, rho0, ux0, uy0, F, G, geo, c);
     HIP_TRY(h, hipGetLastError());
     const int gu = grid_for(9 * (size_t)geo.plane, 256);
-    hipLaunchKernelGGL(k_unstream, dim3(gu), dim3(256), 0, h->stream, F, view_of(h, 0, 0), geo);
+    hipLaunchKernelGGL(k_unstream, dim3(gu), dim3(256), 0, h->stream, F, view_of(h, 0, 0), geo, false);
     HIP_TRY(h, hipGetLastError());
-    hipLaunchKernelGGL(k_unstream, dim3(gu), dim3(256), 0, h->stream, G, view_of(h, 0, 1), geo);
+    hipLaunchKernelGGL(k_unstream, dim3(gu), dim3(256), 0, h->stream, G, view_of(h, 0, 1), geo, true);
     HIP_TRY(h, hipGetLastError());
     hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(1), 0, h->stream, h->flag);
     HIP_TRY(h, hipGetLastError());

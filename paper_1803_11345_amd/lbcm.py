@@ -40,6 +40,7 @@ class lbcm_params(ctypes.Structure):
         ("a", ctypes.c_double), ("gamma", ctypes.c_double), ("mobility", ctypes.c_double),
         ("Gamma", ctypes.c_double), ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double),
         ("omega3", ctypes.c_double), ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
+        ("wall_vx_bottom", ctypes.c_double), ("wall_vx_top", ctypes.c_double), ("wall_gradient", ctypes.c_double),
         ("k8_variant", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("tile_rows", ctypes.c_int32), ("tile_wx", ctypes.c_int32),
         ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
@@ -56,13 +57,15 @@ class lbcm_diagnostics(ctypes.Structure):
 
 
 def make_params(nx, ny, *, bc_y=0, precision="fp32", a=0.04, gamma=0.08, mobility=0.1, Gamma=1.0,
-                nu_l=1 / 6, nu_g=1 / 6, omega3=1.0, force_x=0.0, force_y=0.0, k8_variant=0,
+                nu_l=1 / 6, nu_g=1 / 6, omega3=1.0, force_x=0.0, force_y=0.0, wall_vx_bottom=0.0,
+                wall_vx_top=0.0, wall_gradient=0.0, k8_variant=0,
                 check_every=0, tile_rows=0, tile_wx=0, stream=None, workspace=None, workspace_bytes=0):
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     return lbcm_params(nx=nx, ny=ny, bc_y=bc_y, precision=precision, a=a, gamma=gamma,
                        mobility=mobility, Gamma=Gamma, nu_l=nu_l, nu_g=nu_g, omega3=omega3,
-                       force_x=force_x, force_y=force_y, k8_variant=k8_variant,
+                       force_x=force_x, force_y=force_y, wall_vx_bottom=wall_vx_bottom,
+                       wall_vx_top=wall_vx_top, wall_gradient=wall_gradient, k8_variant=k8_variant,
                        check_every=check_every, tile_rows=tile_rows, tile_wx=tile_wx,
                        stream=stream, workspace=workspace, workspace_bytes=workspace_bytes)
 

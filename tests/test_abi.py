@@ -30,8 +30,8 @@ def test_library_has_no_oracle_dependency():
 
 
 def test_struct_layout_matches_header():
-    # int32 x4, double x9, int32 x4, two pointers and a size_t
-    assert ctypes.sizeof(lbcm.lbcm_params) == 16 + 72 + 16 + 24
+    # int32 x4, double x12, int32 x4, two pointers and a size_t
+    assert ctypes.sizeof(lbcm.lbcm_params) == 16 + 96 + 16 + 24
     assert ctypes.sizeof(lbcm.lbcm_diagnostics) == 8 * 8
 
 
@@ -63,6 +63,7 @@ def test_workspace_size_16bit(prec):
     (dict(nx=4, ny=4, precision=7), "precision"),
     (dict(nx=4, ny=4, k8_variant=3), "k8_variant"),
     (dict(nx=4, ny=4, a=float("nan")), "finite"),
+    (dict(nx=4, ny=4, bc_y=1, wall_gradient=float("inf")), "wall"),
     (dict(nx=70000, ny=70000, precision="fp32"), "too large"),
 ])
 def test_bad_params_rejected_on_host(kw, frag):

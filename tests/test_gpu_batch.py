@@ -32,6 +32,7 @@ BOXES = [
     dict(nx=1, ny=1),
     dict(nx=200, ny=3, nu_l=0.1, nu_g=0.1),
     dict(nx=257, ny=129, nu_l=0.1, nu_g=0.002),
+    dict(nx=90, ny=40, bc_y=1, nu_l=0.1, nu_g=0.1, wall_vx_bottom=-2e-3, wall_vx_top=4e-3, wall_gradient=0.04),
 ]
 
 

@@ -39,6 +39,9 @@ def both(nx, ny, phi, rho=None, ux=None, uy=None, steps=1, prec="fp64", tile_row
     okw = dict(kw)
     if "bc_y" in okw:
         okw["walls"] = okw.pop("bc_y")
+    for side in ("bottom", "top"):  # the oracle names the wall velocities by their component
+        if f"wall_vx_{side}" in okw:
+            okw[f"wall_ux_{side}"] = okw.pop(f"wall_vx_{side}")
     p = oracle.Params(nx, ny, **okw)
     fo, go = oracle.init(p, phi, rho, ux, uy)
     fo, go = oracle.run(p, fo, go, steps)
@@ -292,3 +295,56 @@ def test_torch_stream_and_device_io():
     m = ref.fields()
     for k, o in zip(("phi", "rho", "ux", "uy", "p0"), out):
         assert np.array_equal(o.cpu().numpy(), m[k]), k
+
+
+WALLS = dict(bc_y=1, wall_vx_bottom=-3e-3, wall_vx_top=5e-3, wall_gradient=0.05)
+
+
+@pytest.mark.parametrize("steps,tol", [(1, 1e-14), (200, 1e-12)])
+def test_moving_wetting_walls_fp64(steps, tol):
+    """Walls moving at -3e-3 and +5e-3 with the wall gradient 0.05: the step, the readers and the
+    initial unstreaming all carry the moving-wall terms and the ghost rows."""
+    nx, ny = 70, 45
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=41)
+    (f, g, m), (fo, go, mo) = both(nx, ny, phi, rho, ux, uy, steps=steps, tile_rows=16, force_x=1e-5,
+                                   **WALLS, **PHYS)
+    ef, eg = maxerr(f, fo), maxerr(g, go)
+    say(f"  max |df| = {ef:.2e}  max |dg| = {eg:.2e}")
+    assert ef < tol and eg < tol
+    for k in ("phi", "rho", "ux", "uy", "p0"):
+        assert maxerr(m[k], mo[k]) < 10 * tol, k
+
+
+@pytest.mark.parametrize("prec,tol1,tol50", [("fp32", 2e-6, 2e-5), ("fp16s", 3e-5, 3e-4), ("bf16s", 3e-4, 3e-3)])
+def test_moving_wetting_walls_reduced_precision(prec, tol1, tol50):
+    nx, ny = 70, 45
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=42)
+    for steps, tol in ((1, tol1), (50, tol50)):
+        (f, g, m), (fo, go, mo) = both(nx, ny, phi, rho, ux, uy, steps=steps, prec=prec, tile_rows=2, **WALLS,
+                                       **PHYS)
+        ef, eg = maxerr(f, fo), maxerr(g, go)
+        say(f"  {prec} {steps} steps: max |df| = {ef:.2e}  max |dg| = {eg:.2e}")
+        assert ef < tol and eg < tol
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (6, 1), (2, 3), (65, 2), (5, 130)])
+def test_moving_wetting_walls_edge_sizes(nx, ny):
+    """One-row channels (both walls on the same row), two rows, ragged tiles."""
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=43)
+    (f, g, m), (fo, go, mo) = both(nx, ny, phi, rho, ux, uy, steps=3, **WALLS, **PHYS)
+    assert maxerr(f, fo) < 1e-14 and maxerr(g, go) < 1e-14
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-7)])
+def test_couette_flow(prec, tol):
+    """Walls moving at -U and +U drive the exact linear profile through the wall velocities."""
+    L, U = 32, 1e-3
+    lat = lbcm.Lattice(4, L, precision=prec, bc_y=1, wall_vx_bottom=-U, wall_vx_top=U, nu_l=1 / 6, nu_g=1 / 6)
+    lat.init(np.ones((L, 4)))
+    lat.step(60000)
+    u = lat.fields()["ux"]
+    ua = -U + 2 * U * (np.arange(L) + 0.5) / L
+    err = maxerr(u, ua[:, None])
+    say(f"  {prec} Couette max |u - u_a| = {err:.2e}")
+    assert err < tol
+    lat.close()
