@@ -348,3 +348,39 @@ def test_couette_flow(prec, tol):
     say(f"  {prec} Couette max |u - u_a| = {err:.2e}")
     assert err < tol
     lat.close()
+
+
+def test_droplet_deformation_in_shear_follows_taylor():
+    """The paper's shear test: a droplet (R = 30) between walls moving at -v_w and +v_w
+    (2H = 200, nu = 0.2, Re = v_w R^2 / (H nu) = 0.1), capillary numbers Ca = v_w R nu / (H sigma)
+    from 0.05 to 0.2 set through sigma = sqrt(8 gamma a / 9) at the interface width 2.  The
+    deformation D = (A - B) / (A + B) grows linearly in Ca with Taylor's slope 35/32 for equal
+    viscosities; the fitted slope must lie within 5 % of it."""
+    n, R, H, nu, W = 200, 30, 100, 0.2, 2.0
+    vw = 0.1 * H * nu / R ** 2
+    y = np.arange(n) + 0.5
+    u0 = np.repeat((vw * (2 * y / n - 1))[:, None], n, axis=1)
+    yy, xx = np.mgrid[0:n, 0:n].astype(float)
+    cas, ds = [], []
+    for Ca in (0.05, 0.1, 0.15, 0.2):
+        sigma = vw * R * nu / (H * Ca)
+        a = 3 * sigma / (2 * W)  # sigma = (2 / 3) a W at W = sqrt(2 gamma / a)
+        lat = lbcm.Lattice(n, n, precision="fp32", bc_y=1, a=a, gamma=a * W * W / 2, mobility=0.1, nu_l=nu, nu_g=nu,
+                           wall_vx_bottom=-vw, wall_vx_top=vw)
+        lat.init(inputs.droplet(n, n, R, W), None, u0, None)
+        lat.step(240000)
+        phi = lat.fields()["phi"]
+        lat.close()
+        w = np.clip((1 + phi) / 2, 0, 1)
+        m = w.sum()
+        cx, cy = (w * xx).sum() / m, (w * yy).sum() / m
+        I = np.array([[(w * (xx - cx) ** 2).sum(), (w * (xx - cx) * (yy - cy)).sum()],
+                      [(w * (xx - cx) * (yy - cy)).sum(), (w * (yy - cy) ** 2).sum()]]) / m
+        ev = np.linalg.eigvalsh(I)
+        A, B = math.sqrt(ev[1]), math.sqrt(ev[0])  # axes in proportion to the semi-axes
+        cas.append(Ca)
+        ds.append((A - B) / (A + B))
+        say(f"  Ca {Ca}: D = {ds[-1]:.4f}")
+    slope, icpt = np.polyfit(cas, ds, 1)
+    say(f"  fitted slope {slope:.4f} (Taylor {35 / 32:.5f}), intercept {icpt:.4f}")
+    assert abs(slope / (35 / 32) - 1) < 0.05
