@@ -54,7 +54,8 @@ int lbcm_net_get_params(lbcm_net *n, float *host, size_t count);
 int lbcm_net_forward(lbcm_net *n, const float *in, float *out);
 
 /* Forward pass from device FP64 planes [B][H][W] of phi, v_x, v_y, rho (scaled on the way in as
-   in the state tensor, and back on the way out) into device FP64 planes. */
+   in the state tensor, and back on the way out) into device FP64 planes.  The output planes may
+   be the input planes (in place).  The conversions run inside the first and last layers. */
 int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, const double *rho,
                             double u_scale, double rho_scale, double *phi_out, double *ux_out, double *uy_out,
                             double *rho_out);
@@ -63,8 +64,8 @@ int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, co
 int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, const double *rho,
                                double u_scale, double rho_scale, float *state);
 
-/* Gradient of the loss mean(((out - target) / alpha)^2) over pixels and the 4 channels, after a
-   forward pass, into the internal FP32 gradient vector (same layout as the parameters).  *loss
+/* Gradient of the loss mean(((out - target) / alpha)^2) over pixels and the 4 channels, after
+   lbcm_net_forward (lbcm_net_forward_planes keeps no output state for it), into the internal FP32 gradient vector (same layout as the parameters).  *loss
    (host, may be NULL) receives the loss (then the call synchronises). */
 int lbcm_net_backward(lbcm_net *n, const float *target, float *loss);
 

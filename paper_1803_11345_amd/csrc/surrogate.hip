@@ -117,97 +117,89 @@ __device__ __forceinline__ void stage_state(const float *__restrict__ s, TileCoo
 }
 
 // ------------------------------------------------------------------------------------------
-// layer 0 on the vector ALU over 8 x 32 tiles: Y[p][co] = bf16(relu(b[co] + sum_{t, ci}
-// s[p + d_t][ci] W0[t][ci][co])), one tile per workgroup.  The state patch and the 36 x C weights
-// are staged in LDS.  Wave
-// w of the 8 computes output channels [C/8 w, C/8 (w + 1)) and each lane 4 pixels of the tile,
-// so that every weight read (a wave-uniform LDS broadcast) feeds 4 FMAs.
+// layer 0 on the matrix cores in FP32 over 8 x 32 tiles: Y[p][co] = bf16(relu(b[co] + sum_{t, ci}
+// s[p + d_t][ci] W0[t][ci][co])), one tile per workgroup.  v_mfma_f32_16x16x4_f32 takes K = 4,
+// exactly the state channels of one tap, so each tap is one MFMA per 16-channel x 16-pixel block
+// with FP32 products and sums.  Wave w computes tile row w (two 16-pixel blocks) for all C / 16
+// channel blocks; its A operands (W0 of 9 taps x C / 16 blocks, one value per lane) stay in
+// registers.  The state patch (tile plus circular halo) is staged in LDS.  With PLANES the
+// patch is read from the four FP64 field planes and converted to the state (phi, v / u_scale,
+// (rho - 1) / rho_scale) as k_from_planes does, and the tile's own state goes to s_out (the
+// residual of the last layer).
 
-constexpr int kFirstThreads = 512;
+constexpr int kFirstThreads = 64 * kTileH;  // one wave per tile row
 
-template <int C>
-__global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict__ s, const float *__restrict__ W0,
-                                                         const float *__restrict__ b0, int H, int W,
+struct PlaneIn {
+    const double *phi, *ux, *uy, *rho;
+    float inv_u, inv_r;
+};
+
+template <int C, bool PLANES>
+__global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict__ s, PlaneIn pin, float *__restrict__ s_out,
+                                                         const float *__restrict__ W0, const float *__restrict__ b0, int H, int W,
                                                          __bf16 *__restrict__ Y)
 {
-    constexpr int CW = C / 8;  // channels per wave
-    __shared__ float sp[kPatchH * kPatchW * kStateC];
-    __shared__ __align__(16) float sw[kFirstRows * C];  // rows kStateC t + ci: W0[t][ci][co]; last row: bias
+    constexpr int NB = C / 16;  // channel blocks
+    __shared__ __align__(16) float sp[kPatchH * kPatchW * kStateC];
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int c0 = CW * wave;
-    const int base = (((lane >> 5) + 1) * kPatchW + (lane & 31) + 1) * kStateC;  // patch index of pixel `lane`
-    for (int k = threadIdx.x; k < kFirstRows * C; k += kFirstThreads)
-        sw[k] = k < (kFirstRows - 1) * C ? W0[k] : b0[k - (kFirstRows - 1) * C];
+    const int row = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = lane & 15, q = lane >> 4;
     const TileCoord tc = tile_coord(blockIdx.x, H, W);
-    {
-        constexpr int NV = kPatchH * kPatchW * kStateC, NI = (NV + kFirstThreads - 1) / kFirstThreads;
-        float v[NI];
+    // A operand of block cb at tap t: lane (r, q) holds W0[t][ci = q][co = 16 cb + r]
+    float wa[9][NB];
 #pragma unroll
-        for (int i = 0; i < NI; ++i) {
-            const int k = threadIdx.x + i * kFirstThreads;
-            if (k < NV) {
-                const int px = k / kStateC, c = k % kStateC;
-                const int gy = wrap_near(tc.y0 - 1 + px / kPatchW, H), gx = wrap_near(tc.x0 - 1 + px % kPatchW, W);
-                v[i] = s[(((size_t)tc.n * H + gy) * W + gx) * kStateC + c];
-            }
-        }
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int i = 0; i < NI; ++i) {
-            const int k = threadIdx.x + i * kFirstThreads;
-            if (k < NV) sp[k] = v[i];
+        for (int cb = 0; cb < NB; ++cb) wa[t][cb] = W0[(kStateC * t + q) * C + 16 * cb + r];
+    // D of a block: lane (r, q) holds channels 16 cb + 4 q + e of pixel r
+    f32x4 acc[2][NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[0][cb][e] = acc[1][cb][e] = b0[16 * cb + 4 * q + e];
+    }
+    for (int k = threadIdx.x; k < kPatchH * kPatchW; k += kFirstThreads) {
+        const int py = k / kPatchW, px = k % kPatchW;
+        const int gy = wrap_near(tc.y0 - 1 + py, H), gx = wrap_near(tc.x0 - 1 + px, W);
+        const size_t p = ((size_t)tc.n * H + gy) * W + gx;
+        f32x4 v;
+        if constexpr (PLANES) {
+            v[0] = (float)pin.phi[p];
+            v[1] = (float)pin.ux[p] * pin.inv_u;
+            v[2] = (float)pin.uy[p] * pin.inv_u;
+            v[3] = (float)(pin.rho[p] - 1.0) * pin.inv_r;
+            // the tile's own pixels (each belongs to exactly one tile)
+            if (py >= 1 && py <= kTileH && px >= 1 && px <= kTileW && tc.y0 + py - 1 < H && tc.x0 + px - 1 < W)
+                *(f32x4 *)(s_out + p * kStateC) = v;
+        } else {
+            v = *(const f32x4 *)(s + p * kStateC);
         }
+        *(f32x4 *)(sp + k * kStateC) = v;
     }
     __syncthreads();
-    float acc[4][CW];
-#pragma unroll
-    for (int j = 0; j < CW; ++j) {
-        const float b = sw[(kFirstRows - 1) * C + c0 + j];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k][j] = b;
-    }
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
+        float x[2];  // B operand: lane (r, q) holds channel q of pixel r of the block
 #pragma unroll
-        for (int ci = 0; ci < kStateC; ++ci) {
-            float x[4];
+        for (int h = 0; h < 2; ++h)
+            x[h] = sp[((row + 1 + tap_dy(t)) * kPatchW + 16 * h + r + 1 + tap_dx(t)) * kStateC + q];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)  // pixel lane + 64 k sits 2 k rows below pixel lane
-                x[k] = sp[base + ((2 * k + tap_dy(t)) * kPatchW + tap_dx(t)) * kStateC + ci];
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int j = 0; j < CW; ++j) {
-                const float w = sw[(kStateC * t + ci) * C + c0 + j];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k][j] = fmaf(x[k], w, acc[k][j]);
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);  // keep each tap's weight reads next to its FMAs
+            for (int cb = 0; cb < NB; ++cb) acc[h][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[t][cb], x[h], acc[h][cb], 0, 0, 0);
     }
-    // materialise the sums here: otherwise the FMAs are sunk into the per-pixel store branches
-    // below, and every LDS read ahead of them stays live at once
+    const int y = tc.y0 + row;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int j = 0; j < CW; ++j) asm volatile("" : "+v"(acc[k][j]));
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int pix = lane + 64 * k, y = tc.y0 + pix / kTileW, xg = tc.x0 + pix % kTileW;
+    for (int h = 0; h < 2; ++h) {
+        const int xg = tc.x0 + 16 * h + r;
         if (y >= H || xg >= W) continue;
-        __bf16 *out = Y + (((size_t)tc.n * H + y) * W + xg) * C + c0;
-        if constexpr (CW % 8 == 0) {
+        __bf16 *out = Y + (((size_t)tc.n * H + y) * W + xg) * C + 4 * q;
 #pragma unroll
-            for (int j = 0; j < CW; j += 8) {
-                bf16x8 v;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = (__bf16)fmaxf(acc[k][j + e], 0.f);
-                *(u32x4 *)(out + j) = __builtin_bit_cast(u32x4, v);
-            }
-        } else {
-            static_assert(CW == 4, "4 or a multiple of 8 channels per wave");
+        for (int cb = 0; cb < NB; ++cb) {
             bf16x4 v;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = (__bf16)fmaxf(acc[k][e], 0.f);
-            *(u32x2 *)out = __builtin_bit_cast(u32x2, v);
+            for (int e = 0; e < 4; ++e) v[e] = (__bf16)fmaxf(acc[h][cb][e], 0.f);
+            *(u32x2 *)(out + 16 * cb) = __builtin_bit_cast(u32x2, v);
         }
     }
 }
@@ -295,7 +287,8 @@ __global__ __launch_bounds__(256) void k_sum_rows(const float *__restrict__ part
 //
 // MODE 0: Y = bf16(relu(bias + conv));  MODE 2: Y = bf16(conv * [mask > 0]) (the input gradient
 // times the ReLU derivative of the layer input);  MODE 1: Yf[p][c] = resid[p][c] + alpha_c (bias
-// + conv) for c < kStateC (the last layer, FP32).
+// + conv) for c < kStateC (the last layer, FP32);  MODE 3: the same state written to the FP64
+// field planes (phi, v = u_scale v', rho = 1 + rho_scale rho').
 
 constexpr int kConvThreads = 512;
 
@@ -306,6 +299,8 @@ struct OutArgs {
     const float *resid;
     float *Yf;
     float alpha0, alpha1, alpha2, alpha3;
+    double *phi, *ux, *uy, *rho;  // MODE 3: FP64 field planes
+    double u_scale, r_scale;
 };
 
 template <int CIN>
@@ -346,23 +341,117 @@ struct ConvLds {
     static constexpr size_t bytes = (size_t)(patch_elems + weight_elems) * sizeof(__bf16);
 };
 
+// Work split of a conv layer over the 8 waves: wave (mg, ng) computes output channels
+// [16 ng, 16 ng + 16) for tile rows [RW mg, RW mg + RW) (COUT / 16 channel groups times
+// 8 / (COUT / 16) row groups).
+template <int COUT>
+struct WaveSplit {
+    static constexpr int NG = COUT / 16, MG = 8 / NG, RW = kTileH / MG, MT = 2 * RW;
+};
+
+// One output tile of a conv layer from its input patch in LDS (the tile plus a one-pixel halo,
+// 10 x 34 pixels, pixel stride CIN + 8), with this wave's A fragments wa (W[t][co = 16 ng + r][ci
+// = 32 ks + 8 q .. + 8] in lane (r, q)) and the bias of its 4 output channels.  Input-stationary
+// order: each pixel fragment of the wave's RW + 2 patch rows is read from LDS once and applied to
+// every output row (tap dy) that uses it.  Stage s covers patch row s / 2 and column half s % 2
+// (3 horizontal taps x KS fragments); the fragments of stage s + 1 are read before the MFMAs of
+// stage s, in a second register buffer.  Every output sums its taps in the order t = 0 .. 8 and
+// K-steps within a tap.
+template <int CIN, int COUT, int MODE>
+__device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa)[9][CIN / 32], const float (&bias)[4],
+                                          TileCoord tc, const OutArgs &o, int H, int W)
+{
+    constexpr int PS = CIN + 8, KS = CIN / 32;
+    using S = WaveSplit<COUT>;
+    constexpr int RW = S::RW, MT = S::MT;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int mg = wave % S::MG, ng = wave / S::MG;
+    const int r = lane & 15, q = lane >> 4;
+    f32x4 acc[MT];
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi) acc[mi] = f32x4{0, 0, 0, 0};
+    constexpr int NS = 2 * (RW + 2);
+    bf16x8 fr[2][3][KS];
+    auto load_stage = [&](int st, bf16x8 (&f)[3][KS]) {
+        const int py = st >> 1, half = st & 1;
+#pragma unroll
+        for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                f[dxi][ks] = ld8(patch + ((RW * mg + py) * kPatchW + 16 * half + r + dxi) * PS + 32 * ks + 8 * q);
+    };
+    load_stage(0, fr[0]);
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+        if (st + 1 < NS) load_stage(st + 1, fr[(st + 1) & 1]);
+        const int py = st >> 1, half = st & 1;
+#pragma unroll
+        for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int rho = 0; rho < RW; ++rho) {
+                    const int dyi = py - rho;  // tap row index dy + 1
+                    if (dyi < 0 || dyi > 2) continue;
+                    acc[2 * rho + half] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 * dyi + dxi][ks], fr[st & 1][dxi][ks],
+                                                                                  acc[2 * rho + half], 0, 0, 0);
+                }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // D[co][pixel]: lane (r, q) holds channels 16 ng + 4 q .. + 3 of pixel r of each tile
+    const int c0 = 16 * ng + 4 * q;
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi) {
+        const int yy = tc.y0 + RW * mg + (mi >> 1), xx = tc.x0 + 16 * (mi & 1) + r;
+        if (yy >= H || xx >= W) continue;
+        const size_t p = ((size_t)tc.n * H + yy) * W + xx;
+        if (MODE == 1 || MODE == 3) {
+            if (c0 == 0) {  // the 4 state channels are those of the q = 0 lanes of the first channel group
+                static_assert(kStateC == 4, "one lane holds the four state channels of a pixel");
+                const f32x4 rs = *(const f32x4 *)(o.resid + p * kStateC);
+                f32x4 v;
+                v[0] = rs[0] + o.alpha0 * (acc[mi][0] + bias[0]);
+                v[1] = rs[1] + o.alpha1 * (acc[mi][1] + bias[1]);
+                v[2] = rs[2] + o.alpha2 * (acc[mi][2] + bias[2]);
+                v[3] = rs[3] + o.alpha3 * (acc[mi][3] + bias[3]);
+                if (MODE == 1) {
+                    *(f32x4 *)(o.Yf + p * kStateC) = v;
+                } else {
+                    o.phi[p] = v[0];
+                    o.ux[p] = v[1] * o.u_scale;
+                    o.uy[p] = v[2] * o.u_scale;
+                    o.rho[p] = 1.0 + v[3] * o.r_scale;
+                }
+            }
+        } else {
+            bf16x4 m4 = {};
+            if (MODE == 2) m4 = __builtin_bit_cast(bf16x4, *(const u32x2 *)(o.mask + p * COUT + c0));
+            bf16x4 v4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float v = acc[mi][e] + bias[e];
+                v4[e] = (__bf16)(MODE == 2 ? (((float)m4[e] > 0.f) ? v : 0.f) : fmaxf(v, 0.f));
+            }
+            *(u32x2 *)(o.Y + p * COUT + c0) = __builtin_bit_cast(u32x2, v4);
+        }
+    }
+}
+
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wp, OutArgs o,
                                                        int ntiles, int H, int W)
 {
     using Lds = ConvLds<CIN, COUT>;
-    constexpr int PS = Lds::PS, WS = Lds::WS;
-    static_assert(PS == Patch<CIN>::PS, "patch stride");
-    constexpr int KS = CIN / 32;      // K-steps per tap
-    constexpr int NG = COUT / 16;     // channel groups (one 16-channel tile each)
-    constexpr int MG = 8 / NG;        // row groups
-    constexpr int RW = kTileH / MG;   // tile rows per wave
-    constexpr int MT = 2 * RW;        // pixel tiles (16 pixels) per wave
+    constexpr int WS = Lds::WS;
+    static_assert(Lds::PS == Patch<CIN>::PS, "patch stride");
+    constexpr int KS = CIN / 32;  // K-steps per tap
+    using S = WaveSplit<COUT>;
     __bf16 *patch = lbcm_conv_lds, *wl = lbcm_conv_lds + Lds::patch_elems;
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int mg = wave % MG, ng = wave / MG;
+    const int ng = wave / S::MG;
     const int r = lane & 15, q = lane >> 4;
     const int cbase = 16 * ng;
 
@@ -387,7 +476,6 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
     Patch<CIN> pre;
     pre.load(X, tile_coord(tile, H, W), H, W);
     __syncthreads();
-    // A fragments: lane (r, q) holds W[t][co = cbase + r][ci = 32 ks + 8 q .. + 8]
     bf16x8 wa[9][KS];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
@@ -404,22 +492,100 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
         pre.store(patch);
         __syncthreads();
         if (tile + (int)gridDim.x < ntiles) pre.load(X, tile_coord(tile + gridDim.x, H, W), H, W);
-        f32x4 acc[MT];
+        conv_tile<CIN, COUT, MODE>(patch, wa, bias, tc, o, H, W);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Two consecutive 64-channel conv layers in one pass (inference): Z = bf16(relu(ba + conv(X, Wa)))
+// and then layer b on Z as k_conv does (MODE 0: bf16 ReLU output; MODE 3: the last layer into the
+// FP64 planes), one 8 x 32 output tile per workgroup.  Z never leaves LDS: the workgroup stages
+// the 12 x 36 input patch (tile plus a two-pixel circular halo), computes Z on the tile plus a
+// one-pixel halo (10 x 34) and runs layer b from there, recomputing the halo ring of Z that the
+// neighbouring tiles also compute.  Every output sums its taps in the same order as k_conv, so
+// the result equals two k_conv launches bit for bit.
+//
+// Layer a: wave (mg, ng) computes channels [16 ng, 16 ng + 16) of Z rows [5 mg, 5 mg + 5) at Z
+// columns 1 .. 32 (ten 16-pixel blocks, input-stationary as in conv_tile) and of Z column 0
+// (mg = 0) or 33 (mg = 1), rows 0 .. 9 (one block whose lanes gather their pixels; lanes 10 .. 15
+// repeat row 9 and store nothing).  Its A fragments come straight from global memory (L2), and so
+// do layer b's (loaded after layer a: requested earlier they slowed the kernel down), so LDS holds
+// only the two patches.
+
+struct PairLds {
+    static constexpr int C = 64, PS = C + 8;
+    static constexpr int XH = kTileH + 4, XW = kTileW + 4;  // input patch
+    static constexpr int ZH = kTileH + 2, ZW = kTileW + 2;  // intermediate
+    static constexpr int x_elems = XH * XW * PS, z_elems = ZH * ZW * PS;
+    static constexpr size_t bytes = (size_t)(x_elems + z_elems) * sizeof(__bf16);
+};
+static_assert(PairLds::ZW == kPatchW && PairLds::ZH == kPatchH, "layer b reads Z as a conv patch");
+
+template <int KS>
+__device__ __forceinline__ void load_frags(const __bf16 *__restrict__ Wp, int cout, int co, int q, bf16x8 (&wa)[9][KS])
+{
 #pragma unroll
-        for (int mi = 0; mi < MT; ++mi) acc[mi] = f32x4{0, 0, 0, 0};
-        // input-stationary order: each pixel fragment of the wave's RW + 2 patch rows is read from
-        // LDS once and applied to every output row (tap dy) that uses it.  Stage s covers patch
-        // row s / 2 and column half s % 2 (3 horizontal taps x KS fragments); the fragments of
-        // stage s + 1 are read before the MFMAs of stage s, in a second register buffer.
-        constexpr int NS = 2 * (RW + 2);
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) wa[t][ks] = ld8(Wp + ((size_t)t * cout + co) * (32 * KS) + 32 * ks + 8 * q);
+}
+
+template <int COUT, int MODE>
+__global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wa,
+                                                       const float *__restrict__ ba, const __bf16 *__restrict__ Wb, OutArgs o,
+                                                       int ntiles, int H, int W)
+{
+    using L = PairLds;
+    constexpr int C = L::C, PS = L::PS, KS = C / 32, XW = L::XW, ZW = L::ZW;
+    __bf16 *xs = lbcm_conv_lds, *zs = lbcm_conv_lds + L::x_elems;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = lane & 15, q = lane >> 4;
+    const int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const TileCoord tc = tile_coord(tile, H, W);
+    {
+        constexpr int NV = L::XH * XW * (C / 8), NI = (NV + kConvThreads - 1) / kConvThreads;
+        const __bf16 *Xn = X + (size_t)tc.n * H * W * C;
+        u32x4 v[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kConvThreads;
+            if (k < NV) {
+                const int px = k / (C / 8), ch = (k % (C / 8)) * 8;
+                const int gy = wrap(tc.y0 - 2 + px / XW, H), gx = wrap(tc.x0 - 2 + px % XW, W);
+                v[i] = *(const u32x4 *)(Xn + ((size_t)gy * W + gx) * C + ch);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kConvThreads;
+            if (k < NV) *(u32x4 *)(xs + (k / (C / 8)) * PS + (k % (C / 8)) * 8) = v[i];
+        }
+    }
+    const int mg = wave & 1, ng = wave >> 1;
+    using S = WaveSplit<COUT>;
+    const int ngb = wave / S::MG;
+    bf16x8 wa[9][KS], wb[9][KS];
+    load_frags<KS>(Wa, C, 16 * ng + r, q, wa);
+    float bias[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bias[e] = ba[16 * ng + 4 * q + e];
+    __syncthreads();
+    {
+        // Z rows 5 mg + rho (rho < 5) at Z columns 1 + 16 half + r: X rows 5 mg + rho + dyi,
+        // X columns 1 + 16 half + r + dxi
+        constexpr int RW = 5, NS = 2 * (RW + 2);
+        f32x4 acc[2 * RW];
+#pragma unroll
+        for (int mi = 0; mi < 2 * RW; ++mi) acc[mi] = f32x4{0, 0, 0, 0};
         bf16x8 fr[2][3][KS];
         auto load_stage = [&](int st, bf16x8 (&f)[3][KS]) {
-            const int py = st >> 1, half = st & 1;
+            const int xr = RW * mg + (st >> 1), half = st & 1;
 #pragma unroll
             for (int dxi = 0; dxi < 3; ++dxi)
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-                    f[dxi][ks] = ld8(patch + ((RW * mg + py) * kPatchW + 16 * half + r + dxi) * PS + 32 * ks + 8 * q);
+                for (int ks = 0; ks < KS; ++ks) f[dxi][ks] = ld8(xs + (xr * XW + 1 + 16 * half + r + dxi) * PS + 32 * ks + 8 * q);
         };
         load_stage(0, fr[0]);
 #pragma unroll
@@ -432,44 +598,124 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
                 for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
                     for (int rho = 0; rho < RW; ++rho) {
-                        const int dyi = py - rho;  // tap row index dy + 1
+                        const int dyi = py - rho;
                         if (dyi < 0 || dyi > 2) continue;
                         acc[2 * rho + half] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 * dyi + dxi][ks], fr[st & 1][dxi][ks],
                                                                                       acc[2 * rho + half], 0, 0, 0);
                     }
             __builtin_amdgcn_sched_barrier(0);
         }
-        // D[co][pixel]: lane (r, q) holds channels cbase + 4 q .. + 3 of pixel r of each tile
-        const int c0 = cbase + 4 * q;
+        // the edge column of Z
+        const int zr = r < L::ZH ? r : L::ZH - 1, zc = mg ? ZW - 1 : 0;
+        f32x4 ae = f32x4{0, 0, 0, 0};
 #pragma unroll
-        for (int mi = 0; mi < MT; ++mi) {
-            const int yy = tc.y0 + RW * mg + (mi >> 1), xx = tc.x0 + 16 * (mi & 1) + r;
-            if (yy >= H || xx >= W) continue;
-            const size_t p = ((size_t)tc.n * H + yy) * W + xx;
-            if (MODE == 1) {
-                if (c0 == 0) {  // the 4 state channels are those of the q = 0 lanes of the first channel group
-                    static_assert(kStateC == 4, "one lane holds the four state channels of a pixel");
-                    const f32x4 rs = *(const f32x4 *)(o.resid + p * kStateC);
-                    f32x4 v;
-                    v[0] = rs[0] + o.alpha0 * (acc[mi][0] + bias[0]);
-                    v[1] = rs[1] + o.alpha1 * (acc[mi][1] + bias[1]);
-                    v[2] = rs[2] + o.alpha2 * (acc[mi][2] + bias[2]);
-                    v[3] = rs[3] + o.alpha3 * (acc[mi][3] + bias[3]);
-                    *(f32x4 *)(o.Yf + p * kStateC) = v;
-                }
-            } else {
-                bf16x4 m4 = {};
-                if (MODE == 2) m4 = __builtin_bit_cast(bf16x4, *(const u32x2 *)(o.mask + p * COUT + c0));
-                bf16x4 v4;
+        for (int t = 0; t < 9; ++t)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float v = acc[mi][e] + bias[e];
-                    v4[e] = (__bf16)(MODE == 2 ? (((float)m4[e] > 0.f) ? v : 0.f) : fmaxf(v, 0.f));
-                }
-                *(u32x2 *)(o.Y + p * COUT + c0) = __builtin_bit_cast(u32x2, v4);
-            }
-        }
+            for (int ks = 0; ks < KS; ++ks)
+                ae = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    wa[t][ks], ld8(xs + ((zr + t / 3) * XW + zc + t % 3) * PS + 32 * ks + 8 * q), ae, 0, 0, 0);
+        auto zstore = [&](int y, int x, const f32x4 &a) {
+            bf16x4 v4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v4[e] = (__bf16)fmaxf(a[e] + bias[e], 0.f);
+            *(u32x2 *)(zs + (y * ZW + x) * PS + 16 * ng + 4 * q) = __builtin_bit_cast(u32x2, v4);
+        };
+#pragma unroll
+        for (int mi = 0; mi < 2 * RW; ++mi) zstore(RW * mg + (mi >> 1), 1 + 16 * (mi & 1) + r, acc[mi]);
+        if (r < L::ZH) zstore(zr, zc, ae);
     }
+    // layer b
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bias[e] = o.bias[16 * ngb + 4 * q + e];
+    load_frags<KS>(Wb, COUT, 16 * ngb + r, q, wb);
+    __syncthreads();
+    conv_tile<C, COUT, MODE>(zs, wb, bias, tc, o, H, W);
+}
+
+// Layers 0 and 1 in one pass (inference): layer 0 as k_first (FP32 MFMA, the bias as the starting
+// sum, taps in order) on the tile plus a one-pixel halo, kept in LDS as bf16(relu), then layer 1
+// on it as k_conv does (MODE 0), one 8 x 32 tile per workgroup; bit for bit the result of k_first
+// and one k_conv launch.  The FP32 state patch covers the tile plus a two-pixel halo; with PLANES
+// it is read from the FP64 field planes (the tile's own state also goes to s_out).  The wave
+// split of layer 0 over the 10 x 34 intermediate is that of k_pair's layer a.
+template <bool PLANES>
+__global__ __launch_bounds__(kConvThreads) void k_first_pair(const float *__restrict__ s, PlaneIn pin, float *__restrict__ s_out,
+                                                             const float *__restrict__ W0, const float *__restrict__ b0,
+                                                             const __bf16 *__restrict__ W1, OutArgs o, int ntiles, int H, int W)
+{
+    using L = PairLds;
+    constexpr int C = L::C, KS = C / 32, XH = L::XH, XW = L::XW, ZW = L::ZW;
+    __shared__ __align__(16) float sp[XH * XW * kStateC];
+    __bf16 *zs = lbcm_conv_lds;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = lane & 15, q = lane >> 4;
+    const int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const TileCoord tc = tile_coord(tile, H, W);
+    for (int k = threadIdx.x; k < XH * XW; k += kConvThreads) {
+        const int py = k / XW, px = k % XW;
+        const int gy = wrap(tc.y0 - 2 + py, H), gx = wrap(tc.x0 - 2 + px, W);
+        const size_t p = ((size_t)tc.n * H + gy) * W + gx;
+        f32x4 v;
+        if constexpr (PLANES) {
+            v[0] = (float)pin.phi[p];
+            v[1] = (float)pin.ux[p] * pin.inv_u;
+            v[2] = (float)pin.uy[p] * pin.inv_u;
+            v[3] = (float)(pin.rho[p] - 1.0) * pin.inv_r;
+            if (py >= 2 && py < 2 + kTileH && px >= 2 && px < 2 + kTileW && tc.y0 + py - 2 < H && tc.x0 + px - 2 < W)
+                *(f32x4 *)(s_out + p * kStateC) = v;
+        } else {
+            v = *(const f32x4 *)(s + p * kStateC);
+        }
+        *(f32x4 *)(sp + k * kStateC) = v;
+    }
+    const int mg = wave & 1, ng = wave >> 1;
+    float w0[9];  // A operand at tap t: lane (r, q) holds W0[t][ci = q][co = 16 ng + r]
+#pragma unroll
+    for (int t = 0; t < 9; ++t) w0[t] = W0[(kStateC * t + q) * C + 16 * ng + r];
+    float bias0[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bias0[e] = b0[16 * ng + 4 * q + e];
+    bf16x8 w1[9][KS];
+    load_frags<KS>(W1, C, 16 * ng + r, q, w1);
+    __syncthreads();
+    {
+        // Z rows 5 mg + rho at Z columns 1 + 16 half + r, and the edge column of Z (lanes 10 .. 15
+        // repeat row 9); Z (zr, zc) reads the patch at (zr + dy + 1, zc + dx + 1)
+        constexpr int RW = 5;
+        const int zr = r < L::ZH ? r : L::ZH - 1, zc = mg ? ZW - 1 : 0;
+        f32x4 acc[2 * RW + 1];
+#pragma unroll
+        for (int mi = 0; mi <= 2 * RW; ++mi)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[mi][e] = bias0[e];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dyi = t / 3, dxi = t % 3;
+#pragma unroll
+            for (int mi = 0; mi < 2 * RW; ++mi) {
+                const float x = sp[((RW * mg + (mi >> 1) + dyi) * XW + 1 + 16 * (mi & 1) + r + dxi) * kStateC + q];
+                acc[mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(w0[t], x, acc[mi], 0, 0, 0);
+            }
+            const float x = sp[((zr + dyi) * XW + zc + dxi) * kStateC + q];
+            acc[2 * RW] = __builtin_amdgcn_mfma_f32_16x16x4f32(w0[t], x, acc[2 * RW], 0, 0, 0);
+        }
+        auto zstore = [&](int y, int x, const f32x4 &a) {
+            bf16x4 v4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v4[e] = (__bf16)fmaxf(a[e], 0.f);
+            *(u32x2 *)(zs + (y * ZW + x) * L::PS + 16 * ng + 4 * q) = __builtin_bit_cast(u32x2, v4);
+        };
+#pragma unroll
+        for (int mi = 0; mi < 2 * RW; ++mi) zstore(RW * mg + (mi >> 1), 1 + 16 * (mi & 1) + r, acc[mi]);
+        if (r < L::ZH) zstore(zr, zc, acc[2 * RW]);
+    }
+    float bias1[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bias1[e] = o.bias[16 * ng + 4 * q + e];
+    __syncthreads();
+    conv_tile<C, C, 0>(zs, w1, bias1, tc, o, H, W);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -640,7 +886,7 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 }
 
 // state planes (FP64, [B][H][W] each) -> FP32 [P][4] = (phi, v_x / u_scale, v_y / u_scale,
-// (rho - 1) / rho_scale), and back
+// (rho - 1) / rho_scale)
 __global__ void k_from_planes(const double *__restrict__ phi, const double *__restrict__ ux, const double *__restrict__ uy,
                               const double *__restrict__ rho, float inv_u, float inv_r, uint32_t P, float *__restrict__ s)
 {
@@ -651,18 +897,6 @@ __global__ void k_from_planes(const double *__restrict__ phi, const double *__re
         v[2] = (float)uy[p] * inv_u;
         v[3] = (float)(rho[p] - 1.0) * inv_r;
         *(f32x4 *)(s + (size_t)p * kStateC) = v;
-    }
-}
-
-__global__ void k_to_planes(const float *__restrict__ s, double u_scale, double r_scale, uint32_t P, double *__restrict__ phi,
-                            double *__restrict__ ux, double *__restrict__ uy, double *__restrict__ rho)
-{
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
-        const f32x4 v = *(const f32x4 *)(s + (size_t)p * kStateC);
-        phi[p] = v[0];
-        ux[p] = v[1] * u_scale;
-        uy[p] = v[2] * u_scale;
-        rho[p] = 1.0 + v[3] * r_scale;
     }
 }
 
@@ -746,6 +980,13 @@ int grid_of(size_t n, int threads)
     return (int)std::max<size_t>(1, std::min<size_t>(b, 65535));
 }
 
+// FP64 field planes in and out of one forward pass
+struct PlaneIO {
+    PlaneIn in;
+    double *phi, *ux, *uy, *rho;
+    double u_scale, r_scale;
+};
+
 template <int CI, int CO, int MO>
 int launch_conv_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wp, const OutArgs &o)
 {
@@ -762,14 +1003,41 @@ int launch_conv_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wp, const OutArgs 
     return LBCM_OK;
 }
 
+template <int CO, int MO>
+int launch_pair_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wa, const float *ba, const __bf16 *Wb, const OutArgs &o)
+{
+    constexpr size_t bytes = PairLds::bytes;
+    static bool attr = false;
+    if (!attr) {
+        NHIP(n, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pair<CO, MO>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)bytes));
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_pair<CO, MO>), dim3(n->ntiles), dim3(kConvThreads), bytes, n->stream, X, Wa, ba, Wb, o, n->ntiles, n->H,
+                       n->W);
+    NHIP(n, hipGetLastError());
+    return LBCM_OK;
+}
+
+int launch_first_pair(lbcm_net *n, const PlaneIO *io, const OutArgs &o)
+{
+    constexpr size_t bytes = (size_t)PairLds::z_elems * sizeof(__bf16);
+    hipLaunchKernelGGL((k_first_pair<true>), dim3(n->ntiles), dim3(kConvThreads), bytes, n->stream, nullptr, io->in, n->resid,
+                       n->params + n->w_off[0], n->params + n->b_off[0], n->Wf[1], o, n->ntiles, n->H, n->W);
+    NHIP(n, hipGetLastError());
+    return LBCM_OK;
+}
+
 int launch_conv(lbcm_net *n, const __bf16 *X, int cin, const __bf16 *Wp, int cout, int mode, const OutArgs &o)
 {
     if (cin == 64 && cout == 64 && mode == 0) return launch_conv_t<64, 64, 0>(n, X, Wp, o);
     if (cin == 64 && cout == 64 && mode == 2) return launch_conv_t<64, 64, 2>(n, X, Wp, o);
     if (cin == 64 && cout == 32 && mode == 1) return launch_conv_t<64, 32, 1>(n, X, Wp, o);
+    if (cin == 64 && cout == 32 && mode == 3) return launch_conv_t<64, 32, 3>(n, X, Wp, o);
     if (cin == 32 && cout == 64 && mode == 2) return launch_conv_t<32, 64, 2>(n, X, Wp, o);
     if (cin == 32 && cout == 32 && mode == 0) return launch_conv_t<32, 32, 0>(n, X, Wp, o);
     if (cin == 32 && cout == 32 && mode == 1) return launch_conv_t<32, 32, 1>(n, X, Wp, o);
+    if (cin == 32 && cout == 32 && mode == 3) return launch_conv_t<32, 32, 3>(n, X, Wp, o);
     if (cin == 32 && cout == 32 && mode == 2) return launch_conv_t<32, 32, 2>(n, X, Wp, o);
     return nfail(n, LBCM_EINVAL, "unsupported channel counts");
 }
@@ -785,34 +1053,77 @@ int pack_all(lbcm_net *n)
     return LBCM_OK;
 }
 
-// forward from the FP32 state in n->resid ([P][kStateC]); result in n->out
-int forward(lbcm_net *n)
+
+template <int C>
+void launch_first(lbcm_net *n, const PlaneIO *io)
+{
+    const dim3 g(n->ntiles), b(kFirstThreads);
+    const float *W0 = n->params + n->w_off[0], *b0 = n->params + n->b_off[0];
+    if (io)
+        hipLaunchKernelGGL((k_first<C, true>), g, b, 0, n->stream, nullptr, io->in, n->resid, W0, b0, n->H, n->W, n->act[1]);
+    else
+        hipLaunchKernelGGL((k_first<C, false>), g, b, 0, n->stream, n->resid, PlaneIn{}, nullptr, W0, b0, n->H, n->W, n->act[1]);
+}
+
+// forward from the FP32 state in n->resid ([P][kStateC]) into n->out, or with io from and into
+// FP64 field planes (the input state is then also left in n->resid)
+int forward(lbcm_net *n, const PlaneIO *io = nullptr)
 {
     if (!n->packed) {
         int rc = pack_all(n);
         if (rc) return rc;
     }
-    const dim3 g1(n->ntiles), b1(kFirstThreads);
-    if (n->C == 64)
-        hipLaunchKernelGGL(k_first<64>, g1, b1, 0, n->stream, n->resid, n->params + n->w_off[0], n->params + n->b_off[0], n->H,
-                           n->W, n->act[1]);
-    else
-        hipLaunchKernelGGL(k_first<32>, g1, b1, 0, n->stream, n->resid, n->params + n->w_off[0], n->params + n->b_off[0], n->H,
-                           n->W, n->act[1]);
-    NHIP(n, hipGetLastError());
-    for (int l = 1; l < n->L; ++l) {
-        const bool last = l == n->L - 1;
+    // output arguments of a launch whose last layer is lb
+    auto out_args = [&](int lb) {
+        const bool last = lb == n->L - 1;
         OutArgs o{};
-        o.bias = n->params + n->b_off[l];
-        o.Y = last ? nullptr : n->act[l + 1];
+        o.bias = n->params + n->b_off[lb];
+        o.Y = last ? nullptr : n->act[lb + 1];
         o.resid = n->resid;
         o.Yf = n->out;
         o.alpha0 = n->alpha[0];
         o.alpha1 = n->alpha[1];
         o.alpha2 = n->alpha[2];
         o.alpha3 = n->alpha[3];
-        int rc = launch_conv(n, n->act[l], n->cin[l], n->Wf[l], n->cout[l], last ? 1 : 0, o);
+        if (io) {
+            o.phi = io->phi;
+            o.ux = io->ux;
+            o.uy = io->uy;
+            o.rho = io->rho;
+            o.u_scale = io->u_scale;
+            o.r_scale = io->r_scale;
+        }
+        return o;
+    };
+    // inference from planes with 64 channels runs the layers in fused pairs (the activation
+    // between the two layers of a pair stays in LDS): layers 0 and 1, then 2 and 3, ..., and a
+    // last single layer if one is left
+    const bool pairs = io && n->C == 64;
+    int l = 1;
+    if (pairs && n->L > 2) {
+        int rc = launch_first_pair(n, io, out_args(1));
         if (rc) return rc;
+        l = 2;
+    } else {
+        if (n->C == 64)
+            launch_first<64>(n, io);
+        else
+            launch_first<32>(n, io);
+        NHIP(n, hipGetLastError());
+    }
+    while (l < n->L) {
+        const bool paired = pairs && l + 1 < n->L;
+        const int lb = paired ? l + 1 : l;  // the layer that writes the output
+        const bool last = lb == n->L - 1;
+        const OutArgs o = out_args(lb);
+        int rc;
+        if (paired)
+            rc = last ? launch_pair_t<kOutC, 3>(n, n->act[l], n->Wf[l], n->params + n->b_off[l], n->Wf[lb], o)
+                      : launch_pair_t<64, 0>(n, n->act[l], n->Wf[l], n->params + n->b_off[l], n->Wf[lb], o);
+        else
+            rc = launch_conv(n, n->act[l], n->cin[l], n->Wf[l], n->cout[l], last ? (io ? 3 : 1) : 0, o);
+        if (rc) return rc;
+        l = lb + 1;
     }
     return LBCM_OK;
 }
@@ -955,15 +1266,9 @@ int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, co
 {
     if (!n || !phi || !ux || !uy || !rho || !phi_out || !ux_out || !uy_out || !rho_out || !(u_scale > 0) || !(rho_scale > 0))
         return LBCM_EINVAL;
-    hipLaunchKernelGGL(k_from_planes, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, phi, ux, uy, rho, (float)(1.0 / u_scale),
-                       (float)(1.0 / rho_scale), n->P, n->resid);
-    NHIP(n, hipGetLastError());
-    int rc = forward(n);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_to_planes, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, n->out, u_scale, rho_scale, n->P, phi_out,
-                       ux_out, uy_out, rho_out);
-    NHIP(n, hipGetLastError());
-    return LBCM_OK;
+    const PlaneIO io{{phi, ux, uy, rho, (float)(1.0 / u_scale), (float)(1.0 / rho_scale)}, phi_out, ux_out, uy_out, rho_out,
+                     u_scale, rho_scale};
+    return forward(n, &io);
 }
 
 int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, const double *rho,
@@ -1081,10 +1386,18 @@ struct lbcm_hybrid {
     double u_scale = 1, rho_scale = 1, threshold = 0, vthreshold = 0;
     uint32_t P = 0;
     double *start = nullptr, *a = nullptr, *b = nullptr;  // (phi, v_x, v_y, rho) planes
-    double *lb = nullptr;                                 // the check's lattice Boltzmann (phi, v_x, v_y)
+    double *lb = nullptr;                                 // the check's lattice Boltzmann fields (same planes)
     double *err_partial = nullptr;
+    double *err_host = nullptr;       // pinned copy of the partial sums
+    hipEvent_t err_ready = nullptr;   // recorded after that copy
     int64_t cooldown = 0;  // plain windows still to run after failed checks
     int streak = 0;        // consecutive failed checks
+    // Within one lbcm_hybrid_advance call, after an accepted check: the next window starts from
+    // the check's lattice fields (lb, equal to those of the caller's lattice after the copy), and
+    // its first `spec_done` jumps were launched before the decision, the last into spec_cur.
+    bool start_ready = false;
+    int spec_done = 0;
+    double *spec_cur = nullptr;
     lbcm_hybrid_stats st{};
     std::string err;
 };
@@ -1111,18 +1424,26 @@ int hfail(lbcm_hybrid *h, int code, const std::string &m)
 double *plane(double *base, uint32_t P, int k) { return base + (size_t)k * P; }
 
 // the four check sums of k_err_partial, read back (synchronises)
-int check_sums(lbcm_hybrid *h, const double *x, const double *ref, double (&sum)[kErrSums])
+// the check's FP64 partial sums: k_err_partial, then an asynchronous copy into pinned host memory
+// and an event; wait_sums waits for that event only (work queued after it keeps the GPU busy)
+int launch_sums(lbcm_hybrid *h, const double *x, const double *ref)
 {
     hipStream_t s = h->net->stream;
     hipLaunchKernelGGL(k_err_partial, dim3(kErrBlocks), dim3(256), 0, s, x, ref, h->P, h->err_partial);
     if (hipGetLastError() != hipSuccess) return hfail(h, LBCM_EHIP, "k_err_partial launch failed");
-    double part[kErrSums * kErrBlocks];
-    if (hipMemcpyAsync(part, h->err_partial, sizeof(part), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return hfail(h, LBCM_EHIP, "reading the error sums failed");
+    if (hipMemcpyAsync(h->err_host, h->err_partial, kErrSums * kErrBlocks * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipEventRecord(h->err_ready, s) != hipSuccess)
+        return hfail(h, LBCM_EHIP, "queueing the error sums failed");
+    return LBCM_OK;
+}
+
+int wait_sums(lbcm_hybrid *h, double (&sum)[kErrSums])
+{
+    if (hipEventSynchronize(h->err_ready) != hipSuccess) return hfail(h, LBCM_EHIP, "reading the error sums failed");
     for (int k = 0; k < kErrSums; ++k) sum[k] = 0;
     for (int i = 0; i < kErrBlocks; ++i)
-        for (int k = 0; k < kErrSums; ++k) sum[k] += part[i * kErrSums + k];
+        for (int k = 0; k < kErrSums; ++k) sum[k] += h->err_host[i * kErrSums + k];
     return LBCM_OK;
 }
 
@@ -1134,28 +1455,46 @@ double rel_l2(double d2, double r2)
     return r2 > 0 ? std::sqrt(d2 / r2) : (d2 > 0 ? INFINITY : 0.0);
 }
 
-// one window of J * K lattice steps
-int hybrid_window(lbcm_hybrid *h)
+// jumps of the next window launched before a check's decision (they hide the wait for it)
+constexpr int kSpecJumps = 2;
+
+// one window of J * K lattice steps; `more`: another window follows in this advance call
+int hybrid_window(lbcm_hybrid *h, bool more)
 {
     const uint32_t P = h->P;
     const int64_t span = (int64_t)h->J * h->K;
     if (h->cooldown > 0) {  // plain lattice Boltzmann window after failed checks
+        h->start_ready = false;
+        h->spec_done = 0;
         HLAT(h, lbcm_step(h->lat, span), "lbcm_step");
         h->st.lb_steps_run += span;
         h->st.steps += span;
         h->cooldown -= 1;
         return LBCM_OK;
     }
-    double *x = h->a, *y = h->b;
     auto pl = [&](double *base, int k) { return plane(base, P, k); };
-    HLAT(h, lbcm_fields_device(h->lat, pl(h->start, 0), pl(h->start, 3), pl(h->start, 1), pl(h->start, 2), nullptr),
-         "lbcm_fields_device");
-    double *cur = h->start;
     auto jump = [&](double *in, double *outp) {
         return lbcm_net_forward_planes(h->net, pl(in, 0), pl(in, 1), pl(in, 2), pl(in, 3), h->u_scale, h->rho_scale, pl(outp, 0),
                                        pl(outp, 1), pl(outp, 2), pl(outp, 3));
     };
-    for (int j = 0; j < h->J - 1; ++j) {  // J - 1 surrogate jumps
+    double *cur, *x = h->a, *y = h->b;
+    int done = 0;
+    if (h->start_ready) {
+        cur = h->lb;
+        if (h->spec_done > 0) {
+            cur = h->spec_cur;
+            done = h->spec_done;
+            x = cur;
+            y = cur == h->a ? h->b : h->a;
+        }
+    } else {
+        HLAT(h, lbcm_fields_device(h->lat, pl(h->start, 0), pl(h->start, 3), pl(h->start, 1), pl(h->start, 2), nullptr),
+             "lbcm_fields_device");
+        cur = h->start;
+    }
+    h->start_ready = false;
+    h->spec_done = 0;
+    for (int j = done; j < h->J - 1; ++j) {  // J - 1 surrogate jumps
         HNET(h, jump(cur, y), "lbcm_net_forward_planes");
         cur = y;
         std::swap(x, y);
@@ -1165,9 +1504,21 @@ int hybrid_window(lbcm_hybrid *h)
     HNET(h, jump(cur, y), "lbcm_net_forward_planes");
     HSCR(h, lbcm_init_device(h->scratch, pl(cur, 0), pl(cur, 3), pl(cur, 1), pl(cur, 2)), "lbcm_init_device");
     HSCR(h, lbcm_step(h->scratch, h->K), "lbcm_step");
-    HSCR(h, lbcm_fields_device(h->scratch, pl(h->lb, 0), nullptr, pl(h->lb, 1), pl(h->lb, 2), nullptr), "lbcm_fields_device");
+    HSCR(h, lbcm_fields_device(h->scratch, pl(h->lb, 0), pl(h->lb, 3), pl(h->lb, 1), pl(h->lb, 2), nullptr),
+         "lbcm_fields_device");
+    int rc = launch_sums(h, y, h->lb);
+    if (rc) return rc;
+    // the next window's first jumps, from the check's lattice state, while the sums travel; kept
+    // only if the check accepts (x and y are free once the sums are queued)
+    const int spec = more ? std::min(kSpecJumps, h->J - 1) : 0;
+    double *sc = h->lb;
+    for (int j = 0; j < spec; ++j) {
+        double *o = (j & 1) ? h->b : h->a;
+        HNET(h, jump(sc, o), "lbcm_net_forward_planes");
+        sc = o;
+    }
     double sum[kErrSums];
-    int rc = check_sums(h, y, h->lb, sum);
+    rc = wait_sums(h, sum);
     if (rc) return rc;
     const double e = rel_l2(sum[0], sum[1]), ev = rel_l2(sum[2], sum[3]);
     h->st.checks += 1;
@@ -1178,7 +1529,7 @@ int hybrid_window(lbcm_hybrid *h)
     if (!ok) {
         // rejected: the caller's lattice still holds the window's starting populations; run the
         // window with the plain step from there, then 2^(k-1) more plain windows (at most 16)
-        // after k failures in a row
+        // after k failures in a row; the speculative jumps are dropped
         h->st.failed_checks += 1;
         HLAT(h, lbcm_step(h->lat, span), "lbcm_step");
         h->st.lb_steps_run += h->K + span;
@@ -1191,6 +1542,9 @@ int hybrid_window(lbcm_hybrid *h)
         h->st.max_accepted_error = std::max(h->st.max_accepted_error, e);
         h->st.max_accepted_velocity_error = std::max(h->st.max_accepted_velocity_error, ev);
         h->streak = 0;
+        h->start_ready = more;
+        h->spec_done = spec;
+        h->spec_cur = sc;
     }
     h->st.steps += span;
     return LBCM_OK;
@@ -1245,8 +1599,10 @@ int lbcm_hybrid_create(lbcm_handle *lattice, lbcm_net *net, int32_t steps_per_ju
     }
     const size_t pb = (size_t)h->P * sizeof(double);
     if (hipMalloc((void **)&h->start, 4 * pb) != hipSuccess || hipMalloc((void **)&h->a, 4 * pb) != hipSuccess ||
-        hipMalloc((void **)&h->b, 4 * pb) != hipSuccess || hipMalloc((void **)&h->lb, 3 * pb) != hipSuccess ||
-        hipMalloc((void **)&h->err_partial, kErrSums * kErrBlocks * sizeof(double)) != hipSuccess) {
+        hipMalloc((void **)&h->b, 4 * pb) != hipSuccess || hipMalloc((void **)&h->lb, 4 * pb) != hipSuccess ||
+        hipMalloc((void **)&h->err_partial, kErrSums * kErrBlocks * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&h->err_host, kErrSums * kErrBlocks * sizeof(double)) != hipSuccess ||
+        hipEventCreateWithFlags(&h->err_ready, hipEventDisableTiming) != hipSuccess) {
         g_hybrid_error = "out of device memory";
         lbcm_hybrid_destroy(h);
         return LBCM_ENOMEM;
@@ -1258,8 +1614,10 @@ int lbcm_hybrid_create(lbcm_handle *lattice, lbcm_net *net, int32_t steps_per_ju
 int lbcm_hybrid_advance(lbcm_hybrid *h, int64_t windows)
 {
     if (!h || windows < 0) return LBCM_EINVAL;
+    h->start_ready = false;  // the caller may have changed the lattice since the last call
+    h->spec_done = 0;
     for (int64_t w = 0; w < windows; ++w) {
-        int rc = hybrid_window(h);
+        int rc = hybrid_window(h, w + 1 < windows);
         if (rc) return rc;
     }
     return LBCM_OK;
@@ -1279,6 +1637,8 @@ int lbcm_hybrid_destroy(lbcm_hybrid *h)
     else (void)hipDeviceSynchronize();
     for (void *q : {(void *)h->start, (void *)h->a, (void *)h->b, (void *)h->lb, (void *)h->err_partial})
         if (q) (void)hipFree(q);
+    if (h->err_host) (void)hipHostFree(h->err_host);
+    if (h->err_ready) (void)hipEventDestroy(h->err_ready);
     if (h->scratch) lbcm_destroy(h->scratch);
     delete h;
     return LBCM_OK;

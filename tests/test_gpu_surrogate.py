@@ -346,6 +346,40 @@ def test_zero_network_is_identity_and_planes_roundtrip():
     m.close()
 
 
+@pytest.mark.parametrize("B,H,W,C,L", [(1, 64, 64, 64, 6), (2, 13, 40, 32, 3), (2, 3, 20, 64, 3), (1, 1, 8, 64, 5),
+                                       (1, 17, 70, 64, 4), (1, 256, 256, 64, 6)])
+def test_forward_planes_equals_state_forward(B, H, W, C, L):
+    """The planes path converts inside the first and last layers and, with 64 channels, runs the
+    conv layers in fused pairs (the activation between them stays on chip, its halo recomputed);
+    it must give bit for bit the state path's output converted back to planes (v = u_scale v',
+    rho = 1 + rho_scale rho'), also when the output planes are the input planes.  The shapes
+    cover a paired and a single last layer, ragged tiles, and boxes smaller than the halo."""
+    import torch
+
+    _note(f"forward_planes vs forward {B}x{H}x{W} C={C} L={L}")
+    us, rs = 0.03, 0.01
+    m = net.Surrogate(B, H, W, channels=C, layers=L)
+    m.set_params(_params(C, L, seed=5, last_scale=0.1))
+    m.set_output_scale(ALPHA)
+    fields = [inputs.smooth_state(W, H, seed=20 + b) for b in range(B)]
+    ph, rho, ux, uy = (np.stack([f[k] for f in fields]) for k in range(4))
+    planes = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (ph, ux, uy, rho)]
+    st = torch.empty(B, H, W, S, dtype=torch.float32, device="cuda")
+    m.state_from_planes(*planes, us, rs, st)
+    out = torch.empty_like(st)
+    m.forward(st, out)
+    out = out.cpu().numpy().astype(np.float64)
+    expect = [out[..., 0], out[..., 1] * us, out[..., 2] * us, 1.0 + out[..., 3] * rs]
+    outs = [torch.empty_like(planes[0]) for _ in range(4)]
+    m.forward_planes(*planes, us, rs, *outs)
+    for e, b in zip(expect, outs):
+        assert np.array_equal(b.cpu().numpy(), e)
+    m.forward_planes(*planes, us, rs, *planes)  # in place
+    for e, b in zip(expect, planes):
+        assert np.array_equal(b.cpu().numpy(), e)
+    m.close()
+
+
 def _hybrid_setup(threshold, n=64, J=4, K=8):
     import torch
 
@@ -406,6 +440,42 @@ def test_hybrid_check_error_is_the_relative_phi_l2():
     assert np.array_equal(lat.fields()["phi"], phi_lb)
     for o in (hy, m, lat, ref):
         o.close()
+
+
+@pytest.mark.parametrize("mode", ["accept", "reject", "mixed"])
+def test_hybrid_one_call_equals_window_by_window(mode):
+    """Inside one advance call an accepted window hands its check's lattice fields to the next
+    window and the next window's first jumps are launched before the decision; the result must
+    equal, bit for bit and in every statistic, the same windows advanced one call at a time
+    (where neither shortcut applies).  A random network makes the jumps non-trivial; "mixed"
+    puts the threshold at the median error of a first run."""
+    _note(f"hybrid one call vs window by window: {mode}")
+    J, K, n, W = 4, 8, 64, 6
+
+    def run(threshold, calls):
+        lat, m, hy, torch = _hybrid_setup(threshold, n=n, J=J, K=K)
+        m.set_params(_params(32, 3, seed=11, last_scale=0.02))
+        errs = []
+        for c in calls:
+            hy.advance(c)
+            errs.append(hy.stats()["last_error"])
+        out = (lat.get_state(), hy.stats(), errs)
+        for o in (hy, m, lat):
+            o.close()
+        return out
+
+    threshold = {"accept": np.inf, "reject": 0.0}.get(mode)
+    if threshold is None:
+        threshold = float(np.median(run(np.inf, [1] * W)[2]))
+    s1, st1, _ = run(threshold, [W])
+    s2, st2, _ = run(threshold, [1] * W)
+    _note(f"  threshold {threshold:.3e}: {st1['checks']} checks, {st1['failed_checks']} failed")
+    assert st1 == st2
+    assert np.array_equal(s1, s2)
+    if mode == "accept":
+        assert st1["failed_checks"] == 0 and st1["checks"] == W
+    if mode == "reject":
+        assert st1["jumps"] == 0
 
 
 def test_rejected_window_continues_the_exact_lattice_state():
