@@ -635,13 +635,12 @@ __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict_
 // Layers 0 and 1 in one pass (inference): layer 0 as k_first (FP32 MFMA, the bias as the starting
 // sum, taps in order) on the tile plus a one-pixel halo, kept in LDS as bf16(relu), then layer 1
 // on it as k_conv does (MODE 0), one 8 x 32 tile per workgroup; bit for bit the result of k_first
-// and one k_conv launch.  The FP32 state patch covers the tile plus a two-pixel halo; with PLANES
-// it is read from the FP64 field planes (the tile's own state also goes to s_out).  The wave
-// split of layer 0 over the 10 x 34 intermediate is that of k_pair's layer a.
-template <bool PLANES>
-__global__ __launch_bounds__(kConvThreads) void k_first_pair(const float *__restrict__ s, PlaneIn pin, float *__restrict__ s_out,
-                                                             const float *__restrict__ W0, const float *__restrict__ b0,
-                                                             const __bf16 *__restrict__ W1, OutArgs o, int ntiles, int H, int W)
+// and one k_conv launch.  The FP32 state patch covers the tile plus a two-pixel halo and is read
+// from the FP64 field planes (the tile's own state also goes to s_out, the residual of the last
+// layer).  The wave split of layer 0 over the 10 x 34 intermediate is that of k_pair's layer a.
+__global__ __launch_bounds__(kConvThreads) void k_first_pair(PlaneIn pin, float *__restrict__ s_out, const float *__restrict__ W0,
+                                                             const float *__restrict__ b0, const __bf16 *__restrict__ W1,
+                                                             OutArgs o, int ntiles, int H, int W)
 {
     using L = PairLds;
     constexpr int C = L::C, KS = C / 32, XH = L::XH, XW = L::XW, ZW = L::ZW;
@@ -658,16 +657,12 @@ __global__ __launch_bounds__(kConvThreads) void k_first_pair(const float *__rest
         const int gy = wrap(tc.y0 - 2 + py, H), gx = wrap(tc.x0 - 2 + px, W);
         const size_t p = ((size_t)tc.n * H + gy) * W + gx;
         f32x4 v;
-        if constexpr (PLANES) {
-            v[0] = (float)pin.phi[p];
-            v[1] = (float)pin.ux[p] * pin.inv_u;
-            v[2] = (float)pin.uy[p] * pin.inv_u;
-            v[3] = (float)(pin.rho[p] - 1.0) * pin.inv_r;
-            if (py >= 2 && py < 2 + kTileH && px >= 2 && px < 2 + kTileW && tc.y0 + py - 2 < H && tc.x0 + px - 2 < W)
-                *(f32x4 *)(s_out + p * kStateC) = v;
-        } else {
-            v = *(const f32x4 *)(s + p * kStateC);
-        }
+        v[0] = (float)pin.phi[p];
+        v[1] = (float)pin.ux[p] * pin.inv_u;
+        v[2] = (float)pin.uy[p] * pin.inv_u;
+        v[3] = (float)(pin.rho[p] - 1.0) * pin.inv_r;
+        if (py >= 2 && py < 2 + kTileH && px >= 2 && px < 2 + kTileW && tc.y0 + py - 2 < H && tc.x0 + px - 2 < W)
+            *(f32x4 *)(s_out + p * kStateC) = v;
         *(f32x4 *)(sp + k * kStateC) = v;
     }
     const int mg = wave & 1, ng = wave >> 1;
@@ -1022,8 +1017,8 @@ int launch_pair_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wa, const float *b
 int launch_first_pair(lbcm_net *n, const PlaneIO *io, const OutArgs &o)
 {
     constexpr size_t bytes = (size_t)PairLds::z_elems * sizeof(__bf16);
-    hipLaunchKernelGGL((k_first_pair<true>), dim3(n->ntiles), dim3(kConvThreads), bytes, n->stream, nullptr, io->in, n->resid,
-                       n->params + n->w_off[0], n->params + n->b_off[0], n->Wf[1], o, n->ntiles, n->H, n->W);
+    hipLaunchKernelGGL(k_first_pair, dim3(n->ntiles), dim3(kConvThreads), bytes, n->stream, io->in, n->resid, n->params + n->w_off[0],
+                       n->params + n->b_off[0], n->Wf[1], o, n->ntiles, n->H, n->W);
     NHIP(n, hipGetLastError());
     return LBCM_OK;
 }
