@@ -7,7 +7,11 @@ which updates both population sets of every node (one LUP per node).
 
 Prints one JSON line: MLUPS over the timed steps (HIP events on the stream the kernel runs on),
 the HBM roofline of the step kernel (144 algorithmic bytes per LUP: 9 f + 9 g read, 9 f + 9 g
-written, 4 bytes each) and the FP64 CPU oracle timed on a bounded sample on the host cores.
+written, 4 bytes each) beside a plain device copy, and the FP64 CPU oracle timed on a bounded
+sample on the host cores (all threads and one), plus the 64 x 64 droplet in full.  Further legs
+in the same line: reduced-precision storage (throughput, and phi / sum-phi / structure-factor
+errors against an FP64 GPU run at 2000 and 20000 steps), the 512-box ensemble, the learned
+surrogate, and the two cache-resident correctness configurations.
 """
 from __future__ import annotations
 
@@ -38,10 +42,19 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_LUP))
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--tile-wx", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps in the CPU sample (0 = skip)")
-    ap.add_argument("--copy-probe", action="store_true", help="also time a plain device copy")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps in the CPU sample (0 = skip)")
+    ap.add_argument("--cpu-single-steps", type=int, default=1,
+                    help="oracle steps of the single-thread CPU sample (0 = skip it)")
+    ap.add_argument("--copy-probe", action="store_true", default=True,
+                    help="time a plain device copy beside the step (the default)")
+    ap.add_argument("--no-copy-probe", dest="copy_probe", action="store_false")
     ap.add_argument("--acc-steps", type=int, default=2000,
                     help="steps of the reduced-precision accuracy comparison (0 = skip the report)")
+    ap.add_argument("--acc-long-steps", type=int, default=20000,
+                    help="the same comparison continued to this many steps, with the structure factor "
+                         "(0 = stop at --acc-steps)")
+    ap.add_argument("--small-steps", type=int, default=2000,
+                    help="steps of the cache-resident 64x64 and 4x256 cases (0 = skip them)")
     ap.add_argument("--ens-boxes", type=int, default=512, help="boxes of the ensemble leg (0 = skip it)")
     ap.add_argument("--ens-steps", type=int, default=5000, help="batched steps of the ensemble leg")
     ap.add_argument("--ens-looped-steps", type=int, default=40, help="looped steps timed for comparison")
@@ -50,24 +63,42 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(n: int, steps: int) -> dict:
+def cpu_baseline(n: int, steps: int, single_steps: int, small_steps: int) -> dict:
+    """The FP64 oracle on the host: the 4096^2 workload on all threads given by OMP_NUM_THREADS
+    (a bounded sample of steps), on one thread, and the 64 x 64 static droplet run in full."""
     import numpy as np
 
     import oracle
     from paper_1803_11345_amd import inputs
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    p = oracle.Params(n, n, a=0.04, gamma=0.08, mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05,
-                      nthreads=threads)
-    f, g = oracle.init(p, inputs.spinodal(n, n, seed=1))
-    t0 = time.perf_counter()
-    f, g = oracle.run(p, f, g, steps)
-    dt = time.perf_counter() - t0
-    assert np.isfinite(f).all()
-    return {"value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"FP64 oracle, {n}x{n} spinodal (same initial state), {steps} steps after "
-                      f"initialisation, {dt:.1f} s on {threads} OpenMP threads"}
+
+    def timed(nx, ny, phi, k, nthreads, **kw):
+        phys = dict(a=0.04, gamma=0.08, mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05)
+        phys.update(kw)
+        p = oracle.Params(nx, ny, nthreads=nthreads, **phys)
+        f, g = oracle.init(p, phi)
+        t0 = time.perf_counter()
+        f, g = oracle.run(p, f, g, k)
+        dt = time.perf_counter() - t0
+        assert np.isfinite(f).all()
+        return nx * ny * k / dt / 1e6, dt
+
+    phi0 = inputs.spinodal(n, n, seed=1)
+    v, dt = timed(n, n, phi0, steps, threads)
+    out = {"value": round(v, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 oracle, {n}x{n} spinodal (same initial state), {steps} steps after "
+                     f"initialisation, {dt:.1f} s on {threads} OpenMP threads"}
+    if single_steps > 0:
+        v1, dt1 = timed(n, n, phi0, single_steps, 1)
+        out["single_thread"] = {"value": round(v1, 3), "unit": "MLUPS", "cores": 1,
+                                "sample": f"the same, {single_steps} step(s), {dt1:.1f} s on one thread"}
+    if small_steps > 0:
+        w = inputs.interface_width(0.04, 0.08)
+        vs, dts = timed(64, 64, inputs.droplet(64, 64, 16, w), small_steps, threads, nu_l=1 / 6, nu_g=1 / 6)
+        out["droplet64"] = {"value": round(vs, 3), "unit": "MLUPS", "cores": threads,
+                            "sample": f"64x64 static droplet (R = 16, nu = 1/6), {small_steps} steps, {dts:.2f} s"}
+    return out
 
 
 def copy_probe(nbytes: int = 1 << 31, reps: int = 20) -> float:
@@ -121,34 +152,92 @@ def time_steps(lat, steps, warmup):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
+def structure_factor(phi):
+    """Radially averaged structure factor of phi - mean(phi): the mean of |FFT|^2 / N over the
+    wavevectors whose length (in units of 2 pi / n) rounds to k, for k = 1 .. n / 2."""
+    import torch
+
+    t = torch.from_numpy(phi).cuda()
+    t = t - t.mean()
+    F = torch.fft.fft2(t)
+    pw = (F.real ** 2 + F.imag ** 2) / t.numel()
+    ny, nx = t.shape
+    ky = torch.fft.fftfreq(ny, d=1.0 / ny, device="cuda", dtype=torch.float64)
+    kx = torch.fft.fftfreq(nx, d=1.0 / nx, device="cuda", dtype=torch.float64)
+    shell = torch.round(torch.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2)).long()
+    kmax = min(nx, ny) // 2
+    m = (shell >= 1) & (shell <= kmax)
+    s = torch.zeros(kmax + 1, dtype=torch.float64, device="cuda").index_add_(0, shell[m], pw[m])
+    c = torch.zeros(kmax + 1, dtype=torch.float64, device="cuda").index_add_(0, shell[m], torch.ones_like(pw[m]))
+    return (s[1:] / c[1:]).cpu().numpy()
+
+
 def precision_report(lbcm, phi0, n, args, fp32_sec):
-    """Reduced-precision storage against the plain FP32 step: throughput, speedup, and the phi
-    error against an FP64 run of the same workload after acc_steps steps."""
+    """Reduced-precision storage against the plain FP32 step: throughput, speedup, and the error
+    against an FP64 GPU run of the same workload after acc_steps steps (phi L2, sum phi drift) and
+    after acc_long_steps (the same, and the radially averaged structure factor, which the chaotic
+    growth of round-off leaves comparable where phi itself is not)."""
     import numpy as np
 
+    marks = [args.acc_steps] + ([args.acc_long_steps] if args.acc_long_steps > args.acc_steps else [])
     phis, drift = {}, {}
     for prec in ("fp64", "fp32", "fp16s", "bf16s"):
         lat = make_lattice(lbcm, n, prec, args).init(phi0)
         d0 = lat.diag()
-        lat.step(args.acc_steps)
-        phis[prec] = lat.fields()["phi"]
-        d1 = lat.diag()
-        drift[prec] = abs(d1["sum_phi"] - d0["sum_phi"]) / d0["sum_abs_phi"]
+        done = 0
+        for mark in marks:
+            lat.step(mark - done)
+            done = mark
+            phis[prec, mark] = lat.fields()["phi"]
+            d1 = lat.diag()
+            drift[prec, mark] = abs(d1["sum_phi"] - d0["sum_phi"]) / d0["sum_abs_phi"]
         lat.close()
-    ref = phis["fp64"]
-    out = {"acc_steps": args.acc_steps, "reference": "fp64 GPU run, same initial state",
-           "fp64_sum_phi_drift": drift["fp64"],
-           "fp32": {"phi_rel_l2": float(np.linalg.norm(phis["fp32"] - ref) / np.linalg.norm(ref)),
-                    "sum_phi_drift": drift["fp32"]}}
+
+    def errors(prec, mark):
+        ref = phis["fp64", mark]
+        e = {"phi_rel_l2": float(np.linalg.norm(phis[prec, mark] - ref) / np.linalg.norm(ref)),
+             "sum_phi_drift": drift[prec, mark]}
+        if mark != args.acc_steps:
+            sk, sref = structure_factor(phis[prec, mark]), structure_factor(ref)
+            e["sk_rel_l2"] = float(np.linalg.norm(sk - sref) / np.linalg.norm(sref))
+        return e
+
+    a = args.acc_steps
+    out = {"acc_steps": a, "reference": "fp64 GPU run, same initial state",
+           "fp64_sum_phi_drift": drift["fp64", a], "fp32": errors("fp32", a)}
+    if len(marks) > 1:
+        out["long"] = {"steps": marks[1], "fp64_sum_phi_drift": drift["fp64", marks[1]],
+                       **{prec: errors(prec, marks[1]) for prec in ("fp32", "fp16s", "bf16s")}}
     for prec in ("fp16s", "bf16s"):
         lat = make_lattice(lbcm, n, prec, args).init(phi0)
         sec = time_steps(lat, args.steps, args.warmup)
         lat.close()
         out[prec] = {"value": round(n * n / sec / 1e6, 1), "unit": "MLUPS",
                      "speedup_vs_fp32": round(fp32_sec / sec, 3),
-                     "hbm_gbs_alg": round(BYTES_PER_LUP[prec] * n * n / sec / 1e9, 1),
-                     "phi_rel_l2": float(np.linalg.norm(phis[prec] - ref) / np.linalg.norm(ref)),
-                     "sum_phi_drift": drift[prec]}
+                     "hbm_gbs_alg": round(BYTES_PER_LUP[prec] * n * n / sec / 1e9, 1), **errors(prec, a)}
+    return out
+
+
+def small_report(lbcm, steps, warmup):
+    """MLUPS of the two correctness configurations, whose data stay in the caches (launch
+    latency, not HBM, bounds them): the 64 x 64 static droplet in FP64 and the 4 x 256 layered
+    channel (walls, body force, viscosity ratio 1000) in FP32."""
+    from paper_1803_11345_amd import inputs
+
+    w = inputs.interface_width(0.04, 0.08)
+    cases = {
+        "droplet64_fp64": (64, 64, inputs.droplet(64, 64, 16, w),
+                           dict(precision="fp64", a=0.04, gamma=0.08, mobility=0.1, nu_l=1 / 6, nu_g=1 / 6)),
+        "channel4x256_fp32": (4, 256, inputs.layered(4, 256, w),
+                              dict(precision="fp32", a=0.04, gamma=0.08, mobility=0.1, nu_l=0.1, nu_g=100.0,
+                                   bc_y=lbcm.LBCM_BC_WALLS, force_x=1e-6)),
+    }
+    out = {"note": "cache-resident: MLUPS only, no HBM fraction"}
+    for name, (nx, ny, phi, kw) in cases.items():
+        lat = lbcm.Lattice(nx, ny, **kw).init(phi)
+        sec = time_steps(lat, steps, warmup)
+        lat.close()
+        out[name] = {"value": round(nx * ny / sec / 1e6, 1), "unit": "MLUPS", "us_per_step": round(sec * 1e6, 2)}
     return out
 
 
@@ -305,10 +394,14 @@ def main():
         out["ensemble"] = ensemble_report(lbcm, args)
     if args.sur_iters > 0 and args.precision == "fp32":
         out["surrogate"] = surrogate_report(lbcm, args)
+    if args.small_steps > 0 and args.precision == "fp32":
+        out["cache_resident"] = small_report(lbcm, args.small_steps, args.warmup)
     if args.copy_probe:
-        out["copy_probe_gbs"] = round(copy_probe(), 1)
+        out["roofline"]["copy_probe_gbs"] = round(copy_probe(), 1)
+        out["roofline"]["copy_probe"] = "torch device copy of 2 GiB (reads + writes)"
     if args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, args.cpu_single_steps,
+                                           args.small_steps if args.precision == "fp32" else 0)
     print(json.dumps(out), flush=True)
 
 
