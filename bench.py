@@ -329,7 +329,7 @@ def surrogate_report(lbcm, args) -> dict:
     for name, phi0 in (("spinodal", T.spinodal_phi(n, 106)), ("coalescence", T.coalescence_phi(n, cases[9]))):
         hybrid[name] = T.hybrid_vs_lb(m1, phi0, us, rs, args.sur_windows)
     m1.close()
-    return {"box": f"{n}x{n} periodic", "network": "3x3 conv x6, 64 channels, first layer FP32 VALU, "
+    return {"box": f"{n}x{n} periodic", "network": "3x3 conv x6, 64 channels, first layer FP32 MFMA, "
             "others BF16 MFMA with FP32 accumulation", "steps_per_jump": K, "jumps_per_check": 8,
             "threshold_phi_rel_l2": 1e-2, "threshold_velocity_rel_l2": 0.25, "train": info, "one_jump_rel_l2": gains,
             "jump_us": round(jump_us, 2), "jump_mfma_tflops": round(flops / jump_us / 1e6, 1),

@@ -3,8 +3,9 @@
  * convolutions with circular padding that maps the macroscopic state (phi, v_x, v_y, rho) of
  * periodic boxes to the state K lattice steps later, as state + alpha * network(state) with a
  * fixed per-channel output scale alpha.  The density carries the pressure field, without which
- * the velocity K steps on is not determined by the state.  The first layer runs in FP32 on the vector ALU; the others
- * run on the MFMA units (BF16 activations and weights, FP32 accumulation); master parameters,
+ * the velocity K steps on is not determined by the state.  The first layer runs in FP32 on the
+ * matrix cores; the others run on them in BF16 (BF16 activations and weights, FP32
+ * accumulation); master parameters,
  * gradients and the Adam moments are FP32.  This is not part of the paper's method: it is
  * trained on trajectories of the method and checked against it (see lbcm_step).
  *

@@ -8,12 +8,14 @@
 // per-channel output scale).  Loss: mean over pixels and channels of ((out - target) / alpha)^2.
 //
 // Precision and units.  Layer 0 (4 real input channels, 36 products per output) runs on the
-// vector ALU in FP32 with FP32 state and weights, so the state enters at full precision.  Layers
-// 1 .. L-1 are implicit GEMMs on the MFMA units (v_mfma_f32_16x16x32_bf16: BF16 activations and
-// weights, FP32 accumulation); their weights are packed to BF16 from the FP32 masters after every
-// update.  Activations are NHWC BF16 [P][C]; the last layer's 4 outputs are padded to 32.
+// matrix cores in FP32 (v_mfma_f32_16x16x4_f32) with FP32 state and weights, so the state enters
+// at full precision.  Layers 1 .. L-1 are implicit GEMMs on the MFMA units
+// (v_mfma_f32_16x16x32_bf16: BF16 activations and weights, FP32 accumulation); their weights are
+// packed to BF16 from the FP32 masters after every update.  Activations are NHWC BF16 [P][C]; the
+// last layer's 4 outputs are padded to 32.  Inference from field planes runs the layers in fused
+// pairs whose intermediate activation stays in LDS (k_first_pair, k_pair).
 //
-// Packs.  Wf[t][co][ci] feeds the forward pass (the MFMA B operand takes 8 consecutive K = input
+// Packs.  Wf[t][co][ci] feeds the forward pass (the MFMA A operand takes 8 consecutive K = input
 // channels per lane).  Wb[t][ci][co] = W[8 - t][ci][co] feeds the input gradient: tap t of the
 // mirrored pack sits at d_t = -d_{8-t}, so the forward kernel run on dZ with it gives
 // dX[p] = sum_t dZ[p - d_t] W[t]^T.  The weight gradient dW[t] = sum_p X[p + d_t]^T dZ[p] is a GEMM
@@ -1308,7 +1310,7 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
         if (rc) return rc;
         std::swap(dz, dn);
     }
-    // layer 0 on the vector ALU, per tile: its 36 x C weights and C biases are contiguous in the vector
+    // layer 0 gradients on the vector ALU, per tile: its 36 x C weights and C biases are contiguous in the vector
     if (n->C == 64)
         hipLaunchKernelGGL(k_first_dw<64>, dim3(n->ntiles), dim3(kThreads), 0, n->stream, n->resid, dz, n->H, n->W,
                            n->first_partial);
