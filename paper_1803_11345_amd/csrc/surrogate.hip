@@ -510,27 +510,64 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
 // Layer a: wave (mg, ng) computes channels [16 ng, 16 ng + 16) of Z rows [5 mg, 5 mg + 5) at Z
 // columns 1 .. 32 (ten 16-pixel blocks, input-stationary as in conv_tile) and of Z column 0
 // (mg = 0) or 33 (mg = 1), rows 0 .. 9 (one block whose lanes gather their pixels; lanes 10 .. 15
-// repeat row 9 and store nothing).  Its A fragments come straight from global memory (L2), and so
-// do layer b's (loaded after layer a: requested earlier they slowed the kernel down), so LDS holds
-// only the two patches.
+// repeat row 9 and store nothing).  Each layer's weights are staged in LDS once per workgroup
+// (every wave takes its A fragments from there); layer b's are requested together with the patch
+// and layer a's, kept in registers across LDS-only barriers, and written to LDS once layer a is
+// done, when Z also replaces the patch.  LDS: patch (then Z) and one layer's weights.
 
 struct PairLds {
-    static constexpr int C = 64, PS = C + 8;
+    static constexpr int C = 64, PS = C + 8, WS = C + 8;
     static constexpr int XH = kTileH + 4, XW = kTileW + 4;  // input patch
-    static constexpr int ZH = kTileH + 2, ZW = kTileW + 2;  // intermediate
+    static constexpr int ZH = kTileH + 2, ZW = kTileW + 2;  // intermediate (written over the patch)
     static constexpr int x_elems = XH * XW * PS, z_elems = ZH * ZW * PS;
-    static constexpr size_t bytes = (size_t)(x_elems + z_elems) * sizeof(__bf16);
+    static constexpr int w_elems = 9 * C * WS;               // one layer's weights, up to 64 outputs
+    static constexpr size_t bytes = (size_t)(x_elems + w_elems) * sizeof(__bf16);
 };
+static_assert(PairLds::z_elems <= PairLds::x_elems, "Z fits where the patch was");
 static_assert(PairLds::ZW == kPatchW && PairLds::ZH == kPatchH, "layer b reads Z as a conv patch");
 
-template <int KS>
-__device__ __forceinline__ void load_frags(const __bf16 *__restrict__ Wp, int cout, int co, int q, bf16x8 (&wa)[9][KS])
+// One layer's packed weights Wp[t][co][ci] on their way to LDS (rows of CIN padded to CIN + 8,
+// as the patch), in the registers of all threads of the workgroup: load() issues the global
+// loads, store() writes them to LDS once they have arrived.
+template <int CIN, int COUT>
+struct WeightStage {
+    static constexpr int WS = CIN + 8;
+    static constexpr int NV = 9 * COUT * CIN / 8, NI = (NV + kConvThreads - 1) / kConvThreads;
+    u32x4 v[NI];
+
+    __device__ __forceinline__ void load(const __bf16 *__restrict__ Wp)
+    {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kConvThreads;
+            if (k < NV) v[i] = *(const u32x4 *)(Wp + (size_t)k * 8);
+        }
+    }
+    __device__ __forceinline__ void store(__bf16 *wl) const
+    {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = threadIdx.x + i * kConvThreads;
+            if (k < NV) *(u32x4 *)(wl + (k / (CIN / 8)) * WS + (k % (CIN / 8)) * 8) = v[i];
+        }
+    }
+};
+
+// A fragments of channel group co / 16 from weights staged in LDS: lane (r, q) takes
+// W[t][co][ci = 32 ks + 8 q .. + 8]
+template <int CIN, int COUT>
+__device__ __forceinline__ void lds_frags(const __bf16 *wl, int co, int q, bf16x8 (&wa)[9][CIN / 32])
 {
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) wa[t][ks] = ld8(Wp + ((size_t)t * cout + co) * (32 * KS) + 32 * ks + 8 * q);
+        for (int ks = 0; ks < CIN / 32; ++ks) wa[t][ks] = ld8(wl + (t * COUT + co) * (CIN + 8) + 32 * ks + 8 * q);
 }
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, not for its
+// global loads, so loads issued before it (weights prefetched into registers) stay in flight
+// across it.  (__syncthreads also waits for every outstanding global load.)
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <int COUT, int MODE>
 __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wa,
@@ -539,13 +576,22 @@ __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict_
 {
     using L = PairLds;
     constexpr int C = L::C, PS = L::PS, KS = C / 32, XW = L::XW, ZW = L::ZW;
-    __bf16 *xs = lbcm_conv_lds, *zs = lbcm_conv_lds + L::x_elems;
+    __bf16 *xs = lbcm_conv_lds, *zs = lbcm_conv_lds, *wl = lbcm_conv_lds + L::x_elems;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = lane & 15, q = lane >> 4;
     const int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const TileCoord tc = tile_coord(tile, H, W);
+    const int mg = wave & 1, ng = wave >> 1;
+    using S = WaveSplit<COUT>;
+    const int ngb = wave / S::MG;
+    bf16x8 wa[9][KS];
+    float bias[4];
+    // every global load at once: the patch, layer a's weights, then layer b's, which stay in
+    // registers (in flight) until layer a is done
+    WeightStage<C, C> sa;
+    WeightStage<C, COUT> sb;
     {
         constexpr int NV = L::XH * XW * (C / 8), NI = (NV + kConvThreads - 1) / kConvThreads;
         const __bf16 *Xn = X + (size_t)tc.n * H * W * C;
@@ -559,28 +605,26 @@ __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict_
                 v[i] = *(const u32x4 *)(Xn + ((size_t)gy * W + gx) * C + ch);
             }
         }
+        sa.load(Wa);
+        sb.load(Wb);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[e] = ba[16 * ng + 4 * q + e];
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             const int k = threadIdx.x + i * kConvThreads;
             if (k < NV) *(u32x4 *)(xs + (k / (C / 8)) * PS + (k % (C / 8)) * 8) = v[i];
         }
+        sa.store(wl);
     }
-    const int mg = wave & 1, ng = wave >> 1;
-    using S = WaveSplit<COUT>;
-    const int ngb = wave / S::MG;
-    bf16x8 wa[9][KS], wb[9][KS];
-    load_frags<KS>(Wa, C, 16 * ng + r, q, wa);
-    float bias[4];
+    lds_barrier();
+    lds_frags<C, C>(wl, 16 * ng + r, q, wa);
+    // Z rows 5 mg + rho (rho < 5) at Z columns 1 + 16 half + r: X rows 5 mg + rho + dyi, X columns
+    // 1 + 16 half + r + dxi; then the edge column of Z
+    constexpr int RW = 5, NS = 2 * (RW + 2);
+    f32x4 acc[2 * RW + 1];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bias[e] = ba[16 * ng + 4 * q + e];
-    __syncthreads();
+    for (int mi = 0; mi <= 2 * RW; ++mi) acc[mi] = f32x4{0, 0, 0, 0};
     {
-        // Z rows 5 mg + rho (rho < 5) at Z columns 1 + 16 half + r: X rows 5 mg + rho + dyi,
-        // X columns 1 + 16 half + r + dxi
-        constexpr int RW = 5, NS = 2 * (RW + 2);
-        f32x4 acc[2 * RW];
-#pragma unroll
-        for (int mi = 0; mi < 2 * RW; ++mi) acc[mi] = f32x4{0, 0, 0, 0};
         bf16x8 fr[2][3][KS];
         auto load_stage = [&](int st, bf16x8 (&f)[3][KS]) {
             const int xr = RW * mg + (st >> 1), half = st & 1;
@@ -607,31 +651,31 @@ __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict_
                     }
             __builtin_amdgcn_sched_barrier(0);
         }
-        // the edge column of Z
-        const int zr = r < L::ZH ? r : L::ZH - 1, zc = mg ? ZW - 1 : 0;
-        f32x4 ae = f32x4{0, 0, 0, 0};
-#pragma unroll
-        for (int t = 0; t < 9; ++t)
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-                ae = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    wa[t][ks], ld8(xs + ((zr + t / 3) * XW + zc + t % 3) * PS + 32 * ks + 8 * q), ae, 0, 0, 0);
-        auto zstore = [&](int y, int x, const f32x4 &a) {
-            bf16x4 v4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v4[e] = (__bf16)fmaxf(a[e] + bias[e], 0.f);
-            *(u32x2 *)(zs + (y * ZW + x) * PS + 16 * ng + 4 * q) = __builtin_bit_cast(u32x2, v4);
-        };
-#pragma unroll
-        for (int mi = 0; mi < 2 * RW; ++mi) zstore(RW * mg + (mi >> 1), 1 + 16 * (mi & 1) + r, acc[mi]);
-        if (r < L::ZH) zstore(zr, zc, ae);
     }
+    const int zr = r < L::ZH ? r : L::ZH - 1, zc = mg ? ZW - 1 : 0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            acc[2 * RW] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                wa[t][ks], ld8(xs + ((zr + t / 3) * XW + zc + t % 3) * PS + 32 * ks + 8 * q), acc[2 * RW], 0, 0, 0);
+    lds_barrier();  // every wave is done with the patch and layer a's weights
+    auto zstore = [&](int y, int x, const f32x4 &a) {
+        bf16x4 v4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v4[e] = (__bf16)fmaxf(a[e] + bias[e], 0.f);
+        *(u32x2 *)(zs + (y * ZW + x) * PS + 16 * ng + 4 * q) = __builtin_bit_cast(u32x2, v4);
+    };
+#pragma unroll
+    for (int mi = 0; mi < 2 * RW; ++mi) zstore(RW * mg + (mi >> 1), 1 + 16 * (mi & 1) + r, acc[mi]);
+    if (r < L::ZH) zstore(zr, zc, acc[2 * RW]);
+    sb.store(wl);
     // layer b
 #pragma unroll
     for (int e = 0; e < 4; ++e) bias[e] = o.bias[16 * ngb + 4 * q + e];
-    load_frags<KS>(Wb, COUT, 16 * ngb + r, q, wb);
-    __syncthreads();
-    conv_tile<C, COUT, MODE>(zs, wb, bias, tc, o, H, W);
+    lds_barrier();
+    lds_frags<C, COUT>(wl, 16 * ngb + r, q, wa);
+    conv_tile<C, COUT, MODE>(zs, wa, bias, tc, o, H, W);
 }
 
 // Layers 0 and 1 in one pass (inference): layer 0 as k_first (FP32 MFMA, the bias as the starting
@@ -639,7 +683,9 @@ __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict_
 // on it as k_conv does (MODE 0), one 8 x 32 tile per workgroup; bit for bit the result of k_first
 // and one k_conv launch.  The FP32 state patch covers the tile plus a two-pixel halo and is read
 // from the FP64 field planes (the tile's own state also goes to s_out, the residual of the last
-// layer).  The wave split of layer 0 over the 10 x 34 intermediate is that of k_pair's layer a.
+// layer).  The wave split of layer 0 over the 10 x 34 intermediate is that of k_pair's layer a;
+// layer 1's weights are requested at the start and staged in LDS once layer 0 is done.
+// Dynamic LDS: Z and one layer's weights.
 __global__ __launch_bounds__(kConvThreads) void k_first_pair(PlaneIn pin, float *__restrict__ s_out, const float *__restrict__ W0,
                                                              const float *__restrict__ b0, const __bf16 *__restrict__ W1,
                                                              OutArgs o, int ntiles, int H, int W)
@@ -647,36 +693,49 @@ __global__ __launch_bounds__(kConvThreads) void k_first_pair(PlaneIn pin, float 
     using L = PairLds;
     constexpr int C = L::C, KS = C / 32, XH = L::XH, XW = L::XW, ZW = L::ZW;
     __shared__ __align__(16) float sp[XH * XW * kStateC];
-    __bf16 *zs = lbcm_conv_lds;
+    __bf16 *zs = lbcm_conv_lds, *wl = lbcm_conv_lds + L::z_elems;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = lane & 15, q = lane >> 4;
     const int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const TileCoord tc = tile_coord(tile, H, W);
-    for (int k = threadIdx.x; k < XH * XW; k += kConvThreads) {
-        const int py = k / XW, px = k % XW;
-        const int gy = wrap(tc.y0 - 2 + py, H), gx = wrap(tc.x0 - 2 + px, W);
-        const size_t p = ((size_t)tc.n * H + gy) * W + gx;
-        f32x4 v;
-        v[0] = (float)pin.phi[p];
-        v[1] = (float)pin.ux[p] * pin.inv_u;
-        v[2] = (float)pin.uy[p] * pin.inv_u;
-        v[3] = (float)(pin.rho[p] - 1.0) * pin.inv_r;
-        if (py >= 2 && py < 2 + kTileH && px >= 2 && px < 2 + kTileW && tc.y0 + py - 2 < H && tc.x0 + px - 2 < W)
-            *(f32x4 *)(s_out + p * kStateC) = v;
-        *(f32x4 *)(sp + k * kStateC) = v;
-    }
+    static_assert(XH * XW <= kConvThreads, "one patch pixel per thread");
     const int mg = wave & 1, ng = wave >> 1;
     float w0[9];  // A operand at tap t: lane (r, q) holds W0[t][ci = q][co = 16 ng + r]
-#pragma unroll
-    for (int t = 0; t < 9; ++t) w0[t] = W0[(kStateC * t + q) * C + 16 * ng + r];
     float bias0[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) bias0[e] = b0[16 * ng + 4 * q + e];
     bf16x8 w1[9][KS];
-    load_frags<KS>(W1, C, 16 * ng + r, q, w1);
-    __syncthreads();
+    WeightStage<C, C> s1;  // layer 1's weights, in flight during layer 0
+    {
+        // every global load at once: this thread's patch pixel first, then both layers' weights
+        const int k = threadIdx.x, py = k / XW, px = k % XW;
+        size_t p = 0;
+        double ph = 0, ux = 0, uy = 0, rh = 1;
+        if (k < XH * XW) {
+            const int gy = wrap(tc.y0 - 2 + py, H), gx = wrap(tc.x0 - 2 + px, W);
+            p = ((size_t)tc.n * H + gy) * W + gx;
+            ph = pin.phi[p];
+            ux = pin.ux[p];
+            uy = pin.uy[p];
+            rh = pin.rho[p];
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) w0[t] = W0[(kStateC * t + q) * C + 16 * ng + r];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias0[e] = b0[16 * ng + 4 * q + e];
+        s1.load(W1);
+        if (k < XH * XW) {
+            f32x4 v;
+            v[0] = (float)ph;
+            v[1] = (float)ux * pin.inv_u;
+            v[2] = (float)uy * pin.inv_u;
+            v[3] = (float)(rh - 1.0) * pin.inv_r;
+            if (py >= 2 && py < 2 + kTileH && px >= 2 && px < 2 + kTileW && tc.y0 + py - 2 < H && tc.x0 + px - 2 < W)
+                *(f32x4 *)(s_out + p * kStateC) = v;
+            *(f32x4 *)(sp + k * kStateC) = v;
+        }
+    }
+    lds_barrier();
     {
         // Z rows 5 mg + rho at Z columns 1 + 16 half + r, and the edge column of Z (lanes 10 .. 15
         // repeat row 9); Z (zr, zc) reads the patch at (zr + dy + 1, zc + dx + 1)
@@ -708,10 +767,12 @@ __global__ __launch_bounds__(kConvThreads) void k_first_pair(PlaneIn pin, float 
         for (int mi = 0; mi < 2 * RW; ++mi) zstore(RW * mg + (mi >> 1), 1 + 16 * (mi & 1) + r, acc[mi]);
         if (r < L::ZH) zstore(zr, zc, acc[2 * RW]);
     }
+    s1.store(wl);
     float bias1[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) bias1[e] = o.bias[16 * ng + 4 * q + e];
-    __syncthreads();
+    lds_barrier();
+    lds_frags<C, C>(wl, 16 * ng + r, q, w1);
     conv_tile<C, C, 0>(zs, w1, bias1, tc, o, H, W);
 }
 
@@ -984,16 +1045,28 @@ struct PlaneIO {
     double u_scale, r_scale;
 };
 
+// A kernel that uses more than 64 KiB of dynamic LDS must be allowed it explicitly, once per
+// device (done[] is the kernel's own record of the devices already set up).
+constexpr int kMaxDevices = 64;
+int allow_dynamic_lds(lbcm_net *n, const void *kernel, size_t bytes, bool (&done)[kMaxDevices])
+{
+    int dev = 0;
+    NHIP(n, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return nfail(n, LBCM_EHIP, "device index out of range");
+    if (!done[dev]) {
+        NHIP(n, hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        done[dev] = true;
+    }
+    return LBCM_OK;
+}
+
 template <int CI, int CO, int MO>
 int launch_conv_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wp, const OutArgs &o)
 {
     constexpr size_t bytes = ConvLds<CI, CO>::bytes;
-    static bool attr = false;  // beyond 64 KiB of dynamic LDS must be allowed explicitly, once
-    if (!attr) {
-        NHIP(n, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv<CI, CO, MO>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-        attr = true;
-    }
+    static bool done[kMaxDevices] = {};
+    int rc = allow_dynamic_lds(n, reinterpret_cast<const void *>(&k_conv<CI, CO, MO>), bytes, done);
+    if (rc) return rc;
     hipLaunchKernelGGL((k_conv<CI, CO, MO>), dim3(n->conv_grid), dim3(kConvThreads), bytes, n->stream, X, Wp, o, n->ntiles,
                        n->H, n->W);
     NHIP(n, hipGetLastError());
@@ -1004,12 +1077,9 @@ template <int CO, int MO>
 int launch_pair_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wa, const float *ba, const __bf16 *Wb, const OutArgs &o)
 {
     constexpr size_t bytes = PairLds::bytes;
-    static bool attr = false;
-    if (!attr) {
-        NHIP(n, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pair<CO, MO>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)bytes));
-        attr = true;
-    }
+    static bool done[kMaxDevices] = {};
+    int rc = allow_dynamic_lds(n, reinterpret_cast<const void *>(&k_pair<CO, MO>), bytes, done);
+    if (rc) return rc;
     hipLaunchKernelGGL((k_pair<CO, MO>), dim3(n->ntiles), dim3(kConvThreads), bytes, n->stream, X, Wa, ba, Wb, o, n->ntiles, n->H,
                        n->W);
     NHIP(n, hipGetLastError());
@@ -1018,7 +1088,10 @@ int launch_pair_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wa, const float *b
 
 int launch_first_pair(lbcm_net *n, const PlaneIO *io, const OutArgs &o)
 {
-    constexpr size_t bytes = (size_t)PairLds::z_elems * sizeof(__bf16);
+    constexpr size_t bytes = (size_t)(PairLds::z_elems + PairLds::w_elems) * sizeof(__bf16);
+    static bool done[kMaxDevices] = {};
+    int rc = allow_dynamic_lds(n, reinterpret_cast<const void *>(&k_first_pair), bytes, done);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_first_pair, dim3(n->ntiles), dim3(kConvThreads), bytes, n->stream, io->in, n->resid, n->params + n->w_off[0],
                        n->params + n->b_off[0], n->Wf[1], o, n->ntiles, n->H, n->W);
     NHIP(n, hipGetLastError());
