@@ -56,7 +56,9 @@ int lbcm_net_forward(lbcm_net *n, const float *in, float *out);
 
 /* Forward pass from device FP64 planes [B][H][W] of phi, v_x, v_y, rho (scaled on the way in as
    in the state tensor, and back on the way out) into device FP64 planes.  The output planes may
-   be the input planes (in place).  The conversions run inside the first and last layers. */
+   be the input planes (in place).  The conversions run inside the first and last layers; with 64
+   channels the layers run in fused pairs.  The result equals lbcm_net_forward's on the converted
+   state, converted back, bit for bit. */
 int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, const double *rho,
                             double u_scale, double rho_scale, double *phi_out, double *ux_out, double *uy_out,
                             double *rho_out);
@@ -117,7 +119,11 @@ int lbcm_hybrid_create(lbcm_handle *lattice, lbcm_net *net, int32_t steps_per_ju
                        double u_scale, double rho_scale, double threshold, double velocity_threshold,
                        lbcm_hybrid **out);
 
-/* Advance by `windows` windows (each J * K lattice steps; synchronises once per window). */
+/* Advance by `windows` windows (each J * K lattice steps; waits once per window for the check's
+   sums).  Within one call, a window that follows an accepted one starts from that check's
+   lattice fields, and its first jumps (at most 2) are queued before the wait for the previous
+   check; a rejection drops them.  The results equal those of `windows` calls of one window,
+   bit for bit.  The lattice must not be used by the caller during the call. */
 int lbcm_hybrid_advance(lbcm_hybrid *h, int64_t windows);
 
 int lbcm_hybrid_get_stats(const lbcm_hybrid *h, lbcm_hybrid_stats *out);
