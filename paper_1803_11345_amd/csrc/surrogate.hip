@@ -208,13 +208,14 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
 
 // layer 0 gradients, one 8 x 32 tile per workgroup: partial[tile][r][co] for r = kStateC t + ci
 // (r < 36: sum_p s[p + d_t][ci] dZ[p][co]) and r = 36 (sum_p dZ[p][co], the bias).  The state
-// patch and the tile's dZ are staged in LDS; thread (g, co) accumulates rows r = g, g + G, ...
-// with G = kThreads / C.
+// patch and the tile's dZ are staged in LDS; thread (g, c4) accumulates output channels 4 c4 ..
+// 4 c4 + 3 of rows r = g, g + G, ... with G = kThreads / (C / 4), over the pixels in order (one
+// dZ read and one state read feed four FMAs).
 template <int C>
 __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__ s, const __bf16 *__restrict__ dz, int H,
                                                        int W, float *__restrict__ partial)
 {
-    constexpr int G = kThreads / C, R = (kFirstRows + G - 1) / G;
+    constexpr int G = kThreads / (C / 4), R = (kFirstRows + G - 1) / G;
     __shared__ float sp[kPatchH * kPatchW * kStateC];
     __shared__ __align__(16) __bf16 sd[kTileH * kTileW * C];
     const TileCoord tc = tile_coord(blockIdx.x, H, W);
@@ -229,28 +230,43 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
         *(u32x4 *)(sd + px * C + ch) = v;
     }
     __syncthreads();
-    const int co = threadIdx.x % C, g = threadIdx.x / C;
-    float acc[R];
+    const int c4 = threadIdx.x % (C / 4), g = threadIdx.x / (C / 4);
+    // row r of this thread: the state value at patch offset off from the pixel, times m, plus a
+    // (m = 1, a = 0 for r < 36; m = 0, a = 1 for the bias row; rows past it are not stored)
+    int off[R];
+    float m[R], a[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) acc[k] = 0.f;
+    for (int k = 0; k < R; ++k) {
+        const int r = g + k * G, t = r / kStateC;
+        const bool prod = r < kFirstRows - 1;
+        off[k] = prod ? ((1 + tap_dy(t)) * kPatchW + 1 + tap_dx(t)) * kStateC + r % kStateC : 0;
+        m[k] = prod ? 1.f : 0.f;
+        a[k] = prod ? 0.f : 1.f;
+    }
+    float acc[R][4];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[k][e] = 0.f;
     for (int px = 0; px < kTileH * kTileW; ++px) {
-        const float d = (float)sd[px * C + co];
-        const int ly = px / kTileW, lx = px % kTileW;
+        const bf16x4 d4 = __builtin_bit_cast(bf16x4, *(const u32x2 *)(sd + px * C + 4 * c4));
+        float d[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[e] = (float)d4[e];
+        const int base = ((px / kTileW) * kPatchW + px % kTileW) * kStateC;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int r = g + k * G;
-            if (r < kFirstRows - 1) {
-                const int t = r / kStateC;
-                acc[k] = fmaf(sp[((ly + 1 + tap_dy(t)) * kPatchW + lx + 1 + tap_dx(t)) * kStateC + r % kStateC], d, acc[k]);
-            } else if (r == kFirstRows - 1) {
-                acc[k] += d;
-            }
+            const float x = fmaf(sp[base + off[k]], m[k], a[k]);  // exact: x or 1
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[k][e] = fmaf(x, d[e], acc[k][e]);
         }
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int r = g + k * G;
-        if (r < kFirstRows) partial[((size_t)blockIdx.x * kFirstRows + r) * C + co] = acc[k];
+        if (r < kFirstRows)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) partial[((size_t)blockIdx.x * kFirstRows + r) * C + 4 * c4 + e] = acc[k][e];
     }
 }
 
@@ -777,10 +793,11 @@ __global__ __launch_bounds__(kConvThreads) void k_first_pair(PlaneIn pin, float 
 }
 
 // ------------------------------------------------------------------------------------------
-// weight gradient of layers 1 .. L-1: partial[chunk][t][ci][co] = sum over the chunk's pixels p
-// of X[p + d_t][ci] dZ[p][co].  A workgroup owns one tap and one chunk; it stages 64 pixels of X
-// (shifted) and dZ in LDS with 16-byte loads (pixel stride padded by 16 bytes), then each wave
-// accumulates its share of the (ci, co) 16 x 16 tiles with MFMAs whose K dimension is the pixels.
+// weight gradient of layers with 32 input channels (64: k_conv_dw_strip below):
+// partial[chunk][t][ci][co] = sum over the chunk's pixels p of X[p + d_t][ci] dZ[p][co].  A
+// workgroup owns one tap and one chunk; it stages 64 pixels of X (shifted) and dZ in LDS with
+// 16-byte loads (pixel stride padded by 16 bytes), then each wave accumulates its share of the
+// (ci, co) 16 x 16 tiles with MFMAs whose K dimension is the pixels.
 
 __global__ __launch_bounds__(kThreads) void k_conv_dw(const __bf16 *__restrict__ X, int cin, const __bf16 *__restrict__ dZ,
                                                       int cout, uint32_t P, int H, int W, float *__restrict__ partial)
@@ -840,18 +857,192 @@ __global__ __launch_bounds__(kThreads) void k_conv_dw(const __bf16 *__restrict__
     }
 }
 
+// Weight gradient of a layer with 64 input channels, all 9 taps in one pass: partial[g][t][ci][co]
+// = sum over the pixels p of work unit g of X[p + d_t][ci] dZ[p][co].  A work unit is a run of
+// rows of one 32-column strip of one sample, walked row by row.  The pixels are the K dimension
+// of the MFMAs and must be the packed one of both operands, so the rows of X are kept in LDS
+// transposed (channel-major), in a ring of three rows (y - 1, y, y + 1) with three copies of each
+// shifted by dx = -1, 0, 1: every A fragment is then one aligned 16-byte read.  The row of dZ is
+// staged transposed as well.  Wave w owns input channels [16 w, 16 w + 16) and keeps the 9 taps x
+// COUT / 16 output blocks in registers; per row it reads its COUT / 16 B fragments once and one A
+// fragment per tap (9 x COUT / 16 MFMAs).  The global loads of a row are issued kDwAhead rows
+// before it is needed.  The unit's bias gradient (sum of dZ over its pixels) goes to
+// db_partial[g][co].
+
+constexpr int kDwStrip = 32;                 // strip width: one MFMA K step
+constexpr int kDwRS = kDwStrip + 8;          // LDS stride (bf16) of a transposed row
+constexpr int kDwThreads = 256;              // four waves: one per 16 input channels
+constexpr int kDwRowChunks = (kDwStrip + 2) * 8;  // 16-byte chunks of one X row (34 pixels x 64 channels)
+constexpr int kDwAhead = 4;                  // rows of global loads in flight
+
+template <int COUT>
+struct DwLds {
+    static constexpr int ring_elems = 3 * 3 * 64 * kDwRS;  // [slot][dx + 1][ci][column]
+    static constexpr int z_elems = COUT * kDwRS;           // [co][column]
+    static constexpr size_t bytes = (size_t)(ring_elems + z_elems) * sizeof(__bf16);
+};
+
+template <int COUT>
+__global__ __launch_bounds__(kDwThreads) void k_conv_dw_strip(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dZ, int H,
+                                                              int W, int seg, int units_per_strip, float *__restrict__ partial,
+                                                              float *__restrict__ db_partial)
+{
+    constexpr int NJ = COUT / 16, NZ = kDwStrip * COUT / 8;  // output blocks, 16-byte chunks of a dZ row
+    static_assert(NZ <= kDwThreads && kDwRowChunks <= 2 * kDwThreads, "one or two chunks per thread");
+    __shared__ __align__(16) __bf16 ring[DwLds<COUT>::ring_elems];
+    __shared__ __align__(16) __bf16 zt[DwLds<COUT>::z_elems];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = lane & 15, q = lane >> 4;
+    const int nstrips = (W + kDwStrip - 1) / kDwStrip;
+    const int strip = blockIdx.x / units_per_strip, part = blockIdx.x % units_per_strip;
+    const int n = strip / nstrips, sx = (strip % nstrips) * kDwStrip;
+    const int ya = part * seg, yb = min(H, ya + seg);
+    const __bf16 *Xn = X + (size_t)n * H * W * 64;
+    const __bf16 *Zn = dZ + (size_t)n * H * W * COUT;
+
+    // The loads carry no branches (clamped indices, zeros selected afterwards), so that the
+    // compiler can wait for exactly the row it stores while later rows stay in flight.
+    // One X row (34 pixels from column sx - 1, wrapped): chunk c = pixel c % 34, channels 8 (c / 34).
+    auto load_x = [&](int y, u32x4 (&xv)[2]) {
+        const int yy = wrap(y, H);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int c = min((int)threadIdx.x + i * kDwThreads, kDwRowChunks - 1);
+            const int j = c % (kDwStrip + 2), g = c / (kDwStrip + 2);
+            xv[i] = *(const u32x4 *)(Xn + ((size_t)yy * W + wrap(sx - 1 + j, W)) * 64 + 8 * g);
+        }
+    };
+    // copy dx + 1 = d holds X[y][sx + col + dx] at column col: pixel j goes to column j - d
+    auto store_x = [&](int slot, const u32x4 (&xv)[2]) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int c = threadIdx.x + i * kDwThreads;
+            if (c < kDwRowChunks) {
+                const int j = c % (kDwStrip + 2), g = c / (kDwStrip + 2);
+                const bf16x8 v = __builtin_bit_cast(bf16x8, xv[i]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const int col = j - d;
+                    if (col < 0 || col >= kDwStrip) continue;
+                    __bf16 *dst = ring + ((slot * 3 + d) * 64 + 8 * g) * kDwRS + col;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) dst[e * kDwRS] = v[e];
+                }
+            }
+        }
+    };
+    // one dZ row of the strip: chunk c = pixel c % 32, channels 8 (c / 32); stored as zero past
+    // the box and for rows at or past yb (the row loop runs to a multiple of kDwAhead)
+    auto load_z = [&](int y, u32x4 &zv) {
+        const int c = min((int)threadIdx.x, NZ - 1);
+        const int j = c % kDwStrip, g = c / kDwStrip;
+        zv = *(const u32x4 *)(Zn + ((size_t)min(y, H - 1) * W + min(sx + j, W - 1)) * COUT + 8 * g);
+    };
+    // the bias gradient rides along: thread c sums channels 8 (c / 32) .. + 7 of pixel c % 32 of
+    // every stored dZ row, in row order
+    float bsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    auto store_z = [&](int y, const u32x4 &zv) {
+        const int c = threadIdx.x;
+        if (c < NZ) {
+            const int j = c % kDwStrip, g = c / kDwStrip;
+            const bf16x8 v = __builtin_bit_cast(bf16x8, (sx + j < W && y < yb) ? zv : u32x4{0, 0, 0, 0});
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                zt[(8 * g + e) * kDwRS + j] = v[e];
+                bsum[e] += (float)v[e];
+            }
+        }
+    };
+    auto slot_of = [&](int y) { return (y - ya + 1) % 3; };  // y >= ya - 1
+
+    f32x4 acc[9][NJ];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int jn = 0; jn < NJ; ++jn) acc[t][jn] = f32x4{0, 0, 0, 0};
+    // FIFO slot u holds the loads of the rows that iteration y stores when y = ya + u (mod
+    // kDwAhead): X row y + 2 and dZ row y + 1, requested kDwAhead iterations earlier (one row of
+    // MFMAs is much shorter than a global load)
+    u32x4 fx[kDwAhead][2], fz[kDwAhead];
+    {
+        u32x4 xv[2], zv;
+        for (int y = ya - 1; y <= ya + 1; ++y) {
+            load_x(y, xv);
+            store_x(slot_of(y), xv);
+        }
+        load_z(ya, zv);
+        store_z(ya, zv);
+    }
+#pragma unroll
+    for (int u = 0; u < kDwAhead; ++u) {
+        load_x(ya + u + 2, fx[u]);
+        load_z(ya + u + 1, fz[u]);
+    }
+    lds_barrier();
+    const int yend = ya + (yb - ya + kDwAhead - 1) / kDwAhead * kDwAhead;  // rows past yb add zero
+    for (int y0 = ya; y0 < yend; y0 += kDwAhead) {
+#pragma unroll
+        for (int u = 0; u < kDwAhead; ++u) {
+            const int y = y0 + u;
+            bf16x8 b[NJ];
+#pragma unroll
+            for (int jn = 0; jn < NJ; ++jn) b[jn] = ld8(zt + (16 * jn + r) * kDwRS + 8 * q);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int slot = slot_of(y + t / 3 - 1), d = t % 3;
+                const bf16x8 a = ld8(ring + ((slot * 3 + d) * 64 + 16 * w + r) * kDwRS + 8 * q);
+#pragma unroll
+                for (int jn = 0; jn < NJ; ++jn) acc[t][jn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[jn], acc[t][jn], 0, 0, 0);
+            }
+            lds_barrier();  // every wave is done with row y - 1 and the dZ row
+            store_x(slot_of(y + 2), fx[u]);
+            store_z(y + 1, fz[u]);
+            load_x(y + kDwAhead + 2, fx[u]);
+            load_z(y + kDwAhead + 1, fz[u]);
+            lds_barrier();
+        }
+    }
+    // bias partial of this unit: the 32 pixel lanes of a channel group (one half of a wave) in a
+    // fixed butterfly
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsum[e] += __shfl_xor(bsum[e], m, 64);
+    if ((int)threadIdx.x < NZ && threadIdx.x % kDwStrip == 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) db_partial[(size_t)blockIdx.x * 64 + 8 * (threadIdx.x / kDwStrip) + e] = bsum[e];
+    }
+    // D of block (t, jn): lane (r, q) holds ci = 16 w + 4 q + e, co = 16 jn + r
+    float *out = partial + (size_t)blockIdx.x * 9 * 64 * COUT;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int jn = 0; jn < NJ; ++jn)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) out[((size_t)t * 64 + 16 * w + 4 * q + e) * COUT + 16 * jn + r] = acc[t][jn][e];
+}
+
 // sum of the per-chunk partials in chunk order (deterministic), into the real-size gradient
 // dW[t][ci][co] (ci < cin_r, co < cout_r) of the padded partials
-__global__ void k_dw_reduce(const float *__restrict__ partial, int nchunks, int cin, int cout, int cin_r, int cout_r,
-                            float *__restrict__ dW)
+__global__ __launch_bounds__(256) void k_dw_reduce(const float *__restrict__ partial, int nchunks, int cin, int cout, int cin_r,
+                                                   int cout_r, float *__restrict__ dW)
 {
-    const int n = 9 * cin_r * cout_r;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    // 64 outputs per block; wave p sums the chunks p, p + 4, ... and the four sums are added in
+    // a fixed order
+    __shared__ float red[4][64];
+    const int n = 9 * cin_r * cout_r, l = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + l;
+    float s = 0;
+    if (i < n) {
         const int t = i / (cin_r * cout_r), rem = i % (cin_r * cout_r), ci = rem / cout_r, co = rem % cout_r;
-        float s = 0;
-        for (int c = 0; c < nchunks; ++c) s += partial[(((size_t)c * 9 + t) * cin + ci) * cout + co];
-        dW[i] = s;
+        const float *src = partial + ((size_t)t * cin + ci) * cout + co;
+        const size_t stride = (size_t)9 * cin * cout;
+        for (int c = part; c < nchunks; c += 4) s += src[c * stride];
     }
+    red[part][l] = s;
+    __syncthreads();
+    if (part == 0 && i < n) dW[i] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
 }
 
 // bias gradient db[co] = sum_p dZ[p][co]: per-block partial sums (then k_sum_rows)
@@ -1011,6 +1202,7 @@ struct lbcm_net {
     float *resid = nullptr, *out = nullptr;     // FP32 [P][kStateC]: input state, output state
     float *dw_partial = nullptr, *db_partial = nullptr, *loss_partial = nullptr, *first_partial = nullptr;
     int loss_blocks = 0;
+    int dw_seg = 0, dw_units_per_strip = 0, dw_units = 0;  // work units of k_conv_dw_strip
     bool packed = false;
     std::string err;
 };
@@ -1270,8 +1462,17 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
     if (!dmalloc((void **)&n->resid, P * kStateC * sizeof(float)) || !dmalloc((void **)&n->out, P * kStateC * sizeof(float)))
         return bail("out of device memory (state)");
     const size_t nchunks = (P + kDwChunk - 1) / kDwChunk;
-    if (!dmalloc((void **)&n->dw_partial, nchunks * 9 * 64 * 64 * sizeof(float))) return bail("out of device memory (dW)");
-    if (!dmalloc((void **)&n->db_partial, ((P + 1023) / 1024) * 64 * sizeof(float))) return bail("out of device memory (db)");
+    {
+        // strip work units of the 64-input-channel weight gradient: runs of seg rows, about 256 in all
+        const size_t nstrips = (width + kDwStrip - 1) / kDwStrip, rows = (size_t)batch * nstrips * height;
+        n->dw_seg = (int)std::max<size_t>(4, (rows + 255) / 256);
+        n->dw_units_per_strip = (height + n->dw_seg - 1) / n->dw_seg;
+        n->dw_units = (int)((size_t)batch * nstrips * n->dw_units_per_strip);
+    }
+    const size_t npartials = std::max<size_t>(nchunks, (size_t)n->dw_units);
+    if (!dmalloc((void **)&n->dw_partial, npartials * 9 * 64 * 64 * sizeof(float))) return bail("out of device memory (dW)");
+    if (!dmalloc((void **)&n->db_partial, std::max<size_t>((P + 1023) / 1024, (size_t)n->dw_units) * 64 * sizeof(float)))
+        return bail("out of device memory (db)");
     if (!dmalloc((void **)&n->first_partial, ntiles * kFirstRows * channels * sizeof(float)))
         return bail("out of device memory (first layer)");
     n->loss_blocks = grid_of(P, 256) > 1024 ? 1024 : grid_of(P, 256);
@@ -1364,15 +1565,31 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
     const int dbb = (int)((P + 1023) / 1024);
     for (int l = L - 1; l >= 1; --l) {
         // weight and bias gradients of layer l from its input act[l] and dz (gradient of its output)
-        hipLaunchKernelGGL(k_conv_dw, dim3(nchunks, 9), dim3(kThreads), 0, n->stream, n->act[l], n->cin[l], dz, n->cout[l], P,
-                           n->H, n->W, n->dw_partial);
+        int parts = nchunks;
+        const bool strip = n->cin[l] == 64 && (n->cout[l] == 64 || n->cout[l] == 32);
+        if (strip) {
+            parts = n->dw_units;
+            if (n->cout[l] == 64)
+                hipLaunchKernelGGL(k_conv_dw_strip<64>, dim3(parts), dim3(kDwThreads), 0, n->stream, n->act[l], dz, n->H, n->W,
+                                   n->dw_seg, n->dw_units_per_strip, n->dw_partial, n->db_partial);
+            else
+                hipLaunchKernelGGL(k_conv_dw_strip<32>, dim3(parts), dim3(kDwThreads), 0, n->stream, n->act[l], dz, n->H, n->W,
+                                   n->dw_seg, n->dw_units_per_strip, n->dw_partial, n->db_partial);
+        } else {
+            hipLaunchKernelGGL(k_conv_dw, dim3(nchunks, 9), dim3(kThreads), 0, n->stream, n->act[l], n->cin[l], dz, n->cout[l], P,
+                               n->H, n->W, n->dw_partial);
+        }
         NHIP(n, hipGetLastError());
-        hipLaunchKernelGGL(k_dw_reduce, dim3(grid_of(9 * (size_t)n->cin_r[l] * n->cout_r[l], 256)), dim3(256), 0, n->stream,
-                           n->dw_partial, nchunks, n->cin[l], n->cout[l], n->cin_r[l], n->cout_r[l], n->grads + n->w_off[l]);
+        hipLaunchKernelGGL(k_dw_reduce, dim3((9 * n->cin_r[l] * n->cout_r[l] + 63) / 64), dim3(256), 0, n->stream, n->dw_partial,
+                           parts, n->cin[l], n->cout[l], n->cin_r[l], n->cout_r[l], n->grads + n->w_off[l]);
         NHIP(n, hipGetLastError());
-        hipLaunchKernelGGL(k_db_partial, dim3(dbb), dim3(256), 0, n->stream, dz, n->cout[l], P, n->db_partial);
-        NHIP(n, hipGetLastError());
-        hipLaunchKernelGGL(k_sum_rows, dim3(n->cout[l]), dim3(256), 0, n->stream, n->db_partial, dbb, 64, n->cout[l],
+        int db_rows = parts;  // the strip kernel left one bias partial per work unit
+        if (!strip) {
+            hipLaunchKernelGGL(k_db_partial, dim3(dbb), dim3(256), 0, n->stream, dz, n->cout[l], P, n->db_partial);
+            NHIP(n, hipGetLastError());
+            db_rows = dbb;
+        }
+        hipLaunchKernelGGL(k_sum_rows, dim3(n->cout[l]), dim3(256), 0, n->stream, n->db_partial, db_rows, 64, n->cout[l],
                            n->grads + n->b_off[l]);
         NHIP(n, hipGetLastError());
         // gradient of the layer input times the ReLU derivative of that input (act[l] > 0)
