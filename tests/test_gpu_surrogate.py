@@ -258,6 +258,33 @@ def test_full_size_forward_matches_oracle():
     m.close()
 
 
+@pytest.mark.parametrize("B,H,W,C,L", [(2, 40, 70, 64, 6), (1, 12, 40, 32, 3)])
+def test_gradients_are_deterministic(B, H, W, C, L):
+    """Every reduction of the backward pass runs in a fixed order (per-unit partials summed in
+    unit order, fixed trees, no atomics): two passes on the same data, and a second network with
+    the same parameters, give bitwise equal gradients and losses."""
+    import torch
+
+    _note(f"deterministic gradients B={B} H={H} W={W} C={C} L={L}")
+    p = _params(C, L, seed=21)
+    s = torch.from_numpy(_state(B, H, W, seed=22)).cuda()
+    tgt = torch.from_numpy(_state(B, H, W, seed=23, amp=0.5)).cuda()
+    out = torch.empty_like(s)
+    runs = []
+    for _ in range(2):
+        m = net.Surrogate(B, H, W, channels=C, layers=L)
+        m.set_params(p)
+        m.set_output_scale(ALPHA)
+        for _ in range(2):
+            m.forward(s, out)
+            loss = m.backward(tgt)
+            runs.append((m.grads(), loss))
+        m.close()
+    for g, loss in runs[1:]:
+        assert np.array_equal(g, runs[0][0]) and loss == runs[0][1]
+    assert np.abs(runs[0][0]).max() > 0
+
+
 def test_training_steps_follow_the_oracle():
     """Five Adam iterations (forward, backward, update) of the kernels against the same
     iterations of the oracle, each started from the device parameters."""
