@@ -67,6 +67,16 @@ int lbcm_net_forward_planes(lbcm_net *n, const double *phi, const double *ux, co
 int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux, const double *uy, const double *rho,
                                double u_scale, double rho_scale, float *state);
 
+/* A training batch from recorded frames: state sample b (b < B) is frame frame_index[b] of the
+   device FP64 planes frames[c][f][y][x] (c = phi, v_x, v_y, rho, f < nframes, each H x W as the
+   network), transformed by element `symmetry` (0..7) of the square's symmetry group (transpose
+   if bit 2 is set, then flip y if bit 1, then flip x if bit 0; velocity components are swapped
+   and negated with the grid) and scaled as in lbcm_net_state_from_planes.  frame_index: host
+   int32[B], copied (each in [0, nframes)); state: device [B][H][W][4].  A transposing symmetry
+   needs H == W.  Asynchronous on the network's stream. */
+int lbcm_net_gather_states(lbcm_net *n, const double *frames, int64_t nframes, const int32_t *frame_index, int32_t symmetry,
+                           double u_scale, double rho_scale, float *state);
+
 /* Gradient of the loss mean(((out - target) / alpha)^2) over pixels and the 4 channels, after
    lbcm_net_forward (lbcm_net_forward_planes keeps no output state for it), into the internal FP32 gradient vector (same layout as the parameters).  *loss
    (host, may be NULL) receives the loss (then the call synchronises). */

@@ -1149,6 +1149,33 @@ __global__ void k_from_planes(const double *__restrict__ phi, const double *__re
     }
 }
 
+// A training batch from recorded frames: sample b of the state is frame idx[b] of the FP64 field
+// planes frames[c][f][y][x] (c = phi, v_x, v_y, rho), under symmetry k of the square lattice
+// (transpose if k & 4, then flip y if k & 2, then flip x if k & 1, velocity components swapped and
+// negated with it), converted as k_from_planes does.  The transform only moves and negates
+// values, so the result equals transforming the planes first.
+__global__ void k_gather_states(const double *__restrict__ frames, int64_t nframes, const int32_t *__restrict__ idx, int k, int B,
+                                int H, int W, float inv_u, float inv_r, float *__restrict__ s)
+{
+    const uint32_t hw = (uint32_t)H * W, total = (uint32_t)B * hw;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
+        const uint32_t b = p / hw, rem = p - b * hw;
+        int y = (int)(rem / W), x = (int)(rem % W);
+        if (k & 2) y = H - 1 - y;
+        if (k & 1) x = W - 1 - x;
+        const int ys = (k & 4) ? x : y, xs = (k & 4) ? y : x;
+        const size_t plane = (size_t)nframes * hw, at = (size_t)idx[b] * hw + (size_t)ys * W + xs;
+        const double vx = frames[plane + at], vy = frames[2 * plane + at];
+        const double ux = (k & 4) ? vy : vx, uy = (k & 4) ? vx : vy;
+        f32x4 v;
+        v[0] = (float)frames[at];
+        v[1] = (float)((k & 1) ? -ux : ux) * inv_u;
+        v[2] = (float)((k & 2) ? -uy : uy) * inv_u;
+        v[3] = (float)(frames[3 * plane + at] - 1.0) * inv_r;
+        *(f32x4 *)(s + (size_t)p * kStateC) = v;
+    }
+}
+
 // partial sums, one set per block (FP64), of the check: (phi_a - phi_b)^2, phi_b^2,
 // |v_a - v_b|^2 and |v_b|^2 over P points; a and b hold (phi, v_x, v_y) planes
 constexpr int kErrBlocks = 256, kErrSums = 4;
@@ -1199,6 +1226,7 @@ struct lbcm_net {
     std::vector<__bf16 *> Wf, Wb;               // BF16 packs of layers 1 .. L-1
     std::vector<__bf16 *> act;                  // act[l] = input of layer l >= 1 (relu output of layer l - 1)
     __bf16 *dz_a = nullptr, *dz_b = nullptr;    // gradient ping-pong buffers (P x 64)
+    int32_t *gather_idx = nullptr;              // frame indices of lbcm_net_gather_states (batch)
     float *resid = nullptr, *out = nullptr;     // FP32 [P][kStateC]: input state, output state
     float *dw_partial = nullptr, *db_partial = nullptr, *loss_partial = nullptr, *first_partial = nullptr;
     int loss_blocks = 0;
@@ -1459,7 +1487,8 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
         if (!dmalloc((void **)&n->act[l], P * channels * sizeof(__bf16))) return bail("out of device memory (activations)");
     if (!dmalloc((void **)&n->dz_a, P * 64 * sizeof(__bf16)) || !dmalloc((void **)&n->dz_b, P * 64 * sizeof(__bf16)))
         return bail("out of device memory (gradients)");
-    if (!dmalloc((void **)&n->resid, P * kStateC * sizeof(float)) || !dmalloc((void **)&n->out, P * kStateC * sizeof(float)))
+    if (!dmalloc((void **)&n->resid, P * kStateC * sizeof(float)) || !dmalloc((void **)&n->out, P * kStateC * sizeof(float)) ||
+        !dmalloc((void **)&n->gather_idx, (size_t)batch * sizeof(int32_t)))
         return bail("out of device memory (state)");
     const size_t nchunks = (P + kDwChunk - 1) / kDwChunk;
     {
@@ -1548,6 +1577,21 @@ int lbcm_net_state_from_planes(lbcm_net *n, const double *phi, const double *ux,
     if (!n || !phi || !ux || !uy || !rho || !state || !(u_scale > 0) || !(rho_scale > 0)) return LBCM_EINVAL;
     hipLaunchKernelGGL(k_from_planes, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, phi, ux, uy, rho, (float)(1.0 / u_scale),
                        (float)(1.0 / rho_scale), n->P, state);
+    NHIP(n, hipGetLastError());
+    return LBCM_OK;
+}
+
+int lbcm_net_gather_states(lbcm_net *n, const double *frames, int64_t nframes, const int32_t *frame_index, int32_t symmetry,
+                           double u_scale, double rho_scale, float *state)
+{
+    if (!n || !frames || !frame_index || !state || !(u_scale > 0) || !(rho_scale > 0)) return LBCM_EINVAL;
+    if (symmetry < 0 || symmetry > 7) return nfail(n, LBCM_EINVAL, "symmetry must be in [0, 7]");
+    if ((symmetry & 4) && n->H != n->W) return nfail(n, LBCM_EINVAL, "a transposing symmetry needs a square box");
+    for (int b = 0; b < n->batch; ++b)
+        if (frame_index[b] < 0 || frame_index[b] >= nframes) return nfail(n, LBCM_EINVAL, "frame index out of range");
+    NHIP(n, hipMemcpyAsync(n->gather_idx, frame_index, (size_t)n->batch * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+    hipLaunchKernelGGL(k_gather_states, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, frames, nframes, n->gather_idx, symmetry,
+                       n->batch, n->H, n->W, (float)(1.0 / u_scale), (float)(1.0 / rho_scale), state);
     NHIP(n, hipGetLastError());
     return LBCM_OK;
 }
@@ -1650,6 +1694,7 @@ int lbcm_net_destroy(lbcm_net *n)
     f(n->dz_b);
     f(n->resid);
     f(n->out);
+    f(n->gather_idx);
     f(n->dw_partial);
     f(n->db_partial);
     f(n->first_partial);

@@ -42,6 +42,7 @@ def load():
     lib.lbcm_net_forward.argtypes = [_H, _V, _V]
     lib.lbcm_net_forward_planes.argtypes = [_H, _V, _V, _V, _V, D, D, _V, _V, _V, _V]
     lib.lbcm_net_state_from_planes.argtypes = [_H, _V, _V, _V, _V, D, D, _V]
+    lib.lbcm_net_gather_states.argtypes = [_H, _V, ctypes.c_int64, ctypes.POINTER(I32), I32, D, D, _V]
     lib.lbcm_net_backward.argtypes = [_H, _V, _F]
     lib.lbcm_net_adam.argtypes = [_H, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int64]
     lib.lbcm_net_destroy.argtypes = [_H]
@@ -146,6 +147,18 @@ def lbcm_net_state_from_planes(n, phi, ux, uy, rho, u_scale, rho_scale, state):
     d = torch.float64
     _nchk(n, load().lbcm_net_state_from_planes(n, _dev(phi, d), _dev(ux, d), _dev(uy, d), _dev(rho, d), u_scale,
                                                rho_scale, _dev(state, torch.float32)))
+
+
+def lbcm_net_gather_states(n, frames, frame_index, symmetry, u_scale, rho_scale, state):
+    """frames: contiguous FP64 CUDA tensor [4, nframes, H, W]; frame_index: one int per sample."""
+    import torch
+
+    if frames.dim() != 4 or frames.shape[0] != 4:
+        raise ValueError("frames must have the shape [4, nframes, H, W]")
+    idx = np.ascontiguousarray(frame_index, dtype=np.int32)
+    _nchk(n, load().lbcm_net_gather_states(n, _dev(frames, torch.float64), frames.shape[1],
+                                           idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(symmetry), u_scale,
+                                           rho_scale, _dev(state, torch.float32)))
 
 
 def lbcm_net_backward(n, target, want_loss=True):
@@ -254,6 +267,11 @@ class Surrogate:
 
     def state_from_planes(self, phi, ux, uy, rho, u_scale, rho_scale, state):
         lbcm_net_state_from_planes(self.h, phi, ux, uy, rho, u_scale, rho_scale, state)
+
+    def gather_states(self, frames, frame_index, symmetry, u_scale, rho_scale, state):
+        if len(frame_index) != self.batch:
+            raise ValueError(f"expected {self.batch} frame indices")
+        lbcm_net_gather_states(self.h, frames, frame_index, symmetry, u_scale, rho_scale, state)
 
     def backward(self, target, want_loss=True):
         return lbcm_net_backward(self.h, target, want_loss)

@@ -91,19 +91,6 @@ def output_scale(frames, pairs, u_scale: float, rho_scale: float, sample: int = 
     return tuple(float(max(r, 1e-12)) for r in rms)
 
 
-def dihedral(planes, k: int):
-    """Element k (0..7) of the symmetry group of the square lattice applied to (phi, vx, vy, rho)
-    planes of shape [B, n, n]: optional transpose, then optional flips of y and of x."""
-    phi, vx, vy, rho = planes
-    if k & 4:
-        phi, vx, vy, rho = phi.transpose(1, 2), vy.transpose(1, 2), vx.transpose(1, 2), rho.transpose(1, 2)
-    if k & 2:
-        phi, vx, vy, rho = phi.flip(1), vx.flip(1), -vy.flip(1), rho.flip(1)
-    if k & 1:
-        phi, vx, vy, rho = phi.flip(2), -vx.flip(2), vy.flip(2), rho.flip(2)
-    return [p.contiguous() for p in (phi, vx, vy, rho)]
-
-
 def lr_at(it: int, iters: int, lr: float, warmup: int = 100, floor: float = 0.02) -> float:
     """Linear warm-up, then cosine decay to floor * lr."""
     if it < warmup:
@@ -146,12 +133,9 @@ def train(model: Surrogate, frames, pairs, u_scale: float, rho_scale: float, ite
             shift = np.maximum(0, m + 1 - room)
             sel[:, 0] -= shift
             sel[:, 1] = sel[:, 0] + m + 1
-        sel = torch.from_numpy(sel).to(frames.device)
-        k = int(d[B] % 8) if augment else 0
-        a = dihedral([frames[c].index_select(0, sel[:, 0]) for c in range(4)], k)
-        b = dihedral([frames[c].index_select(0, sel[:, 1]) for c in range(4)], k)
-        model.state_from_planes(*a, u_scale, rho_scale, xin)
-        model.state_from_planes(*b, u_scale, rho_scale, tgt)
+        k = int(d[B] % 8) if augment else 0  # one of the 8 symmetries of the square for the batch
+        model.gather_states(frames, sel[:, 0], k, u_scale, rho_scale, xin)
+        model.gather_states(frames, sel[:, 1], k, u_scale, rho_scale, tgt)
         if noise > 0:
             xin.add_(torch.randn(xin.shape, generator=gen, device=xin.device) * sigma)
         for _ in range(m):  # the network's own rollout, no gradient through it

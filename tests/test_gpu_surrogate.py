@@ -407,6 +407,55 @@ def test_forward_planes_equals_state_forward(B, H, W, C, L):
     m.close()
 
 
+def _dihedral(ph, vx, vy, rho, k):
+    """Reference symmetry k of the square on [n, n] planes: transpose, then flip y, then flip x,
+    the velocity swapped and negated with the grid."""
+    if k & 4:
+        ph, vx, vy, rho = ph.T, vy.T, vx.T, rho.T
+    if k & 2:
+        ph, vx, vy, rho = ph[::-1], vx[::-1], -vy[::-1], rho[::-1]
+    if k & 1:
+        ph, vx, vy, rho = ph[:, ::-1], -vx[:, ::-1], vy[:, ::-1], rho[:, ::-1]
+    return ph, vx, vy, rho
+
+
+@pytest.mark.parametrize("k", range(8))
+def test_gather_states_applies_the_symmetry(k):
+    """The training batch kernel equals, bit for bit, the symmetry applied to the FP64 planes
+    followed by the state conversion, for every element of the group."""
+    import torch
+
+    _note(f"gather states k={k}")
+    n, nf, us, rs = 12, 5, 0.03, 0.01
+    frames = np.stack([np.stack(inputs.smooth_state(n, n, seed=40 + f)) for f in range(nf)], axis=1)
+    frames = frames[[0, 2, 3, 1]]  # smooth_state gives (phi, rho, ux, uy): reorder to (phi, vx, vy, rho)
+    m = net.Surrogate(2, n, n, channels=32, layers=2)
+    st = torch.empty(2, n, n, S, dtype=torch.float32, device="cuda")
+    idx = [3, 1]
+    m.gather_states(torch.from_numpy(np.ascontiguousarray(frames)).cuda(), idx, k, us, rs, st)
+    got = st.cpu().numpy()
+    inv_u, inv_r = np.float32(1 / us), np.float32(1 / rs)
+    for b, f in enumerate(idx):
+        ph, vx, vy, rho = _dihedral(*frames[:, f], k)
+        expect = np.stack([ph.astype(np.float32), vx.astype(np.float32) * inv_u, vy.astype(np.float32) * inv_u,
+                           (rho - 1.0).astype(np.float32) * inv_r], axis=-1)
+        assert np.array_equal(got[b], expect)
+    m.close()
+
+
+def test_gather_states_rejects_bad_arguments():
+    import torch
+
+    m = net.Surrogate(2, 8, 12, channels=32, layers=2)
+    frames = torch.zeros(4, 3, 8, 12, dtype=torch.float64, device="cuda")
+    st = torch.empty(2, 8, 12, S, dtype=torch.float32, device="cuda")
+    m.gather_states(frames, [0, 2], 3, 1.0, 1.0, st)  # flips only: fine on a rectangle
+    for idx, k in (([0, 3], 0), ([0, -1], 0), ([0, 1], 4), ([0, 1], 8)):
+        with pytest.raises(lbcm.LbcmError):
+            m.gather_states(frames, idx, k, 1.0, 1.0, st)
+    m.close()
+
+
 def _hybrid_setup(threshold, n=64, J=4, K=8):
     import torch
 
