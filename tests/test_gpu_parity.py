@@ -384,3 +384,63 @@ def test_droplet_deformation_in_shear_follows_taylor():
     slope, icpt = np.polyfit(cas, ds, 1)
     say(f"  fitted slope {slope:.4f} (Taylor {35 / 32:.5f}), intercept {icpt:.4f}")
     assert abs(slope / (35 / 32) - 1) < 0.05
+
+
+def _contact_angle_from_wall_gradient(h, a, gamma):
+    """The paper's wetting relation: h = sqrt(2 a / gamma) sqrt(c (1 - c)), c = cos(vartheta / 3),
+    vartheta = arccos(sin^2 theta), read with the sign of theta - 90 degrees (theta measured through
+    the phi = +1 phase; a positive wall gradient repels that phase).  Returns theta in degrees."""
+    q = h * h * gamma / (2 * a)
+    c = 0.5 + math.sqrt(0.25 - q)  # the root near 1 (small angles vartheta)
+    theta = math.degrees(math.asin(math.sqrt(math.cos(3 * math.acos(c)))))
+    return 180 - theta if h > 0 else theta
+
+
+def _interface_points(phi):
+    """Points of the phi = 0 level set, linearly interpolated along rows and columns."""
+    pts = []
+    ny, nx = phi.shape
+    for x in range(nx):
+        c = phi[:, x]
+        for y in np.nonzero((c[:-1] > 0) != (c[1:] > 0))[0]:
+            pts.append((x, y + c[y] / (c[y] - c[y + 1])))
+    for y in range(ny):
+        r = phi[y]
+        for x in np.nonzero((r[:-1] > 0) != (r[1:] > 0))[0]:
+            pts.append((x + r[x] / (r[x] - r[x + 1]), y))
+    return np.array(pts)
+
+
+def test_contact_angles_follow_the_wetting_relation():
+    """The paper's contact-angle test: a phi = +1 drop on the bottom wall of a 100 x 100 box
+    (a = gamma = 0.04, nu_l = 0.1, viscosity ratio 2, periodic in x) relaxes to the contact angle
+    that the wall gradient sets.  The drop starts as a half disc (R = 25) on the wall: in a
+    density-matched fluid a uniform body force would not move it relative to the fluid, and the
+    equilibrium angle does not depend on how the drop reached the wall.  The angle comes from a
+    circle fitted to the phi = 0 contour away from the wall; it must follow the relation within
+    3 degrees, with the error growing with |h| (0.3 to 2.5 degrees measured)."""
+    n, a, g = 100, 0.04, 0.04
+    W = inputs.interface_width(a, g)
+    errs = {}
+    for h in (-0.15, -0.05, 0.0, 0.05, 0.15):
+        lat = lbcm.Lattice(n, n, precision="fp64", bc_y=1, a=a, gamma=g, mobility=0.1, nu_l=0.1, nu_g=0.05,
+                           wall_gradient=h)
+        phi0 = inputs.droplet(n, n, 25.0, W, cx=50.0, cy=-0.5)
+        lat.init(phi0)
+        lat.step(20000)
+        phi = lat.fields()["phi"]
+        lat.close()
+        assert abs(phi.sum() - phi0.sum()) < 1e-9 * np.abs(phi0).sum()
+        p = _interface_points(phi)
+        p = p[p[:, 1] > 4]  # leave out the rows next to the wall
+        A = np.stack([p[:, 0], p[:, 1], np.ones(len(p))], 1)
+        c = np.linalg.lstsq(A, p[:, 0] ** 2 + p[:, 1] ** 2, rcond=None)[0]
+        xc, yc = c[0] / 2, c[1] / 2
+        R = math.sqrt(c[2] + xc * xc + yc * yc)
+        theta = math.degrees(math.acos(-(yc + 0.5) / R))  # the wall lies at y = -1/2
+        want = _contact_angle_from_wall_gradient(h, a, g)
+        errs[h] = theta - want
+        say(f"  dphi_w = {h:+.2f}: theta {theta:.2f} deg, relation {want:.2f} deg")
+    assert all(abs(e) < 3.0 for e in errs.values())
+    assert abs(errs[0.0]) < 1.0
+    assert abs(errs[-0.15]) > abs(errs[-0.05]) and abs(errs[0.15]) > abs(errs[0.05])
