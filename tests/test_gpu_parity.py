@@ -444,3 +444,35 @@ def test_contact_angles_follow_the_wetting_relation():
     assert all(abs(e) < 3.0 for e in errs.values())
     assert abs(errs[0.0]) < 1.0
     assert abs(errs[-0.15]) > abs(errs[-0.05]) and abs(errs[0.15]) > abs(errs[0.05])
+
+
+def _pair_bytes(nodes, prec):
+    """Bytes of one (f, g) population pair in the workspace: the f set and the g set, each rounded
+    up to 256 bytes (16-bit modes keep g_0 in FP32)."""
+    f, g0, g = {"fp64": (8, 8, 8), "fp32": (4, 4, 4), "fp16s": (2, 4, 2), "bf16s": (2, 4, 2)}[prec]
+    up = lambda v: (v + 255) // 256 * 256
+    return up(9 * nodes * f) + up(nodes * g0 + 8 * nodes * g)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_every_slot_of_the_output_pair_is_written(prec):
+    """Poison test: before each step the pair it writes is filled with NaN bytes; a step that
+    left any slot unwritten (a ragged tile edge, a wall row) would carry them into the state.
+    The state must equal that of an unpoisoned run bit for bit.  Ragged tiles, walls (moving,
+    wetting) and a force."""
+    nx, ny = 70, 45
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=50)
+    kw = dict(precision=prec, bc_y=1, force_x=1e-5, wall_vx_top=1e-3, wall_gradient=0.02, nu_l=0.1, nu_g=0.02)
+    lat = lbcm.Lattice(nx, ny, **kw).init(phi, rho, ux, uy)
+    ref = lbcm.Lattice(nx, ny, **kw).init(phi, rho, ux, uy)
+    pb = _pair_bytes(nx * ny, prec)
+    assert lat.workspace.numel() >= 2 * pb
+    for s in range(4):
+        out = 1 - s % 2  # init leaves the state in pair 0; each step writes the other pair
+        lat.workspace[out * pb:(out + 1) * pb].fill_(255)
+        lat.step(1)
+        ref.step(1)
+        assert np.array_equal(lat.get_state(), ref.get_state()), s
+    assert np.isfinite(lat.fields()["phi"]).all()
+    lat.close()
+    ref.close()
