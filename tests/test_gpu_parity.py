@@ -260,6 +260,29 @@ def test_checkpoint_resume_bitwise():
     assert b.diag()["step"] == 10
 
 
+def test_recovery_from_a_corrupted_state():
+    """Snapshot, then the whole workspace corrupted (populations, partial sums and the divergence
+    flag filled with NaN bytes): the next checked step reports the divergence; restoring the
+    snapshot and continuing gives bitwise the uninterrupted run, with the check (every step)
+    quiet after the restore."""
+    nx, ny = 66, 33
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=37)
+    kw = dict(precision="fp32", check_every=1, **PHYS)
+    a = lbcm.Lattice(nx, ny, **kw).init(phi, rho, ux, uy).step(5)
+    snap = a.get_state()
+    a.step(5)
+    b = lbcm.Lattice(nx, ny, **kw).init(phi, rho, ux, uy).step(5)
+    b.workspace.fill_(255)
+    with pytest.raises(lbcm.LbcmError):
+        b.step(1)
+    b.set_state(snap, step=5)
+    b.step(5)
+    assert np.array_equal(a.get_state(), b.get_state())
+    assert b.diag()["step"] == 10 and b.diag()["nonfinite"] == 0
+    a.close()
+    b.close()
+
+
 def test_errors_and_divergence_flag():
     lat = lbcm.Lattice(16, 16, precision="fp32", check_every=1)
     with pytest.raises(lbcm.LbcmError) as e:
