@@ -72,9 +72,10 @@ typedef struct lbcm_params {
     int32_t check_every; /* > 0: lbcm_step synchronises every check_every steps and at its end
                             and returns LBCM_EDIVERGED once a non-finite rho or phi was seen;
                             0: no check (lbcm_diag still reports it) */
-    int32_t tile_rows;   /* step-kernel tile height in rows (one wave per row), 0 = default */
+    int32_t tile_rows;   /* step-kernel tile height in wave rows, 0 = default; a wave row covers
+                            one lattice row (FP64, FP32) or two (16-bit storage) */
     int32_t tile_wx;     /* step-kernel tile width in waves of 64 columns, 0 = default;
-                            tile_wx * tile_rows is capped at 16 (FP32) or 8 (FP64) waves */
+                            tile_wx * tile_rows is capped at 16 (FP32, 16-bit) or 8 (FP64) waves */
     void *stream;        /* hipStream_t to queue work on; NULL = null stream */
     void *workspace;     /* optional caller-owned device memory of lbcm_workspace_size() bytes,
                             256-byte aligned; NULL = the library allocates and frees it */
@@ -172,7 +173,7 @@ int64_t lbcm_step_count(const lbcm_handle *h);
    workspace: as given at creation, NULL when the library allocated it). */
 int lbcm_info(const lbcm_handle *h, lbcm_params *out);
 
-/* Tile shape the step kernel uses (after clamping to the lattice). */
+/* Tile shape the step kernel uses (after clamping to the lattice): waves across, wave rows down. */
 int lbcm_tile_shape(const lbcm_handle *h, int32_t *wx, int32_t *rows);
 
 /* ---------------------------------------------------------------------------------------------

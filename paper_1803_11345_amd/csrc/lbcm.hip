@@ -42,8 +42,9 @@
 
 namespace {
 
-constexpr int kDefaultRows = 2;  // rows per tile (one wave row each)
+constexpr int kDefaultRows = 2;  // wave rows per tile
 constexpr int kDefaultWx = 8;    // 64-column waves across a tile
+constexpr int kDefaultWx16 = 4;  // the same with 16-bit storage (two lattice rows per wave row)
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
 constexpr int kDiagFields = 7;
@@ -108,11 +109,14 @@ template <> struct Elem<__bf16> {
     }
 };
 
-// Storage modes: compute type R, type of the f planes, of g_0 and of g_1..g_8.
-struct ModeF64 { using R = double; using F = double; using G0 = double; using G = double; };
-struct ModeF32 { using R = float; using F = float; using G0 = float; using G = float; };
-struct ModeF16 { using R = float; using F = _Float16; using G0 = float; using G = _Float16; };
-struct ModeB16 { using R = float; using F = __bf16; using G0 = float; using G = __bf16; };
+// Storage modes: compute type R, type of the f planes, of g_0 and of g_1..g_8, and the lattice
+// rows each wave of the step kernel updates (two with 16-bit storage, whose loads carry half the
+// bytes: two rows per wave keep as many bytes in flight per wave as one FP32 row).
+struct ModeF64 { using R = double; using F = double; using G0 = double; using G = double; static constexpr int kRpw = 1; };
+struct ModeF32 { using R = float; using F = float; using G0 = float; using G = float; static constexpr int kRpw = 1; };
+struct ModeF16 { using R = float; using F = _Float16; using G0 = float; using G = _Float16; static constexpr int kRpw = 2; };
+struct ModeB16 { using R = float; using F = __bf16; using G0 = float; using G = __bf16; static constexpr int kRpw = 2; };
+static_assert(ModeF64::kRpw == ModeF32::kRpw && ModeB16::kRpw == ModeF16::kRpw, "rows per wave follow the storage width");
 
 // Byte offset of plane i in a set whose plane 0 has element type T0 and planes 1..8 type T.
 template <class T0, class T> __device__ __forceinline__ uint32_t plane_off(int i, uint32_t N)
@@ -172,7 +176,8 @@ struct Geo {
     int nx, ny;
     uint32_t plane;     // nx * ny
     int wx;             // wave columns per tile (tile width 64 * wx)
-    int rows;           // rows per tile (one wave row each)
+    int rows;           // wave rows per tile
+    int rpw;            // lattice rows per wave row (the mode's kRpw); tile height rows * rpw
     int nbands, nrows;  // tiles across and down
     int walls;
     double ub6, ut6;    // x velocities of the bottom and top walls, divided by 6
@@ -454,8 +459,10 @@ __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, 
 }
 
 // ------------------------------------------------------------------------------------------
-// the step kernel.  A workgroup owns a tile of 64 * wx columns by `rows` rows; each of its waves
-// owns one 64-column row segment.  Every wave pulls f and g of its own nodes, sums phi into an
+// the step kernel.  A workgroup owns a tile of 64 * wx columns by rows * kRpw lattice rows; each
+// of its waves owns a 64-column segment of kRpw rows (one node per lane and row; two rows with
+// 16-bit storage, so that a wave has as many bytes in flight as with FP32 storage and one row:
+// 2-4 % faster there).  Every wave pulls f and g of its own nodes, sums phi into an
 // LDS tile with a one-node halo, and the halo is filled by the same pulls one node further out:
 // the waves of the first and last tile row also pull g of the rows above and below, and lanes 0
 // and 1 of the first wave column pull the two halo columns.  One barrier later every node reads
@@ -471,6 +478,7 @@ template <class M> constexpr int kMaxThreads = sizeof(typename M::R) == 8 ? 512 
 
 // One tile (band, rg) of one lattice; called by the single-lattice and the batched kernels with
 // the workgroup's LDS.  All threads of the workgroup must call it (it contains the barrier).
+// Wave row wr updates the lattice rows y0 + RPW * wr + k, k < RPW, of the tile.
 template <class M, bool WALLS, bool FORCE>
 __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ ga,
                                           unsigned char *__restrict__ fb, unsigned char *__restrict__ gb,
@@ -481,10 +489,11 @@ __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, 
     using F = typename M::F;
     using G0 = typename M::G0;
     using G = typename M::G;
+    constexpr int RPW = M::kRpw;
 
     const int nx = geo.nx, ny = geo.ny;
     const uint32_t N = geo.plane;
-    const int wx = geo.wx, rows_t = geo.rows;
+    const int wx = geo.wx;
     const int ldw = 64 * wx + 2;
     const int lane = threadIdx.x & 63;
     // wave index made explicitly uniform, so that the row offsets stay scalar
@@ -492,15 +501,12 @@ __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, 
     const int wc = wave % wx, wr = wave / wx;  // wave column and row inside the tile
     const int X0 = band * 64 * wx;
     const int X1 = min(X0 + 64 * wx, nx);
-    const int y0 = rg * rows_t;
-    const int y1 = min(y0 + rows_t, ny);
-    const int y = y0 + wr;
-    const bool row_ok = y < y1;  // uniform per wave
+    const int y0 = rg * geo.rows * RPW;
+    const int y1 = min(y0 + geo.rows * RPW, ny);
+    const int last = y1 - y0 - 1;  // last valid tile row
     const int xr_ = X0 + wc * 64 + lane;
     const bool col_ok = xr_ < X1;
-    const bool valid = row_ok && col_ok;
     const int x = col_ok ? xr_ : X1 - 1;  // clamped for addressing
-    const int yy = row_ok ? y : y1 - 1;
     const uint32_t xl = x == 0 ? nx - 1 : x - 1;
     const uint32_t xr = x == nx - 1 ? 0 : x + 1;
     const rsrc_t rfa = make_rsrc(fa, set_bytes<F, F>(N));
@@ -508,26 +514,23 @@ __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, 
     const rsrc_t rfb = make_rsrc(fb, set_bytes<F, F>(N));
     const rsrc_t rgb = make_rsrc(gb, set_bytes<G0, G>(N));
     const int slot = wc * 64 + lane + 1;  // LDS column of this lane
-    const int last = y1 - y0 - 1;         // last valid tile row
     auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
 
     // own populations; the loads go out at raised wave priority so that the memory pipeline of
     // the CU keeps being fed while other workgroups compute
     __builtin_amdgcn_s_setprio(3);
-    R g[9], f[9];
-    pull_row<F, F, R, WALLS>(rfa, N, nx, ny, yy, (uint32_t)x, xl, xr, f);
-    pull_row<G0, G, R, WALLS>(rga, N, nx, ny, yy, (uint32_t)x, xl, xr, g);
-    const R phi_own = sum9(g);  // the wall corrections of g cancel in the sum
-    if (WALLS) {
-        const bool bot = yy == 0, top = yy == ny - 1;
-        wall_motion(f, (R)1, bot, top, c.ub6, c.ut6);
-        wall_motion(g, phi_own, bot, top, c.ub6, c.ut6);
+    R g[RPW][9], f[RPW][9];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+        const int tr = wr * RPW + k;
+        const int yy = min(y0 + tr, y1 - 1);  // clamped for addressing
+        pull_row<F, F, R, WALLS>(rfa, N, nx, ny, yy, (uint32_t)x, xl, xr, f[k]);
+        pull_row<G0, G, R, WALLS>(rga, N, nx, ny, yy, (uint32_t)x, xl, xr, g[k]);
     }
-    if (valid) phs[(wr + 1) * ldw + slot] = phi_own;
 
     // halo rows: the first tile row fetches the row above, the last valid one the row below;
     // behind a wall the ghost row holds the first / last row's phi minus the wall gradient
-    auto halo_row = [&](int hy, int srow) {
+    auto halo_row = [&](int hy, int srow, R phi_own) {
         if (WALLS && (hy < 0 || hy >= ny)) {
             if (col_ok) phs[srow * ldw + slot] = phi_own - c.wgrad;
         } else {
@@ -536,60 +539,81 @@ __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, 
             if (col_ok) phs[srow * ldw + slot] = sum9(h);
         }
     };
-    if (wr == 0) halo_row(y0 - 1, 0);
-    if (wr == last) halo_row(y1, last + 2);
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+        const int tr = wr * RPW + k;
+        const int yy = min(y0 + tr, y1 - 1);
+        const R phi_own = sum9(g[k]);  // the wall corrections of g cancel in the sum
+        if (WALLS) {
+            const bool bot = yy == 0, top = yy == ny - 1;
+            wall_motion(f[k], (R)1, bot, top, c.ub6, c.ut6);
+            wall_motion(g[k], phi_own, bot, top, c.ub6, c.ut6);
+        }
+        if (tr <= last && col_ok) phs[(tr + 1) * ldw + slot] = phi_own;
+        if (tr == 0) halo_row(y0 - 1, 0, phi_own);
+        if (tr == last) halo_row(y1, last + 2, phi_own);
+    }
 
-    // halo columns (x = X0 - 1 on lane 0, x = X1 on lane 1) for this wave's row and, on the
+    // halo columns (x = X0 - 1 on lane 0, x = X1 on lane 1) for this wave's rows and, on the
     // first / last tile row, the corner rows
-    if (wc == 0 && lane < 2 && wr <= last) {
+    if (wc == 0 && lane < 2) {
         const uint32_t hx = lane == 0 ? (X0 == 0 ? nx - 1 : X0 - 1) : (X1 == nx ? 0 : X1);
         const uint32_t hxl = hx == 0 ? nx - 1 : hx - 1, hxr = hx == (uint32_t)nx - 1 ? 0 : hx + 1;
         const int hs = lane == 0 ? 0 : X1 - X0 + 1;
-        R h[9];
-        pull_row<G0, G, R, WALLS>(rga, N, nx, ny, y, hx, hxl, hxr, h);
-        const R ph = sum9(h);
-        phs[(wr + 1) * ldw + hs] = ph;
-        for (int side = 0; side < 2; ++side) {
-            if (side == 0 && wr != 0) continue;
-            if (side == 1 && wr != last) continue;
-            const int hy = side == 0 ? y0 - 1 : y1;
-            const int srow = side == 0 ? 0 : last + 2;
-            if (WALLS && (hy < 0 || hy >= ny)) {
-                phs[srow * ldw + hs] = ph - c.wgrad;
-            } else {
-                R h2[9];
-                pull_row<G0, G, R, WALLS>(rga, N, nx, ny, wrap_row(hy), hx, hxl, hxr, h2);
-                phs[srow * ldw + hs] = sum9(h2);
+        for (int k = 0; k < RPW; ++k) {
+            const int tr = wr * RPW + k;
+            if (tr > last) break;
+            R h[9];
+            pull_row<G0, G, R, WALLS>(rga, N, nx, ny, y0 + tr, hx, hxl, hxr, h);
+            const R ph = sum9(h);
+            phs[(tr + 1) * ldw + hs] = ph;
+            for (int side = 0; side < 2; ++side) {
+                if (side == 0 && tr != 0) continue;
+                if (side == 1 && tr != last) continue;
+                const int hy = side == 0 ? y0 - 1 : y1;
+                const int srow = side == 0 ? 0 : last + 2;
+                if (WALLS && (hy < 0 || hy >= ny)) {
+                    phs[srow * ldw + hs] = ph - c.wgrad;
+                } else {
+                    R h2[9];
+                    pull_row<G0, G, R, WALLS>(rga, N, nx, ny, wrap_row(hy), hx, hxl, hxr, h2);
+                    phs[srow * ldw + hs] = sum9(h2);
+                }
             }
         }
     }
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
-    if (!row_ok) return;
 
-    const R *rS = phs + wr * ldw, *rC = phs + (wr + 1) * ldw, *rN = phs + (wr + 2) * ldw;
-    const R pS = rS[slot], pSW = rS[slot - 1], pSE = rS[slot + 1];
-    const R pC = rC[slot], pW = rC[slot - 1], pE = rC[slot + 1];
-    const R pN = rN[slot], pNW = rN[slot - 1], pNE = rN[slot + 1];
-    const R dpx = ((R)4 * (pE - pW) + (pNE - pNW) + (pSE - pSW)) * (R)(1.0 / 12.0);
-    const R dpy = ((R)4 * (pN - pS) + (pNE - pSE) + (pNW - pSW)) * (R)(1.0 / 12.0);
-    const R lap = ((R)4 * ((pE + pW) + (pN + pS)) + ((pNE + pNW) + (pSE + pSW)) - (R)20 * pC) *
-                  (R)(1.0 / 6.0);
-
-    R fo[9], go[9], rho;
-    collide_node<R, FORCE>(f, g, pC, dpx, dpy, lap, c, fo, go, rho);
-    const bool bad = !(std::isfinite(rho) && std::isfinite(pC)) && col_ok;
-    if (__any(bad) && lane == 0) atomicOr(flag, 1);
-
-    if (col_ok) {
-        const uint32_t ux_ = (uint32_t)x, uy_ = (uint32_t)y, unx = (uint32_t)nx;
-        constexpr uint32_t bf = sizeof(F), bg0 = sizeof(G0), bg = sizeof(G);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Elem<F>::template st<R>(rfb, ux_ * bf, plane_off<F, F>(i, N) + uy_ * unx * bf, fo[i]);
-        Elem<G0>::template st<R>(rgb, ux_ * bg0, uy_ * unx * bg0, go[0]);
+    for (int k = 0; k < RPW; ++k) {
+        const int tr = wr * RPW + k;
+        if (tr > last) break;  // uniform per wave
+        const int y = y0 + tr;
+        const R *rS = phs + tr * ldw, *rC = phs + (tr + 1) * ldw, *rN = phs + (tr + 2) * ldw;
+        const R pS = rS[slot], pSW = rS[slot - 1], pSE = rS[slot + 1];
+        const R pC = rC[slot], pW = rC[slot - 1], pE = rC[slot + 1];
+        const R pN = rN[slot], pNW = rN[slot - 1], pNE = rN[slot + 1];
+        const R dpx = ((R)4 * (pE - pW) + (pNE - pNW) + (pSE - pSW)) * (R)(1.0 / 12.0);
+        const R dpy = ((R)4 * (pN - pS) + (pNE - pSE) + (pNW - pSW)) * (R)(1.0 / 12.0);
+        const R lap = ((R)4 * ((pE + pW) + (pN + pS)) + ((pNE + pNW) + (pSE + pSW)) - (R)20 * pC) *
+                      (R)(1.0 / 6.0);
+
+        R fo[9], go[9], rho;
+        collide_node<R, FORCE>(f[k], g[k], pC, dpx, dpy, lap, c, fo, go, rho);
+        const bool bad = !(std::isfinite(rho) && std::isfinite(pC)) && col_ok;
+        if (__any(bad) && lane == 0) atomicOr(flag, 1);
+
+        if (col_ok) {
+            const uint32_t ux_ = (uint32_t)x, uy_ = (uint32_t)y, unx = (uint32_t)nx;
+            constexpr uint32_t bf = sizeof(F), bg0 = sizeof(G0), bg = sizeof(G);
 #pragma unroll
-        for (int i = 1; i < 9; ++i)
-            Elem<G>::template st<R>(rgb, ux_ * bg, plane_off<G0, G>(i, N) + uy_ * unx * bg, go[i]);
+            for (int i = 0; i < 9; ++i) Elem<F>::template st<R>(rfb, ux_ * bf, plane_off<F, F>(i, N) + uy_ * unx * bf, fo[i]);
+            Elem<G0>::template st<R>(rgb, ux_ * bg0, uy_ * unx * bg0, go[0]);
+#pragma unroll
+            for (int i = 1; i < 9; ++i)
+                Elem<G>::template st<R>(rgb, ux_ * bg, plane_off<G0, G>(i, N) + uy_ * unx * bg, go[i]);
+        }
     }
 }
 
@@ -950,6 +974,14 @@ template <class R> Phys<R> make_phys(const lbcm_params &p)
     return c;
 }
 
+int rows_per_wave(int precision)
+{
+    return precision == LBCM_FP16_SHIFTED || precision == LBCM_BF16_SHIFTED ? ModeF16::kRpw : ModeF32::kRpw;
+}
+
+// LDS of one step tile: its phi with a one-node halo
+size_t tile_lds_bytes(const Geo &g, size_t elem) { return (size_t)(g.rows * g.rpw + 2) * (64 * g.wx + 2) * elem; }
+
 Geo make_geo(const lbcm_params &p)
 {
     Geo g;
@@ -958,15 +990,16 @@ Geo make_geo(const lbcm_params &p)
     g.plane = (uint32_t)((size_t)p.nx * p.ny);
     const int max_waves = (p.precision == LBCM_FP64 ? 512 : 1024) / 64;
     const int need = (p.nx + 63) / 64;
-    g.wx = p.tile_wx > 0 ? p.tile_wx : kDefaultWx;
+    g.rpw = rows_per_wave(p.precision);
+    g.wx = p.tile_wx > 0 ? p.tile_wx : (g.rpw == 2 ? kDefaultWx16 : kDefaultWx);
     if (g.wx > need) g.wx = need;
     if (g.wx > max_waves) g.wx = max_waves;
     int rows = p.tile_rows > 0 ? p.tile_rows : kDefaultRows;
     if (rows > max_waves / g.wx) rows = max_waves / g.wx;
-    if (rows > p.ny) rows = p.ny;
+    if (rows > (p.ny + g.rpw - 1) / g.rpw) rows = (p.ny + g.rpw - 1) / g.rpw;
     g.rows = rows;
     g.nbands = (p.nx + 64 * g.wx - 1) / (64 * g.wx);
-    g.nrows = (p.ny + g.rows - 1) / g.rows;
+    g.nrows = (p.ny + g.rows * g.rpw - 1) / (g.rows * g.rpw);
     g.walls = p.bc_y;
     g.ub6 = p.wall_vx_bottom / 6.0;
     g.ut6 = p.wall_vx_top / 6.0;
@@ -1011,8 +1044,9 @@ template <class M> int launch_steps(lbcm_handle *h, int64_t nsteps)
     const bool force = h->p.force_x != 0 || h->p.force_y != 0;
     const int64_t nblk = (int64_t)geo.nbands * geo.nrows;
     if (nblk > 0x7fffffff) return fail(h, LBCM_EINVAL, "too many tiles");
+    if (geo.rpw != M::kRpw) return fail(h, LBCM_EINVAL, "tile geometry does not match the storage mode");
     const dim3 grid((unsigned)nblk), block(64 * geo.wx * geo.rows);
-    const size_t lds = (size_t)(geo.rows + 2) * (64 * geo.wx + 2) * sizeof(R);
+    const size_t lds = tile_lds_bytes(geo, sizeof(R));
     for (int64_t s = 0; s < nsteps; ++s) {
         const unsigned char *fa = set_base(h, h->cur, 0), *ga = set_base(h, h->cur, 1);
         unsigned char *fb = set_base(h, 1 - h->cur, 0), *gb = set_base(h, 1 - h->cur, 1);
@@ -1048,7 +1082,7 @@ template <class M> float time_tiles(lbcm_handle *h, int wx, int rows, int trials
     const Phys<R> c = make_phys<R>(q);
     const bool walls = q.bc_y == LBCM_BC_WALLS, force = q.force_x != 0 || q.force_y != 0;
     const dim3 grid((unsigned)(geo.nbands * geo.nrows)), block(64 * geo.wx * geo.rows);
-    const size_t lds = (size_t)(geo.rows + 2) * (64 * geo.wx + 2) * sizeof(R);
+    const size_t lds = tile_lds_bytes(geo, sizeof(R));
     const unsigned char *fa = set_base(h, h->cur, 0), *ga = set_base(h, h->cur, 1);
     unsigned char *fb = set_base(h, 1 - h->cur, 0), *gb = set_base(h, 1 - h->cur, 1);
     hipEvent_t e0, e1;
@@ -1251,7 +1285,7 @@ template <class M> int build_tables(lbcm_batch *b)
         const size_t nt = (size_t)d.geo.nbands * d.geo.nrows;
         if (tile_box.size() + nt > 0x7fffffff) return bfail(b, LBCM_EINVAL, "too many tiles");
         tile_box.insert(tile_box.end(), nt, i);
-        lds = std::max(lds, (size_t)(d.geo.rows + 2) * (64 * d.geo.wx + 2) * sizeof(R));
+        lds = std::max(lds, tile_lds_bytes(d.geo, sizeof(R)));
     }
     drop_graph(b);
     if (b->d_desc) (void)hipFree(b->d_desc);
