@@ -476,10 +476,136 @@ __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, 
 
 template <class M> constexpr int kMaxThreads = sizeof(typename M::R) == 8 ? 512 : 1024;
 
-// One tile (band, rg) of one lattice; called by the single-lattice and the batched kernels with
-// the workgroup's LDS.  All threads of the workgroup must call it (it contains the barrier).
-// Wave row wr updates the lattice rows y0 + RPW * wr + k, k < RPW, of the tile.
+// One tile (band, rg) of one lattice, one lattice row per wave row; called by the kernels with the
+// workgroup's LDS.  All threads of the workgroup must call it (it contains the barrier).  The
+// two-row tile below computes the same thing; this one is kept separate because written as its
+// RPW = 1 case the compiler needs ~35 more scalar registers (100 and more with walls), which
+// leaves room for one 1024-thread workgroup per CU instead of two.
 template <class M, bool WALLS, bool FORCE>
+__device__ __forceinline__ void step_tile_row(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ ga,
+                                          unsigned char *__restrict__ fb, unsigned char *__restrict__ gb,
+                                          const Geo &geo, const Phys<typename M::R> &c, int *__restrict__ flag,
+                                          int band, int rg, typename M::R *phs)
+{
+    using R = typename M::R;
+    using F = typename M::F;
+    using G0 = typename M::G0;
+    using G = typename M::G;
+
+    const int nx = geo.nx, ny = geo.ny;
+    const uint32_t N = geo.plane;
+    const int wx = geo.wx, rows_t = geo.rows;
+    const int ldw = 64 * wx + 2;
+    const int lane = threadIdx.x & 63;
+    // wave index made explicitly uniform, so that the row offsets stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wc = wave % wx, wr = wave / wx;  // wave column and row inside the tile
+    const int X0 = band * 64 * wx;
+    const int X1 = min(X0 + 64 * wx, nx);
+    const int y0 = rg * rows_t;
+    const int y1 = min(y0 + rows_t, ny);
+    const int y = y0 + wr;
+    const bool row_ok = y < y1;  // uniform per wave
+    const int xr_ = X0 + wc * 64 + lane;
+    const bool col_ok = xr_ < X1;
+    const bool valid = row_ok && col_ok;
+    const int x = col_ok ? xr_ : X1 - 1;  // clamped for addressing
+    const int yy = row_ok ? y : y1 - 1;
+    const uint32_t xl = x == 0 ? nx - 1 : x - 1;
+    const uint32_t xr = x == nx - 1 ? 0 : x + 1;
+    const rsrc_t rfa = make_rsrc(fa, set_bytes<F, F>(N));
+    const rsrc_t rga = make_rsrc(ga, set_bytes<G0, G>(N));
+    const rsrc_t rfb = make_rsrc(fb, set_bytes<F, F>(N));
+    const rsrc_t rgb = make_rsrc(gb, set_bytes<G0, G>(N));
+    const int slot = wc * 64 + lane + 1;  // LDS column of this lane
+    const int last = y1 - y0 - 1;         // last valid tile row
+    auto wrap_row = [&](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
+
+    // own populations; the loads go out at raised wave priority so that the memory pipeline of
+    // the CU keeps being fed while other workgroups compute
+    __builtin_amdgcn_s_setprio(3);
+    R g[9], f[9];
+    pull_row<F, F, R, WALLS>(rfa, N, nx, ny, yy, (uint32_t)x, xl, xr, f);
+    pull_row<G0, G, R, WALLS>(rga, N, nx, ny, yy, (uint32_t)x, xl, xr, g);
+    const R phi_own = sum9(g);  // the wall corrections of g cancel in the sum
+    if (WALLS) {
+        const bool bot = yy == 0, top = yy == ny - 1;
+        wall_motion(f, (R)1, bot, top, c.ub6, c.ut6);
+        wall_motion(g, phi_own, bot, top, c.ub6, c.ut6);
+    }
+    if (valid) phs[(wr + 1) * ldw + slot] = phi_own;
+
+    // halo rows: the first tile row fetches the row above, the last valid one the row below;
+    // behind a wall the ghost row holds the first / last row's phi minus the wall gradient
+    auto halo_row = [&](int hy, int srow) {
+        if (WALLS && (hy < 0 || hy >= ny)) {
+            if (col_ok) phs[srow * ldw + slot] = phi_own - c.wgrad;
+        } else {
+            R h[9];
+            pull_row<G0, G, R, WALLS>(rga, N, nx, ny, wrap_row(hy), (uint32_t)x, xl, xr, h);
+            if (col_ok) phs[srow * ldw + slot] = sum9(h);
+        }
+    };
+    if (wr == 0) halo_row(y0 - 1, 0);
+    if (wr == last) halo_row(y1, last + 2);
+
+    // halo columns (x = X0 - 1 on lane 0, x = X1 on lane 1) for this wave's row and, on the
+    // first / last tile row, the corner rows
+    if (wc == 0 && lane < 2 && wr <= last) {
+        const uint32_t hx = lane == 0 ? (X0 == 0 ? nx - 1 : X0 - 1) : (X1 == nx ? 0 : X1);
+        const uint32_t hxl = hx == 0 ? nx - 1 : hx - 1, hxr = hx == (uint32_t)nx - 1 ? 0 : hx + 1;
+        const int hs = lane == 0 ? 0 : X1 - X0 + 1;
+        R h[9];
+        pull_row<G0, G, R, WALLS>(rga, N, nx, ny, y, hx, hxl, hxr, h);
+        const R ph = sum9(h);
+        phs[(wr + 1) * ldw + hs] = ph;
+        for (int side = 0; side < 2; ++side) {
+            if (side == 0 && wr != 0) continue;
+            if (side == 1 && wr != last) continue;
+            const int hy = side == 0 ? y0 - 1 : y1;
+            const int srow = side == 0 ? 0 : last + 2;
+            if (WALLS && (hy < 0 || hy >= ny)) {
+                phs[srow * ldw + hs] = ph - c.wgrad;
+            } else {
+                R h2[9];
+                pull_row<G0, G, R, WALLS>(rga, N, nx, ny, wrap_row(hy), hx, hxl, hxr, h2);
+                phs[srow * ldw + hs] = sum9(h2);
+            }
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
+    if (!row_ok) return;
+
+    const R *rS = phs + wr * ldw, *rC = phs + (wr + 1) * ldw, *rN = phs + (wr + 2) * ldw;
+    const R pS = rS[slot], pSW = rS[slot - 1], pSE = rS[slot + 1];
+    const R pC = rC[slot], pW = rC[slot - 1], pE = rC[slot + 1];
+    const R pN = rN[slot], pNW = rN[slot - 1], pNE = rN[slot + 1];
+    const R dpx = ((R)4 * (pE - pW) + (pNE - pNW) + (pSE - pSW)) * (R)(1.0 / 12.0);
+    const R dpy = ((R)4 * (pN - pS) + (pNE - pSE) + (pNW - pSW)) * (R)(1.0 / 12.0);
+    const R lap = ((R)4 * ((pE + pW) + (pN + pS)) + ((pNE + pNW) + (pSE + pSW)) - (R)20 * pC) *
+                  (R)(1.0 / 6.0);
+
+    R fo[9], go[9], rho;
+    collide_node<R, FORCE>(f, g, pC, dpx, dpy, lap, c, fo, go, rho);
+    const bool bad = !(std::isfinite(rho) && std::isfinite(pC)) && col_ok;
+    if (__any(bad) && lane == 0) atomicOr(flag, 1);
+
+    if (col_ok) {
+        const uint32_t ux_ = (uint32_t)x, uy_ = (uint32_t)y, unx = (uint32_t)nx;
+        constexpr uint32_t bf = sizeof(F), bg0 = sizeof(G0), bg = sizeof(G);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Elem<F>::template st<R>(rfb, ux_ * bf, plane_off<F, F>(i, N) + uy_ * unx * bf, fo[i]);
+        Elem<G0>::template st<R>(rgb, ux_ * bg0, uy_ * unx * bg0, go[0]);
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+            Elem<G>::template st<R>(rgb, ux_ * bg, plane_off<G0, G>(i, N) + uy_ * unx * bg, go[i]);
+    }
+}
+
+// One tile (band, rg) of one lattice with RPW lattice rows per wave row: wave row wr updates the
+// rows y0 + RPW * wr + k, k < RPW, of the tile.  All threads of the workgroup must call it.
+template <class M, int RPW, bool WALLS, bool FORCE>
 __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ ga,
                                           unsigned char *__restrict__ fb, unsigned char *__restrict__ gb,
                                           const Geo &geo, const Phys<typename M::R> &c, int *__restrict__ flag,
@@ -489,7 +615,10 @@ __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, 
     using F = typename M::F;
     using G0 = typename M::G0;
     using G = typename M::G;
-    constexpr int RPW = M::kRpw;
+    if constexpr (RPW == 1) {
+        step_tile_row<M, WALLS, FORCE>(fa, ga, fb, gb, geo, c, flag, band, rg, phs);
+        return;
+    }
 
     const int nx = geo.nx, ny = geo.ny;
     const uint32_t N = geo.plane;
@@ -617,7 +746,7 @@ __device__ __forceinline__ void step_tile(const unsigned char *__restrict__ fa, 
     }
 }
 
-template <class M, bool WALLS, bool FORCE>
+template <class M, int RPW, bool WALLS, bool FORCE>
 __global__ __launch_bounds__(kMaxThreads<M>) void
 k_step(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ ga,
        unsigned char *__restrict__ fb, unsigned char *__restrict__ gb, Geo geo,
@@ -625,14 +754,16 @@ k_step(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ g
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int band = blockIdx.x % geo.nbands, rg = blockIdx.x / geo.nbands;
-    step_tile<M, WALLS, FORCE>(fa, ga, fb, gb, geo, c, flag, band, rg, reinterpret_cast<typename M::R *>(lds_raw));
+    step_tile<M, RPW, WALLS, FORCE>(fa, ga, fb, gb, geo, c, flag, band, rg, reinterpret_cast<typename M::R *>(lds_raw));
 }
 
 // ------------------------------------------------------------------------------------------
 // batched step: every tile of every box of an ensemble in one launch.  The tiles of box b are
 // the flat grid indices [first_tile, first_tile + nbands * nrows) in the box's row-major order;
 // tile_box maps a grid index to its box.  Each box has its own size, tile shape (within the
-// launch's workgroup size), boundaries, force and physics.
+// launch's workgroup size), boundaries, force and physics.  Every wave updates one lattice row,
+// in the 16-bit modes too: the small tiles of an ensemble gain nothing from the longer loads in
+// flight of two-row waves, and lose the occupancy their registers cost.
 
 template <class R> struct BoxDesc {
     Geo geo;
@@ -658,11 +789,11 @@ __global__ __launch_bounds__(kMaxThreads<M>) void k_step_batch(const BoxDesc<typ
     unsigned char *fb = const_cast<unsigned char *>(d.set[1 - cur][0]);
     unsigned char *gb = const_cast<unsigned char *>(d.set[1 - cur][1]);
     if (d.walls) {
-        if (d.force) step_tile<M, true, true>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
-        else step_tile<M, true, false>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
+        if (d.force) step_tile<M, 1, true, true>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
+        else step_tile<M, 1, true, false>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
     } else {
-        if (d.force) step_tile<M, false, true>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
-        else step_tile<M, false, false>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
+        if (d.force) step_tile<M, 1, false, true>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
+        else step_tile<M, 1, false, false>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
     }
 }
 
@@ -982,7 +1113,8 @@ int rows_per_wave(int precision)
 // LDS of one step tile: its phi with a one-node halo
 size_t tile_lds_bytes(const Geo &g, size_t elem) { return (size_t)(g.rows * g.rpw + 2) * (64 * g.wx + 2) * elem; }
 
-Geo make_geo(const lbcm_params &p)
+// geometry of the step tiles; rpw: lattice rows per wave row of the kernel that runs them
+Geo make_geo(const lbcm_params &p, int rpw)
 {
     Geo g;
     g.nx = p.nx;
@@ -990,7 +1122,7 @@ Geo make_geo(const lbcm_params &p)
     g.plane = (uint32_t)((size_t)p.nx * p.ny);
     const int max_waves = (p.precision == LBCM_FP64 ? 512 : 1024) / 64;
     const int need = (p.nx + 63) / 64;
-    g.rpw = rows_per_wave(p.precision);
+    g.rpw = rpw;
     g.wx = p.tile_wx > 0 ? p.tile_wx : (g.rpw == 2 ? kDefaultWx16 : kDefaultWx);
     if (g.wx > need) g.wx = need;
     if (g.wx > max_waves) g.wx = max_waves;
@@ -1006,6 +1138,9 @@ Geo make_geo(const lbcm_params &p)
     g.wgrad = p.wall_gradient;
     return g;
 }
+
+// the single-lattice kernel's geometry (the storage mode's rows per wave)
+Geo make_geo(const lbcm_params &p) { return make_geo(p, rows_per_wave(p.precision)); }
 
 unsigned char *set_base(lbcm_handle *h, int pair, int set)  // set 0 = f, 1 = g
 {
@@ -1038,6 +1173,7 @@ int grid_for(size_t n, int threads)
 template <class M> int launch_steps(lbcm_handle *h, int64_t nsteps)
 {
     using R = typename M::R;
+    constexpr int RPW = M::kRpw;
     const Geo geo = make_geo(h->p);
     const Phys<R> c = make_phys<R>(h->p);
     const bool walls = h->p.bc_y == LBCM_BC_WALLS;
@@ -1051,11 +1187,11 @@ template <class M> int launch_steps(lbcm_handle *h, int64_t nsteps)
         const unsigned char *fa = set_base(h, h->cur, 0), *ga = set_base(h, h->cur, 1);
         unsigned char *fb = set_base(h, 1 - h->cur, 0), *gb = set_base(h, 1 - h->cur, 1);
         if (walls) {
-            if (force) hipLaunchKernelGGL((k_step<M, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            else hipLaunchKernelGGL((k_step<M, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            if (force) hipLaunchKernelGGL((k_step<M, RPW, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            else hipLaunchKernelGGL((k_step<M, RPW, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
         } else {
-            if (force) hipLaunchKernelGGL((k_step<M, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            else hipLaunchKernelGGL((k_step<M, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            if (force) hipLaunchKernelGGL((k_step<M, RPW, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+            else hipLaunchKernelGGL((k_step<M, RPW, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
         }
         HIP_TRY(h, hipGetLastError());
         h->cur = 1 - h->cur;
@@ -1072,13 +1208,13 @@ template <class M> int launch_steps(lbcm_handle *h, int64_t nsteps)
 
 // Time `trials` launches of the step kernel with tile shape (wx, rows) that read the current
 // pair and write the spare one (the state is left as it was).  Returns ms per launch, < 0 on error.
-template <class M> float time_tiles(lbcm_handle *h, int wx, int rows, int trials)
+template <class M, int RPW> float time_tiles(lbcm_handle *h, int wx, int rows, int trials)
 {
     using R = typename M::R;
     lbcm_params q = h->p;
     q.tile_wx = wx;
     q.tile_rows = rows;
-    const Geo geo = make_geo(q);
+    const Geo geo = make_geo(q, RPW);
     const Phys<R> c = make_phys<R>(q);
     const bool walls = q.bc_y == LBCM_BC_WALLS, force = q.force_x != 0 || q.force_y != 0;
     const dim3 grid((unsigned)(geo.nbands * geo.nrows)), block(64 * geo.wx * geo.rows);
@@ -1096,11 +1232,11 @@ template <class M> float time_tiles(lbcm_handle *h, int wx, int rows, int trials
         if (pass == 1 && hipEventRecord(e0, h->stream) != hipSuccess) break;
         for (int s = 0; s < (pass ? trials : 1); ++s) {
             if (walls) {
-                if (force) hipLaunchKernelGGL((k_step<M, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-                else hipLaunchKernelGGL((k_step<M, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+                if (force) hipLaunchKernelGGL((k_step<M, RPW, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+                else hipLaunchKernelGGL((k_step<M, RPW, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
             } else {
-                if (force) hipLaunchKernelGGL((k_step<M, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-                else hipLaunchKernelGGL((k_step<M, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+                if (force) hipLaunchKernelGGL((k_step<M, RPW, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
+                else hipLaunchKernelGGL((k_step<M, RPW, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
             }
         }
         if (hipGetLastError() != hipSuccess) break;
@@ -1271,7 +1407,7 @@ template <class M> int build_tables(lbcm_batch *b)
         q.tile_wx = b->wx[i];
         q.tile_rows = b->rows[i];
         BoxDesc<R> &d = desc[i];
-        d.geo = make_geo(q);
+        d.geo = make_geo(q, 1);  // the batched kernel updates one row per wave in every mode
         if (d.geo.wx * d.geo.rows > b->waves) return bfail(b, LBCM_EINVAL, "tile larger than the workgroup");
         d.c = make_phys<R>(q);
         b->base_cur[i] = h->cur;
@@ -1406,7 +1542,7 @@ template <class M> int batch_autotune(lbcm_batch *b, int trials)
                 float bms = -1;
                 std::pair<int, int> bc{1, waves};
                 for (auto cand : tile_candidates(h->p, waves)) {
-                    const float ms = time_tiles<M>(h, cand.first, cand.second, trials);
+                    const float ms = time_tiles<M, 1>(h, cand.first, cand.second, trials);
                     if (ms < 0) return bfail(b, LBCM_EHIP, "timing a tile shape failed");
                     if (bms < 0 || ms < bms) {
                         bms = ms;
@@ -1441,10 +1577,12 @@ template <class M> int batch_autotune(lbcm_batch *b, int trials)
     b->rows = best_rows;
     b->waves = best_waves;
     b->order = best_order;
-    // the looped single-box launches use the same per-box shapes
+    // the looped single-box launches use the same per-box tiles (with two-row waves in the
+    // 16-bit modes, half the wave rows)
+    const int rpw = rows_per_wave(b->precision);
     for (int i = 0; i < b->n; ++i) {
         b->box[i]->p.tile_wx = b->wx[i];
-        b->box[i]->p.tile_rows = b->rows[i];
+        b->box[i]->p.tile_rows = std::max(1, b->rows[i] / rpw);
     }
     return build_tables<M>(b);
 }
@@ -1711,7 +1849,7 @@ int lbcm_autotune(lbcm_handle *h, int trials)
         float best = -1;
         std::pair<int, int> bc{h->p.tile_wx, h->p.tile_rows};
         for (auto cand : tile_candidates(h->p, 0)) {
-            const float ms = time_tiles<M>(h, cand.first, cand.second, trials);
+            const float ms = time_tiles<M, M::kRpw>(h, cand.first, cand.second, trials);
             if (ms < 0) return fail(h, LBCM_EHIP, "timing a tile shape failed");
             if (best < 0 || ms < best) {
                 best = ms;
@@ -1805,7 +1943,7 @@ int lbcm_batch_create(const lbcm_params *boxes, int32_t nboxes, lbcm_batch **out
         int rc = lbcm_create(&q, &b->box[i]);
         if (rc) return bail(rc, "box " + std::to_string(i) + ": " + g_create_error);
         // default tile: as wide as the box allows, the rest of the workgroup in rows
-        const Geo g = make_geo(q);
+        const Geo g = make_geo(q, 1);
         b->wx[i] = g.wx;
         b->rows[i] = std::max(1, b->waves / g.wx);
     }
