@@ -8,6 +8,7 @@ Measured oracle errors (stated bounds are these with margin):
   spinodal linear growth vs. M k^2 (a - gamma k^2):               < 0.4 %
   flat tanh interface after 2000 steps:                           max |phi - tanh| = 0.015
   Couette flow between walls moving at -U and +U:                 1e-15 U (exact)
+  phi flux of that flow at uniform phi0 vs phi0 v:                1e-16 (exact)
   wetting wall profile vs. the shifted tanh, W = 2 / 4:           1.2e-3 / 3.4e-4
 """
 import json
@@ -215,6 +216,26 @@ def test_couette_between_moving_walls(orc):
     assert np.max(np.abs(m["ux"] - ua[:, None])) < 1e-12 * U * 1e3
     assert np.max(np.abs(m["uy"])) < 1e-13
     assert np.max(np.abs(m["phi"] - 1)) < 1e-13
+
+
+@pytest.mark.parametrize("phi0", [0.5, -0.7])
+def test_phi_flux_of_couette_flow_at_uniform_phi(orc, phi0):
+    """A uniform phi0 carried by the same Couette flow: phi stays phi0, the flow is the exact
+    linear profile, and the phi flux sum_i c_i g_i of the post-streaming g is exactly phi0 v in
+    every row, the wall rows included.  This pins the moving-wall term of g: weighted by the
+    node's phi it hands back the flux a wall moving through a uniform phase carries (weighted by
+    1, the wall rows of the phi0 = 0.5 run are off by U / 6)."""
+    L, U = 16, 1e-3
+    cx = np.array(GOLD["lattice"]["cx"])
+    p = orc.Params(4, L, walls=1, nu_l=1 / 6, nu_g=1 / 6, wall_ux_bottom=-U, wall_ux_top=U, nthreads=1)
+    f, g = orc.init(p, np.full((L, 4), phi0))
+    f, g = orc.run(p, f, g, 20000)
+    m = orc.macro(p, f, g)
+    ua = -U + 2 * U * (np.arange(L) + 0.5) / L
+    assert np.max(np.abs(m["ux"] - ua[:, None])) < 1e-13
+    assert np.max(np.abs(m["phi"] - phi0)) < 1e-12
+    J = np.tensordot(cx, g, axes=(0, 0))
+    assert np.max(np.abs(J - phi0 * m["ux"])) < 1e-13
 
 
 def _wetting_run(orc, W, hW=0.36, L=64, steps=30000):
