@@ -256,7 +256,7 @@ def ensemble_report(lbcm, args) -> dict:
         box.init(phi0)
     del spec
     t0 = time.perf_counter()
-    info = bt.autotune(trials=3)
+    info = bt.autotune(trials=10)
     tune_s = time.perf_counter() - t0
 
     def timed(fn, steps):
