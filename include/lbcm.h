@@ -176,6 +176,10 @@ int lbcm_info(const lbcm_handle *h, lbcm_params *out);
 /* Tile shape the step kernel uses (after clamping to the lattice): waves across, wave rows down. */
 int lbcm_tile_shape(const lbcm_handle *h, int32_t *wx, int32_t *rows);
 
+/* Lattice rows each wave of the step kernel updates: 2 with 16-bit storage on lattices of at least
+   2^22 nodes (bandwidth-bound; a wave then has as many bytes in flight as an FP32 wave), else 1. */
+int lbcm_tile_rows_per_wave(const lbcm_handle *h, int32_t *rpw);
+
 /* ---------------------------------------------------------------------------------------------
    Ensembles: many independent lattices (boxes) of any sizes, boundaries, forces and viscosities,
    advanced together by one launch per time step that covers every tile of every box.  Each box
@@ -203,8 +207,11 @@ int lbcm_batch_step_looped(lbcm_batch *b, int64_t nsteps);
 
 /* Autotuner: for each box size, the fastest tile split of a workgroup of 8 or 16 waves (timed
    on that box), then the workgroup size and the tile order (box order or largest boxes first)
-   of the batched launch by timing whole launches.  Timing runs read the current populations and
-   write the spare copies, so no state changes.  Synchronises. */
+   of the batched launch by timing whole launches; the boxes' own tiles (lbcm_step,
+   lbcm_batch_step_looped) become the same tiles, or with 16-bit storage, whose single-lattice
+   kernel differs from the batched one, the fastest split for that kernel per box size.  Timing
+   runs read the current populations and write the spare copies, so no state changes.
+   Synchronises. */
 int lbcm_batch_autotune(lbcm_batch *b, int32_t trials);
 
 /* Enable (1, default) or disable (0) hipGraph replay in lbcm_batch_step. */

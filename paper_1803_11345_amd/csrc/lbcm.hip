@@ -109,9 +109,10 @@ template <> struct Elem<__bf16> {
     }
 };
 
-// Storage modes: compute type R, type of the f planes, of g_0 and of g_1..g_8, and the lattice
-// rows each wave of the step kernel updates (two with 16-bit storage, whose loads carry half the
-// bytes: two rows per wave keep as many bytes in flight per wave as one FP32 row).
+// Storage modes: compute type R, type of the f planes, of g_0 and of g_1..g_8, and the most
+// lattice rows each wave of the step kernel updates (two with 16-bit storage, whose loads carry
+// half the bytes: two rows per wave keep as many bytes in flight per wave as one FP32 row; used
+// on lattices large enough to be bandwidth-bound, see rows_per_wave).
 struct ModeF64 { using R = double; using F = double; using G0 = double; using G = double; static constexpr int kRpw = 1; };
 struct ModeF32 { using R = float; using F = float; using G0 = float; using G = float; static constexpr int kRpw = 1; };
 struct ModeF16 { using R = float; using F = _Float16; using G0 = float; using G = _Float16; static constexpr int kRpw = 2; };
@@ -177,7 +178,7 @@ struct Geo {
     uint32_t plane;     // nx * ny
     int wx;             // wave columns per tile (tile width 64 * wx)
     int rows;           // wave rows per tile
-    int rpw;            // lattice rows per wave row (the mode's kRpw); tile height rows * rpw
+    int rpw;            // lattice rows per wave row (1 or the mode's kRpw); tile height rows * rpw
     int nbands, nrows;  // tiles across and down
     int walls;
     double ub6, ut6;    // x velocities of the bottom and top walls, divided by 6
@@ -459,10 +460,10 @@ __device__ __forceinline__ void collide_node(const R f[9], const R g[9], R phi, 
 }
 
 // ------------------------------------------------------------------------------------------
-// the step kernel.  A workgroup owns a tile of 64 * wx columns by rows * kRpw lattice rows; each
-// of its waves owns a 64-column segment of kRpw rows (one node per lane and row; two rows with
-// 16-bit storage, so that a wave has as many bytes in flight as with FP32 storage and one row:
-// 2-4 % faster there).  Every wave pulls f and g of its own nodes, sums phi into an
+// the step kernel.  A workgroup owns a tile of 64 * wx columns by rows * RPW lattice rows; each
+// of its waves owns a 64-column segment of RPW rows (one node per lane and row; two rows on large
+// lattices with 16-bit storage, so that a wave has as many bytes in flight as with FP32 storage
+// and one row: 2-4 % faster there).  Every wave pulls f and g of its own nodes, sums phi into an
 // LDS tile with a one-node halo, and the halo is filled by the same pulls one node further out:
 // the waves of the first and last tile row also pull g of the rows above and below, and lanes 0
 // and 1 of the first wave column pull the two halo columns.  One barrier later every node reads
@@ -1105,9 +1106,14 @@ template <class R> Phys<R> make_phys(const lbcm_params &p)
     return c;
 }
 
-int rows_per_wave(int precision)
+// Lattice rows per wave of the single-lattice step kernel: two with 16-bit storage on lattices of
+// at least kTwoRowMinNodes nodes, where the step is bandwidth-bound; one otherwise (on small,
+// latency-bound lattices a wave's second row only lengthens the critical path).
+constexpr size_t kTwoRowMinNodes = size_t(1) << 22;
+int rows_per_wave(const lbcm_params &p)
 {
-    return precision == LBCM_FP16_SHIFTED || precision == LBCM_BF16_SHIFTED ? ModeF16::kRpw : ModeF32::kRpw;
+    const bool b16 = p.precision == LBCM_FP16_SHIFTED || p.precision == LBCM_BF16_SHIFTED;
+    return b16 && (size_t)p.nx * p.ny >= kTwoRowMinNodes ? ModeF16::kRpw : 1;
 }
 
 // LDS of one step tile: its phi with a one-node halo
@@ -1140,7 +1146,7 @@ Geo make_geo(const lbcm_params &p, int rpw)
 }
 
 // the single-lattice kernel's geometry (the storage mode's rows per wave)
-Geo make_geo(const lbcm_params &p) { return make_geo(p, rows_per_wave(p.precision)); }
+Geo make_geo(const lbcm_params &p) { return make_geo(p, rows_per_wave(p)); }
 
 unsigned char *set_base(lbcm_handle *h, int pair, int set)  // set 0 = f, 1 = g
 {
@@ -1170,29 +1176,43 @@ int grid_for(size_t n, int threads)
     return (int)b;
 }
 
+// One launch of the step kernel for the tile geometry geo (its rows per wave: 1 or the mode's kRpw).
+template <class M, int RPW>
+void launch_k_step_rpw(const Geo &geo, const Phys<typename M::R> &c, bool walls, bool force, size_t lds, hipStream_t st,
+                       const unsigned char *fa, const unsigned char *ga, unsigned char *fb, unsigned char *gb, int *flag)
+{
+    const dim3 grid((unsigned)(geo.nbands * geo.nrows)), block(64 * geo.wx * geo.rows);
+    if (walls) {
+        if (force) hipLaunchKernelGGL((k_step<M, RPW, true, true>), grid, block, lds, st, fa, ga, fb, gb, geo, c, flag);
+        else hipLaunchKernelGGL((k_step<M, RPW, true, false>), grid, block, lds, st, fa, ga, fb, gb, geo, c, flag);
+    } else {
+        if (force) hipLaunchKernelGGL((k_step<M, RPW, false, true>), grid, block, lds, st, fa, ga, fb, gb, geo, c, flag);
+        else hipLaunchKernelGGL((k_step<M, RPW, false, false>), grid, block, lds, st, fa, ga, fb, gb, geo, c, flag);
+    }
+}
+template <class M>
+void launch_k_step(const Geo &geo, const Phys<typename M::R> &c, bool walls, bool force, size_t lds, hipStream_t st,
+                   const unsigned char *fa, const unsigned char *ga, unsigned char *fb, unsigned char *gb, int *flag)
+{
+    if (geo.rpw == 1) launch_k_step_rpw<M, 1>(geo, c, walls, force, lds, st, fa, ga, fb, gb, flag);
+    else launch_k_step_rpw<M, M::kRpw>(geo, c, walls, force, lds, st, fa, ga, fb, gb, flag);
+}
+
 template <class M> int launch_steps(lbcm_handle *h, int64_t nsteps)
 {
     using R = typename M::R;
-    constexpr int RPW = M::kRpw;
     const Geo geo = make_geo(h->p);
     const Phys<R> c = make_phys<R>(h->p);
     const bool walls = h->p.bc_y == LBCM_BC_WALLS;
     const bool force = h->p.force_x != 0 || h->p.force_y != 0;
     const int64_t nblk = (int64_t)geo.nbands * geo.nrows;
     if (nblk > 0x7fffffff) return fail(h, LBCM_EINVAL, "too many tiles");
-    if (geo.rpw != M::kRpw) return fail(h, LBCM_EINVAL, "tile geometry does not match the storage mode");
-    const dim3 grid((unsigned)nblk), block(64 * geo.wx * geo.rows);
+    if (geo.rpw != 1 && geo.rpw != M::kRpw) return fail(h, LBCM_EINVAL, "tile geometry does not match the storage mode");
     const size_t lds = tile_lds_bytes(geo, sizeof(R));
     for (int64_t s = 0; s < nsteps; ++s) {
         const unsigned char *fa = set_base(h, h->cur, 0), *ga = set_base(h, h->cur, 1);
         unsigned char *fb = set_base(h, 1 - h->cur, 0), *gb = set_base(h, 1 - h->cur, 1);
-        if (walls) {
-            if (force) hipLaunchKernelGGL((k_step<M, RPW, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            else hipLaunchKernelGGL((k_step<M, RPW, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-        } else {
-            if (force) hipLaunchKernelGGL((k_step<M, RPW, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            else hipLaunchKernelGGL((k_step<M, RPW, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-        }
+        launch_k_step<M>(geo, c, walls, force, lds, h->stream, fa, ga, fb, gb, h->flag);
         HIP_TRY(h, hipGetLastError());
         h->cur = 1 - h->cur;
         h->step += 1;
@@ -1206,18 +1226,18 @@ template <class M> int launch_steps(lbcm_handle *h, int64_t nsteps)
     return LBCM_OK;
 }
 
-// Time `trials` launches of the step kernel with tile shape (wx, rows) that read the current
-// pair and write the spare one (the state is left as it was).  Returns ms per launch, < 0 on error.
-template <class M, int RPW> float time_tiles(lbcm_handle *h, int wx, int rows, int trials)
+// Time `trials` launches of the step kernel with tile shape (wx, rows) and rpw rows per wave (1 or
+// the mode's kRpw) that read the current pair and write the spare one (the state is left as it
+// was).  Returns ms per launch, < 0 on error.
+template <class M> float time_tiles(lbcm_handle *h, int wx, int rows, int rpw, int trials)
 {
     using R = typename M::R;
     lbcm_params q = h->p;
     q.tile_wx = wx;
     q.tile_rows = rows;
-    const Geo geo = make_geo(q, RPW);
+    const Geo geo = make_geo(q, rpw);
     const Phys<R> c = make_phys<R>(q);
     const bool walls = q.bc_y == LBCM_BC_WALLS, force = q.force_x != 0 || q.force_y != 0;
-    const dim3 grid((unsigned)(geo.nbands * geo.nrows)), block(64 * geo.wx * geo.rows);
     const size_t lds = tile_lds_bytes(geo, sizeof(R));
     const unsigned char *fa = set_base(h, h->cur, 0), *ga = set_base(h, h->cur, 1);
     unsigned char *fb = set_base(h, 1 - h->cur, 0), *gb = set_base(h, 1 - h->cur, 1);
@@ -1230,15 +1250,8 @@ template <class M, int RPW> float time_tiles(lbcm_handle *h, int wx, int rows, i
     float ms = -1;
     for (int pass = 0; pass < 2; ++pass) {  // pass 0 warms up
         if (pass == 1 && hipEventRecord(e0, h->stream) != hipSuccess) break;
-        for (int s = 0; s < (pass ? trials : 1); ++s) {
-            if (walls) {
-                if (force) hipLaunchKernelGGL((k_step<M, RPW, true, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-                else hipLaunchKernelGGL((k_step<M, RPW, true, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            } else {
-                if (force) hipLaunchKernelGGL((k_step<M, RPW, false, true>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-                else hipLaunchKernelGGL((k_step<M, RPW, false, false>), grid, block, lds, h->stream, fa, ga, fb, gb, geo, c, h->flag);
-            }
-        }
+        for (int s = 0; s < (pass ? trials : 1); ++s)
+            launch_k_step<M>(geo, c, walls, force, lds, h->stream, fa, ga, fb, gb, h->flag);
         if (hipGetLastError() != hipSuccess) break;
         if (pass == 1 && hipEventRecord(e1, h->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
             hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
@@ -1542,7 +1555,7 @@ template <class M> int batch_autotune(lbcm_batch *b, int trials)
                 float bms = -1;
                 std::pair<int, int> bc{1, waves};
                 for (auto cand : tile_candidates(h->p, waves)) {
-                    const float ms = time_tiles<M, 1>(h, cand.first, cand.second, trials);
+                    const float ms = time_tiles<M>(h, cand.first, cand.second, 1, trials);
                     if (ms < 0) return bfail(b, LBCM_EHIP, "timing a tile shape failed");
                     if (bms < 0 || ms < bms) {
                         bms = ms;
@@ -1577,12 +1590,34 @@ template <class M> int batch_autotune(lbcm_batch *b, int trials)
     b->rows = best_rows;
     b->waves = best_waves;
     b->order = best_order;
-    // the looped single-box launches use the same per-box tiles (with two-row waves in the
-    // 16-bit modes, half the wave rows)
-    const int rpw = rows_per_wave(b->precision);
+    // the looped single-box launches: the same per-box tiles where the single-lattice kernel is
+    // the batched one's (one row per wave); where it has two-row waves (large 16-bit boxes) the
+    // fastest tile of that kernel, timed per box size over every split
+    std::vector<std::pair<std::pair<int, int>, std::pair<int, int>>> single;  // (nx, ny) -> (wx, rows)
     for (int i = 0; i < b->n; ++i) {
-        b->box[i]->p.tile_wx = b->wx[i];
-        b->box[i]->p.tile_rows = std::max(1, b->rows[i] / rpw);
+        lbcm_handle *h = b->box[i];
+        std::pair<int, int> bc{b->wx[i], b->rows[i]};
+        const int rpw = rows_per_wave(h->p);
+        if (rpw != 1) {
+            auto key = std::make_pair(h->p.nx, h->p.ny);
+            auto it = std::find_if(single.begin(), single.end(), [&](auto &m) { return m.first == key; });
+            if (it == single.end()) {
+                float bms = -1;
+                for (auto cand : tile_candidates(h->p, 0)) {
+                    const float ms = time_tiles<M>(h, cand.first, cand.second, rpw, trials);
+                    if (ms < 0) return bfail(b, LBCM_EHIP, "timing a tile shape failed");
+                    if (bms < 0 || ms < bms) {
+                        bms = ms;
+                        bc = cand;
+                    }
+                }
+                single.push_back({key, bc});
+            } else {
+                bc = it->second;
+            }
+        }
+        h->p.tile_wx = bc.first;
+        h->p.tile_rows = bc.second;
     }
     return build_tables<M>(b);
 }
@@ -1849,7 +1884,7 @@ int lbcm_autotune(lbcm_handle *h, int trials)
         float best = -1;
         std::pair<int, int> bc{h->p.tile_wx, h->p.tile_rows};
         for (auto cand : tile_candidates(h->p, 0)) {
-            const float ms = time_tiles<M, M::kRpw>(h, cand.first, cand.second, trials);
+            const float ms = time_tiles<M>(h, cand.first, cand.second, rows_per_wave(h->p), trials);
             if (ms < 0) return fail(h, LBCM_EHIP, "timing a tile shape failed");
             if (best < 0 || ms < best) {
                 best = ms;
@@ -1867,6 +1902,13 @@ int lbcm_info(const lbcm_handle *h, lbcm_params *out)
     if (!h || !out) return LBCM_EINVAL;
     *out = h->p;
     out->stream = h->stream;
+    return LBCM_OK;
+}
+
+int lbcm_tile_rows_per_wave(const lbcm_handle *h, int32_t *rpw)
+{
+    if (!h || !rpw) return LBCM_EINVAL;
+    *rpw = make_geo(h->p).rpw;
     return LBCM_OK;
 }
 

@@ -105,6 +105,7 @@ def load():
     PI = ctypes.POINTER(ctypes.c_int32)
     lib.lbcm_autotune.argtypes = [_H, ctypes.c_int]
     lib.lbcm_tile_shape.argtypes = [_H, PI, PI]
+    lib.lbcm_tile_rows_per_wave.argtypes = [_H, PI]
     lib.lbcm_info.argtypes = [_H, P]
     lib.lbcm_copy_state.argtypes = [_H, _H, ctypes.c_int64]
     lib.lbcm_step_count.argtypes = [_H]
@@ -244,6 +245,12 @@ def lbcm_tile_shape(h):
     return wx.value, rows.value
 
 
+def lbcm_tile_rows_per_wave(h):
+    rpw = ctypes.c_int32()
+    _check(h, load().lbcm_tile_rows_per_wave(h, ctypes.byref(rpw)))
+    return rpw.value
+
+
 def _bcheck(b, rc):
     if rc != LBCM_OK:
         raise LbcmError(rc, lbcm_batch_last_error(b))
@@ -347,6 +354,9 @@ class _View:
 
     def tile_shape(self):
         return lbcm_tile_shape(self.h)
+
+    def rows_per_wave(self):
+        return lbcm_tile_rows_per_wave(self.h)
 
 
 class Batch:

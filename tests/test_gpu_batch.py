@@ -81,8 +81,11 @@ def test_batch_looped_equals_batched():
     b.close()
 
 
-def test_batch_autotune_keeps_state_and_results():
-    bt = _batch("fp32", 70)
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+def test_batch_autotune_keeps_state_and_results(prec):
+    """Autotuning changes no state; afterwards the batched launch and the boxes' own tuned
+    single-lattice launches (two-row waves with 16-bit storage) both match fresh single runs."""
+    bt = _batch(prec, 70)
     before = [box.get_state() for box in bt]
     info = bt.autotune(trials=2)
     say(f"  autotuned: {info}")
@@ -93,7 +96,11 @@ def test_batch_autotune_keeps_state_and_results():
     for box, st in zip(bt, before):
         assert np.array_equal(box.get_state(), st)
     bt.step(6)
-    ref = _singles("fp32", 6, 70)
+    ref = _singles(prec, 6, 70)
+    for k, box in enumerate(bt):
+        assert np.array_equal(box.get_state(), ref[k]), k
+    bt.step_looped(3)
+    ref = _singles(prec, 9, 70)
     for k, box in enumerate(bt):
         assert np.array_equal(box.get_state(), ref[k]), k
     bt.close()

@@ -151,16 +151,41 @@ def test_segment_rows_do_not_change_results(rows):
 @pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
 @pytest.mark.parametrize("wx,rows", [(1, 1), (1, 3), (2, 2), (4, 2), (2, 8), (1, 16), (4, 4)])
 @pytest.mark.parametrize("ny,bc_y", [(51, 0), (50, 1), (3, 0), (1, 1)])
-def test_tiles_of_two_row_waves_do_not_change_results(prec, wx, rows, ny, bc_y):
-    """With 16-bit storage each wave updates two lattice rows; any tile shape, with an odd row
-    count (a wave whose second row lies past the lattice) or a single row, and walls, gives the
-    same state bit for bit."""
+def test_16bit_tiles_do_not_change_results(prec, wx, rows, ny, bc_y):
+    """16-bit storage on small lattices (one row per wave): any tile shape, with odd and single
+    row counts, periodic or with walls, gives the same state bit for bit."""
     nx = 100
     phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=36)
     kw = dict(precision=prec, bc_y=bc_y, force_x=1e-5, **PHYS)
     ref = lbcm.Lattice(nx, ny, tile_wx=1, tile_rows=1, **kw).init(phi, rho, ux, uy).step(5)
     lat = lbcm.Lattice(nx, ny, tile_wx=wx, tile_rows=rows, **kw).init(phi, rho, ux, uy).step(5)
     assert np.array_equal(ref.get_state(), lat.get_state())
+
+
+@pytest.mark.parametrize("prec", ["fp16s", "bf16s"])
+@pytest.mark.parametrize("bc_y", [0, 1])
+def test_two_row_waves_equal_one_row_waves(prec, bc_y):
+    """Above 2^22 nodes a 16-bit lattice runs the step with two lattice rows per wave; the same box
+    in an ensemble runs the one-row kernel.  With an odd row count (the last wave's second row lies
+    past the lattice), walls, force and several tile shapes the states agree bit for bit."""
+    nx, ny = 2048, 2049
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=37)
+    kw = dict(nx=nx, ny=ny, bc_y=bc_y, force_x=1e-5, **PHYS)
+    say(f"case two-row vs one-row {prec} {nx}x{ny} bc_y={bc_y}")
+    bt = lbcm.Batch([kw], precision=prec)
+    bt[0].init(phi, rho, ux, uy)
+    bt.step(4)
+    ref = bt[0].get_state()
+    bt.close()
+    for wx, rows in ((0, 0), (1, 3), (8, 1), (2, 8)):
+        lat = lbcm.Lattice(precision=prec, tile_wx=wx, tile_rows=rows, **kw).init(phi, rho, ux, uy)
+        assert lat.rows_per_wave() == 2
+        lat.step(4)
+        assert np.array_equal(lat.get_state(), ref), (wx, rows)
+        lat.close()
+    small = lbcm.Lattice(precision=prec, nx=64, ny=64)
+    assert small.rows_per_wave() == 1
+    small.close()
 
 
 def test_static_droplet_fp64_2000_steps():
