@@ -277,7 +277,8 @@ def ensemble_report(lbcm, args) -> dict:
     mlups_loop = nodes * args.ens_looped_steps / sec_loop / 1e6
     bt.close()
     return {"boxes": args.ens_boxes, "nodes": nodes, "precision": "fp16s", "steps": args.ens_steps,
-            "value": round(mlups, 1), "unit": "MLUPS", "looped_single_box_mlups": round(mlups_loop, 1),
+            "value": round(mlups, 1), "unit": "MLUPS", "hbm_gbs_alg": round(mlups * 76 / 1e3, 1),
+            "looped_single_box_mlups": round(mlups_loop, 1),
             "speedup_vs_looped": round(mlups / mlups_loop, 3), "graph": True,
             "tuned": {"waves": info["waves"], "order": ["box order", "largest first"][info["order"]],
                       "tiles": info["ntiles"], "autotune_s": round(tune_s, 2)},
