@@ -280,7 +280,7 @@ def ensemble_report(lbcm, args) -> dict:
             "value": round(mlups, 1), "unit": "MLUPS", "hbm_gbs_alg": round(mlups * 76 / 1e3, 1),
             "looped_single_box_mlups": round(mlups_loop, 1),
             "speedup_vs_looped": round(mlups / mlups_loop, 3), "graph": True,
-            "tuned": {"waves": info["waves"], "order": ["box order", "largest first"][info["order"]],
+            "tuned": {"waves": info["waves"], "order": ["box order", "largest first", "one XCD per box"][info["order"]],
                       "tiles": info["ntiles"], "autotune_s": round(tune_s, 2)},
             "nonfinite_nodes": int(nonfinite)}
 

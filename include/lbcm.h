@@ -206,7 +206,7 @@ int lbcm_batch_step(lbcm_batch *b, int64_t nsteps);
 int lbcm_batch_step_looped(lbcm_batch *b, int64_t nsteps);
 
 /* Autotuner: for each box size, the fastest tile split of a workgroup of 8 or 16 waves (timed
-   on that box), then the workgroup size and the tile order (box order or largest boxes first)
+   on that box), then the workgroup size and the tile order (see lbcm_batch_set_order)
    of the batched launch by timing whole launches; the boxes' own tiles (lbcm_step,
    lbcm_batch_step_looped) become the same tiles, or with 16-bit storage, whose single-lattice
    kernel differs from the batched one, the fastest split for that kernel per box size.  Timing
@@ -216,6 +216,11 @@ int lbcm_batch_autotune(lbcm_batch *b, int32_t trials);
 
 /* Enable (1, default) or disable (0) hipGraph replay in lbcm_batch_step. */
 int lbcm_batch_set_graph(lbcm_batch *b, int32_t enable);
+
+/* Order of the tiles in the batched launch: 0 the boxes in turn, 1 largest boxes first (default),
+   2 one XCD per box (boxes dealt largest first to the XCD with the fewest tiles; a box's halo
+   lines are then hits in that XCD's L2).  The order changes no result.  Errors: LBCM_EINVAL. */
+int lbcm_batch_set_order(lbcm_batch *b, int32_t order);
 
 /* Current launch configuration: waves per workgroup, tile order, number of tiles, and per box
    the tile shape (arrays of nboxes entries; any pointer may be NULL). */

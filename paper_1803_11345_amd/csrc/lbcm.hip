@@ -45,6 +45,7 @@ namespace {
 constexpr int kDefaultRows = 2;  // wave rows per tile
 constexpr int kDefaultWx = 8;    // 64-column waves across a tile
 constexpr int kDefaultWx16 = 4;  // the same with 16-bit storage (two lattice rows per wave row)
+constexpr int kXcds = 8;         // XCDs of the device, to which workgroups are dealt in turn
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
 constexpr int kDiagFields = 7;
@@ -759,10 +760,10 @@ k_step(const unsigned char *__restrict__ fa, const unsigned char *__restrict__ g
 }
 
 // ------------------------------------------------------------------------------------------
-// batched step: every tile of every box of an ensemble in one launch.  The tiles of box b are
-// the flat grid indices [first_tile, first_tile + nbands * nrows) in the box's row-major order;
-// tile_box maps a grid index to its box.  Each box has its own size, tile shape (within the
-// launch's workgroup size), boundaries, force and physics.  Every wave updates one lattice row,
+// batched step: every tile of every box of an ensemble in one launch.  tiles[g] = (box, t) is
+// the tile of grid index g: tile t of the box in its row-major order (box < 0: an empty slot,
+// whose workgroup returns at once).  Each box has its own size, tile shape (within the launch's
+// workgroup size), boundaries, force and physics.  Every wave updates one lattice row,
 // in the 16-bit modes too: the small tiles of an ensemble gain nothing from the longer loads in
 // flight of two-row waves, and lose the occupancy their registers cost.
 
@@ -770,22 +771,21 @@ template <class R> struct BoxDesc {
     Geo geo;
     Phys<R> c;
     const unsigned char *set[2][2];  // [pair][f or g]
-    int first_tile;
     int walls, force;
 };
 
 template <class M>
 __global__ __launch_bounds__(kMaxThreads<M>) void k_step_batch(const BoxDesc<typename M::R> *__restrict__ boxes,
-                                                               const int *__restrict__ tile_box, int cur,
+                                                               const int2 *__restrict__ tiles, int cur,
                                                                int *__restrict__ flag)
 {
     using R = typename M::R;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     R *phs = reinterpret_cast<R *>(lds_raw);
-    const int b = tile_box[blockIdx.x];
-    const BoxDesc<R> &d = boxes[b];
-    const int t = (int)blockIdx.x - d.first_tile;
-    const int band = t % d.geo.nbands, rg = t / d.geo.nbands;
+    const int2 e = tiles[blockIdx.x];
+    if (e.x < 0) return;  // empty slot: the whole workgroup leaves before any barrier
+    const BoxDesc<R> &d = boxes[e.x];
+    const int band = e.y % d.geo.nbands, rg = e.y / d.geo.nbands;
     const unsigned char *fa = d.set[cur][0], *ga = d.set[cur][1];
     unsigned char *fb = const_cast<unsigned char *>(d.set[1 - cur][0]);
     unsigned char *gb = const_cast<unsigned char *>(d.set[1 - cur][1]);
@@ -1363,11 +1363,12 @@ struct lbcm_batch {
     std::vector<lbcm_handle *> box;
     std::vector<int> wx, rows;     // tile shape of each box in the batched launch
     int waves = 16;                // waves per workgroup of the batched launch
-    int order = 1;                 // 0: tiles in box order, 1: largest boxes first
+    int order = 1;                 // 0: tiles in box order, 1: largest boxes first, 2: one XCD per box
     void *d_desc = nullptr;        // BoxDesc table
-    int *d_tile_box = nullptr;     // grid index -> box
+    int2 *d_tiles = nullptr;       // grid index -> (box, tile of the box), box -1: empty slot
     int *flag = nullptr;
-    int ntiles = 0;
+    int ntiles = 0;                // tiles of all boxes
+    int grid = 0;                  // workgroups of the batched launch (tiles and empty slots)
     size_t lds = 0;
     std::vector<int> base_cur;     // pair that was current in each box when the table was built
     int phase = 0;                 // steps taken since the table was built, mod 2
@@ -1405,13 +1406,14 @@ template <class M> int build_tables(lbcm_batch *b)
     using R = typename M::R;
     std::vector<int> idx(b->n);
     for (int i = 0; i < b->n; ++i) idx[i] = i;
-    if (b->order == 1)
+    if (b->order >= 1)
         std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) {
             return (size_t)b->box[u]->p.nx * b->box[u]->p.ny > (size_t)b->box[v]->p.nx * b->box[v]->p.ny;
         });
     std::vector<BoxDesc<R>> desc(b->n);
-    std::vector<int> tile_box;
-    size_t lds = 0;
+    std::vector<std::vector<int2>> streams(b->order == 2 ? kXcds : 1);
+    std::vector<size_t> load(streams.size(), 0);
+    size_t ntiles = 0, lds = 0;
     b->base_cur.assign(b->n, 0);
     for (int i : idx) {
         lbcm_handle *h = b->box[i];
@@ -1430,23 +1432,39 @@ template <class M> int build_tables(lbcm_batch *b)
         }
         d.walls = q.bc_y == LBCM_BC_WALLS;
         d.force = q.force_x != 0 || q.force_y != 0;
-        d.first_tile = (int)tile_box.size();
         const size_t nt = (size_t)d.geo.nbands * d.geo.nrows;
-        if (tile_box.size() + nt > 0x7fffffff) return bfail(b, LBCM_EINVAL, "too many tiles");
-        tile_box.insert(tile_box.end(), nt, i);
+        ntiles += nt;
+        if (ntiles > 0x7fffffff / kXcds) return bfail(b, LBCM_EINVAL, "too many tiles");
+        // the least-loaded stream takes the box (with one stream: every box in turn)
+        const size_t s = std::min_element(load.begin(), load.end()) - load.begin();
+        for (size_t t = 0; t < nt; ++t) streams[s].push_back(make_int2(i, (int)t));
+        load[s] += nt;
         lds = std::max(lds, tile_lds_bytes(d.geo, sizeof(R)));
+    }
+    // grid index g = kXcds k + x runs tile k of stream x: workgroups are dealt to the XCDs in
+    // turn, so each stream's tiles run on one XCD (order 2); with one stream the grid is the
+    // boxes' tiles back to back
+    std::vector<int2> tiles;
+    if (streams.size() == 1) {
+        tiles = std::move(streams[0]);
+    } else {
+        const size_t len = *std::max_element(load.begin(), load.end());
+        tiles.assign(len * streams.size(), make_int2(-1, 0));
+        for (size_t x = 0; x < streams.size(); ++x)
+            for (size_t k = 0; k < streams[x].size(); ++k) tiles[k * streams.size() + x] = streams[x][k];
     }
     drop_graph(b);
     if (b->d_desc) (void)hipFree(b->d_desc);
-    if (b->d_tile_box) (void)hipFree(b->d_tile_box);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
     b->d_desc = nullptr;
-    b->d_tile_box = nullptr;
+    b->d_tiles = nullptr;
     BHIP_TRY(b, hipMalloc(&b->d_desc, desc.size() * sizeof(BoxDesc<R>)));
-    BHIP_TRY(b, hipMalloc((void **)&b->d_tile_box, tile_box.size() * sizeof(int)));
+    BHIP_TRY(b, hipMalloc((void **)&b->d_tiles, tiles.size() * sizeof(int2)));
     BHIP_TRY(b, hipMemcpyAsync(b->d_desc, desc.data(), desc.size() * sizeof(BoxDesc<R>), hipMemcpyHostToDevice, b->stream));
-    BHIP_TRY(b, hipMemcpyAsync(b->d_tile_box, tile_box.data(), tile_box.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BHIP_TRY(b, hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
-    b->ntiles = (int)tile_box.size();
+    b->ntiles = (int)ntiles;
+    b->grid = (int)tiles.size();
     b->lds = lds;
     b->phase = 0;
     return LBCM_OK;
@@ -1462,8 +1480,8 @@ bool tables_stale(lbcm_batch *b)
 
 template <class M> void launch_batch(lbcm_batch *b, int phase)
 {
-    hipLaunchKernelGGL((k_step_batch<M>), dim3(b->ntiles), dim3(64 * b->waves), b->lds, b->stream,
-                       (const BoxDesc<typename M::R> *)b->d_desc, b->d_tile_box, phase, b->flag);
+    hipLaunchKernelGGL((k_step_batch<M>), dim3(b->grid), dim3(64 * b->waves), b->lds, b->stream,
+                       (const BoxDesc<typename M::R> *)b->d_desc, b->d_tiles, phase, b->flag);
 }
 
 void advance_boxes(lbcm_batch *b, int64_t steps)
@@ -1568,7 +1586,7 @@ template <class M> int batch_autotune(lbcm_batch *b, int trials)
             wx[i] = it->second.first;
             rows[i] = it->second.second;
         }
-        for (int order = 0; order < 2; ++order) {
+        for (int order = 0; order < 3; ++order) {
             b->wx = wx;
             b->rows = rows;
             b->waves = waves;
@@ -2006,6 +2024,19 @@ int lbcm_batch_set_graph(lbcm_batch *b, int32_t enable)
     return LBCM_OK;
 }
 
+int lbcm_batch_set_order(lbcm_batch *b, int32_t order)
+{
+    if (!b) return LBCM_EINVAL;
+    if (order < 0 || order > 2) return bfail(b, LBCM_EINVAL, "order must be 0, 1 or 2");
+    if (order != b->order) {
+        b->order = order;
+        drop_graph(b);
+        if (b->d_desc) (void)hipFree(b->d_desc);  // rebuilt by the next step
+        b->d_desc = nullptr;
+    }
+    return LBCM_OK;
+}
+
 int lbcm_batch_autotune(lbcm_batch *b, int32_t trials)
 {
     if (!b) return LBCM_EINVAL;
@@ -2056,7 +2087,7 @@ int lbcm_batch_destroy(lbcm_batch *b)
     for (lbcm_handle *h : b->box)
         if (h && lbcm_destroy(h) != LBCM_OK) rc = LBCM_EHIP;
     if (b->d_desc && hipFree(b->d_desc) != hipSuccess) rc = LBCM_EHIP;
-    if (b->d_tile_box && hipFree(b->d_tile_box) != hipSuccess) rc = LBCM_EHIP;
+    if (b->d_tiles && hipFree(b->d_tiles) != hipSuccess) rc = LBCM_EHIP;
     if (b->arena && hipFree(b->arena) != hipSuccess) rc = LBCM_EHIP;
     if (b->owns_stream && hipStreamDestroy(b->stream) != hipSuccess) rc = LBCM_EHIP;
     delete b;

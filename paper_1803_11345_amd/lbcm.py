@@ -117,6 +117,7 @@ def load():
     lib.lbcm_batch_step_looped.argtypes = [_H, ctypes.c_int64]
     lib.lbcm_batch_autotune.argtypes = [_H, I32]
     lib.lbcm_batch_set_graph.argtypes = [_H, I32]
+    lib.lbcm_batch_set_order.argtypes = [_H, I32]
     lib.lbcm_batch_info.argtypes = [_H, PI, PI, PI, PI, PI]
     lib.lbcm_batch_destroy.argtypes = [_H]
     lib.lbcm_batch_last_error.argtypes = [_H]
@@ -289,6 +290,10 @@ def lbcm_batch_set_graph(b, enable: bool):
     return _bcheck(b, load().lbcm_batch_set_graph(b, int(bool(enable))))
 
 
+def lbcm_batch_set_order(b, order: int):
+    return _bcheck(b, load().lbcm_batch_set_order(b, int(order)))
+
+
 def lbcm_batch_info(b, nboxes: int) -> dict:
     waves, order, ntiles = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     wx = (ctypes.c_int32 * nboxes)()
@@ -396,6 +401,9 @@ class Batch:
 
     def set_graph(self, enable):
         lbcm_batch_set_graph(self.b, enable)
+
+    def set_order(self, order):
+        lbcm_batch_set_order(self.b, order)
 
     def info(self):
         return lbcm_batch_info(self.b, len(self.boxes))
