@@ -98,6 +98,10 @@ def test_null_handle_calls_are_rejected():
     assert lib.lbcm_step(None, 1) == lbcm.LBCM_EINVAL
     assert lib.lbcm_destroy(None) == lbcm.LBCM_OK
     assert lib.lbcm_state_size(None) == 0
+    rpw = ctypes.c_int32()
+    assert lib.lbcm_tile_rows_per_wave(None, ctypes.byref(rpw)) == lbcm.LBCM_EINVAL
+    assert lib.lbcm_batch_set_order(None, 1) == lbcm.LBCM_EINVAL
+    assert lib.lbcm_batch_set_graph(None, 1) == lbcm.LBCM_EINVAL
 
 
 def test_bad_network_shapes_rejected_on_host():

@@ -67,6 +67,8 @@ def test_batch_matches_single_lattices(prec, graph, order):
     bt = _batch(prec, 50)
     bt.set_graph(graph)
     bt.set_order(order)
+    with pytest.raises(lbcm.LbcmError):
+        bt.set_order(3)
     bt.step(3).step(4)  # odd first call: phase handling around the two-step graph
     for k, box in enumerate(bt):
         assert np.array_equal(box.get_state(), ref[k]), k
