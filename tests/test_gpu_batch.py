@@ -150,3 +150,28 @@ def test_ensemble_generator_runs_finite():
     for box in bt:
         assert box.diag()["nonfinite"] == 0
     bt.close()
+
+
+def test_full_ensemble_matches_single_lattices_on_sampled_boxes():
+    """The 512-box FP16 ensemble of the benchmark (seed 7, sides 64 ... 1024, droplets and
+    layered channels), autotuned and advanced with graphs as the benchmark does: sampled boxes
+    (the first and last box, the largest and smallest of each kind) equal the same boxes stepped
+    as single lattices, bit for bit."""
+    spec = inputs.ensemble(512, seed=7)
+    bt = lbcm.Batch([p for p, _ in spec], precision="fp16s")
+    for box, (_, phi0) in zip(bt, spec):
+        box.init(phi0)
+    info = bt.autotune(trials=3)
+    say(f"  ensemble: waves {info['waves']} order {info['order']} tiles {info['ntiles']}")
+    bt.step(11)
+    size = [p["nx"] * p["ny"] for p, _ in spec]
+    picks = {0, len(spec) - 1}
+    for walls in (0, 1):
+        kind = [k for k, (p, _) in enumerate(spec) if p["bc_y"] == walls]
+        picks |= {max(kind, key=lambda k: size[k]), min(kind, key=lambda k: size[k])}
+    for k in sorted(picks):
+        p, phi0 = spec[k]
+        lat = lbcm.Lattice(precision="fp16s", **p).init(phi0).step(11)
+        assert np.array_equal(lat.get_state(), bt[k].get_state()), (k, p["nx"], p["bc_y"])
+        lat.close()
+    bt.close()
