@@ -260,14 +260,18 @@ def _window(full_phi, y0, x0, h, w, steps, **kw):
     return fo[:, m:m + h, m:m + w], go[:, m:m + h, m:m + w]
 
 
-def test_spinodal_4096_fp32_sampled_windows():
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("fp16s", 3e-5), ("bf16s", 3e-4)])
+def test_spinodal_4096_sampled_windows(prec, tol):
     """4096^2 periodic spinodal (phi0 uniform in [-0.05, 0.05], SplitMix64 seed 1, a = 0.04,
-    gamma = 0.08, M = 0.1, nu = 0.05) in the benchmark's launch configuration: after 10 steps,
-    windows (including ones that wrap around the periodic edges) match the oracle."""
+    gamma = 0.08, M = 0.1, nu = 0.05) in the benchmark's launch configuration (the 16-bit modes
+    with two-row waves): after 10 steps, windows (including ones that wrap around the periodic
+    edges) match the oracle, within the tier of each storage (measured 2.5e-8, 2.9e-6, 2.4e-5;
+    the 16-bit bounds are those of one step of the small-lattice test)."""
     n, steps = 4096, 10
     phi0 = inputs.spinodal(n, n, seed=1)
-    say("case spinodal 4096^2 fp32 10 steps")
-    lat = lbcm.Lattice(n, n, precision="fp32", nu_l=0.05, nu_g=0.05).init(phi0)
+    say(f"case spinodal 4096^2 {prec} 10 steps")
+    lat = lbcm.Lattice(n, n, precision=prec, nu_l=0.05, nu_g=0.05).init(phi0)
+    assert lat.rows_per_wave() == (1 if prec == "fp32" else 2)
     lat.step(steps)
     f, g = lat.populations()
     d = lat.diag()
@@ -284,7 +288,7 @@ def test_spinodal_4096_fp32_sampled_windows():
         e = max(maxerr(fw, fo), maxerr(gw, go))
         worst = max(worst, e)
     say(f"  worst window |GPU - oracle| = {worst:.2e}")
-    assert worst < 2e-6
+    assert worst < tol
 
 
 def test_checkpoint_resume_bitwise():
