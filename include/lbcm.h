@@ -73,7 +73,8 @@ typedef struct lbcm_params {
                             and returns LBCM_EDIVERGED once a non-finite rho or phi was seen;
                             0: no check (lbcm_diag still reports it) */
     int32_t tile_rows;   /* step-kernel tile height in wave rows, 0 = default; a wave row covers
-                            one lattice row (FP64, FP32) or two (16-bit storage) */
+                            one lattice row, or two with 16-bit storage on lattices of 2^22
+                            nodes or more (lbcm_tile_rows_per_wave) */
     int32_t tile_wx;     /* step-kernel tile width in waves of 64 columns, 0 = default;
                             tile_wx * tile_rows is capped at 16 (FP32, 16-bit) or 8 (FP64) waves */
     void *stream;        /* hipStream_t to queue work on; NULL = null stream */
