@@ -45,6 +45,7 @@ namespace {
 constexpr int kDefaultRows = 2;  // wave rows per tile
 constexpr int kDefaultWx = 8;    // 64-column waves across a tile
 constexpr int kDefaultWx16 = 4;  // the same with 16-bit storage (two lattice rows per wave row)
+constexpr int kDefaultWx64 = 2, kDefaultRows64 = 4;  // FP64 (512-thread workgroups)
 constexpr int kXcds = 8;         // XCDs of the device, to which workgroups are dealt in turn
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
@@ -1129,10 +1130,11 @@ Geo make_geo(const lbcm_params &p, int rpw)
     const int max_waves = (p.precision == LBCM_FP64 ? 512 : 1024) / 64;
     const int need = (p.nx + 63) / 64;
     g.rpw = rpw;
-    g.wx = p.tile_wx > 0 ? p.tile_wx : (g.rpw == 2 ? kDefaultWx16 : kDefaultWx);
+    const bool f64 = p.precision == LBCM_FP64;
+    g.wx = p.tile_wx > 0 ? p.tile_wx : (f64 ? kDefaultWx64 : g.rpw == 2 ? kDefaultWx16 : kDefaultWx);
     if (g.wx > need) g.wx = need;
     if (g.wx > max_waves) g.wx = max_waves;
-    int rows = p.tile_rows > 0 ? p.tile_rows : kDefaultRows;
+    int rows = p.tile_rows > 0 ? p.tile_rows : (f64 ? kDefaultRows64 : kDefaultRows);
     if (rows > max_waves / g.wx) rows = max_waves / g.wx;
     if (rows > (p.ny + g.rpw - 1) / g.rpw) rows = (p.ny + g.rpw - 1) / g.rpw;
     g.rows = rows;
