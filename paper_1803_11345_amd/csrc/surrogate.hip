@@ -542,10 +542,11 @@ struct PairLds {
 static_assert(PairLds::z_elems <= PairLds::x_elems, "Z fits where the patch was");
 static_assert(PairLds::ZW == kPatchW && PairLds::ZH == kPatchH, "layer b reads Z as a conv patch");
 
-// One layer's packed weights Wp[t][co][ci] on their way to LDS (rows of CIN padded to CIN + 8,
-// as the patch), in the registers of all threads of the workgroup: load() issues the global
-// loads, store() writes them to LDS once they have arrived.
-template <int CIN, int COUT>
+// One layer's packed weights Wp[t][co][ci] (PACK output channels per tap, of which the first
+// COUT are staged) on their way to LDS (rows of CIN padded to CIN + 8, as the patch), in the
+// registers of all threads of the workgroup: load() issues the global loads, store() writes
+// them to LDS once they have arrived.
+template <int CIN, int COUT, int PACK = COUT>
 struct WeightStage {
     static constexpr int WS = CIN + 8;
     static constexpr int NV = 9 * COUT * CIN / 8, NI = (NV + kConvThreads - 1) / kConvThreads;
@@ -556,7 +557,8 @@ struct WeightStage {
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             const int k = threadIdx.x + i * kConvThreads;
-            if (k < NV) v[i] = *(const u32x4 *)(Wp + (size_t)k * 8);
+            const int t = k / (COUT * CIN / 8), rem = k % (COUT * CIN / 8);  // tap, (co, ci / 8) in it
+            if (k < NV) v[i] = *(const u32x4 *)(Wp + ((size_t)t * PACK * CIN / 8 + rem) * 8);
         }
     }
     __device__ __forceinline__ void store(__bf16 *wl) const
@@ -585,7 +587,7 @@ __device__ __forceinline__ void lds_frags(const __bf16 *wl, int co, int q, bf16x
 // across it.  (__syncthreads also waits for every outstanding global load.)
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <int COUT, int MODE>
+template <int COUT, int MODE, int PACK = COUT>
 __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wa,
                                                        const float *__restrict__ ba, const __bf16 *__restrict__ Wb, OutArgs o,
                                                        int ntiles, int H, int W)
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict_
     // every global load at once: the patch, layer a's weights, then layer b's, which stay in
     // registers (in flight) until layer a is done
     WeightStage<C, C> sa;
-    WeightStage<C, COUT> sb;
+    WeightStage<C, COUT, PACK> sb;
     {
         constexpr int NV = L::XH * XW * (C / 8), NI = (NV + kConvThreads - 1) / kConvThreads;
         const __bf16 *Xn = X + (size_t)tc.n * H * W * C;
@@ -1293,15 +1295,15 @@ int launch_conv_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wp, const OutArgs 
     return LBCM_OK;
 }
 
-template <int CO, int MO>
+template <int CO, int MO, int PK = CO>
 int launch_pair_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wa, const float *ba, const __bf16 *Wb, const OutArgs &o)
 {
     constexpr size_t bytes = PairLds::bytes;
     static bool done[kMaxDevices] = {};
-    int rc = allow_dynamic_lds(n, reinterpret_cast<const void *>(&k_pair<CO, MO>), bytes, done);
+    int rc = allow_dynamic_lds(n, reinterpret_cast<const void *>(&k_pair<CO, MO, PK>), bytes, done);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_pair<CO, MO>), dim3(n->ntiles), dim3(kConvThreads), bytes, n->stream, X, Wa, ba, Wb, o, n->ntiles, n->H,
-                       n->W);
+    hipLaunchKernelGGL((k_pair<CO, MO, PK>), dim3(n->ntiles), dim3(kConvThreads), bytes, n->stream, X, Wa, ba, Wb, o, n->ntiles,
+                       n->H, n->W);
     NHIP(n, hipGetLastError());
     return LBCM_OK;
 }
@@ -1408,7 +1410,9 @@ int forward(lbcm_net *n, const PlaneIO *io = nullptr)
         const OutArgs o = out_args(lb);
         int rc;
         if (paired)
-            rc = last ? launch_pair_t<kOutC, 3>(n, n->act[l], n->Wf[l], n->params + n->b_off[l], n->Wf[lb], o)
+            // the last layer into the planes: only its first 16 padded output channels (the 4
+            // state channels and 12 zero ones) are computed, from its 32-channel weight pack
+            rc = last ? launch_pair_t<16, 3, kOutC>(n, n->act[l], n->Wf[l], n->params + n->b_off[l], n->Wf[lb], o)
                       : launch_pair_t<64, 0>(n, n->act[l], n->Wf[l], n->params + n->b_off[l], n->Wf[lb], o);
         else
             rc = launch_conv(n, n->act[l], n->cin[l], n->Wf[l], n->cout[l], last ? (io ? 3 : 1) : 0, o);
