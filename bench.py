@@ -324,8 +324,9 @@ def surrogate_report(lbcm, args) -> dict:
     jump_us = e0.elapsed_time(e1) * 1e3 / 100
     del frames, ins
     torch.cuda.empty_cache()
-    # padded MFMA work of one jump: layers 1..L-2 are 64 -> 64, the last 64 -> 32 (4 real)
-    flops = 2 * n * n * 9 * 64 * (4 * 64 + 32)
+    # padded MFMA work of one jump: layers 1..L-2 are 64 -> 64, the last 64 -> 16 computed
+    # channels (4 real) in the fused inference path
+    flops = 2 * n * n * 9 * 64 * (4 * 64 + 16)
     hybrid = {}
     for name, phi0 in (("spinodal", T.spinodal_phi(n, 106)), ("coalescence", T.coalescence_phi(n, cases[9]))):
         hybrid[name] = T.hybrid_vs_lb(m1, phi0, us, rs, args.sur_windows)
