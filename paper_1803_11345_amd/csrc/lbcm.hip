@@ -42,10 +42,15 @@
 
 namespace {
 
-constexpr int kDefaultRows = 2;  // wave rows per tile
-constexpr int kDefaultWx = 8;    // 64-column waves across a tile
-constexpr int kDefaultWx16 = 4;  // the same with 16-bit storage (two lattice rows per wave row)
-constexpr int kDefaultWx64 = 2, kDefaultRows64 = 4;  // FP64 (512-thread workgroups)
+// Default step tiles, in waves of 64 columns across (wx) and wave rows down.  Lattices from
+// kLargeNodes nodes on are bandwidth-bound: there the measured best tiles of the 4096^2 step
+// (FP32 4 x 4, FP64 2 x 4, 16-bit storage 4 x 2 with two-row waves); below, where a launch is a
+// latency chain and more workgroups pay, 8 x 2.
+constexpr size_t kLargeNodes = size_t(1) << 22;
+constexpr int kDefaultWx = 8, kDefaultRows = 2;
+constexpr int kLargeWx = 4, kLargeRows = 4;
+constexpr int kLargeWx16 = 4, kLargeRows16 = 2;
+constexpr int kLargeWx64 = 2, kLargeRows64 = 4;
 constexpr int kXcds = 8;         // XCDs of the device, to which workgroups are dealt in turn
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
@@ -1107,14 +1112,15 @@ template <class R> Phys<R> make_phys(const lbcm_params &p)
     return c;
 }
 
-// Lattice rows per wave of the single-lattice step kernel: two with 16-bit storage on lattices of
-// at least kTwoRowMinNodes nodes, where the step is bandwidth-bound; one otherwise (on small,
-// latency-bound lattices a wave's second row only lengthens the critical path).
-constexpr size_t kTwoRowMinNodes = size_t(1) << 22;
+bool large_lattice(const lbcm_params &p) { return (size_t)p.nx * p.ny >= kLargeNodes; }
+
+// Lattice rows per wave of the single-lattice step kernel: two with 16-bit storage on large
+// lattices, where the step is bandwidth-bound; one otherwise (on small, latency-bound lattices a
+// wave's second row only lengthens the critical path).
 int rows_per_wave(const lbcm_params &p)
 {
     const bool b16 = p.precision == LBCM_FP16_SHIFTED || p.precision == LBCM_BF16_SHIFTED;
-    return b16 && (size_t)p.nx * p.ny >= kTwoRowMinNodes ? ModeF16::kRpw : 1;
+    return b16 && large_lattice(p) ? ModeF16::kRpw : 1;
 }
 
 // LDS of one step tile: its phi with a one-node halo
@@ -1130,11 +1136,13 @@ Geo make_geo(const lbcm_params &p, int rpw)
     const int max_waves = (p.precision == LBCM_FP64 ? 512 : 1024) / 64;
     const int need = (p.nx + 63) / 64;
     g.rpw = rpw;
-    const bool f64 = p.precision == LBCM_FP64;
-    g.wx = p.tile_wx > 0 ? p.tile_wx : (f64 ? kDefaultWx64 : g.rpw == 2 ? kDefaultWx16 : kDefaultWx);
+    const bool f64 = p.precision == LBCM_FP64, large = large_lattice(p);
+    const int dwx = !large ? kDefaultWx : f64 ? kLargeWx64 : g.rpw == 2 ? kLargeWx16 : kLargeWx;
+    const int drows = !large ? kDefaultRows : f64 ? kLargeRows64 : g.rpw == 2 ? kLargeRows16 : kLargeRows;
+    g.wx = p.tile_wx > 0 ? p.tile_wx : dwx;
     if (g.wx > need) g.wx = need;
     if (g.wx > max_waves) g.wx = max_waves;
-    int rows = p.tile_rows > 0 ? p.tile_rows : (f64 ? kDefaultRows64 : kDefaultRows);
+    int rows = p.tile_rows > 0 ? p.tile_rows : drows;
     if (rows > max_waves / g.wx) rows = max_waves / g.wx;
     if (rows > (p.ny + g.rpw - 1) / g.rpw) rows = (p.ny + g.rpw - 1) / g.rpw;
     g.rows = rows;
