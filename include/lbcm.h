@@ -77,8 +77,8 @@ typedef struct lbcm_params {
                             nodes or more (lbcm_tile_rows_per_wave) */
     int32_t tile_wx;     /* step-kernel tile width in waves of 64 columns, 0 = default;
                             tile_wx * tile_rows is capped at 16 (FP32, 16-bit) or 8 (FP64) waves.
-                            Defaults (wx x rows): 8 x 2 below 2^22 nodes; from there FP32 4 x 4,
-                            FP64 2 x 4, 16-bit 4 x 2 (two-row waves) */
+                            Defaults (wx x rows): 8 x 2 below 2^22 nodes; from there FP32 4 x 3,
+                            FP64 2 x 4, 16-bit 4 x 3 (two-row waves) */
     void *stream;        /* hipStream_t to queue work on; NULL = null stream */
     void *workspace;     /* optional caller-owned device memory of lbcm_workspace_size() bytes,
                             256-byte aligned; NULL = the library allocates and frees it */
@@ -157,9 +157,9 @@ int lbcm_destroy(lbcm_handle *h);
 const char *lbcm_last_error(const lbcm_handle *h);
 
 /* Pick the step kernel's tile shape by timing: every (tile_wx, tile_rows) split with tile_wx a
-   power of two up to the lattice width is run `trials` times (reading the current populations
-   and writing the spare copy, so the state does not change), and the fastest is kept in the
-   handle.  Needs lbcm_init first.  Synchronises. */
+   power of two up to the lattice width and tile_rows a power of two or three times one is run
+   `trials` times (reading the current populations and writing the spare copy, so the state does
+   not change), and the fastest is kept in the handle.  Needs lbcm_init first.  Synchronises. */
 int lbcm_autotune(lbcm_handle *h, int trials);
 
 /* Device-to-device copy of src's populations into dst (same nx, ny and precision; other physics

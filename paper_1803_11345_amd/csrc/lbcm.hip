@@ -44,12 +44,12 @@ namespace {
 
 // Default step tiles, in waves of 64 columns across (wx) and wave rows down.  Lattices from
 // kLargeNodes nodes on are bandwidth-bound: there the measured best tiles of the 4096^2 step
-// (FP32 4 x 4, FP64 2 x 4, 16-bit storage 4 x 2 with two-row waves); below, where a launch is a
+// (FP32 4 x 3, FP64 2 x 4, 16-bit storage 4 x 3 with two-row waves); below, where a launch is a
 // latency chain and more workgroups pay, 8 x 2.
 constexpr size_t kLargeNodes = size_t(1) << 22;
 constexpr int kDefaultWx = 8, kDefaultRows = 2;
-constexpr int kLargeWx = 4, kLargeRows = 4;
-constexpr int kLargeWx16 = 4, kLargeRows16 = 2;
+constexpr int kLargeWx = 4, kLargeRows = 3;
+constexpr int kLargeWx16 = 4, kLargeRows16 = 3;
 constexpr int kLargeWx64 = 2, kLargeRows64 = 4;
 constexpr int kXcds = 8;         // XCDs of the device, to which workgroups are dealt in turn
 constexpr int kReduceBlocks = 1024;
@@ -1282,7 +1282,10 @@ std::vector<std::pair<int, int>> tile_candidates(const lbcm_params &p, int waves
     const int need = (p.nx + 63) / 64, mw = max_waves_of(p.precision);
     for (int wx = 1; wx <= mw; wx *= 2) {
         if (wx > need && wx > 1) break;
-        for (int rows = 1; wx * rows <= mw; rows *= 2) {
+        // wave rows: powers of two, and 3 times them (3 rows is the best height of the large
+        // FP32 and 16-bit steps)
+        for (int rows : {1, 2, 3, 4, 6, 8, 12, 16}) {
+            if (wx * rows > mw) break;
             if (rows > p.ny && rows > 1) break;
             if (waves == 0 || wx * rows == waves) out.push_back({wx, rows});
         }
