@@ -208,7 +208,7 @@ int lbcm_batch_step(lbcm_batch *b, int64_t nsteps);
    measured against). */
 int lbcm_batch_step_looped(lbcm_batch *b, int64_t nsteps);
 
-/* Autotuner: for each box size, the fastest tile split of a workgroup of 8 or 16 waves (timed
+/* Autotuner: for each box size, the fastest tile split of a workgroup of 8, 12 or 16 waves (timed
    on that box), then the workgroup size and the tile order (see lbcm_batch_set_order)
    of the batched launch by timing whole launches; the boxes' own tiles (lbcm_step,
    lbcm_batch_step_looped) become the same tiles, or with 16-bit storage, whose single-lattice

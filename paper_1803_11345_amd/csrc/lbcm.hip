@@ -1575,7 +1575,7 @@ template <class M> int batch_autotune(lbcm_batch *b, int trials)
     float best_ms = -1;
     std::vector<int> best_wx, best_rows;
     int best_waves = 0, best_order = 0;
-    for (int waves = mw / 2; waves <= mw; waves *= 2) {
+    for (int waves : {mw / 2, 3 * mw / 4, mw}) {  // 8, 12, 16 waves (FP64: 4, 6, 8)
         std::vector<int> wx(b->n, 1), rows(b->n, 1);
         std::vector<std::pair<std::pair<int, int>, std::pair<int, int>>> memo;  // (nx, ny) -> (wx, rows)
         for (int i = 0; i < b->n; ++i) {

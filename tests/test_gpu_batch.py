@@ -95,7 +95,7 @@ def test_batch_autotune_keeps_state_and_results(prec):
     before = [box.get_state() for box in bt]
     info = bt.autotune(trials=2)
     say(f"  autotuned: {info}")
-    assert info["waves"] in (8, 16) and info["order"] in (0, 1, 2)
+    assert info["waves"] in (8, 12, 16) and info["order"] in (0, 1, 2)
     for b, w, r in zip(BOXES, info["wx"], info["rows"]):
         # a full workgroup unless the box is smaller than the tile
         assert w * r == info["waves"] or (w * 64 >= b["nx"] and r >= b["ny"]) or r * w < info["waves"] and r >= b["ny"]
