@@ -342,7 +342,7 @@ def surrogate_report(lbcm, args) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+        print(f"bench.py: the step runs on one GPU only (asked for --gpus {args.gpus}); the "
               "multi-GPU slab decomposition is a design note, not code", file=sys.stderr)
         sys.exit(2)
     import numpy as np
