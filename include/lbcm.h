@@ -77,8 +77,9 @@ typedef struct lbcm_params {
                             nodes or more (lbcm_tile_rows_per_wave) */
     int32_t tile_wx;     /* step-kernel tile width in waves of 64 columns, 0 = default;
                             tile_wx * tile_rows is capped at 16 (FP32, 16-bit) or 8 (FP64) waves.
-                            Defaults (wx x rows): 8 x 2 below 2^22 nodes; from there FP32 4 x 3,
-                            FP64 2 x 4, 16-bit 4 x 3 (two-row waves) */
+                            Defaults (wx x rows): 8 x 2 on small lattices; from 2^20 nodes
+                            (FP32) or 2^22 (the others) FP32 4 x 3, FP64 2 x 4, 16-bit 4 x 3
+                            (two-row waves) */
     void *stream;        /* hipStream_t to queue work on; NULL = null stream */
     void *workspace;     /* optional caller-owned device memory of lbcm_workspace_size() bytes,
                             256-byte aligned; NULL = the library allocates and frees it */

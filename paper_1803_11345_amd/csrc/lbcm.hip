@@ -42,11 +42,13 @@
 
 namespace {
 
-// Default step tiles, in waves of 64 columns across (wx) and wave rows down.  Lattices from
-// kLargeNodes nodes on are bandwidth-bound: there the measured best tiles of the 4096^2 step
-// (FP32 4 x 3, FP64 2 x 4, 16-bit storage 4 x 3 with two-row waves); below, where a launch is a
-// latency chain and more workgroups pay, 8 x 2.
-constexpr size_t kLargeNodes = size_t(1) << 22;
+// Default step tiles, in waves of 64 columns across (wx) and wave rows down.  Large lattices are
+// bandwidth-bound: there the measured best tiles of the 4096^2 step (FP32 4 x 3, FP64 2 x 4,
+// 16-bit storage 4 x 3 with two-row waves); below, where a launch is a latency chain and more
+// workgroups pay, 8 x 2.  Large: from kLargeNodes nodes on, for FP32 from kLargeNodes32 (at
+// 1024^2 the 4 x 3 tile is 15 % faster than 8 x 2 in FP32, while 16-bit storage gains nothing
+// there).
+constexpr size_t kLargeNodes = size_t(1) << 22, kLargeNodes32 = size_t(1) << 20;
 constexpr int kDefaultWx = 8, kDefaultRows = 2;
 constexpr int kLargeWx = 4, kLargeRows = 3;
 constexpr int kLargeWx16 = 4, kLargeRows16 = 3;
@@ -1112,7 +1114,10 @@ template <class R> Phys<R> make_phys(const lbcm_params &p)
     return c;
 }
 
-bool large_lattice(const lbcm_params &p) { return (size_t)p.nx * p.ny >= kLargeNodes; }
+bool large_lattice(const lbcm_params &p)
+{
+    return (size_t)p.nx * p.ny >= (p.precision == LBCM_FP32 ? kLargeNodes32 : kLargeNodes);
+}
 
 // Lattice rows per wave of the single-lattice step kernel: two with 16-bit storage on large
 // lattices, where the step is bandwidth-bound; one otherwise (on small, latency-bound lattices a
