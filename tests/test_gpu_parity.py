@@ -188,6 +188,28 @@ def test_two_row_waves_equal_one_row_waves(prec, bc_y):
     small.close()
 
 
+@pytest.mark.parametrize("prec,nx,ny", [("fp32", 100, 50), ("fp64", 130, 37), ("fp16s", 2048, 2049)])
+def test_autotune_keeps_state_and_results(prec, nx, ny):
+    """lbcm_autotune times tile shapes on the spare pair: the state is unchanged, the chosen shape
+    is a valid split (heights powers of two or three times one), and the tuned lattice then
+    steps bit for bit like an untuned one (two-row waves in the 16-bit case)."""
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=40)
+    kw = dict(precision=prec, bc_y=1, force_x=1e-5, **PHYS)
+    a = lbcm.Lattice(nx, ny, **kw).init(phi, rho, ux, uy).step(2)
+    b = lbcm.Lattice(nx, ny, **kw).init(phi, rho, ux, uy).step(2)
+    before = a.get_state()
+    wx, rows = a.autotune(trials=2)
+    say(f"  {prec} {nx}x{ny}: autotuned tile {wx} x {rows}, rows per wave {a.rows_per_wave()}")
+    assert np.array_equal(a.get_state(), before)
+    assert wx >= 1 and rows >= 1 and wx * rows <= (8 if prec == "fp64" else 16)
+    assert rows in (1, 2, 3, 4, 6, 8, 12, 16) or rows >= ny
+    a.step(3)
+    b.step(3)
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.close()
+    b.close()
+
+
 def test_static_droplet_fp64_2000_steps():
     """64^2 static droplet, R = 16, a = 0.04, gamma = 0.08, M = 0.1, nu = 1/6, 2000 steps."""
     n = 64
