@@ -95,6 +95,12 @@ typedef struct lbcm_diagnostics {
     double max_u;        /* max |v| */
     int64_t nonfinite;   /* number of nodes with a non-finite rho or phi */
     int64_t step;        /* steps taken since lbcm_init */
+    double max_du;       /* max |v(t) - v(t-1)|: the largest change of the velocity over the last
+                            step (the steady-state measure of a driven channel), from the two
+                            population copies the handle keeps; NaN when the spare copy does not
+                            hold the previous step's state: before the first step after lbcm_init,
+                            lbcm_set_state or lbcm_copy_state, and after lbcm_fields,
+                            lbcm_populations or a tile timing, which stage through that copy */
 } lbcm_diagnostics;
 
 typedef struct lbcm_handle lbcm_handle;
@@ -137,7 +143,9 @@ int lbcm_fields_device(lbcm_handle *h, double *phi, double *rho, double *ux, dou
    NULL.  Synchronises. */
 int lbcm_populations(lbcm_handle *h, double *f, double *g);
 
-/* FP64 reductions of the current state (deterministic order).  Synchronises. */
+/* FP64 reductions of the current state (deterministic order): sums over the nodes of phi, |phi|,
+   rho and rho v, the maxima of |v| and of |v(t) - v(t-1)|, with v = (sum f c + F/2) / rho as
+   defined after Eq. (14).  Synchronises. */
 int lbcm_diag(lbcm_handle *h, lbcm_diagnostics *out);
 
 /* Bytes of the raw population state: 18 planes (f_0..f_8 then g_0..g_8) in storage precision. */
@@ -202,7 +210,10 @@ lbcm_handle *lbcm_batch_box(lbcm_batch *b, int32_t i);
 
 /* Advance every box by nsteps with one kernel launch per step (every box must be initialised).
    With graphs enabled (the default) pairs of steps are replayed from a captured hipGraph.
-   Asynchronous. */
+   Asynchronous, unless a box has check_every > 0: then the call synchronises every c steps (c
+   the shortest positive check_every of the boxes) and at its end, and returns LBCM_EDIVERGED
+   once any box has seen a non-finite rho or phi (the message names the first such box; each
+   box's flag is cleared by lbcm_init, lbcm_set_state and lbcm_copy_state of that box). */
 int lbcm_batch_step(lbcm_batch *b, int64_t nsteps);
 
 /* The same steps as single-box launches, box after box (the baseline the batched launch is

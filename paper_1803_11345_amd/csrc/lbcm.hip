@@ -56,7 +56,7 @@ constexpr int kLargeWx64 = 2, kLargeRows64 = 4;
 constexpr int kXcds = 8;         // XCDs of the device, to which workgroups are dealt in turn
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
-constexpr int kDiagFields = 7;
+constexpr int kDiagFields = 8;  // phi, |phi|, rho, jx, jy, max|v|, nonfinite, max|dv|
 
 // ------------------------------------------------------------------------------------------
 // raw buffer access
@@ -779,13 +779,13 @@ template <class R> struct BoxDesc {
     Geo geo;
     Phys<R> c;
     const unsigned char *set[2][2];  // [pair][f or g]
+    int *flag;                       // the box's divergence flag (set on a non-finite rho or phi)
     int walls, force;
 };
 
 template <class M>
 __global__ __launch_bounds__(kMaxThreads<M>) void k_step_batch(const BoxDesc<typename M::R> *__restrict__ boxes,
-                                                               const int2 *__restrict__ tiles, int cur,
-                                                               int *__restrict__ flag)
+                                                               const int2 *__restrict__ tiles, int cur)
 {
     using R = typename M::R;
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -797,12 +797,41 @@ __global__ __launch_bounds__(kMaxThreads<M>) void k_step_batch(const BoxDesc<typ
     const unsigned char *fa = d.set[cur][0], *ga = d.set[cur][1];
     unsigned char *fb = const_cast<unsigned char *>(d.set[1 - cur][0]);
     unsigned char *gb = const_cast<unsigned char *>(d.set[1 - cur][1]);
+    int *flag = d.flag;
     if (d.walls) {
         if (d.force) step_tile<M, 1, true, true>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
         else step_tile<M, 1, true, false>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
     } else {
         if (d.force) step_tile<M, 1, false, true>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
         else step_tile<M, 1, false, false>(fa, ga, fb, gb, d.geo, d.c, flag, band, rg, phs);
+    }
+}
+
+// Divergence flags of an ensemble: out[0] = number of boxes whose flag is set, out[1] = the
+// smallest such box index (n if none).  One workgroup of kReduceThreads threads.
+template <class R>
+__global__ __launch_bounds__(kReduceThreads) void k_batch_flags(const BoxDesc<R> *__restrict__ boxes, int n, int *out)
+{
+    __shared__ int cnt[kReduceThreads], first[kReduceThreads];
+    int c = 0, f = n;
+    for (int i = threadIdx.x; i < n; i += kReduceThreads)
+        if (*boxes[i].flag) {
+            ++c;
+            f = min(f, i);
+        }
+    cnt[threadIdx.x] = c;
+    first[threadIdx.x] = f;
+    __syncthreads();
+    for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            cnt[threadIdx.x] += cnt[threadIdx.x + s];
+            first[threadIdx.x] = min(first[threadIdx.x], first[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = cnt[0];
+        out[1] = first[0];
     }
 }
 
@@ -929,10 +958,15 @@ __global__ void k_population(SetView f, SetView g, Geo geo, int which, double *o
     }
 }
 
-__global__ __launch_bounds__(kReduceThreads) void k_diag(SetView f, SetView g, Geo geo, double hFx,
-                                                         double hFy, double *partial)
+// max-type fields of the diagnostics (the others are sums)
+__device__ __forceinline__ bool diag_is_max(int k) { return k == 5 || k == 7; }
+
+// FP64 reductions of one state (f, g); with have_prev also the largest change of v against the
+// previous state (pf), max |v(t) - v(t - 1)|.  Each block writes its kDiagFields partials.
+__global__ __launch_bounds__(kReduceThreads) void k_diag(SetView f, SetView g, SetView pf, int have_prev, Geo geo,
+                                                         double hFx, double hFy, double *partial)
 {
-    double acc[kDiagFields] = {0, 0, 0, 0, 0, 0, 0};  // phi, |phi|, rho, jx, jy, max|u|, nonfinite
+    double acc[kDiagFields] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < geo.plane;
          n += (size_t)gridDim.x * blockDim.x) {
         double fv[9], gv[9];
@@ -951,6 +985,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_diag(SetView f, SetView g, G
         acc[3] += jx;
         acc[4] += jy;
         acc[5] = fmax(acc[5], sqrt(jx * jx + jy * jy) / r);
+        if (have_prev) {
+            double qv[9];
+            pull_node(pf, geo, n, qv, false);
+            const double rp = 1.0 + sum9(qv);
+            const double jxp = (qv[1] + qv[5] + qv[8]) - (qv[3] + qv[6] + qv[7]) + hFx;
+            const double jyp = (qv[2] + qv[5] + qv[6]) - (qv[4] + qv[7] + qv[8]) + hFy;
+            const double dx = jx / r - jxp / rp, dy = jy / r - jyp / rp;
+            acc[7] = fmax(acc[7], sqrt(dx * dx + dy * dy));  // fmax drops a NaN of the previous state
+        }
     }
     __shared__ double red[kDiagFields][kReduceThreads];
     for (int k = 0; k < kDiagFields; ++k) red[k][threadIdx.x] = acc[k];
@@ -958,8 +1001,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_diag(SetView f, SetView g, G
     for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s)
             for (int k = 0; k < kDiagFields; ++k)
-                red[k][threadIdx.x] = k == 5 ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + s])
-                                             : red[k][threadIdx.x] + red[k][threadIdx.x + s];
+                red[k][threadIdx.x] = diag_is_max(k) ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + s])
+                                                     : red[k][threadIdx.x] + red[k][threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x < kDiagFields) partial[blockIdx.x * kDiagFields + threadIdx.x] = red[threadIdx.x][0];
@@ -969,19 +1012,19 @@ __global__ __launch_bounds__(kReduceThreads) void k_diag_finish(const double *pa
                                                                 double *out)
 {
     __shared__ double red[kDiagFields][kReduceThreads];
-    double acc[kDiagFields] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[kDiagFields] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += kReduceThreads)
         for (int k = 0; k < kDiagFields; ++k) {
             const double v = partial[b * kDiagFields + k];
-            acc[k] = k == 5 ? fmax(acc[k], v) : acc[k] + v;
+            acc[k] = diag_is_max(k) ? fmax(acc[k], v) : acc[k] + v;
         }
     for (int k = 0; k < kDiagFields; ++k) red[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s)
             for (int k = 0; k < kDiagFields; ++k)
-                red[k][threadIdx.x] = k == 5 ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + s])
-                                             : red[k][threadIdx.x] + red[k][threadIdx.x + s];
+                red[k][threadIdx.x] = diag_is_max(k) ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + s])
+                                                     : red[k][threadIdx.x] + red[k][threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x < kDiagFields) out[threadIdx.x] = red[threadIdx.x][0];
@@ -1005,6 +1048,7 @@ struct lbcm_handle {
     bool owns_ws = false;
     int cur = 0;                // pair holding the current state
     bool ready = false;
+    bool prev_ok = false;       // the spare pair holds the state one step before the current one
     int64_t step = 0;
     double *diag_partial = nullptr;
     double *diag_out = nullptr;
@@ -1015,6 +1059,7 @@ struct lbcm_handle {
 namespace {
 
 std::string g_create_error;
+
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -1231,6 +1276,7 @@ template <class M> int launch_steps(lbcm_handle *h, int64_t nsteps)
         HIP_TRY(h, hipGetLastError());
         h->cur = 1 - h->cur;
         h->step += 1;
+        h->prev_ok = true;
         if (h->p.check_every > 0 && ((s + 1) % h->p.check_every == 0 || s + 1 == nsteps)) {
             int flag = 0;
             HIP_TRY(h, hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -1256,6 +1302,7 @@ template <class M> float time_tiles(lbcm_handle *h, int wx, int rows, int rpw, i
     const size_t lds = tile_lds_bytes(geo, sizeof(R));
     const unsigned char *fa = set_base(h, h->cur, 0), *ga = set_base(h, h->cur, 1);
     unsigned char *fb = set_base(h, 1 - h->cur, 0), *gb = set_base(h, 1 - h->cur, 1);
+    h->prev_ok = false;  // the timed launches overwrite the spare pair
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1320,6 +1367,7 @@ int do_init(lbcm_handle *h, const double *phi0, const double *rho0, const double
     h->cur = 0;
     h->step = 0;
     h->ready = true;
+    h->prev_ok = false;
     return LBCM_OK;
 }
 
@@ -1347,7 +1395,8 @@ int do_diag(lbcm_handle *h)
 {
     const Geo geo = make_geo(h->p);
     hipLaunchKernelGGL(k_diag, dim3(kReduceBlocks), dim3(kReduceThreads), 0, h->stream, view_of(h, h->cur, 0),
-                       view_of(h, h->cur, 1), geo, 0.5 * h->p.force_x, 0.5 * h->p.force_y, h->diag_partial);
+                       view_of(h, h->cur, 1), view_of(h, 1 - h->cur, 0), (int)h->prev_ok, geo, 0.5 * h->p.force_x,
+                       0.5 * h->p.force_y, h->diag_partial);
     HIP_TRY(h, hipGetLastError());
     hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(kReduceThreads), 0, h->stream, h->diag_partial, kReduceBlocks,
                        h->diag_out);
@@ -1448,6 +1497,7 @@ template <class M> int build_tables(lbcm_batch *b)
             d.set[k][0] = set_base(h, h->cur ^ k, 0);
             d.set[k][1] = set_base(h, h->cur ^ k, 1);
         }
+        d.flag = h->flag;
         d.walls = q.bc_y == LBCM_BC_WALLS;
         d.force = q.force_x != 0 || q.force_y != 0;
         const size_t nt = (size_t)d.geo.nbands * d.geo.nrows;
@@ -1499,7 +1549,7 @@ bool tables_stale(lbcm_batch *b)
 template <class M> void launch_batch(lbcm_batch *b, int phase)
 {
     hipLaunchKernelGGL((k_step_batch<M>), dim3(b->grid), dim3(64 * b->waves), b->lds, b->stream,
-                       (const BoxDesc<typename M::R> *)b->d_desc, b->d_tiles, phase, b->flag);
+                       (const BoxDesc<typename M::R> *)b->d_desc, b->d_tiles, phase);
 }
 
 void advance_boxes(lbcm_batch *b, int64_t steps)
@@ -1507,8 +1557,26 @@ void advance_boxes(lbcm_batch *b, int64_t steps)
     for (lbcm_handle *h : b->box) {
         h->cur ^= (int)(steps & 1);
         h->step += steps;
+        if (steps > 0) h->prev_ok = true;
     }
     b->phase ^= (int)(steps & 1);
+}
+
+// Divergence check of an ensemble: synchronises and returns LBCM_EDIVERGED if any box's flag is
+// set (the flags are cleared by lbcm_init, lbcm_set_state and lbcm_copy_state of that box).
+template <class M> int check_batch(lbcm_batch *b)
+{
+    hipLaunchKernelGGL((k_batch_flags<typename M::R>), dim3(1), dim3(kReduceThreads), 0, b->stream,
+                       (const BoxDesc<typename M::R> *)b->d_desc, b->n, b->flag);
+    BHIP_TRY(b, hipGetLastError());
+    int v[2] = {0, 0};
+    BHIP_TRY(b, hipMemcpyAsync(v, b->flag, sizeof v, hipMemcpyDeviceToHost, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    if (v[0])
+        return bfail(b, LBCM_EDIVERGED,
+                     "non-finite rho or phi in " + std::to_string(v[0]) + " box(es), the first of them box " +
+                         std::to_string(v[1]) + ", by step " + std::to_string(b->box[v[1]]->step));
+    return LBCM_OK;
 }
 
 template <class M> int batch_steps(lbcm_batch *b, int64_t nsteps)
@@ -1517,12 +1585,24 @@ template <class M> int batch_steps(lbcm_batch *b, int64_t nsteps)
         int rc = build_tables<M>(b);
         if (rc) return rc;
     }
-    int64_t s = 0;
+    // divergence checks: every `every` steps (the shortest positive check_every of the boxes)
+    // and at the end of the call
+    int every = 0;
+    for (lbcm_handle *h : b->box)
+        if (h->p.check_every > 0) every = every ? std::min(every, h->p.check_every) : h->p.check_every;
+    int64_t s = 0, since = 0;
+    auto checked = [&](int64_t k) -> int {  // k steps were just queued
+        advance_boxes(b, k);
+        s += k;
+        since += k;
+        if (every <= 0 || (since < every && s < nsteps)) return LBCM_OK;
+        since = 0;
+        return check_batch<M>(b);
+    };
     if (b->phase == 1 && s < nsteps) {  // get to an even phase for the two-step graph
         launch_batch<M>(b, 1);
         BHIP_TRY(b, hipGetLastError());
-        advance_boxes(b, 1);
-        ++s;
+        if (int rc = checked(1)) return rc;
     }
     if (b->use_graph && nsteps - s >= 2) {
         if (!b->graph_ok) {
@@ -1537,15 +1617,15 @@ template <class M> int batch_steps(lbcm_batch *b, int64_t nsteps)
             if (e != hipSuccess) return bfail(b, LBCM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
             b->graph_ok = true;
         }
-        for (; s + 2 <= nsteps; s += 2) {
+        while (s + 2 <= nsteps) {
             BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream));
-            advance_boxes(b, 2);
+            if (int rc = checked(2)) return rc;
         }
     }
-    for (; s < nsteps; ++s) {
+    while (s < nsteps) {
         launch_batch<M>(b, b->phase);
         BHIP_TRY(b, hipGetLastError());
-        advance_boxes(b, 1);
+        if (int rc = checked(1)) return rc;
     }
     return LBCM_OK;
 }
@@ -1554,6 +1634,7 @@ template <class M> int batch_steps(lbcm_batch *b, int64_t nsteps)
 template <class M> float time_batch(lbcm_batch *b, int trials)
 {
     if (tables_stale(b) && build_tables<M>(b) != LBCM_OK) return -1;
+    for (lbcm_handle *h : b->box) h->prev_ok = false;  // the timed launches overwrite the spare pairs
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1789,6 +1870,7 @@ int lbcm_fields(lbcm_handle *h, double *phi, double *rho, double *ux, double *uy
     // one plane at a time through the spare pair (>= 8 bytes per node in every mode)
     const size_t N = (size_t)h->p.nx * h->p.ny;
     double *stage = (double *)(h->ws + (size_t)(1 - h->cur) * h->pair_bytes);
+    h->prev_ok = false;  // staged through the spare pair
     double *dst[5] = {phi, rho, ux, uy, p0};
     for (int k = 0; k < 5; ++k) {
         if (!dst[k]) continue;
@@ -1808,6 +1890,7 @@ int lbcm_populations(lbcm_handle *h, double *f, double *g)
     if (!h->ready) return fail(h, LBCM_ESTATE, "lbcm_populations before lbcm_init");
     const size_t N = (size_t)h->p.nx * h->p.ny;
     double *stage = (double *)(h->ws + (size_t)(1 - h->cur) * h->pair_bytes);
+    h->prev_ok = false;  // staged through the spare pair
     for (int k = 0; k < 18; ++k) {
         double *dst = k < 9 ? f : g;
         if (!dst) continue;
@@ -1836,6 +1919,7 @@ int lbcm_diag(lbcm_handle *h, lbcm_diagnostics *out)
     out->max_u = v[5];
     out->nonfinite = (int64_t)v[6];
     out->step = h->step;
+    out->max_du = h->prev_ok ? v[7] : std::nan("");
     return LBCM_OK;
 }
 
@@ -1867,6 +1951,7 @@ int lbcm_set_state(lbcm_handle *h, const void *host, size_t bytes, int64_t step)
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->ready = true;
+    h->prev_ok = false;
     h->step = step;
     return LBCM_OK;
 }
@@ -1887,6 +1972,7 @@ int lbcm_copy_state(lbcm_handle *dst, const lbcm_handle *src, int64_t step)
     hipLaunchKernelGGL(k_clear_int, dim3(1), dim3(1), 0, dst->stream, dst->flag);
     HIP_TRY(dst, hipGetLastError());
     dst->ready = true;
+    dst->prev_ok = false;
     dst->step = step;
     return LBCM_OK;
 }
@@ -1909,6 +1995,7 @@ const char *lbcm_last_error(const lbcm_handle *h)
 {
     return h ? h->err.c_str() : g_create_error.c_str();
 }
+
 
 int lbcm_autotune(lbcm_handle *h, int trials)
 {

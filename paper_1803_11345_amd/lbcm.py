@@ -52,7 +52,7 @@ class lbcm_diagnostics(ctypes.Structure):
     _fields_ = [
         ("sum_phi", ctypes.c_double), ("sum_abs_phi", ctypes.c_double), ("sum_rho", ctypes.c_double),
         ("sum_jx", ctypes.c_double), ("sum_jy", ctypes.c_double), ("max_u", ctypes.c_double),
-        ("nonfinite", ctypes.c_int64), ("step", ctypes.c_int64),
+        ("nonfinite", ctypes.c_int64), ("step", ctypes.c_int64), ("max_du", ctypes.c_double),
     ]
 
 

@@ -32,7 +32,7 @@ def test_library_has_no_oracle_dependency():
 def test_struct_layout_matches_header():
     # int32 x4, double x12, int32 x4, two pointers and a size_t
     assert ctypes.sizeof(lbcm.lbcm_params) == 16 + 96 + 16 + 24
-    assert ctypes.sizeof(lbcm.lbcm_diagnostics) == 8 * 8
+    assert ctypes.sizeof(lbcm.lbcm_diagnostics) == 9 * 8
 
 
 @pytest.mark.parametrize("prec,elem", [("fp64", 8), ("fp32", 4)])

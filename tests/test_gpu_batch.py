@@ -175,3 +175,92 @@ def test_full_ensemble_matches_single_lattices_on_sampled_boxes():
         assert np.array_equal(lat.get_state(), bt[k].get_state()), (k, p["nx"], p["bc_y"])
         lat.close()
     bt.close()
+
+
+# ---------------------------------------------------------------------------------------------
+# ensembles against the oracle directly (not only against single-lattice GPU runs)
+
+def _oracle_run(p, phi, steps, rho=None, ux=None, uy=None, nthreads=0):
+    import oracle
+
+    okw = {k: v for k, v in p.items() if k not in ("nx", "ny")}
+    if "bc_y" in okw:
+        okw["walls"] = okw.pop("bc_y")
+    for side in ("bottom", "top"):
+        if f"wall_vx_{side}" in okw:
+            okw[f"wall_ux_{side}"] = okw.pop(f"wall_vx_{side}")
+    q = oracle.Params(p["nx"], p["ny"], nthreads=nthreads, **okw)
+    return oracle.run(q, *oracle.init(q, phi, rho, ux, uy), steps)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-5), ("fp16s", 3e-4)])
+def test_batch_boxes_match_the_oracle(prec, tol):
+    """Every box of a mixed ensemble (periodic, walls, force, moving and wetting walls, ragged and
+    tiny sizes) advanced 7 steps by the batched launch with graphs, element by element against
+    the oracle, within the single-lattice tiers of each storage (FP64 1e-14 per step; FP32 and
+    FP16 storage the 50-step tiers)."""
+    say(f"case batch vs oracle {prec}")
+    steps = 7
+    bt = _batch(prec, 110)
+    bt.step(steps)
+    worst = 0.0
+    for k, (b, st) in enumerate(zip(BOXES, _states(110))):
+        fo, go = _oracle_run(b, st[0], steps, *st[1:])
+        f, g = bt[k].populations()
+        e = max(float(np.abs(f - fo).max()), float(np.abs(g - go).max()))
+        say(f"  box {k} {b['nx']}x{b['ny']} bc_y={b.get('bc_y', 0)}: max |GPU - oracle| = {e:.2e}")
+        worst = max(worst, e)
+        assert e < tol, k
+    bt.close()
+
+
+def test_full_ensemble_sampled_boxes_match_the_oracle():
+    """The 512-box FP16-storage ensemble of the benchmark, autotuned and advanced with graphs:
+    after 11 steps the first and last box and the smallest and largest box of each kind
+    (droplets, layered channels with walls and force) against the oracle, element by element,
+    within the FP16 tier (3e-4)."""
+    spec = inputs.ensemble(512, seed=7)
+    bt = lbcm.Batch([p for p, _ in spec], precision="fp16s")
+    for box, (_, phi0) in zip(bt, spec):
+        box.init(phi0)
+    bt.autotune(trials=3)
+    bt.step(11)
+    size = [p["nx"] * p["ny"] for p, _ in spec]
+    picks = {0, len(spec) - 1}
+    for walls in (0, 1):
+        kind = [k for k, (p, _) in enumerate(spec) if p["bc_y"] == walls]
+        picks |= {max(kind, key=lambda k: size[k]), min(kind, key=lambda k: size[k])}
+    for k in sorted(picks):
+        p, phi0 = spec[k]
+        say(f"case ensemble box {k}: {p['nx']}x{p['ny']} bc_y={p['bc_y']}")
+        fo, go = _oracle_run(p, phi0, 11)
+        f, g = bt[k].populations()
+        e = max(float(np.abs(f - fo).max()), float(np.abs(g - go).max()))
+        say(f"  max |GPU - oracle| = {e:.2e}")
+        assert e < 3e-4, k
+    bt.close()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_reports_divergence_of_one_box(graph):
+    """A box whose state holds a NaN: with check_every on any box, lbcm_batch_step returns
+    LBCM_EDIVERGED naming that box; re-initialising the box clears its flag and the batch steps
+    on without error."""
+    boxes = [dict(b, check_every=4 if k == 1 else 0) for k, b in enumerate(BOXES)]
+    bt = lbcm.Batch(boxes, precision="fp32")
+    states = _states(120)
+    for box, st in zip(bt, states):
+        box.init(*st)
+    bt.set_graph(graph)
+    bt.step(9)  # all finite: no error
+    bad = states[3][0].copy()
+    bad[10, 10] = np.nan
+    bt[3].init(bad, *states[3][1:])
+    with pytest.raises(lbcm.LbcmError) as e:
+        bt.step(6)
+    assert e.value.code == lbcm.LBCM_EDIVERGED and "box 3" in str(e.value)
+    bt[3].init(*states[3])
+    bt.step(6)
+    for box in bt:
+        assert box.diag()["nonfinite"] == 0
+    bt.close()

@@ -1,0 +1,114 @@
+"""GPU parity of the FP64 diagnostics (lbcm_diag) against the same reductions of the oracle's
+fields: sums of phi, |phi|, rho and rho v over the nodes, max |v| and the largest change of v over
+the last step, with v = (sum f c + F/2) / rho as defined after Eq. (14).
+
+Bounds.  FP64: the GPU state equals the oracle's to a few 1e-16 per node and step, and both
+reductions add N terms in FP64 (in different orders), so a sum differs by at most about
+N * 1e-15 times the size of its terms: the bound is 1e-12 relative to the sum of the absolute
+values.  FP32 / 16-bit storage: each node carries the storage tier of the population parity
+tests (after 20 steps: FP32 2e-5, FP16 3e-4 per population); a moment of 9 populations is off
+by at most 9 times that, so the sums are bounded by 9 * tier * N (absolute) and the maxima by
+9 * tier, divided by the smallest density (> 0.95 here).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1803_11345_amd import inputs, lbcm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_params(nx, ny, kw):
+    okw = dict(kw)
+    if "bc_y" in okw:
+        okw["walls"] = okw.pop("bc_y")
+    for side in ("bottom", "top"):
+        if f"wall_vx_{side}" in okw:
+            okw[f"wall_ux_{side}"] = okw.pop(f"wall_vx_{side}")
+    return oracle.Params(nx, ny, **okw)
+
+
+def oracle_diag(p, f, g, fprev, gprev):
+    """The diagnostics computed from the oracle's fields (plain numpy sums in FP64)."""
+    m = oracle.macro(p, f, g)
+    q = oracle.macro(p, fprev, gprev)
+    jx, jy = m["rho"] * m["ux"], m["rho"] * m["uy"]
+    return {"sum_phi": m["phi"].sum(), "sum_abs_phi": np.abs(m["phi"]).sum(), "sum_rho": m["rho"].sum(),
+            "sum_jx": jx.sum(), "sum_jy": jy.sum(), "max_u": np.sqrt(m["ux"] ** 2 + m["uy"] ** 2).max(),
+            "max_du": np.sqrt((m["ux"] - q["ux"]) ** 2 + (m["uy"] - q["uy"]) ** 2).max(),
+            "scale": {"sum_phi": np.abs(m["phi"]).sum(), "sum_abs_phi": np.abs(m["phi"]).sum(),
+                      "sum_rho": m["rho"].sum(), "sum_jx": np.abs(jx).sum(), "sum_jy": np.abs(jy).sum()},
+            "min_rho": m["rho"].min()}
+
+
+CASES = {
+    "periodic": dict(nu_l=0.1, nu_g=0.02),
+    "periodic_force": dict(nu_l=0.1, nu_g=0.02, force_x=2e-5, force_y=-1e-5),
+    "walls_force": dict(bc_y=1, nu_l=0.1, nu_g=0.02, force_x=1e-5),
+    "moving_wetting_walls": dict(bc_y=1, nu_l=0.1, nu_g=0.02, wall_vx_bottom=-3e-3, wall_vx_top=5e-3,
+                                 wall_gradient=0.05),
+}
+TIER = {"fp64": None, "fp32": 2e-5, "fp16s": 3e-4}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_diag_matches_oracle_reductions(case, prec):
+    kw = CASES[case]
+    nx, ny, steps = 70, 45, 20
+    phi, rho, ux, uy = inputs.smooth_state(nx, ny, seed=61)
+    say(f"case diag {case} {prec} {nx}x{ny} {steps} steps")
+    p = oracle_params(nx, ny, kw)
+    f0, g0 = oracle.init(p, phi, rho, ux, uy)
+    fp, gp = oracle.run(p, f0, g0, steps - 1)
+    fo, go = oracle.step(p, fp, gp)
+    want = oracle_diag(p, fo, go, fp, gp)
+    lat = lbcm.Lattice(nx, ny, precision=prec, tile_rows=2, **kw).init(phi, rho, ux, uy)
+    d_init = lat.diag()
+    assert np.isnan(d_init["max_du"])  # no previous step yet
+    lat.step(steps)
+    d = lat.diag()  # before any reader that stages through the spare pair
+    lat.fields()
+    assert np.isnan(lat.diag()["max_du"])  # the spare pair now holds staged fields
+    lat.close()
+    N = nx * ny
+    assert d["step"] == steps and d["nonfinite"] == 0
+    for k in ("sum_phi", "sum_abs_phi", "sum_rho", "sum_jx", "sum_jy"):
+        err = abs(d[k] - want[k])
+        bound = 1e-12 * want["scale"][k] if prec == "fp64" else 9 * TIER[prec] * N
+        say(f"  {k}: gpu {d[k]:.15e} oracle {want[k]:.15e} |diff| {err:.2e} (bound {bound:.1e})")
+        assert err <= bound, k
+    for k in ("max_u", "max_du"):
+        err = abs(d[k] - want[k])
+        bound = 1e-12 * want["max_u"] if prec == "fp64" else 2 * 9 * TIER[prec] / want["min_rho"]
+        say(f"  {k}: gpu {d[k]:.6e} oracle {want[k]:.6e} |diff| {err:.2e} (bound {bound:.1e})")
+        assert err <= bound, k
+    assert want["max_du"] > 0
+
+
+def test_diag_counts_nonfinite_nodes():
+    nx, ny = 40, 30
+    phi = inputs.smooth_state(nx, ny, seed=62)[0].copy()
+    phi[7, 11] = np.nan
+    phi[20, 3] = np.inf
+    lat = lbcm.Lattice(nx, ny, precision="fp64").init(phi)
+    d = lat.diag()
+    # the initial equilibria of a node read the 3x3 neighbourhood of phi0 (its stencils), and the
+    # pull returns exactly those equilibria: the 3x3 block around each planted value is non-finite
+    assert d["nonfinite"] == 2 * 9
+    lat.close()

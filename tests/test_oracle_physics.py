@@ -17,9 +17,9 @@ import os
 
 import numpy as np
 import pytest
-from scipy.integrate import quad
 
 from paper_1803_11345_amd import inputs
+from tests.analytic import diffuse_poiseuille, sharp_poiseuille
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
 
@@ -91,31 +91,6 @@ def test_flat_interface_profile(orc):
     assert np.max(np.abs(m["uy"])) < 1e-6
 
 
-def _diffuse_poiseuille(L, nu1, nu2, G, W):
-    """Steady two-layer channel flow for the actual diffuse viscosity profile: the shear stress
-    nu u' = C - G y is linear across the channel and u(0) = u(L) = 0 fixes C (Stokes flow,
-    walls half a node outside the first and last rows)."""
-    wl, wg = 1 / (3 * nu1 + 0.5), 1 / (3 * nu2 + 0.5)
-
-    def nu(s):
-        ph = math.tanh((L / 2 - s) / W)
-        w = wg + 0.5 * (ph + 1) * (wl - wg)
-        return (1 / w - 0.5) / 3
-
-    I0 = quad(lambda s: 1 / nu(s), 0, L, points=[L / 2], limit=200)[0]
-    I1 = quad(lambda s: s / nu(s), 0, L, points=[L / 2], limit=200)[0]
-    C = G * I1 / I0
-    yp = np.arange(L) + 0.5
-    return np.array([quad(lambda s: (C - G * s) / nu(s), 0, y, limit=200)[0] for y in yp])
-
-
-def _sharp_poiseuille(L, nu1, nu2, G):
-    h = L / 2
-    C = G * (h * h / nu1 + (L * L - h * h) / nu2) / (2 * (h / nu1 + (L - h) / nu2))
-    yp = np.arange(L) + 0.5
-    return np.where(yp <= h, (C * yp - G * yp ** 2 / 2) / nu1, (G * (L * L - yp ** 2) / 2 - C * (L - yp)) / nu2)
-
-
 @pytest.mark.parametrize("ratio", [1, 10, 100, 1000])
 def test_layered_poiseuille(orc, ratio):
     """Two-layer channel flow with viscosity contrast (phi = +1 below, -1 above, nu1 = 0.1 and
@@ -123,9 +98,9 @@ def test_layered_poiseuille(orc, ratio):
     L, G, nu1 = 64, 1e-6, 0.1
     a, gamma = 0.04, 0.08
     W = inputs.interface_width(a, gamma)
-    ua = _diffuse_poiseuille(L, nu1, ratio * nu1, G, W)
+    ua = diffuse_poiseuille(L, nu1, ratio * nu1, G, W)
     if ratio == 1:
-        np.testing.assert_allclose(ua, _sharp_poiseuille(L, nu1, nu1, G), rtol=1e-9, atol=1e-14)
+        np.testing.assert_allclose(ua, sharp_poiseuille(L, nu1, nu1, G), rtol=1e-9, atol=1e-14)
     p = orc.Params(4, L, walls=1, a=a, gamma=gamma, nu_l=nu1, nu_g=ratio * nu1, force_x=G, nthreads=1)
     f, g = orc.init(p, inputs.layered(4, L, W), ux0=np.repeat(ua[:, None], 4, axis=1))
     f, g = orc.run(p, f, g, 6000)
@@ -143,7 +118,7 @@ def test_poiseuille_from_rest(orc):
     f, g = orc.init(p, inputs.layered(4, L, inputs.interface_width(0.04, 0.08)))
     f, g = orc.run(p, f, g, 40000)
     u = orc.macro(p, f, g)["ux"][:, 0]
-    ua = _sharp_poiseuille(L, nu, nu, G)
+    ua = sharp_poiseuille(L, nu, nu, G)
     assert np.linalg.norm(u - ua) / np.linalg.norm(ua) < 1e-3
 
 
