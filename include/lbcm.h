@@ -148,6 +148,23 @@ int lbcm_populations(lbcm_handle *h, double *f, double *g);
    defined after Eq. (14).  Synchronises. */
 int lbcm_diag(lbcm_handle *h, lbcm_diagnostics *out);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): the diagnostics of lbcm_diag for a state held in the
+   caller's device memory, without a handle and without any allocation.  f and g are the two
+   population sets as lbcm_get_state lays them out (f: 9 planes, g: 9 planes, pull layout, f
+   shifted by the weights, storage precision of p->precision), each aligned to its widest element
+   (8 bytes for FP64, 4 otherwise); f_prev, optional, is the f set of the step before, for max_du
+   (NaN when f_prev is NULL).  Only nx, ny, bc_y, precision, force and the wall parameters of *p
+   are used (p must pass lbcm_create's checks); work runs on p->stream, and the call
+   synchronises it.  out->step is set to `step`.
+   The partial sums live in a fixed device array of 65,600 bytes that the library holds on each
+   GPU for the life of the process (any lattice size fits: the kernels stride over the nodes).
+   Calls on the same GPU share that array: calls that overlap in time on one GPU (other host
+   threads, other streams) race and must be serialised by the caller.  Errors: LBCM_EINVAL (bad
+   parameters, NULL or misaligned pointers), LBCM_EHIP; the message is lbcm_last_error(NULL). */
+int lbcm_diag_state(const lbcm_params *p, const void *f, const void *g, const void *f_prev, int64_t step,
+                    lbcm_diagnostics *out);
+
 /* Bytes of the raw population state: 18 planes (f_0..f_8 then g_0..g_8) in storage precision. */
 /* The raw state is in pull layout (plane i at node x holds the post-collision value of the
    previous step at its origin node x) and f is stored shifted, as f_i - w_i. */

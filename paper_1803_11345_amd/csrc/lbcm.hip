@@ -33,6 +33,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -1034,6 +1035,16 @@ __global__ void k_clear_int(int *p) { *p = 0; }
 
 }  // namespace
 
+// ------------------------------------------------------------------------------------------
+// Device scratch of lbcm_diag_state, the allocation-free diagnostics: the partial sums of
+// k_diag (kReduceBlocks blocks of kDiagFields doubles) and the kDiagFields results of
+// k_diag_finish, 65,600 bytes whatever the lattice size (the kernels stride over the nodes).
+// Every GPU the library runs on holds its own copy until the process ends.  Host code never
+// uses this name as an address: it asks the runtime for the copy of the current device
+// (scratch_address) and passes that pointer.
+constexpr size_t kScratchDoubles = (size_t)kReduceBlocks * kDiagFields + kDiagFields;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 // ==========================================================================================
 // host side
 
@@ -1060,6 +1071,24 @@ namespace {
 
 std::string g_create_error;
 
+// Device address of `scratch` on each device, looked up once per device (with that device
+// current) on the first lbcm_diag_state call there.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, double **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -1996,6 +2025,63 @@ const char *lbcm_last_error(const lbcm_handle *h)
     return h ? h->err.c_str() : g_create_error.c_str();
 }
 
+int lbcm_diag_state(const lbcm_params *p, const void *f, const void *g, const void *f_prev, int64_t step,
+                    lbcm_diagnostics *out)
+{
+    auto err = [](int code, const std::string &m) {
+        g_create_error = "lbcm_diag_state: " + m;
+        return code;
+    };
+    if (const char *m = check_params(p)) return err(LBCM_EINVAL, m);
+    if (!f || !g || !out) return err(LBCM_EINVAL, "f, g and out must not be NULL");
+    Kinds k;
+    kinds_of(p->precision, k);
+    const uintptr_t al = kind_bytes(k.f) > kind_bytes(k.g0) ? kind_bytes(k.f) : kind_bytes(k.g0);
+    if ((uintptr_t)f % al || (uintptr_t)g % al || (uintptr_t)f_prev % al)
+        return err(LBCM_EINVAL, "population sets must be aligned to " + std::to_string(al) + " bytes");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return err(LBCM_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return err(LBCM_EINVAL, "device index beyond the scratch table");
+    double *ptr = nullptr;
+    e = scratch_address(dev, &ptr);
+    if (e != hipSuccess) return err(LBCM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    const size_t N = (size_t)p->nx * p->ny;
+    auto view = [&](const void *base, bool is_g) {
+        SetView v;
+        v.base = (unsigned char *)const_cast<void *>(base);
+        const int k0 = is_g ? k.g0 : k.f, k1 = is_g ? k.g : k.f;
+        for (int i = 0; i < 9; ++i) {
+            v.kind[i] = i == 0 ? k0 : k1;
+            v.off[i] = (uint32_t)(i == 0 ? 0 : N * kind_bytes(k0) + (size_t)(i - 1) * N * kind_bytes(k1));
+        }
+        return v;
+    };
+    const Geo geo = make_geo(*p);
+    const hipStream_t st = (hipStream_t)p->stream;
+    double *partial = ptr, *res = ptr + (size_t)kReduceBlocks * kDiagFields;
+    hipLaunchKernelGGL(k_diag, dim3(kReduceBlocks), dim3(kReduceThreads), 0, st, view(f, false), view(g, true),
+                       view(f_prev ? f_prev : f, false), (int)(f_prev != nullptr), geo, 0.5 * p->force_x,
+                       0.5 * p->force_y, partial);
+    if ((e = hipGetLastError()) != hipSuccess) return err(LBCM_EHIP, std::string("k_diag: ") + hipGetErrorString(e));
+    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(kReduceThreads), 0, st, partial, kReduceBlocks, res);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return err(LBCM_EHIP, std::string("k_diag_finish: ") + hipGetErrorString(e));
+    double v[kDiagFields];
+    if ((e = hipMemcpyAsync(v, res, sizeof v, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return err(LBCM_EHIP, std::string("reading the results: ") + hipGetErrorString(e));
+    out->sum_phi = v[0];
+    out->sum_abs_phi = v[1];
+    out->sum_rho = v[2];
+    out->sum_jx = v[3];
+    out->sum_jy = v[4];
+    out->max_u = v[5];
+    out->nonfinite = (int64_t)v[6];
+    out->step = step;
+    out->max_du = f_prev ? v[7] : std::nan("");
+    return LBCM_OK;
+}
 
 int lbcm_autotune(lbcm_handle *h, int trials)
 {

@@ -94,6 +94,8 @@ def load():
     lib.lbcm_fields_device.argtypes = [_H] + [ctypes.c_void_p] * 5
     lib.lbcm_populations.argtypes = [_H, _D, _D]
     lib.lbcm_diag.argtypes = [_H, ctypes.POINTER(lbcm_diagnostics)]
+    lib.lbcm_diag_state.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.POINTER(lbcm_diagnostics)]
     lib.lbcm_state_size.argtypes = [_H]
     lib.lbcm_state_size.restype = ctypes.c_size_t
     lib.lbcm_get_state.argtypes = [_H, ctypes.c_void_p, ctypes.c_size_t]
@@ -198,6 +200,23 @@ def lbcm_populations(h, f=None, g=None):
 def lbcm_diag(h) -> dict:
     d = lbcm_diagnostics()
     _check(h, load().lbcm_diag(h, ctypes.byref(d)))
+    return {name: getattr(d, name) for name, _ in lbcm_diagnostics._fields_}
+
+
+def lbcm_diag_state(params: lbcm_params, f, g, f_prev=None, step: int = 0) -> dict:
+    """Diagnostics of a state in caller device memory (f, g, f_prev: CUDA tensors or raw device
+    addresses); allocation-free."""
+    def addr(t):
+        if t is None or isinstance(t, int):
+            return t
+        if not t.is_cuda or not t.is_contiguous():
+            raise TypeError("expected a contiguous CUDA tensor")
+        return t.data_ptr()
+
+    d = lbcm_diagnostics()
+    rc = load().lbcm_diag_state(ctypes.byref(params), addr(f), addr(g), addr(f_prev), int(step), ctypes.byref(d))
+    if rc != LBCM_OK:
+        raise LbcmError(rc, lbcm_last_error(None))
     return {name: getattr(d, name) for name, _ in lbcm_diagnostics._fields_}
 
 
