@@ -5,7 +5,13 @@ from SplitMix64 seed 1, rho = 1, v = 0, a = 0.04, gamma = 0.08, M = 0.1, Gamma =
 nu = 0.05 in both phases), FP32 populations.  One step = one launch of the fused step kernel,
 which updates both population sets of every node (one LUP per node).
 
-Prints one JSON line: MLUPS over the timed steps (HIP events on the stream the kernel runs on),
+Timing: W warm-up steps, then 5 blocks of K steps, each between HIP events on the stream the
+kernel runs on with the device synchronised on both sides; the line reports the median block
+(and the mean and every block).  The untimed device-copy probe runs right before the warm-up, so
+the GPU is busy when the warm-up starts: after any idle gap the first ~60 steps run up to 5 %
+(FP32) and 8 % (16-bit) slower while the clocks come back up, whatever the state.
+
+Prints one JSON line: MLUPS of the median timed block,
 the HBM roofline of the step kernel (144 algorithmic bytes per LUP: 9 f + 9 g read, 9 f + 9 g
 written, 4 bytes each) beside a plain device copy, and the FP64 CPU oracle timed on a bounded
 sample on the host cores (all threads and one), plus the 64 x 64 droplet in full.  Further legs
@@ -42,7 +48,9 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_LUP))
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--tile-wx", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps in the CPU sample (0 = skip)")
+    ap.add_argument("--blocks", type=int, default=5, help="timed blocks of --steps steps (the median is reported)")
+    ap.add_argument("--cpu-steps", type=int, default=16,
+                    help="oracle steps in the CPU sample, timed as two halves (0 = skip)")
     ap.add_argument("--cpu-single-steps", type=int, default=1,
                     help="oracle steps of the single-thread CPU sample (0 = skip it)")
     ap.add_argument("--copy-probe", action="store_true", default=True,
@@ -63,41 +71,57 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n: int, steps: int, single_steps: int, small_steps: int) -> dict:
     """The FP64 oracle on the host: the 4096^2 workload on all threads given by OMP_NUM_THREADS
-    (a bounded sample of steps), on one thread, and the 64 x 64 static droplet run in full."""
+    (a bounded sample of steps, timed as two halves run in place, so that the spread shows the
+    per-step cost is constant), on one thread, and the 64 x 64 static droplet run in full."""
     import numpy as np
 
     import oracle
     from paper_1803_11345_amd import inputs
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    phys = dict(a=0.04, gamma=0.08, mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05)
 
-    def timed(nx, ny, phi, k, nthreads, **kw):
-        phys = dict(a=0.04, gamma=0.08, mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05)
-        phys.update(kw)
-        p = oracle.Params(nx, ny, nthreads=nthreads, **phys)
+    def timed(nx, ny, phi, parts, nthreads, **kw):
+        q = dict(phys)
+        q.update(kw)
+        p = oracle.Params(nx, ny, nthreads=nthreads, **q)
         f, g = oracle.init(p, phi)
-        t0 = time.perf_counter()
-        f, g = oracle.run(p, f, g, k)
-        dt = time.perf_counter() - t0
+        secs = []
+        for k in parts:
+            t0 = time.perf_counter()
+            oracle.run(p, f, g, k, inplace=True)
+            secs.append(time.perf_counter() - t0)
         assert np.isfinite(f).all()
-        return nx * ny * k / dt / 1e6, dt
+        return nx * ny * sum(parts) / sum(secs) / 1e6, secs
 
     phi0 = inputs.spinodal(n, n, seed=1)
-    v, dt = timed(n, n, phi0, steps, threads)
-    out = {"value": round(v, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-           "sample": f"FP64 oracle, {n}x{n} spinodal (same initial state), {steps} steps after "
-                     f"initialisation, {dt:.1f} s on {threads} OpenMP threads"}
+    half = max(1, steps // 2)
+    v, secs = timed(n, n, phi0, (half, half), threads)
+    out = {"value": round(v, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"FP64 oracle (gcc -O3, OpenMP), {n}x{n} spinodal (same initial state), {2 * half} steps "
+                     f"after initialisation, {sum(secs):.1f} s on {threads} OpenMP threads; halves "
+                     f"{n * n * half / secs[0] / 1e6:.2f} and {n * n * half / secs[1] / 1e6:.2f} MLUPS"}
     if single_steps > 0:
-        v1, dt1 = timed(n, n, phi0, single_steps, 1)
+        v1, s1 = timed(n, n, phi0, (single_steps,), 1)
         out["single_thread"] = {"value": round(v1, 3), "unit": "MLUPS", "cores": 1,
-                                "sample": f"the same, {single_steps} step(s), {dt1:.1f} s on one thread"}
+                                "sample": f"the same, {single_steps} step(s), {sum(s1):.1f} s on one thread"}
     if small_steps > 0:
         w = inputs.interface_width(0.04, 0.08)
-        vs, dts = timed(64, 64, inputs.droplet(64, 64, 16, w), small_steps, threads, nu_l=1 / 6, nu_g=1 / 6)
+        vs, ss = timed(64, 64, inputs.droplet(64, 64, 16, w), (small_steps,), threads, nu_l=1 / 6, nu_g=1 / 6)
         out["droplet64"] = {"value": round(vs, 3), "unit": "MLUPS", "cores": threads,
-                            "sample": f"64x64 static droplet (R = 16, nu = 1/6), {small_steps} steps, {dts:.2f} s"}
+                            "sample": f"64x64 static droplet (R = 16, nu = 1/6), {small_steps} steps, {sum(ss):.2f} s"}
     return out
 
 
@@ -138,18 +162,33 @@ def make_lattice(lbcm, n, precision, args):
                         a=0.04, gamma=0.08, mobility=0.1, Gamma=1.0, nu_l=0.05, nu_g=0.05)
 
 
-def time_steps(lat, steps, warmup):
-    """Average step time (s) over `steps` launches between HIP events on the lattice's stream."""
+def time_blocks(lat, steps, warmup, blocks):
+    """Seconds per step of each of `blocks` blocks of `steps` launches, each between HIP events on
+    the lattice's stream with the device synchronised before and after, after `warmup` untimed
+    steps."""
     import torch
 
     lat.step(warmup)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(lat.stream)
-    lat.step(steps)
-    e1.record(lat.stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / steps
+    out = []
+    for _ in range(blocks):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(steps)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / 1e3 / steps)
+    return out
+
+
+def median(v):
+    import statistics
+
+    return statistics.median(v)
+
+
+# secondary legs (not the headline line) warm up long enough to pass the clock ramp after idle gaps
+LEG_WARMUP = 200
 
 
 def structure_factor(phi):
@@ -210,7 +249,7 @@ def precision_report(lbcm, phi0, n, args, fp32_sec):
                        **{prec: errors(prec, marks[1]) for prec in ("fp32", "fp16s", "bf16s")}}
     for prec in ("fp16s", "bf16s"):
         lat = make_lattice(lbcm, n, prec, args).init(phi0)
-        sec = time_steps(lat, args.steps, args.warmup)
+        sec = median(time_blocks(lat, args.steps, max(args.warmup, LEG_WARMUP), args.blocks))
         lat.close()
         out[prec] = {"value": round(n * n / sec / 1e6, 1), "unit": "MLUPS",
                      "speedup_vs_fp32": round(fp32_sec / sec, 3),
@@ -235,7 +274,7 @@ def small_report(lbcm, steps, warmup):
     out = {"note": "cache-resident: MLUPS only, no HBM fraction"}
     for name, (nx, ny, phi, kw) in cases.items():
         lat = lbcm.Lattice(nx, ny, **kw).init(phi)
-        sec = time_steps(lat, steps, warmup)
+        sec = median(time_blocks(lat, steps, max(warmup, LEG_WARMUP), 5))
         lat.close()
         out[name] = {"value": round(nx * ny / sec / 1e6, 1), "unit": "MLUPS", "us_per_step": round(sec * 1e6, 2)}
     return out
@@ -354,10 +393,11 @@ def main():
     n = args.n
     phi0 = inputs.spinodal(n, n, seed=1)
     lat = make_lattice(lbcm, n, args.precision, args).init(phi0)
+    copy_gbs = copy_probe() if args.copy_probe else None  # untimed; keeps the GPU busy up to the warm-up
     wall0 = time.perf_counter()
-    sec_per_step = time_steps(lat, args.steps, args.warmup)
+    block_sec = time_blocks(lat, args.steps, args.warmup, args.blocks)
     wall = time.perf_counter() - wall0
-    ms = sec_per_step * 1e3 * args.steps
+    sec_per_step = median(block_sec)
     nodes = n * n
     mlups = nodes / sec_per_step / 1e6
     d = lat.diag()
@@ -371,7 +411,11 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 5),
+        "ms_per_step": round(sec_per_step * 1e3, 5),
+        "timing": {"blocks": args.blocks, "steps_per_block": args.steps, "reported": "median block",
+                   "block_ms_per_step": [round(b * 1e3, 5) for b in block_sec],
+                   "mean_ms_per_step": round(sum(block_sec) / len(block_sec) * 1e3, 5),
+                   "mean_mlups": round(nodes / (sum(block_sec) / len(block_sec)) / 1e6, 1)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -398,8 +442,8 @@ def main():
         out["surrogate"] = surrogate_report(lbcm, args)
     if args.small_steps > 0 and args.precision == "fp32":
         out["cache_resident"] = small_report(lbcm, args.small_steps, args.warmup)
-    if args.copy_probe:
-        out["roofline"]["copy_probe_gbs"] = round(copy_probe(), 1)
+    if copy_gbs is not None:
+        out["roofline"]["copy_probe_gbs"] = round(copy_gbs, 1)
         out["roofline"]["copy_probe"] = "torch device copy of 2 GiB (reads + writes)"
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, args.cpu_single_steps,

@@ -23,9 +23,13 @@ _LIB = os.path.join(_HERE, "liblbcm_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP).  Always recompiles."""
+    """Compile the oracle with gcc (-O3 for the x86-64-v3 level (AVX2, FMA units), OpenMP).
+    Floating-point contraction stays off and no fast-math option is given, so every operation
+    rounds as written in the source: the results are those of any IEEE double build.  Always
+    recompiles."""
     tmp = _LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-Wall", "-o", tmp, _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -244,10 +248,16 @@ def step(p: Params, f, g):
     return fo, go
 
 
-def run(p: Params, f, g, nsteps: int):
-    """nsteps steps; returns new (f, g) arrays, inputs untouched."""
-    f = _pops(p, f, "f").copy()
-    g = _pops(p, g, "g").copy()
+def run(p: Params, f, g, nsteps: int, inplace: bool = False):
+    """nsteps steps; returns new (f, g) arrays, inputs untouched (inplace: f and g, C-contiguous
+    float64 arrays of shape (9, ny, nx), are advanced in place and returned)."""
+    if inplace:
+        if not (f.dtype == np.float64 and g.dtype == np.float64 and f.flags.c_contiguous and g.flags.c_contiguous):
+            raise ValueError("inplace needs C-contiguous float64 arrays")
+        f, g = _pops(p, f, "f"), _pops(p, g, "g")
+    else:
+        f = _pops(p, f, "f").copy()
+        g = _pops(p, g, "g").copy()
     rc = _load().orc_run(ctypes.byref(_cp(p)), _ptr(f), _ptr(g), int(nsteps))
     if rc:
         raise ValueError(f"orc_run failed ({rc})")
