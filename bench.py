@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--ens-boxes", type=int, default=512, help="boxes of the ensemble leg (0 = skip it)")
     ap.add_argument("--ens-steps", type=int, default=5000, help="batched steps of the ensemble leg")
     ap.add_argument("--ens-looped-steps", type=int, default=40, help="looped steps timed for comparison")
+    ap.add_argument("--ens-persistent-steps", type=int, default=400,
+                    help="steps timed with each persistent schedule (0 = skip them)")
     ap.add_argument("--sur-iters", type=int, default=2000, help="training iterations of the surrogate leg (0 = skip it)")
     ap.add_argument("--sur-windows", type=int, default=40, help="hybrid windows (8 jumps of 16 steps) timed per case")
     return ap.parse_args()
@@ -283,7 +285,8 @@ def small_report(lbcm, steps, warmup):
 def ensemble_report(lbcm, args) -> dict:
     """Ensemble of independent boxes (sides 64..1024, droplets or layered channels, viscosity
     ratio 1..1000, FP16-shifted storage) advanced by one launch per step under a hipGraph with
-    autotuned tiles, against the same steps as single-box launches."""
+    autotuned tiles, against the same steps as single-box launches, and against one persistent
+    launch per call (grid barrier per step, and per-tile dataflow)."""
     import torch
 
     from paper_1803_11345_amd import inputs
@@ -311,6 +314,15 @@ def ensemble_report(lbcm, args) -> dict:
     sec = timed(bt.step, args.ens_steps)
     timed(bt.step_looped, 2)
     sec_loop = timed(bt.step_looped, args.ens_looped_steps)
+    persistent = {}
+    if args.ens_persistent_steps > 0:
+        for mode, name in ((1, "barrier_per_step"), (2, "dataflow")):
+            bt.set_persistent(mode)
+            timed(bt.step, 10)
+            sp = timed(bt.step, args.ens_persistent_steps)
+            persistent[name] = {"value": round(nodes * args.ens_persistent_steps / sp / 1e6, 1), "unit": "MLUPS",
+                                "steps": args.ens_persistent_steps}
+        bt.set_persistent(0)
     nonfinite = sum(box.diag()["nonfinite"] for box in bt)
     mlups = nodes * args.ens_steps / sec / 1e6
     mlups_loop = nodes * args.ens_looped_steps / sec_loop / 1e6
@@ -318,6 +330,7 @@ def ensemble_report(lbcm, args) -> dict:
     return {"boxes": args.ens_boxes, "nodes": nodes, "precision": "fp16s", "steps": args.ens_steps,
             "value": round(mlups, 1), "unit": "MLUPS", "hbm_gbs_alg": round(mlups * 76 / 1e3, 1),
             "looped_single_box_mlups": round(mlups_loop, 1),
+            "persistent_launch": persistent,
             "speedup_vs_looped": round(mlups / mlups_loop, 3), "graph": True,
             "tuned": {"waves": info["waves"], "order": ["box order", "largest first", "one XCD per box"][info["order"]],
                       "tiles": info["ntiles"], "autotune_s": round(tune_s, 2)},

@@ -249,6 +249,18 @@ int lbcm_batch_autotune(lbcm_batch *b, int32_t trials);
 /* Enable (1, default) or disable (0) hipGraph replay in lbcm_batch_step. */
 int lbcm_batch_set_graph(lbcm_batch *b, int32_t enable);
 
+/* Launch schedule of lbcm_batch_step: 0 (default) one launch per step (graph replays of step
+   pairs); 1 one persistent launch for all the steps of a call, workgroups taking the tiles of all
+   boxes from a global counter in step order, with a grid barrier between steps (a cooperative
+   launch of the resident number of workgroups); 2 one persistent launch with a dataflow
+   schedule: per-tile step counters, a tile starts step s once every tile its reads or writes
+   reach has finished step s - 1 (no barrier; the work is handed out in step order, so every wait
+   is on a running workgroup).  Waits are bounded: a launch whose wait gives up (never expected)
+   makes lbcm_batch_step return LBCM_EHIP with the boxes' state undefined.  The persistent
+   schedules synchronise at the end of every launch (one per call, or one per check_every
+   steps).  The schedule changes no result.  Errors: LBCM_EINVAL. */
+int lbcm_batch_set_persistent(lbcm_batch *b, int32_t mode);
+
 /* Order of the tiles in the batched launch: 0 the boxes in turn, 1 largest boxes first (default),
    2 one XCD per box (boxes dealt largest first to the XCD with the fewest tiles; a box's halo
    lines are then hits in that XCD's L2).  The order changes no result.  Errors: LBCM_EINVAL. */

@@ -782,6 +782,7 @@ template <class R> struct BoxDesc {
     const unsigned char *set[2][2];  // [pair][f or g]
     int *flag;                       // the box's divergence flag (set on a non-finite rho or phi)
     int walls, force;
+    int done_off;                    // persistent dataflow launch: first step counter of this box's tiles
 };
 
 template <class M>
@@ -834,6 +835,199 @@ __global__ __launch_bounds__(kReduceThreads) void k_batch_flags(const BoxDesc<R>
         out[0] = cnt[0];
         out[1] = first[0];
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// persistent ensemble launch: one launch advances every box by nsteps.  Workgroups take work
+// items k = step * ntiles + t from a global counter (work stealing over the tiles of all boxes,
+// step-major), so a workgroup never holds an item whose step is ahead of an item not yet handed
+// out.  Two schedules:
+//  - kPersistBarrier: a grid barrier between steps (the launch must be co-resident: it is a
+//    cooperative launch of at most the resident number of workgroups);
+//  - kPersistDataflow: per-tile step counters; an item (s, t) waits until every tile whose
+//    nodes its reads or writes reach (the rows y0 - 2 .. y1 + 1 and columns x0 - 2 .. x1 + 1:
+//    the pulls of the phi halo) has finished step s - 1.  Those items have smaller indices, so
+//    they were handed out before, to running workgroups; the smallest unfinished item therefore
+//    always has its inputs and progress never depends on which workgroups are resident.
+// Every wait is bounded: after kSpinLimit polls a workgroup sets ctl->abort and leaves, every
+// other wait sees the flag and leaves too, and the host reports the launch as failed.
+// Cross-workgroup hand-offs are agent-scope release / acquire pairs (on this device an L2
+// write-back and an L2 invalidation of the workgroup's XCD); polls are relaxed loads.
+
+constexpr int kPersistBarrier = 1, kPersistDataflow = 2;
+constexpr int kSpinLimit = 1 << 21;
+
+struct PersistCtl {
+    unsigned long long next;  // next work item
+    unsigned int bar_count;   // grid barrier: arrivals in the current generation
+    unsigned int bar_gen;     // grid barrier: generation
+    int abort;                // a wait gave up
+    int pad[3];
+};
+
+__device__ __forceinline__ int relaxed_load(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier over nwg workgroups (all threads of the workgroup call it).  Returns false if a
+// wait gave up.
+__device__ bool grid_barrier(PersistCtl *c, unsigned nwg, int *ok_lds)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned g = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nwg - 1) {
+            __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c->bar_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            for (int n = 0; __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g; ++n) {
+                if (n >= kSpinLimit || ((n & 255) == 255 && relaxed_load(&c->abort))) {
+                    __hip_atomic_store(&c->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+// Dataflow wait of item (s, tile (band, rg) of box d): lanes 0..24 of wave 0 each poll one tile of
+// the 5 x 5 candidate set (tile rows holding rg and rows y0 - 2, y0 - 1, y1, y1 + 1, bands holding
+// band and columns x0 - 2, x0 - 1, x1, x1 + 1, wrapped periodically; rows behind a wall skipped).
+template <class R>
+__device__ bool wait_neighbours(const BoxDesc<R> &d, int band, int rg, int s, const int *done, PersistCtl *c,
+                                int *ok_lds)
+{
+    if (threadIdx.x < 64) {
+        int ok = 1;
+        const int lane = threadIdx.x;
+        if (lane < 25 && s > 0) {
+            const Geo &g = d.geo;
+            const int h = g.rows * g.rpw, w = 64 * g.wx;
+            const int y0 = rg * h, y1 = min(y0 + h, g.ny), x0 = band * w, x1 = min(x0 + w, g.nx);
+            const int ri = lane / 5, ci = lane % 5;
+            const int ry[5] = {y0, y0 - 2, y0 - 1, y1, y1 + 1};
+            const int cx[5] = {x0, x0 - 2, x0 - 1, x1, x1 + 1};
+            int yy = ry[ri];
+            bool skip = false;
+            if (yy < 0 || yy >= g.ny) {
+                if (g.walls) skip = true;
+                else yy = ((yy % g.ny) + g.ny) % g.ny;
+            }
+            const int xx = ((cx[ci] % g.nx) + g.nx) % g.nx;
+            if (!skip) {
+                const int *p = done + d.done_off + (yy / h) * g.nbands + xx / w;
+                for (int n = 0; relaxed_load(p) < s; ++n) {
+                    if (n >= kSpinLimit || ((n & 255) == 255 && relaxed_load(&c->abort))) {
+                        __hip_atomic_store(&c->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+        }
+        ok = __all(ok);
+        if (lane == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            *ok_lds = ok;
+        }
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+// One tile (box e.x, tile e.y) at step s of a persistent launch; all threads of the workgroup call it.
+template <class M>
+__device__ __forceinline__ void persist_tile(const BoxDesc<typename M::R> &d, int2 e, int s, int phase0,
+                                             typename M::R *phs)
+{
+    const int band = e.y % d.geo.nbands, rg = e.y / d.geo.nbands;
+    const int p = (phase0 + s) & 1;
+    const unsigned char *fa = d.set[p][0], *ga = d.set[p][1];
+    unsigned char *fb = const_cast<unsigned char *>(d.set[1 - p][0]);
+    unsigned char *gb = const_cast<unsigned char *>(d.set[1 - p][1]);
+    if (d.walls) {
+        if (d.force) step_tile<M, 1, true, true>(fa, ga, fb, gb, d.geo, d.c, d.flag, band, rg, phs);
+        else step_tile<M, 1, true, false>(fa, ga, fb, gb, d.geo, d.c, d.flag, band, rg, phs);
+    } else {
+        if (d.force) step_tile<M, 1, false, true>(fa, ga, fb, gb, d.geo, d.c, d.flag, band, rg, phs);
+        else step_tile<M, 1, false, false>(fa, ga, fb, gb, d.geo, d.c, d.flag, band, rg, phs);
+    }
+    __syncthreads();  // every wave's stores issued and its reads of the phi tile done
+}
+
+// Items of the dataflow schedule taken per grab of the global counter (fewer atomics on one
+// address); a workgroup runs its items in index order, so the smallest unfinished item is always
+// the next one of its holder and the argument for progress holds unchanged.
+constexpr int kPersistChunk = 8;
+
+template <class M>
+__global__ __launch_bounds__(kMaxThreads<M>) void k_step_persist(const BoxDesc<typename M::R> *__restrict__ boxes,
+                                                                 const int2 *__restrict__ tiles, int ntiles, int nsteps,
+                                                                 int phase0, int mode, PersistCtl *ctl, int *done,
+                                                                 unsigned nwg)
+{
+    using R = typename M::R;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    R *phs = reinterpret_cast<R *>(lds_raw);
+    __shared__ long long item;
+    __shared__ int ok_lds;
+    if (mode == kPersistBarrier) {
+        // workgroup w runs tiles w, w + nwg, ... of every step; a grid barrier between steps
+        for (int s = 0; s < nsteps; ++s) {
+            if (s > 0 && !grid_barrier(ctl, nwg, &ok_lds)) return;
+            for (int t = blockIdx.x; t < ntiles; t += nwg) {
+                const int2 e = tiles[t];
+                if (e.x >= 0) persist_tile<M>(boxes[e.x], e, s, phase0, phs);
+            }
+        }
+        return;
+    }
+    const long long total = (long long)nsteps * ntiles;
+    for (;;) {
+        if (threadIdx.x == 0)
+            item = relaxed_load(&ctl->abort) ? total : (long long)atomicAdd(&ctl->next, (unsigned long long)kPersistChunk);
+        __syncthreads();
+        const long long k0 = item;
+        __syncthreads();  // `item` is rewritten by the next grab
+        if (k0 >= total) break;
+        bool ok = true;
+        for (long long k = k0; ok && k < k0 + kPersistChunk && k < total; ++k) {
+            const int s = (int)(k / ntiles);
+            const int2 e = tiles[k % ntiles];
+            if (e.x < 0) continue;
+            const BoxDesc<R> &d = boxes[e.x];
+            ok = wait_neighbours(d, e.y % d.geo.nbands, e.y / d.geo.nbands, s, done, ctl, &ok_lds);
+            if (!ok) break;
+            persist_tile<M>(d, e, s, phase0, phs);
+            if (threadIdx.x == 0)
+                __hip_atomic_store(done + d.done_off + e.y, s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!ok) break;
+    }
+}
+
+// Resets the control block and the step counters before a persistent launch (a kernel, not a
+// memset, so that the launch sequence stays free of memset nodes).
+__global__ void k_persist_reset(PersistCtl *ctl, int *done, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        ctl->next = 0;
+        ctl->bar_count = 0;
+        ctl->bar_gen = 0;
+        ctl->abort = 0;
+    }
+    for (int j = i; j < n; j += gridDim.x * blockDim.x) done[j] = 0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1471,6 +1665,11 @@ struct lbcm_batch {
     bool use_graph = true;
     bool graph_ok = false;
     hipGraphExec_t gexec = nullptr;
+    int persist = 0;               // 0: one launch per step; kPersistBarrier / kPersistDataflow
+    void *d_ctl = nullptr;         // PersistCtl of the persistent launch
+    int *d_done = nullptr;         // per-tile step counters of the dataflow schedule
+    int ndone = 0;
+    int persist_grid = 0;          // workgroups of the persistent launch (resident count)
     std::string err;
 };
 
@@ -1527,6 +1726,7 @@ template <class M> int build_tables(lbcm_batch *b)
             d.set[k][1] = set_base(h, h->cur ^ k, 1);
         }
         d.flag = h->flag;
+        d.done_off = 0;
         d.walls = q.bc_y == LBCM_BC_WALLS;
         d.force = q.force_x != 0 || q.force_y != 0;
         const size_t nt = (size_t)d.geo.nbands * d.geo.nrows;
@@ -1550,11 +1750,23 @@ template <class M> int build_tables(lbcm_batch *b)
         for (size_t x = 0; x < streams.size(); ++x)
             for (size_t k = 0; k < streams[x].size(); ++k) tiles[k * streams.size() + x] = streams[x][k];
     }
+    // step counters of the persistent dataflow schedule: one per tile, box after box
+    int ndone = 0;
+    for (int i = 0; i < b->n; ++i) {
+        desc[i].done_off = ndone;
+        ndone += desc[i].geo.nbands * desc[i].geo.nrows;
+    }
     drop_graph(b);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_done) (void)hipFree(b->d_done);
     b->d_desc = nullptr;
     b->d_tiles = nullptr;
+    b->d_done = nullptr;
+    b->persist_grid = 0;
+    BHIP_TRY(b, hipMalloc((void **)&b->d_done, (size_t)std::max(ndone, 1) * sizeof(int)));
+    b->ndone = ndone;
+    if (!b->d_ctl) BHIP_TRY(b, hipMalloc(&b->d_ctl, sizeof(PersistCtl)));
     BHIP_TRY(b, hipMalloc(&b->d_desc, desc.size() * sizeof(BoxDesc<R>)));
     BHIP_TRY(b, hipMalloc((void **)&b->d_tiles, tiles.size() * sizeof(int2)));
     BHIP_TRY(b, hipMemcpyAsync(b->d_desc, desc.data(), desc.size() * sizeof(BoxDesc<R>), hipMemcpyHostToDevice, b->stream));
@@ -1608,6 +1820,48 @@ template <class M> int check_batch(lbcm_batch *b)
     return LBCM_OK;
 }
 
+// One persistent launch advancing every box by nsteps (1 <= nsteps < 2^30); synchronises to read
+// the give-up flag.
+template <class M> int persist_launch(lbcm_batch *b, int nsteps)
+{
+    using R = typename M::R;
+    const unsigned threads = 64u * (unsigned)b->waves;
+    if (!b->persist_grid) {
+        int dev = 0, cus = 0, per_cu = 0;
+        BHIP_TRY(b, hipGetDevice(&dev));
+        BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        BHIP_TRY(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_step_persist<M>, (int)threads,
+                                                                 b->lds));
+        if (per_cu < 1) return bfail(b, LBCM_EINVAL, "persistent launch: the workgroup does not fit on a CU");
+        b->persist_grid = per_cu * cus;
+    }
+    PersistCtl *ctl = (PersistCtl *)b->d_ctl;
+    hipLaunchKernelGGL(k_persist_reset, dim3(grid_for((size_t)b->ndone, 256)), dim3(256), 0, b->stream, ctl, b->d_done,
+                       b->ndone);
+    BHIP_TRY(b, hipGetLastError());
+    const BoxDesc<R> *boxes = (const BoxDesc<R> *)b->d_desc;
+    const int2 *tiles = b->d_tiles;
+    int ntiles = b->grid, steps = nsteps, phase0 = b->phase, mode = b->persist;
+    int *done = b->d_done;
+    unsigned nwg = (unsigned)b->persist_grid;
+    if (mode == kPersistBarrier) {
+        void *args[] = {&boxes, &tiles, &ntiles, &steps, &phase0, &mode, &ctl, &done, &nwg};
+        BHIP_TRY(b, hipLaunchCooperativeKernel((const void *)k_step_persist<M>, dim3(nwg), dim3(threads), args, b->lds,
+                                               b->stream));
+    } else {
+        hipLaunchKernelGGL((k_step_persist<M>), dim3(nwg), dim3(threads), b->lds, b->stream, boxes, tiles, ntiles, steps,
+                           phase0, mode, ctl, done, nwg);
+        BHIP_TRY(b, hipGetLastError());
+    }
+    advance_boxes(b, nsteps);
+    int gave_up = 0;
+    BHIP_TRY(b, hipMemcpyAsync(&gave_up, &ctl->abort, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    if (gave_up)
+        return bfail(b, LBCM_EHIP, "persistent launch: a wait gave up; the boxes' state is undefined");
+    return LBCM_OK;
+}
+
 template <class M> int batch_steps(lbcm_batch *b, int64_t nsteps)
 {
     if (tables_stale(b)) {
@@ -1619,6 +1873,17 @@ template <class M> int batch_steps(lbcm_batch *b, int64_t nsteps)
     int every = 0;
     for (lbcm_handle *h : b->box)
         if (h->p.check_every > 0) every = every ? std::min(every, h->p.check_every) : h->p.check_every;
+    if (b->persist) {
+        // one launch per chunk: the whole call, or the steps between two divergence checks
+        const int64_t chunk = std::min<int64_t>(every > 0 ? every : nsteps, int64_t(1) << 29);
+        for (int64_t s = 0; s < nsteps; s += chunk) {
+            const int k = (int)std::min(chunk, nsteps - s);
+            if (int rc = persist_launch<M>(b, k)) return rc;
+            if (every > 0)
+                if (int rc = check_batch<M>(b)) return rc;
+        }
+        return LBCM_OK;
+    }
     int64_t s = 0, since = 0;
     auto checked = [&](int64_t k) -> int {  // k steps were just queued
         advance_boxes(b, k);
@@ -2215,6 +2480,16 @@ int lbcm_batch_set_graph(lbcm_batch *b, int32_t enable)
     return LBCM_OK;
 }
 
+int lbcm_batch_set_persistent(lbcm_batch *b, int32_t mode)
+{
+    if (!b) return LBCM_EINVAL;
+    if (mode != 0 && mode != kPersistBarrier && mode != kPersistDataflow)
+        return bfail(b, LBCM_EINVAL, "persistent mode must be 0, 1 or 2");
+    b->persist = mode;
+    b->persist_grid = 0;
+    return LBCM_OK;
+}
+
 int lbcm_batch_set_order(lbcm_batch *b, int32_t order)
 {
     if (!b) return LBCM_EINVAL;
@@ -2279,6 +2554,8 @@ int lbcm_batch_destroy(lbcm_batch *b)
         if (h && lbcm_destroy(h) != LBCM_OK) rc = LBCM_EHIP;
     if (b->d_desc && hipFree(b->d_desc) != hipSuccess) rc = LBCM_EHIP;
     if (b->d_tiles && hipFree(b->d_tiles) != hipSuccess) rc = LBCM_EHIP;
+    if (b->d_done && hipFree(b->d_done) != hipSuccess) rc = LBCM_EHIP;
+    if (b->d_ctl && hipFree(b->d_ctl) != hipSuccess) rc = LBCM_EHIP;
     if (b->arena && hipFree(b->arena) != hipSuccess) rc = LBCM_EHIP;
     if (b->owns_stream && hipStreamDestroy(b->stream) != hipSuccess) rc = LBCM_EHIP;
     delete b;

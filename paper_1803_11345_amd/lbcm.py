@@ -120,6 +120,7 @@ def load():
     lib.lbcm_batch_autotune.argtypes = [_H, I32]
     lib.lbcm_batch_set_graph.argtypes = [_H, I32]
     lib.lbcm_batch_set_order.argtypes = [_H, I32]
+    lib.lbcm_batch_set_persistent.argtypes = [_H, I32]
     lib.lbcm_batch_info.argtypes = [_H, PI, PI, PI, PI, PI]
     lib.lbcm_batch_destroy.argtypes = [_H]
     lib.lbcm_batch_last_error.argtypes = [_H]
@@ -309,6 +310,10 @@ def lbcm_batch_set_graph(b, enable: bool):
     return _bcheck(b, load().lbcm_batch_set_graph(b, int(bool(enable))))
 
 
+def lbcm_batch_set_persistent(b, mode: int):
+    return _bcheck(b, load().lbcm_batch_set_persistent(b, int(mode)))
+
+
 def lbcm_batch_set_order(b, order: int):
     return _bcheck(b, load().lbcm_batch_set_order(b, int(order)))
 
@@ -423,6 +428,9 @@ class Batch:
 
     def set_order(self, order):
         lbcm_batch_set_order(self.b, order)
+
+    def set_persistent(self, mode):
+        lbcm_batch_set_persistent(self.b, mode)
 
     def info(self):
         return lbcm_batch_info(self.b, len(self.boxes))

@@ -264,3 +264,83 @@ def test_batch_reports_divergence_of_one_box(graph):
     for box in bt:
         assert box.diag()["nonfinite"] == 0
     bt.close()
+
+
+# ---------------------------------------------------------------------------------------------
+# persistent launches (one launch for all the steps of a call)
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("prec", ["fp32", "fp16s", "fp64"])
+@pytest.mark.parametrize("order", [1, 2])
+def test_persistent_launch_matches_single_lattices(mode, prec, order):
+    """Both persistent schedules (grid barrier per step; per-tile dataflow) give the single-lattice
+    result bit for bit, for an odd first call (phase handling) and in both tile orders (order 2
+    has empty slots in its table)."""
+    say(f"case persistent mode={mode} {prec} order={order}")
+    ref = _singles(prec, 7, 130)
+    bt = _batch(prec, 130)
+    bt.set_order(order)
+    bt.set_persistent(mode)
+    bt.step(3).step(4)
+    for k, box in enumerate(bt):
+        assert np.array_equal(box.get_state(), ref[k]), k
+        assert box.diag()["step"] == 7
+    bt.close()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_persistent_full_ensemble_matches_per_step_launches(mode):
+    """The 512-box FP16-storage benchmark ensemble, autotuned: 23 steps in one persistent launch
+    equal 23 per-step launches bit for bit on every box, and sampled boxes match the oracle."""
+    spec = inputs.ensemble(512, seed=7)
+    a = lbcm.Batch([p for p, _ in spec], precision="fp16s")
+    b = lbcm.Batch([p for p, _ in spec], precision="fp16s")
+    for x, y, (_, phi0) in zip(a, b, spec):
+        x.init(phi0)
+        y.init(phi0)
+    a.autotune(trials=2)
+    info = a.info()
+    b.autotune(trials=2)
+    say(f"case persistent full ensemble mode={mode}: waves {info['waves']} order {info['order']}")
+    a.set_persistent(mode)
+    a.step(23)
+    b.step(23)
+    for k in range(len(spec)):
+        assert np.array_equal(a[k].get_state(), b[k].get_state()), k
+    size = [p["nx"] * p["ny"] for p, _ in spec]
+    for k in (min(range(len(spec)), key=lambda k: size[k]), 1):
+        p, phi0 = spec[k]
+        fo, go = _oracle_run(p, phi0, 23)
+        f, g = a[k].populations()
+        assert max(float(np.abs(f - fo).max()), float(np.abs(g - go).max())) < 3e-4, k
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_persistent_launch_checks_divergence(mode):
+    """check_every splits a call into one persistent launch per period with a check after each:
+    a NaN in one box is reported naming it; re-initialised, the batch steps on."""
+    boxes = [dict(b, check_every=3 if k == 2 else 0) for k, b in enumerate(BOXES)]
+    bt = lbcm.Batch(boxes, precision="fp32")
+    states = _states(140)
+    for box, st in zip(bt, states):
+        box.init(*st)
+    bt.set_persistent(mode)
+    bt.step(7)
+    ref = _singles("fp32", 7, 140)
+    for k, box in enumerate(bt):
+        assert np.array_equal(box.get_state(), ref[k]), k
+    bad = states[5][0].copy()
+    bad[1, 50] = np.nan
+    bt[5].init(bad, *states[5][1:])
+    with pytest.raises(lbcm.LbcmError) as e:
+        bt.step(5)
+    assert e.value.code == lbcm.LBCM_EDIVERGED and "box 5" in str(e.value)
+    bt[5].init(*states[5])
+    bt.step(4)
+    for box in bt:
+        assert box.diag()["nonfinite"] == 0
+    with pytest.raises(lbcm.LbcmError):
+        bt.set_persistent(3)
+    bt.close()
