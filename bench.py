@@ -193,32 +193,14 @@ def median(v):
 LEG_WARMUP = 200
 
 
-def structure_factor(phi):
-    """Radially averaged structure factor of phi - mean(phi): the mean of |FFT|^2 / N over the
-    wavevectors whose length (in units of 2 pi / n) rounds to k, for k = 1 .. n / 2."""
-    import torch
-
-    t = torch.from_numpy(phi).cuda()
-    t = t - t.mean()
-    F = torch.fft.fft2(t)
-    pw = (F.real ** 2 + F.imag ** 2) / t.numel()
-    ny, nx = t.shape
-    ky = torch.fft.fftfreq(ny, d=1.0 / ny, device="cuda", dtype=torch.float64)
-    kx = torch.fft.fftfreq(nx, d=1.0 / nx, device="cuda", dtype=torch.float64)
-    shell = torch.round(torch.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2)).long()
-    kmax = min(nx, ny) // 2
-    m = (shell >= 1) & (shell <= kmax)
-    s = torch.zeros(kmax + 1, dtype=torch.float64, device="cuda").index_add_(0, shell[m], pw[m])
-    c = torch.zeros(kmax + 1, dtype=torch.float64, device="cuda").index_add_(0, shell[m], torch.ones_like(pw[m]))
-    return (s[1:] / c[1:]).cpu().numpy()
-
-
 def precision_report(lbcm, phi0, n, args, fp32_sec):
     """Reduced-precision storage against the plain FP32 step: throughput, speedup, and the error
     against an FP64 GPU run of the same workload after acc_steps steps (phi L2, sum phi drift) and
     after acc_long_steps (the same, and the radially averaged structure factor, which the chaotic
     growth of round-off leaves comparable where phi itself is not)."""
     import numpy as np
+
+    from paper_1803_11345_amd import analysis
 
     marks = [args.acc_steps] + ([args.acc_long_steps] if args.acc_long_steps > args.acc_steps else [])
     phis, drift = {}, {}
@@ -239,8 +221,7 @@ def precision_report(lbcm, phi0, n, args, fp32_sec):
         e = {"phi_rel_l2": float(np.linalg.norm(phis[prec, mark] - ref) / np.linalg.norm(ref)),
              "sum_phi_drift": drift[prec, mark]}
         if mark != args.acc_steps:
-            sk, sref = structure_factor(phis[prec, mark]), structure_factor(ref)
-            e["sk_rel_l2"] = float(np.linalg.norm(sk - sref) / np.linalg.norm(sref))
+            e["sk_rel_l2"] = analysis.sk_rel_l2(phis[prec, mark], ref)
         return e
 
     a = args.acc_steps
@@ -379,16 +360,32 @@ def surrogate_report(lbcm, args) -> dict:
     # padded MFMA work of one jump: layers 1..L-2 are 64 -> 64, the last 64 -> 16 computed
     # channels (4 real) in the fused inference path
     flops = 2 * n * n * 9 * 64 * (4 * 64 + 16)
-    hybrid = {}
+    hybrid, audited, identity, restart = {}, {}, {}, {}
+    from paper_1803_11345_amd.net import Surrogate
+
+    m0 = Surrogate(1, n, n, channels=64, layers=6)  # control: the zero network is the identity map
+    m0.set_params(np.zeros(m0.nparams, dtype=np.float32))
+    m0.set_output_scale(m1.alpha)
     for name, phi0 in (("spinodal", T.spinodal_phi(n, 106)), ("coalescence", T.coalescence_phi(n, cases[9]))):
         hybrid[name] = T.hybrid_vs_lb(m1, phi0, us, rs, args.sur_windows)
+        audited[name] = T.hybrid_vs_lb(m1, phi0, us, rs, args.sur_windows, audit_every=4)
+        identity[name] = T.hybrid_vs_lb(m0, phi0, us, rs, args.sur_windows, threshold=float("inf"),
+                                        velocity_threshold=0.0)
+        restart[name] = T.restart_control(phi0, hybrid[name]["steps"], 8 * K)
+    m0.close()
     m1.close()
     return {"box": f"{n}x{n} periodic", "network": "3x3 conv x6, 64 channels, first layer FP32 MFMA, "
             "others BF16 MFMA with FP32 accumulation", "steps_per_jump": K, "jumps_per_check": 8,
             "threshold_phi_rel_l2": 1e-2, "threshold_velocity_rel_l2": 0.25, "train": info, "one_jump_rel_l2": gains,
             "jump_us": round(jump_us, 2), "jump_mfma_tflops": round(flops / jump_us / 1e6, 1),
             "hybrid": hybrid,
-            "speedup_vs_lb": round(float(np.mean([h["speedup"] for h in hybrid.values()])), 3)}
+            "speedup_vs_lb": round(float(np.mean([h["speedup"] for h in hybrid.values()])), 3),
+            "speedup_at_error": {k: {"speedup": h["speedup"], "final_phi_rel_l2_vs_lb": round(h["final_phi_rel_l2_vs_lb"], 5),
+                                     "final_sk_rel_l2_vs_lb": round(h["final_sk_rel_l2_vs_lb"], 5)}
+                                 for k, h in hybrid.items()},
+            "hybrid_audit_every_4_windows": audited,
+            "controls": {"identity_network_no_threshold": identity,
+                         "plain_lb_with_equilibrium_restart_every_window": restart}}
 
 
 def main():

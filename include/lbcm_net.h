@@ -117,6 +117,10 @@ typedef struct lbcm_hybrid_stats {
     double last_velocity_error;          /* ||v_net - v_LB|| / ||v_LB|| of the last check */
     double max_accepted_error;           /* largest check error of an accepted window */
     double max_accepted_velocity_error;  /* largest velocity error of an accepted window */
+    int64_t audits;                      /* audited windows (lbcm_hybrid_set_audit) */
+    int64_t failed_audits;               /* audits above a threshold */
+    double max_audited_error;            /* largest phi error accumulated over an audited window */
+    double max_audited_velocity_error;   /* the same for the velocity */
 } lbcm_hybrid_stats;
 
 /* lattice: a periodic lattice after lbcm_init; net: the trained network (batch 1, same ny x nx);
@@ -135,6 +139,16 @@ int lbcm_hybrid_create(lbcm_handle *lattice, lbcm_net *net, int32_t steps_per_ju
    check; a rejection drops them.  The results equal those of `windows` calls of one window,
    bit for bit.  The lattice must not be used by the caller during the call. */
 int lbcm_hybrid_advance(lbcm_hybrid *h, int64_t windows);
+
+/* Audits (every >= 1; 0, the default, turns them off): every `every`-th window (counted over the
+   driver's life, plain windows included) is an audit instead of a checked window.  The network
+   makes all J jumps from the window's start, the lattice runs the whole window with the lattice
+   Boltzmann step from the window's starting populations, and the network's state is compared with
+   that result with the same errors and thresholds as a check.  The check of an ordinary window
+   tests only its last jump, from equilibrium populations of the network's state; an audit measures
+   the error accumulated over all J jumps.  The lattice ends an audit in the lattice Boltzmann
+   result either way; a failed audit backs off as a failed check does.  Errors: LBCM_EINVAL. */
+int lbcm_hybrid_set_audit(lbcm_hybrid *h, int32_t every);
 
 int lbcm_hybrid_get_stats(const lbcm_hybrid *h, lbcm_hybrid_stats *out);
 int lbcm_hybrid_destroy(lbcm_hybrid *h);

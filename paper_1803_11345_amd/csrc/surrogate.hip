@@ -1728,6 +1728,8 @@ struct lbcm_hybrid {
     hipEvent_t err_ready = nullptr;   // recorded after that copy
     int64_t cooldown = 0;  // plain windows still to run after failed checks
     int streak = 0;        // consecutive failed checks
+    int audit_every = 0;   // every audit_every-th window is an audit (0: none)
+    int64_t windows = 0;   // windows run so far (plain, checked and audited)
     // Within one lbcm_hybrid_advance call, after an accepted check: the next window starts from
     // the check's lattice fields (lb, equal to those of the caller's lattice after the copy), and
     // its first `spec_done` jumps were launched before the decision, the last into spec_cur.
@@ -1799,6 +1801,7 @@ int hybrid_window(lbcm_hybrid *h, bool more)
 {
     const uint32_t P = h->P;
     const int64_t span = (int64_t)h->J * h->K;
+    const int64_t index = h->windows++;
     if (h->cooldown > 0) {  // plain lattice Boltzmann window after failed checks
         h->start_ready = false;
         h->spec_done = 0;
@@ -1808,6 +1811,8 @@ int hybrid_window(lbcm_hybrid *h, bool more)
         h->cooldown -= 1;
         return LBCM_OK;
     }
+    const bool audit = h->audit_every > 0 && (index + 1) % h->audit_every == 0;
+    if (audit) more = false;  // no speculative jumps after an audit: the next window reads the lattice
     auto pl = [&](double *base, int k) { return plane(base, P, k); };
     auto jump = [&](double *in, double *outp) {
         return lbcm_net_forward_planes(h->net, pl(in, 0), pl(in, 1), pl(in, 2), pl(in, 3), h->u_scale, h->rho_scale, pl(outp, 0),
@@ -1838,6 +1843,34 @@ int hybrid_window(lbcm_hybrid *h, bool more)
     // the last jump of the window both ways: the surrogate into y, K lattice steps on the scratch
     // lattice from equilibrium populations of the same state
     HNET(h, jump(cur, y), "lbcm_net_forward_planes");
+    if (audit) {
+        // audit: the caller's lattice, which still holds the window's starting populations, runs
+        // the whole window with the lattice Boltzmann step; the network's state after its J jumps
+        // is compared with that result (the error accumulated over the window).  The lattice keeps
+        // the exact result whatever the outcome; a failure backs off like a failed check.
+        HLAT(h, lbcm_step(h->lat, span), "lbcm_step");
+        HLAT(h, lbcm_fields_device(h->lat, pl(h->lb, 0), pl(h->lb, 3), pl(h->lb, 1), pl(h->lb, 2), nullptr),
+             "lbcm_fields_device");
+        int rc = launch_sums(h, y, h->lb);
+        if (rc) return rc;
+        double sum[kErrSums];
+        rc = wait_sums(h, sum);
+        if (rc) return rc;
+        const double e = rel_l2(sum[0], sum[1]), ev = rel_l2(sum[2], sum[3]);
+        h->st.audits += 1;
+        h->st.max_audited_error = std::max(h->st.max_audited_error, e);
+        h->st.max_audited_velocity_error = std::max(h->st.max_audited_velocity_error, ev);
+        h->st.lb_steps_run += span;
+        h->st.steps += span;
+        if (e <= h->threshold && (h->vthreshold <= 0 || ev <= h->vthreshold)) {
+            h->streak = 0;
+        } else {
+            h->st.failed_audits += 1;
+            h->streak = std::min(h->streak + 1, 5);
+            h->cooldown = (int64_t)1 << (h->streak - 1);
+        }
+        return LBCM_OK;
+    }
     HSCR(h, lbcm_init_device(h->scratch, pl(cur, 0), pl(cur, 3), pl(cur, 1), pl(cur, 2)), "lbcm_init_device");
     HSCR(h, lbcm_step(h->scratch, h->K), "lbcm_step");
     HSCR(h, lbcm_fields_device(h->scratch, pl(h->lb, 0), pl(h->lb, 3), pl(h->lb, 1), pl(h->lb, 2), nullptr),
@@ -1956,6 +1989,14 @@ int lbcm_hybrid_advance(lbcm_hybrid *h, int64_t windows)
         int rc = hybrid_window(h, w + 1 < windows);
         if (rc) return rc;
     }
+    return LBCM_OK;
+}
+
+int lbcm_hybrid_set_audit(lbcm_hybrid *h, int32_t every)
+{
+    if (!h) return LBCM_EINVAL;
+    if (every < 0) return hfail(h, LBCM_EINVAL, "audit period must be >= 0");
+    h->audit_every = every;
     return LBCM_OK;
 }
 

@@ -23,7 +23,9 @@ class lbcm_hybrid_stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("jumps", ctypes.c_int64), ("lb_steps_run", ctypes.c_int64),
                 ("checks", ctypes.c_int64), ("failed_checks", ctypes.c_int64), ("last_error", ctypes.c_double),
                 ("max_error", ctypes.c_double), ("last_velocity_error", ctypes.c_double),
-                ("max_accepted_error", ctypes.c_double), ("max_accepted_velocity_error", ctypes.c_double)]
+                ("max_accepted_error", ctypes.c_double), ("max_accepted_velocity_error", ctypes.c_double),
+                ("audits", ctypes.c_int64), ("failed_audits", ctypes.c_int64),
+                ("max_audited_error", ctypes.c_double), ("max_audited_velocity_error", ctypes.c_double)]
 
 
 def load():
@@ -51,6 +53,7 @@ def load():
     lib.lbcm_hybrid_create.argtypes = [_H, _H, I32, I32, D, D, D, D, ctypes.POINTER(_H)]
     lib.lbcm_hybrid_advance.argtypes = [_H, ctypes.c_int64]
     lib.lbcm_hybrid_get_stats.argtypes = [_H, ctypes.POINTER(lbcm_hybrid_stats)]
+    lib.lbcm_hybrid_set_audit.argtypes = [_H, ctypes.c_int32]
     lib.lbcm_hybrid_destroy.argtypes = [_H]
     lib.lbcm_hybrid_last_error.argtypes = [_H]
     lib.lbcm_hybrid_last_error.restype = ctypes.c_char_p
@@ -194,6 +197,10 @@ def lbcm_hybrid_advance(h, windows):
     _hchk(h, load().lbcm_hybrid_advance(h, windows))
 
 
+def lbcm_hybrid_set_audit(h, every: int):
+    return _hchk(h, load().lbcm_hybrid_set_audit(h, int(every)))
+
+
 def lbcm_hybrid_get_stats(h) -> dict:
     s = lbcm_hybrid_stats()
     _hchk(h, load().lbcm_hybrid_get_stats(h, ctypes.byref(s)))
@@ -297,11 +304,13 @@ class Hybrid:
     ``jumps_per_check`` jumps (see lbcm_hybrid_create)."""
 
     def __init__(self, lattice, net: Surrogate, *, steps_per_jump=16, jumps_per_check=8, u_scale=1.0, rho_scale=1.0,
-                 threshold=1e-2, velocity_threshold=0.0):
+                 threshold=1e-2, velocity_threshold=0.0, audit_every=0):
         self.lattice, self.net = lattice, net
         self.span = steps_per_jump * jumps_per_check
         self.h = lbcm_hybrid_create(lattice.h, net.h, steps_per_jump, jumps_per_check, u_scale, rho_scale, threshold,
                                     velocity_threshold)
+        if audit_every:
+            lbcm_hybrid_set_audit(self.h, audit_every)
 
     def advance(self, windows=1):
         lbcm_hybrid_advance(self.h, windows)

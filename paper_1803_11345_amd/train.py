@@ -215,24 +215,27 @@ def single_box(model: Surrogate, stream=None) -> Surrogate:
 
 
 def hybrid_vs_lb(model1: Surrogate, phi0, u_scale: float, rho_scale: float, windows: int, *, K=16, J=8, threshold=1e-2,
-                 velocity_threshold=0.25):
+                 velocity_threshold=0.25, audit_every=0):
     """Advance phi0 by `windows` hybrid windows and by the same number of plain FP32 lattice steps
-    from the same start; returns wall-clock rates, the hybrid's check statistics and the final
-    phi difference between the two runs."""
+    from the same start; returns wall-clock rates, the hybrid's check (and audit) statistics and
+    the trajectory error of the hybrid against plain lattice Boltzmann at equal simulated time:
+    the relative L2 difference of the final phi and of its structure factor (the measure that
+    stays meaningful where the dynamics amplify small differences, as in spinodal coarsening)."""
     import torch
 
+    from . import analysis
     from .net import Hybrid
 
     n = phi0.shape[0]
+    kw = dict(steps_per_jump=K, jumps_per_check=J, u_scale=u_scale, rho_scale=rho_scale, threshold=threshold,
+              velocity_threshold=velocity_threshold, audit_every=audit_every)
     lat = lbcm.Lattice(n, n, precision="fp32", **PHYSICS)
     lat.init(phi0)
-    hy = Hybrid(lat, model1, steps_per_jump=K, jumps_per_check=J, u_scale=u_scale, rho_scale=rho_scale,
-                threshold=threshold, velocity_threshold=velocity_threshold)
+    hy = Hybrid(lat, model1, **kw)
     hy.advance(1)  # warm-up window (first launches)
     lat.init(phi0)
     hy.close()
-    hy = Hybrid(lat, model1, steps_per_jump=K, jumps_per_check=J, u_scale=u_scale, rho_scale=rho_scale,
-                threshold=threshold, velocity_threshold=velocity_threshold)
+    hy = Hybrid(lat, model1, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hy.advance(windows)
@@ -253,10 +256,45 @@ def hybrid_vs_lb(model1: Surrogate, phi0, u_scale: float, rho_scale: float, wind
     phi_lb = ref.fields()["phi"]
     lat.close()
     ref.close()
-    return {"steps": st["steps"], "hybrid_steps_per_s": round(st["steps"] / t_h, 1),
-            "lb_steps_per_s": round(st["steps"] / t_lb, 1), "speedup": round(t_lb / t_h, 3),
-            "accepted_jumps": st["jumps"], "lb_steps_run": st["lb_steps_run"], "checks": st["checks"],
-            "failed_checks": st["failed_checks"],
-            "max_accepted_phi_error": st["max_accepted_error"],
-            "max_accepted_velocity_error": st["max_accepted_velocity_error"],
-            "final_phi_rel_l2_vs_lb": float(np.linalg.norm(phi_h - phi_lb) / np.linalg.norm(phi_lb))}
+    out = {"steps": st["steps"], "hybrid_steps_per_s": round(st["steps"] / t_h, 1),
+           "lb_steps_per_s": round(st["steps"] / t_lb, 1), "speedup": round(t_lb / t_h, 3),
+           "accepted_jumps": st["jumps"], "lb_steps_run": st["lb_steps_run"], "checks": st["checks"],
+           "failed_checks": st["failed_checks"],
+           "max_accepted_phi_error": st["max_accepted_error"],
+           "max_accepted_velocity_error": st["max_accepted_velocity_error"],
+           "final_phi_rel_l2_vs_lb": analysis.rel_l2(phi_h, phi_lb),
+           "final_sk_rel_l2_vs_lb": analysis.sk_rel_l2(phi_h, phi_lb)}
+    if audit_every:
+        out.update({"audit_every": audit_every, "audits": st["audits"], "failed_audits": st["failed_audits"],
+                    "max_audited_phi_error": st["max_audited_error"],
+                    "max_audited_velocity_error": st["max_audited_velocity_error"]})
+    return out
+
+
+def restart_control(phi0, steps: int, span: int) -> dict:
+    """The cost of the hybrid's equilibrium restarts alone: plain FP32 lattice Boltzmann that is
+    re-initialised every `span` steps from the equilibrium populations of its own fields (phi, v,
+    rho), as an accepted hybrid window's check does, against the same run without restarts, after
+    `steps` steps: the relative L2 difference of phi and of its structure factor."""
+    import torch
+
+    from . import analysis
+
+    n = phi0.shape[0]
+    a = lbcm.Lattice(n, n, precision="fp32", **PHYSICS).init(phi0)
+    b = lbcm.Lattice(n, n, precision="fp32", **PHYSICS).init(phi0)
+    planes = [torch.empty(n, n, dtype=torch.float64, device="cuda") for _ in range(4)]  # phi, rho, v_x, v_y
+    done = 0
+    while done < steps:
+        k = min(span, steps - done)
+        a.step(k)
+        done += k
+        if done < steps:
+            lbcm.lbcm_fields_device(a.h, planes[0], planes[1], planes[2], planes[3], None)
+            lbcm.lbcm_init_device(a.h, *planes)
+    b.step(steps)
+    pa, pb = a.fields()["phi"], b.fields()["phi"]
+    a.close()
+    b.close()
+    return {"steps": steps, "restart_every": span, "phi_rel_l2_vs_lb": analysis.rel_l2(pa, pb),
+            "sk_rel_l2_vs_lb": analysis.sk_rel_l2(pa, pb)}

@@ -574,6 +574,48 @@ def test_rejected_window_continues_the_exact_lattice_state():
         o.close()
 
 
+@pytest.mark.parametrize("threshold", [np.inf, 0.0])
+def test_audited_windows_measure_the_accumulated_error(threshold):
+    """With every window audited (identity jumps) the lattice runs each window with the plain step
+    from its own populations, so after W windows it equals a plain run of W J K steps bit for bit,
+    whatever the outcome; the audited error is ||phi_start' - phi_end|| / ||phi_end|| of the
+    window (phi_start' the starting phi after the FP32 round trip of the identity jumps), the
+    largest over the windows, recomputed here on the host; with a zero threshold every audit fails
+    and the back-off then runs plain windows, which are not audited."""
+    _note(f"hybrid audits threshold={threshold}")
+    J, K, n, W = 2, 8, 64, 3
+    lat, m, hy, torch = _hybrid_setup(threshold, n=n, J=J, K=K)
+    net.lbcm_hybrid_set_audit(hy.h, 1)
+    ref = lbcm.Lattice(n, n, precision="fp32", a=0.04, gamma=0.08, mobility=0.1, nu_l=0.05, nu_g=0.05)
+    ref.init(inputs.droplet(n, n, 16, inputs.interface_width(0.04, 0.08)))
+    want = 0.0
+    audited = 0
+    st = hy.stats()
+    for w in range(W):
+        p0 = ref.fields()["phi"].astype(np.float32).astype(np.float64)
+        ref.step(J * K)
+        before = hy.stats()
+        hy.advance(1)
+        st = hy.stats()
+        if st["audits"] > before["audits"]:
+            audited += 1
+            p1 = ref.fields()["phi"]
+            want = max(want, np.linalg.norm(p0 - p1) / np.linalg.norm(p1))
+        assert np.array_equal(lat.get_state(), ref.get_state()), w
+    _note(f"  {st}")
+    assert st["audits"] == audited and st["checks"] == 0 and st["jumps"] == 0
+    assert st["lb_steps_run"] == st["steps"] == W * J * K
+    assert abs(st["max_audited_error"] - want) <= 1e-12 * want
+    if np.isinf(threshold):
+        assert audited == W and st["failed_audits"] == 0
+    else:
+        assert audited == 2 and st["failed_audits"] == 2  # window 2 is a back-off plain window
+    with pytest.raises(lbcm.LbcmError):
+        net.lbcm_hybrid_set_audit(hy.h, -1)
+    for o in (hy, m, lat, ref):
+        o.close()
+
+
 def test_copy_state_is_exact():
     _note("copy state")
     n = 48
@@ -618,5 +660,6 @@ def test_trained_network_gains_over_the_method_without_it():
     _note(f"  hybrid: {h}")
     assert h["accepted_jumps"] > 0 and h["lb_steps_run"] < h["steps"]
     assert h["max_accepted_phi_error"] <= 1e-2
-    assert np.isfinite(h["final_phi_rel_l2_vs_lb"])
+    # the trajectory at equal simulated time stays close to plain lattice Boltzmann
+    assert h["final_phi_rel_l2_vs_lb"] < 0.1
     m1.close()
