@@ -144,6 +144,21 @@ def copy_probe(nbytes: int = 1 << 31, reps: int = 20) -> float:
     return 2 * nbytes / sec / 1e9
 
 
+def stream_probe(n: int) -> float:
+    """GB/s of the library's streaming reference: 18 planes of n^2 floats read and written, one
+    element per lane (the step kernel's access pattern without shifts, halos and arithmetic)."""
+    import torch
+
+    from paper_1803_11345_amd import lbcm
+
+    N = n * n
+    a = torch.zeros(18 * N, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ms = lbcm.lbcm_stream_probe(a, b, N, 18, 20, torch.cuda.current_stream().cuda_stream)
+    del a, b
+    return 2 * 18 * N * 4 / ms / 1e6
+
+
 def measured_traffic(n, precision, args, sec_per_step):
     """HBM traffic of the step kernel from the committed rocprofv3 counter record of this
     workload, as GB/s at the live step time; None when no record exists, the tiles differ from
@@ -404,6 +419,7 @@ def main():
     phi0 = inputs.spinodal(n, n, seed=1)
     lat = make_lattice(lbcm, n, args.precision, args).init(phi0)
     copy_gbs = copy_probe() if args.copy_probe else None  # untimed; keeps the GPU busy up to the warm-up
+    stream_gbs = stream_probe(n) if args.copy_probe else None
     wall0 = time.perf_counter()
     block_sec = time_blocks(lat, args.steps, args.warmup, args.blocks)
     wall = time.perf_counter() - wall0
@@ -455,6 +471,10 @@ def main():
     if copy_gbs is not None:
         out["roofline"]["copy_probe_gbs"] = round(copy_gbs, 1)
         out["roofline"]["copy_probe"] = "torch device copy of 2 GiB (reads + writes)"
+        out["roofline"]["stream_probe_gbs"] = round(stream_gbs, 1)
+        out["roofline"]["stream_probe"] = ("lbcm_stream_probe: 18 planes of the lattice's size read and written, one "
+                                           "FP32 element per lane, non-temporal stores")
+        out["roofline"]["frac_of_stream_probe"] = round(achieved / stream_gbs, 4)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, args.cpu_single_steps,
                                            args.small_steps if args.precision == "fp32" else 0)

@@ -165,6 +165,14 @@ int lbcm_diag(lbcm_handle *h, lbcm_diagnostics *out);
 int lbcm_diag_state(const lbcm_params *p, const void *f, const void *g, const void *f_prev, int64_t step,
                     lbcm_diagnostics *out);
 
+/* Streaming reference for the step kernel's roofline (a measurement, not part of the method): one
+   launch reads `planes` (9 or 18) planes of n floats from src and writes them to as many planes of
+   dst, one element per lane, non-temporal stores: the step's access pattern without its shifted
+   pulls, halo reads and arithmetic.  *ms receives the average time of `reps` launches on
+   `stream` (after one untimed launch).  src and dst are device buffers of planes * n floats.
+   Synchronises.  Errors: LBCM_EINVAL, LBCM_EHIP (message in lbcm_last_error(NULL)). */
+int lbcm_stream_probe(const float *src, float *dst, size_t n, int32_t planes, int32_t reps, void *stream, float *ms);
+
 /* Bytes of the raw population state: 18 planes (f_0..f_8 then g_0..g_8) in storage precision. */
 /* The raw state is in pull layout (plane i at node x holds the post-collision value of the
    previous step at its origin node x) and f is stored shifted, as f_i - w_i. */

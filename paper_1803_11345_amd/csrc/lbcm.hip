@@ -1227,6 +1227,21 @@ __global__ __launch_bounds__(kReduceThreads) void k_diag_finish(const double *pa
 
 __global__ void k_clear_int(int *p) { *p = 0; }
 
+// Streaming reference: PLANES planes of n floats read and written to PLANES other planes, one
+// element per lane and one launch over all elements (the access pattern of the step kernel
+// without its shifted pulls, halo reads and arithmetic), non-temporal stores like the step's.
+template <int PLANES>
+__global__ __launch_bounds__(512) void k_stream(const float *__restrict__ src, float *__restrict__ dst, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * 512u + threadIdx.x;
+    if (i >= n) return;
+    float v[PLANES];
+#pragma unroll
+    for (int p = 0; p < PLANES; ++p) v[p] = src[(size_t)p * n + i];
+#pragma unroll
+    for (int p = 0; p < PLANES; ++p) __builtin_nontemporal_store(v[PLANES - 1 - p], &dst[(size_t)p * n + i]);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -2288,6 +2303,41 @@ int lbcm_destroy(lbcm_handle *h)
 const char *lbcm_last_error(const lbcm_handle *h)
 {
     return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int lbcm_stream_probe(const float *src, float *dst, size_t n, int32_t planes, int32_t reps, void *stream, float *ms)
+{
+    auto err = [](int code, const std::string &m) {
+        g_create_error = "lbcm_stream_probe: " + m;
+        return code;
+    };
+    if (!src || !dst || !ms || n < 1 || n > 0xffffffffull || reps < 1 || (planes != 9 && planes != 18))
+        return err(LBCM_EINVAL, "need src, dst, ms, 1 <= n < 2^32, reps >= 1 and planes 9 or 18");
+    const hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)((n + 511) / 512)), block(512);
+    auto launch = [&] {
+        if (planes == 18) hipLaunchKernelGGL((k_stream<18>), grid, block, 0, st, src, dst, (uint32_t)n);
+        else hipLaunchKernelGGL((k_stream<9>), grid, block, 0, st, src, dst, (uint32_t)n);
+    };
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return err(LBCM_EHIP, hipGetErrorString(e));
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return err(LBCM_EHIP, hipGetErrorString(e));
+    }
+    launch();
+    e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) launch();
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return err(LBCM_EHIP, hipGetErrorString(e));
+    *ms /= (float)reps;
+    return LBCM_OK;
 }
 
 int lbcm_diag_state(const lbcm_params *p, const void *f, const void *g, const void *f_prev, int64_t step,

@@ -94,6 +94,8 @@ def load():
     lib.lbcm_fields_device.argtypes = [_H] + [ctypes.c_void_p] * 5
     lib.lbcm_populations.argtypes = [_H, _D, _D]
     lib.lbcm_diag.argtypes = [_H, ctypes.POINTER(lbcm_diagnostics)]
+    lib.lbcm_stream_probe.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]
     lib.lbcm_diag_state.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.POINTER(lbcm_diagnostics)]
     lib.lbcm_state_size.argtypes = [_H]
@@ -202,6 +204,17 @@ def lbcm_diag(h) -> dict:
     d = lbcm_diagnostics()
     _check(h, load().lbcm_diag(h, ctypes.byref(d)))
     return {name: getattr(d, name) for name, _ in lbcm_diagnostics._fields_}
+
+
+def lbcm_stream_probe(src, dst, n: int, planes: int = 18, reps: int = 20, stream=None) -> float:
+    """Milliseconds per launch of the library's streaming reference (src, dst: CUDA tensors of
+    planes * n float32)."""
+    ms = ctypes.c_float()
+    rc = load().lbcm_stream_probe(src.data_ptr(), dst.data_ptr(), int(n), int(planes), int(reps), stream,
+                                  ctypes.byref(ms))
+    if rc != LBCM_OK:
+        raise LbcmError(rc, lbcm_last_error(None))
+    return ms.value
 
 
 def lbcm_diag_state(params: lbcm_params, f, g, f_prev=None, step: int = 0) -> dict:

@@ -112,3 +112,20 @@ def test_diag_counts_nonfinite_nodes():
     # pull returns exactly those equilibria: the 3x3 block around each planted value is non-finite
     assert d["nonfinite"] == 2 * 9
     lat.close()
+
+
+def test_stream_probe_moves_every_plane():
+    """The streaming reference of the roofline writes plane p of dst from plane planes - 1 - p of
+    src, every element (a ragged last workgroup included), and reports a positive time."""
+    import torch
+
+    for planes in (9, 18):
+        n = 1000
+        src = torch.arange(planes * n, dtype=torch.float32, device="cuda")
+        dst = torch.full_like(src, -1.0)
+        ms = lbcm.lbcm_stream_probe(src, dst, n, planes, 3)
+        torch.cuda.synchronize()
+        want = src.view(planes, n).flip(0).reshape(-1)
+        assert torch.equal(dst, want) and ms > 0
+    with pytest.raises(lbcm.LbcmError):
+        lbcm.lbcm_stream_probe(src, dst, n, 7, 3)
