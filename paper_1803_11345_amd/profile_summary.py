@@ -29,8 +29,19 @@ def source_digest() -> str:
     return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
 
 
+def _demangle(name: str) -> str:
+    if not name.startswith("_Z"):
+        return name
+    import subprocess
+
+    try:
+        return subprocess.run(["c++filt", name], capture_output=True, text=True, check=True).stdout.strip()
+    except (OSError, subprocess.CalledProcessError):
+        return name
+
+
 def _short(name: str) -> str:
-    name = name.replace("(anonymous namespace)::", "")
+    name = _demangle(name).replace("(anonymous namespace)::", "")
     return name.split("(")[0] if not name.startswith("void ") else name[5:].split("(")[0]
 
 
