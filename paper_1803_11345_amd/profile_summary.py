@@ -35,9 +35,28 @@ def _demangle(name: str) -> str:
     import subprocess
 
     try:
-        return subprocess.run(["c++filt", name], capture_output=True, text=True, check=True).stdout.strip()
+        out = subprocess.run(["c++filt", name], capture_output=True, text=True, check=True).stdout.strip()
+        if out != name:
+            return out
     except (OSError, subprocess.CalledProcessError):
+        pass
+    # names c++filt does not know (bfloat16 parameters): the kernel's identifier inside the anonymous
+    # namespace and its integer template arguments
+    import re
+
+    m = re.match(r"_ZN12_GLOBAL__N_1(\d+)", name)
+    if not m:
         return name
+    n, pos = int(m.group(1)), m.end()
+    ident, pos = name[pos:pos + n], pos + n
+    args = []
+    if name[pos:pos + 1] == "I":
+        for a in re.finditer(r"Li(-?\d+)E", name[pos + 1:]):
+            if a.start() != sum(len(x) for x in args):
+                break
+            args.append(a.group(0))
+    vals = [re.match(r"Li(-?\d+)E", x).group(1) for x in args]
+    return ident + (f"<{', '.join(vals)}>" if vals else "")
 
 
 def _short(name: str) -> str:
