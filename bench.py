@@ -70,6 +70,9 @@ def parse():
                     help="steps timed with each persistent schedule (0 = skip them)")
     ap.add_argument("--sur-iters", type=int, default=2000, help="training iterations of the surrogate leg (0 = skip it)")
     ap.add_argument("--sur-windows", type=int, default=40, help="hybrid windows (8 jumps of 16 steps) timed per case")
+    ap.add_argument("--sur-kernels", type=int, default=0,
+                    help="only a short kernel workload of the surrogate (for counter runs): this many jumps and "
+                         "training iterations on seeded data, with progress lines; every other leg is skipped")
     return ap.parse_args()
 
 
@@ -403,6 +406,49 @@ def surrogate_report(lbcm, args) -> dict:
                          "plain_lb_with_equilibrium_restart_every_window": restart}}
 
 
+def surrogate_kernels(n_iter: int) -> dict:
+    """The surrogate's kernels alone, on seeded data (no lattice runs): n_iter inference jumps of
+    the 6-layer 64-channel network on one 256^2 box from FP64 planes, and n_iter training
+    iterations (forward, backward, Adam) at batch 8.  Prints a line per phase (stderr)."""
+    import numpy as np
+    import torch
+
+    from paper_1803_11345_amd import inputs
+    from paper_1803_11345_amd.net import Surrogate, initial_params
+
+    n = 256
+    p = initial_params(64, 6, seed=1)
+    m1 = Surrogate(1, n, n, channels=64, layers=6)
+    m1.set_params(p)
+    planes = [torch.from_numpy(inputs.uniform(10 + c, n * n).reshape(n, n) * 0.1).cuda() for c in range(4)]
+    outs = [torch.empty(n, n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    print(f"surrogate kernels: {n_iter} jumps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_iter):
+        m1.forward_planes(*planes, 1.0, 1.0, *outs)
+    torch.cuda.synchronize()
+    jump = (time.perf_counter() - t0) / n_iter
+    m1.close()
+    m8 = Surrogate(8, n, n, channels=64, layers=6)
+    m8.set_params(p)
+    x = torch.from_numpy((inputs.uniform(20, 8 * n * n * 4).reshape(8, n, n, 4) * 0.1).astype(np.float32)).cuda()
+    y = torch.from_numpy((inputs.uniform(21, 8 * n * n * 4).reshape(8, n, n, 4) * 0.1).astype(np.float32)).cuda()
+    print(f"surrogate kernels: {n_iter} training iterations", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_iter):
+        m8.forward(x)
+        m8.backward(y, want_loss=False)
+        m8.adam(1e-4)
+    torch.cuda.synchronize()
+    it = (time.perf_counter() - t0) / n_iter
+    m8.close()
+    print("surrogate kernels: done", file=sys.stderr, flush=True)
+    return {"jumps": n_iter, "jump_us_wall": round(jump * 1e6, 2), "iterations": n_iter,
+            "iteration_ms_wall": round(it * 1e3, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -415,6 +461,9 @@ def main():
     from paper_1803_11345_amd import inputs, lbcm
 
     torch.cuda.set_device(0)
+    if args.sur_kernels > 0:
+        print(json.dumps({"surrogate_kernels": surrogate_kernels(args.sur_kernels)}), flush=True)
+        return
     n = args.n
     phi0 = inputs.spinodal(n, n, seed=1)
     lat = make_lattice(lbcm, n, args.precision, args).init(phi0)

@@ -1,6 +1,8 @@
 """Summaries of rocprofv3 output for the profiles/ folder.
 
   python -m paper_1803_11345_amd.profile_summary stats  <kernel_stats.csv> --command "..." --out X.md
+  python -m paper_1803_11345_amd.profile_summary mfma <kernel_stats.csv> <counter_collection.csv>
+         --command "..." --out X.md
   python -m paper_1803_11345_amd.profile_summary traffic <fetch counter_collection.csv>
          <write counter_collection.csv> --kernel k_step --copy-bytes 2147483648 --nodes N
          --bytes-per-lup B --command "..." --out X.json
@@ -115,6 +117,51 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, nodes:
             "write_over_algorithmic": res["write"]["bytes_per_launch"] / (alg / 2), **res}
 
 
+# Work of the surrogate's kernels in the kernel-only workload of bench.py --sur-kernels (FLOP per
+# launch counted as the MFMA computes it, padded channels and recomputed halo rings included;
+# 65,536 pixels for one inference box, 524,288 for the training batch of 8), and the peak of the
+# arithmetic each runs on (MI355X dense: BF16 MFMA 2.5 PFLOP/s, FP32 MFMA and vector FP32 157.3).
+_PX1, _PX8 = 256 * 256, 8 * 256 * 256
+_HALO = 340 / 256  # a fused pair's first layer runs on the tile plus a one-pixel ring (10 x 34 of 8 x 32)
+SURROGATE_WORK = {
+    "k_first_pair": (2 * _PX1 * 9 * (4 * 64 * 1.0 + 64 * 64) * _HALO, "BF16 MFMA (+ FP32 layer 0)", 2500.0),
+    "k_pair<64, 0, 64>": (2 * _PX1 * 9 * 64 * 64 * (_HALO + 1), "BF16 MFMA", 2500.0),
+    "k_pair<16, 3, 32>": (2 * _PX1 * 9 * (64 * 64 * _HALO + 64 * 16), "BF16 MFMA", 2500.0),
+    "k_first<64, false>": (2 * _PX8 * 9 * 4 * 64, "FP32 MFMA", 157.3),
+    "k_conv<64, 64, 0>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
+    "k_conv<64, 32, 1>": (2 * _PX8 * 9 * 64 * 32, "BF16 MFMA", 2500.0),
+    "k_conv<64, 64, 2>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
+    "k_conv<32, 64, 2>": (2 * _PX8 * 9 * 32 * 64, "BF16 MFMA", 2500.0),
+    "k_conv_dw_strip<64>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
+    "k_conv_dw_strip<32>": (2 * _PX8 * 9 * 64 * 32, "BF16 MFMA", 2500.0),
+    "k_first_dw<64>": (2 * _PX8 * 9 * 4 * 64, "FP32 vector", 157.3),
+}
+
+
+def mfma_md(stats_csv: str, counters_csv: str, command: str, xcds: int = 8, simds: int = 1024) -> str:
+    """Per-kernel TF/s (kernel time from a --kernel-trace --stats run) and MFMA busy fraction
+    (SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / xcds x simds): the counter of GPU-active clocks
+    is summed over the XCDs, the busy counter over the SIMDs) of the surrogate's kernels."""
+    times = {_short(r["Name"]): (int(r["Calls"]), float(r["AverageNs"]) / 1e3) for r in csv.DictReader(open(stats_csv))}
+    busy, active = defaultdict(list), defaultdict(list)
+    for r in csv.DictReader(open(counters_csv)):
+        k = _short(r["Kernel_Name"])
+        (busy if r["Counter_Name"] == "SQ_VALU_MFMA_BUSY_CYCLES" else active)[k].append(float(r["Counter_Value"]))
+    lines = ["# Surrogate kernels against their peaks", "", "Commands (from /tmp, TMPDIR=/tmp):", "", "```", command, "```", "",
+             "| kernel | calls | average (us) | GFLOP per launch | TFLOP/s | unit | fraction of peak | MFMA busy |",
+             "|---|---|---|---|---|---|---|---|"]
+    for k, (flop, unit, peak) in SURROGATE_WORK.items():
+        if k not in times:
+            continue
+        calls, us = times[k]
+        tf = flop / us / 1e6
+        mb = ""
+        if busy.get(k) and active.get(k):
+            mb = f"{statistics.mean(busy[k]) / (statistics.mean(active[k]) / xcds * simds):.2f}"
+        lines.append(f"| `{k}` | {calls} | {us:.2f} | {flop / 1e9:.2f} | {tf:.0f} | {unit} | {tf / peak:.3f} | {mb} |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -131,7 +178,15 @@ def main():
     b.add_argument("--bytes-per-lup", type=int, required=True)
     b.add_argument("--command", required=True)
     b.add_argument("--out", required=True)
+    c = sub.add_parser("mfma")
+    c.add_argument("stats_csv")
+    c.add_argument("counters_csv")
+    c.add_argument("--command", required=True)
+    c.add_argument("--out", required=True)
     args = ap.parse_args()
+    if args.what == "mfma":
+        open(args.out, "w").write(mfma_md(args.stats_csv, args.counters_csv, args.command))
+        return
     if args.what == "stats":
         open(args.out, "w").write(stats_md(args.csv, args.command))
     else:
