@@ -359,40 +359,58 @@ struct ConvLds {
     static constexpr size_t bytes = (size_t)(patch_elems + weight_elems) * sizeof(__bf16);
 };
 
-// Work split of a conv layer over the 8 waves: wave (mg, ng) computes output channels
-// [16 ng, 16 ng + 16) for tile rows [RW mg, RW mg + RW) (COUT / 16 channel groups times
-// 8 / (COUT / 16) row groups).
-template <int COUT>
+// Work split of a conv layer over the 8 waves (the layers a of the fused pairs keep their own):
+// wave w computes GPW channel groups of 16 for HPW of the tile's two 16-pixel column halves over
+// RW tile rows.  With HPW = 2 (every layer of the forward pass): one group, both halves,
+// row group mg = w % MG, group w / MG.  With GPW = 2, HPW = 1 (the input gradients and the last
+// layer of training): half = w % 2, row group (w / 2) % MG, groups [2 pair, 2 pair + 2) for
+// pair = (w / 2) / MG; every pixel fragment read from LDS then feeds twice as many MFMAs.  Which
+// split each kernel takes was measured (wave_split_groups).
+constexpr int wave_split_groups(int cout, int mode) { return (mode == 1 || mode == 2) && cout >= 32 ? 2 : 1; }
+
+template <int COUT, int MODE>
 struct WaveSplit {
-    static constexpr int NG = COUT / 16, MG = 8 / NG, RW = kTileH / MG, MT = 2 * RW;
+    static constexpr int NG = COUT / 16, GPW = wave_split_groups(COUT, MODE), HPW = GPW == 2 ? 1 : 2,
+                         NPAIR = NG / GPW, MG = (kConvThreads / 64) * HPW / (2 * NPAIR), RW = kTileH / MG;
+    static_assert(MG * NPAIR * (2 / HPW) == kConvThreads / 64 && RW * MG == kTileH, "eight waves cover the tile");
+    __device__ static int half0(int wave) { return HPW == 2 ? 0 : wave & 1; }
+    __device__ static int mg(int wave) { return HPW == 2 ? wave % MG : (wave >> 1) % MG; }
+    __device__ static int cbase(int wave) { return 16 * GPW * (HPW == 2 ? wave / MG : (wave >> 1) / MG); }
 };
 
 // One output tile of a conv layer from its input patch in LDS (the tile plus a one-pixel halo,
-// 10 x 34 pixels, pixel stride CIN + 8), with this wave's A fragments wa (W[t][co = 16 ng + r][ci
-// = 32 ks + 8 q .. + 8] in lane (r, q)) and the bias of its 4 output channels.  Input-stationary
-// order: each pixel fragment of the wave's RW + 2 patch rows is read from LDS once and applied to
-// every output row (tap dy) that uses it.  Stage s covers patch row s / 2 and column half s % 2
-// (3 horizontal taps x KS fragments); the fragments of stage s + 1 are read before the MFMAs of
-// stage s, in a second register buffer.  Every output sums its taps in the order t = 0 .. 8 and
-// K-steps within a tap.
+// 10 x 34 pixels, pixel stride CIN + 8), with this wave's A fragments wa[g] (W[t][co = cbase +
+// 16 g + r][ci = 32 ks + 8 q .. + 8] in lane (r, q)) and the biases of its output channels.
+// Input-stationary order: each pixel fragment of the wave's RW + 2 patch rows (its column half) is
+// read from LDS once and applied to every output row (tap dy) and channel group that uses it.
+// Stage s covers patch row s (3 horizontal taps x KS fragments); the fragments of stage s + 1 are
+// read before the MFMAs of stage s, in a second register buffer.  Every output sums its taps in
+// the order t = 0 .. 8 and K-steps within a tap.
 template <int CIN, int COUT, int MODE>
-__device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa)[9][CIN / 32], const float (&bias)[4],
-                                          TileCoord tc, const OutArgs &o, int H, int W)
+__device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa)[WaveSplit<COUT, MODE>::GPW][9][CIN / 32],
+                                          const float (&bias)[WaveSplit<COUT, MODE>::GPW][4], TileCoord tc, const OutArgs &o,
+                                          int H, int W)
 {
     constexpr int PS = CIN + 8, KS = CIN / 32;
-    using S = WaveSplit<COUT>;
-    constexpr int RW = S::RW, MT = S::MT;
+    using S = WaveSplit<COUT, MODE>;
+    constexpr int RW = S::RW, GPW = S::GPW, HPW = S::HPW;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int mg = wave % S::MG, ng = wave / S::MG;
+    const int half0 = S::half0(wave), mg = S::mg(wave);
+    const int cbase = S::cbase(wave);
     const int r = lane & 15, q = lane >> 4;
-    f32x4 acc[MT];
+    f32x4 acc[GPW][RW][HPW];
 #pragma unroll
-    for (int mi = 0; mi < MT; ++mi) acc[mi] = f32x4{0, 0, 0, 0};
-    constexpr int NS = 2 * (RW + 2);
+    for (int g = 0; g < GPW; ++g)
+#pragma unroll
+        for (int rho = 0; rho < RW; ++rho)
+#pragma unroll
+            for (int h = 0; h < HPW; ++h) acc[g][rho][h] = f32x4{0, 0, 0, 0};
+    // stage st: patch row st / HPW, column half half0 + st % HPW
+    constexpr int NS = HPW * (RW + 2);
     bf16x8 fr[2][3][KS];
     auto load_stage = [&](int st, bf16x8 (&f)[3][KS]) {
-        const int py = st >> 1, half = st & 1;
+        const int py = st / HPW, half = half0 + st % HPW;
 #pragma unroll
         for (int dxi = 0; dxi < 3; ++dxi)
 #pragma unroll
@@ -403,57 +421,64 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
         if (st + 1 < NS) load_stage(st + 1, fr[(st + 1) & 1]);
-        const int py = st >> 1, half = st & 1;
+        const int py = st / HPW, h = st % HPW;
 #pragma unroll
         for (int dxi = 0; dxi < 3; ++dxi)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                for (int rho = 0; rho < RW; ++rho) {
-                    const int dyi = py - rho;  // tap row index dy + 1
-                    if (dyi < 0 || dyi > 2) continue;
-                    acc[2 * rho + half] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 * dyi + dxi][ks], fr[st & 1][dxi][ks],
-                                                                                  acc[2 * rho + half], 0, 0, 0);
-                }
+                for (int g = 0; g < GPW; ++g)
+#pragma unroll
+                    for (int rho = 0; rho < RW; ++rho) {
+                        const int dyi = py - rho;  // tap row index dy + 1
+                        if (dyi < 0 || dyi > 2) continue;
+                        acc[g][rho][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[g][3 * dyi + dxi][ks], fr[st & 1][dxi][ks],
+                                                                                 acc[g][rho][h], 0, 0, 0);
+                    }
         __builtin_amdgcn_sched_barrier(0);
     }
-    // D[co][pixel]: lane (r, q) holds channels 16 ng + 4 q .. + 3 of pixel r of each tile
-    const int c0 = 16 * ng + 4 * q;
+    // D[co][pixel]: lane (r, q) holds channels cbase + 16 g + 4 q .. + 3 of pixel r of each block
 #pragma unroll
-    for (int mi = 0; mi < MT; ++mi) {
-        const int yy = tc.y0 + RW * mg + (mi >> 1), xx = tc.x0 + 16 * (mi & 1) + r;
-        if (yy >= H || xx >= W) continue;
-        const size_t p = ((size_t)tc.n * H + yy) * W + xx;
-        if (MODE == 1 || MODE == 3) {
-            if (c0 == 0) {  // the 4 state channels are those of the q = 0 lanes of the first channel group
-                static_assert(kStateC == 4, "one lane holds the four state channels of a pixel");
-                const f32x4 rs = *(const f32x4 *)(o.resid + p * kStateC);
-                f32x4 v;
-                v[0] = rs[0] + o.alpha0 * (acc[mi][0] + bias[0]);
-                v[1] = rs[1] + o.alpha1 * (acc[mi][1] + bias[1]);
-                v[2] = rs[2] + o.alpha2 * (acc[mi][2] + bias[2]);
-                v[3] = rs[3] + o.alpha3 * (acc[mi][3] + bias[3]);
-                if (MODE == 1) {
-                    *(f32x4 *)(o.Yf + p * kStateC) = v;
-                } else {
-                    o.phi[p] = v[0];
-                    o.ux[p] = v[1] * o.u_scale;
-                    o.uy[p] = v[2] * o.u_scale;
-                    o.rho[p] = 1.0 + v[3] * o.r_scale;
+    for (int g = 0; g < GPW; ++g)
+#pragma unroll
+        for (int rho = 0; rho < RW; ++rho)
+#pragma unroll
+            for (int h = 0; h < HPW; ++h) {
+            const int c0 = cbase + 16 * g + 4 * q;
+            const int yy = tc.y0 + RW * mg + rho, xx = tc.x0 + 16 * (half0 + h) + r;
+            if (yy >= H || xx >= W) continue;
+            const size_t p = ((size_t)tc.n * H + yy) * W + xx;
+            const f32x4 &a = acc[g][rho][h];
+            if (MODE == 1 || MODE == 3) {
+                if (c0 == 0) {  // the 4 state channels are those of the q = 0 lanes of the first channel group
+                    static_assert(kStateC == 4, "one lane holds the four state channels of a pixel");
+                    const f32x4 rs = *(const f32x4 *)(o.resid + p * kStateC);
+                    f32x4 v;
+                    v[0] = rs[0] + o.alpha0 * (a[0] + bias[g][0]);
+                    v[1] = rs[1] + o.alpha1 * (a[1] + bias[g][1]);
+                    v[2] = rs[2] + o.alpha2 * (a[2] + bias[g][2]);
+                    v[3] = rs[3] + o.alpha3 * (a[3] + bias[g][3]);
+                    if (MODE == 1) {
+                        *(f32x4 *)(o.Yf + p * kStateC) = v;
+                    } else {
+                        o.phi[p] = v[0];
+                        o.ux[p] = v[1] * o.u_scale;
+                        o.uy[p] = v[2] * o.u_scale;
+                        o.rho[p] = 1.0 + v[3] * o.r_scale;
+                    }
                 }
-            }
-        } else {
-            bf16x4 m4 = {};
-            if (MODE == 2) m4 = __builtin_bit_cast(bf16x4, *(const u32x2 *)(o.mask + p * COUT + c0));
-            bf16x4 v4;
+            } else {
+                bf16x4 m4 = {};
+                if (MODE == 2) m4 = __builtin_bit_cast(bf16x4, *(const u32x2 *)(o.mask + p * COUT + c0));
+                bf16x4 v4;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float v = acc[mi][e] + bias[e];
-                v4[e] = (__bf16)(MODE == 2 ? (((float)m4[e] > 0.f) ? v : 0.f) : fmaxf(v, 0.f));
+                for (int e = 0; e < 4; ++e) {
+                    const float v = a[e] + bias[g][e];
+                    v4[e] = (__bf16)(MODE == 2 ? (((float)m4[e] > 0.f) ? v : 0.f) : fmaxf(v, 0.f));
+                }
+                *(u32x2 *)(o.Y + p * COUT + c0) = __builtin_bit_cast(u32x2, v4);
             }
-            *(u32x2 *)(o.Y + p * COUT + c0) = __builtin_bit_cast(u32x2, v4);
         }
-    }
 }
 
 template <int CIN, int COUT, int MODE>
@@ -464,14 +489,13 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
     constexpr int WS = Lds::WS;
     static_assert(Lds::PS == Patch<CIN>::PS, "patch stride");
     constexpr int KS = CIN / 32;  // K-steps per tap
-    using S = WaveSplit<COUT>;
+    constexpr int GPW = WaveSplit<COUT, MODE>::GPW;
     __bf16 *patch = lbcm_conv_lds, *wl = lbcm_conv_lds + Lds::patch_elems;
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ng = wave / S::MG;
     const int r = lane & 15, q = lane >> 4;
-    const int cbase = 16 * ng;
+    const int cbase = WaveSplit<COUT, MODE>::cbase(wave);
 
     int tile = blockIdx.x;
     if (tile >= ntiles) return;
@@ -494,15 +518,19 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
     Patch<CIN> pre;
     pre.load(X, tile_coord(tile, H, W), H, W);
     __syncthreads();
-    bf16x8 wa[9][KS];
+    bf16x8 wa[GPW][9][KS];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int g = 0; g < GPW; ++g)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) wa[t][ks] = ld8(wl + (t * COUT + cbase + r) * WS + 32 * ks + 8 * q);
-    // this lane's output channels: cbase + 4 q + e
-    float bias[4];
+        for (int t = 0; t < 9; ++t)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bias[e] = (MODE != 2) ? o.bias[cbase + 4 * q + e] : 0.f;
+            for (int ks = 0; ks < KS; ++ks) wa[g][t][ks] = ld8(wl + (t * COUT + cbase + 16 * g + r) * WS + 32 * ks + 8 * q);
+    // this lane's output channels: cbase + 16 g + 4 q + e
+    float bias[GPW][4];
+#pragma unroll
+    for (int g = 0; g < GPW; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[g][e] = (MODE != 2) ? o.bias[cbase + 16 * g + 4 * q + e] : 0.f;
 
     for (; tile < ntiles; tile += gridDim.x) {
         const TileCoord tc = tile_coord(tile, H, W);
@@ -602,8 +630,6 @@ __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict_
     if (tile >= ntiles) return;
     const TileCoord tc = tile_coord(tile, H, W);
     const int mg = wave & 1, ng = wave >> 1;
-    using S = WaveSplit<COUT>;
-    const int ngb = wave / S::MG;
     bf16x8 wa[9][KS];
     float bias[4];
     // every global load at once: the patch, layer a's weights, then layer b's, which stay in
@@ -689,11 +715,18 @@ __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict_
     if (r < L::ZH) zstore(zr, zc, acc[2 * RW]);
     sb.store(wl);
     // layer b
+    constexpr int GPW = WaveSplit<COUT, MODE>::GPW;
+    const int cb = WaveSplit<COUT, MODE>::cbase(wave);
+    float biasb[GPW][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bias[e] = o.bias[16 * ngb + 4 * q + e];
+    for (int g = 0; g < GPW; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) biasb[g][e] = o.bias[cb + 16 * g + 4 * q + e];
     lds_barrier();
-    lds_frags<C, COUT>(wl, 16 * ngb + r, q, wa);
-    conv_tile<C, COUT, MODE>(zs, wa, bias, tc, o, H, W);
+    bf16x8 wb[GPW][9][KS];
+#pragma unroll
+    for (int g = 0; g < GPW; ++g) lds_frags<C, COUT>(wl, cb + 16 * g + r, q, wb[g]);
+    conv_tile<C, COUT, MODE>(zs, wb, biasb, tc, o, H, W);
 }
 
 // Layers 0 and 1 in one pass (inference): layer 0 as k_first (FP32 MFMA, the bias as the starting
@@ -722,7 +755,6 @@ __global__ __launch_bounds__(kConvThreads) void k_first_pair(PlaneIn pin, float 
     const int mg = wave & 1, ng = wave >> 1;
     float w0[9];  // A operand at tap t: lane (r, q) holds W0[t][ci = q][co = 16 ng + r]
     float bias0[4];
-    bf16x8 w1[9][KS];
     WeightStage<C, C> s1;  // layer 1's weights, in flight during layer 0
     {
         // every global load at once: this thread's patch pixel first, then both layers' weights
@@ -786,12 +818,18 @@ __global__ __launch_bounds__(kConvThreads) void k_first_pair(PlaneIn pin, float 
         if (r < L::ZH) zstore(zr, zc, acc[2 * RW]);
     }
     s1.store(wl);
-    float bias1[4];
+    constexpr int GPW = WaveSplit<C, 0>::GPW;
+    const int cb = WaveSplit<C, 0>::cbase(wave);
+    float bias1[GPW][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bias1[e] = o.bias[16 * ng + 4 * q + e];
+    for (int g = 0; g < GPW; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias1[g][e] = o.bias[cb + 16 * g + 4 * q + e];
     lds_barrier();
-    lds_frags<C, C>(wl, 16 * ng + r, q, w1);
-    conv_tile<C, C, 0>(zs, w1, bias1, tc, o, H, W);
+    bf16x8 wb[GPW][9][KS];
+#pragma unroll
+    for (int g = 0; g < GPW; ++g) lds_frags<C, C>(wl, cb + 16 * g + r, q, wb[g]);
+    conv_tile<C, C, 0>(zs, wb, bias1, tc, o, H, W);
 }
 
 // ------------------------------------------------------------------------------------------
