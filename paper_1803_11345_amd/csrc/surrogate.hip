@@ -29,6 +29,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lbcm_net.h"
@@ -95,27 +96,6 @@ __device__ __forceinline__ TileCoord tile_coord(int tile, int H, int W)
     const int tx = (W + kTileW - 1) / kTileW, ty = (H + kTileH - 1) / kTileH;
     const int n = tile / (tx * ty), rem = tile % (tx * ty);
     return {n, (rem / tx) * kTileH, (rem % tx) * kTileW};
-}
-
-// stage the FP32 state patch (tile plus circular halo) of one tile in LDS: sp[(py * 34 + px) * kStateC + c]
-__device__ __forceinline__ void stage_state(const float *__restrict__ s, TileCoord tc, int H, int W, float *sp)
-{
-    constexpr int NV = kPatchH * kPatchW * kStateC, NI = (NV + kThreads - 1) / kThreads;
-    float v[NI];
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const int k = threadIdx.x + i * kThreads;
-        if (k < NV) {
-            const int px = k / kStateC, c = k % kStateC;
-            const int gy = wrap_near(tc.y0 - 1 + px / kPatchW, H), gx = wrap_near(tc.x0 - 1 + px % kPatchW, W);
-            v[i] = s[(((size_t)tc.n * H + gy) * W + gx) * kStateC + c];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const int k = threadIdx.x + i * kThreads;
-        if (k < NV) sp[k] = v[i];
-    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -206,87 +186,108 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
     }
 }
 
-// layer 0 gradients, one 8 x 32 tile per workgroup: partial[tile][r][co] for r = kStateC t + ci
-// (r < 36: sum_p s[p + d_t][ci] dZ[p][co]) and r = 36 (sum_p dZ[p][co], the bias).  The state
-// patch and the tile's dZ are staged in LDS; thread (g, c4) accumulates output channels 4 c4 ..
-// 4 c4 + 3 of rows r = g, g + G, ... with G = kThreads / (C / 4), over the pixels in order (one
-// dZ read and one state read feed four FMAs).
+// layer 0 gradients on the matrix cores in FP32 (as its forward): D[co][col] = sum_p dZ[p][co] B[p][col]
+// with col = kStateC t + ci < 36 (B = s[p + d_t][ci], the weight gradient), col 36 (B = 1, the
+// bias gradient) and cols 37 .. 47 (B = 0, padding to three 16-column blocks).
+// v_mfma_f32_16x16x4_f32 takes four pixels as its K: lane (r, q) holds A = dZ[pixel q][co0 + r]
+// (BF16 widened, exact) and B = B[pixel q][col0 + r].  Workgroup b takes the tiles b, b + G, ...
+// (G = the grid), staging each tile's FP32 state patch and dZ in LDS with the next tile's global
+// loads in flight; wave w takes the K steps (four pixels each) w, w + 4, ... of every tile and keeps
+// all C / 16 x 3 output blocks in registers.  Its sums go to partial row 4 b + w ([row][col][co],
+// cols < kFirstRows), added in a fixed order by k_grad_reduce.
+constexpr int kFirstDwBlocks = 256;  // workgroups of k_first_dw at most
+constexpr int kFirstCols = 48;       // kFirstRows columns padded to three 16-column blocks
+
 template <int C>
 __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__ s, const __bf16 *__restrict__ dz, int H,
-                                                       int W, float *__restrict__ partial)
+                                                       int W, int ntiles, float *__restrict__ partial)
 {
-    constexpr int G = kThreads / (C / 4), R = (kFirstRows + G - 1) / G;
-    __shared__ float sp[kPatchH * kPatchW * kStateC];
+    constexpr int NCB = C / 16, NJ = kFirstCols / 16;
+    constexpr int NS = kPatchH * kPatchW * kStateC, NIS = (NS + kThreads - 1) / kThreads;
+    constexpr int NZ = kTileH * kTileW * C / 8, NIZ = NZ / kThreads;
+    static_assert(NZ % kThreads == 0, "whole dZ chunks per thread");
+    __shared__ float sp[NS];
     __shared__ __align__(16) __bf16 sd[kTileH * kTileW * C];
-    const TileCoord tc = tile_coord(blockIdx.x, H, W);
-    stage_state(s, tc, H, W, sp);
-    constexpr int NV = kTileH * kTileW * C / 8;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = lane & 15, q = lane >> 4;
+    // this lane's three B columns: patch offset from the pixel's position, and x m + a = B
+    // (m = 1, a = 0: the state value; m = 0: a, 1 for the bias column and 0 for padding)
+    int boff[NJ];
+    float bm[NJ], ba[NJ];
 #pragma unroll
-    for (int k = threadIdx.x; k < NV; k += kThreads) {
-        const int px = k / (C / 8), ch = (k % (C / 8)) * 8;
-        const int y = tc.y0 + px / kTileW, xg = tc.x0 + px % kTileW;
-        u32x4 v = {0, 0, 0, 0};  // pixels past the box edge contribute nothing
-        if (y < H && xg < W) v = *(const u32x4 *)(dz + (((size_t)tc.n * H + y) * W + xg) * C + ch);
-        *(u32x4 *)(sd + px * C + ch) = v;
+    for (int j = 0; j < NJ; ++j) {
+        const int col = 16 * j + r, t = col / kStateC;
+        const bool prod = col < kFirstRows - 1;
+        boff[j] = prod ? ((1 + tap_dy(t)) * kPatchW + 1 + tap_dx(t)) * kStateC + col % kStateC : 0;
+        bm[j] = prod ? 1.f : 0.f;
+        ba[j] = col == kFirstRows - 1 ? 1.f : 0.f;
     }
-    __syncthreads();
-    const int c4 = threadIdx.x % (C / 4), g = threadIdx.x / (C / 4);
-    // row r of this thread: the state value at patch offset off from the pixel, times m, plus a
-    // (m = 1, a = 0 for r < 36; m = 0, a = 1 for the bias row; rows past it are not stored)
-    int off[R];
-    float m[R], a[R];
+    f32x4 acc[NCB][NJ];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int r = g + k * G, t = r / kStateC;
-        const bool prod = r < kFirstRows - 1;
-        off[k] = prod ? ((1 + tap_dy(t)) * kPatchW + 1 + tap_dx(t)) * kStateC + r % kStateC : 0;
-        m[k] = prod ? 1.f : 0.f;
-        a[k] = prod ? 0.f : 1.f;
-    }
-    float acc[R][4];
+    for (int i = 0; i < NCB; ++i)
 #pragma unroll
-    for (int k = 0; k < R; ++k)
+        for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    float vs[NIS];
+    u32x4 vz[NIZ];
+    // global loads of one tile (state patch with circular halo; dZ, zero past the box edge)
+    auto load = [&](int tile) {
+        const TileCoord tc = tile_coord(tile, H, W);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[k][e] = 0.f;
-    for (int px = 0; px < kTileH * kTileW; ++px) {
-        const bf16x4 d4 = __builtin_bit_cast(bf16x4, *(const u32x2 *)(sd + px * C + 4 * c4));
-        float d[4];
+        for (int i = 0; i < NIS; ++i) {
+            const int k = threadIdx.x + i * kThreads;
+            if (k < NS) {
+                const int px = k / kStateC, c = k % kStateC;
+                const int gy = wrap_near(tc.y0 - 1 + px / kPatchW, H), gx = wrap_near(tc.x0 - 1 + px % kPatchW, W);
+                vs[i] = s[(((size_t)tc.n * H + gy) * W + gx) * kStateC + c];
+            }
+        }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) d[e] = (float)d4[e];
-        const int base = ((px / kTileW) * kPatchW + px % kTileW) * kStateC;
+        for (int i = 0; i < NIZ; ++i) {
+            const int k = threadIdx.x + i * kThreads;
+            const int px = k / (C / 8), ch = (k % (C / 8)) * 8;
+            const int y = tc.y0 + px / kTileW, xg = tc.x0 + px % kTileW;
+            vz[i] = u32x4{0, 0, 0, 0};
+            if (y < H && xg < W) vz[i] = *(const u32x4 *)(dz + (((size_t)tc.n * H + y) * W + xg) * C + ch);
+        }
+    };
+    int tile = blockIdx.x;
+    if (tile < ntiles) load(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        __syncthreads();  // every wave is done with the previous tile's LDS
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const float x = fmaf(sp[base + off[k]], m[k], a[k]);  // exact: x or 1
+        for (int i = 0; i < NIS; ++i) {
+            const int k = threadIdx.x + i * kThreads;
+            if (k < NS) sp[k] = vs[i];
+        }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[k][e] = fmaf(x, d[e], acc[k][e]);
+        for (int i = 0; i < NIZ; ++i) *(u32x4 *)(sd + (threadIdx.x + i * kThreads) * 8) = vz[i];
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
+        for (int k = w; k < kTileH * kTileW / 4; k += 4) {
+            const int px = 4 * k + q;
+            const int base = ((px / kTileW) * kPatchW + px % kTileW) * kStateC;
+            float bv[NJ], av[NCB];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) bv[j] = fmaf(sp[base + boff[j]], bm[j], ba[j]);  // exact: x, 1 or 0
+#pragma unroll
+            for (int i = 0; i < NCB; ++i) av[i] = (float)sd[px * C + 16 * i + r];
+#pragma unroll
+            for (int i = 0; i < NCB; ++i)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
     }
+    // D of block (i, j): lane (r, q) holds co = 16 i + 4 q + e, col = 16 j + r
+    float *out = partial + ((size_t)blockIdx.x * 4 + w) * kFirstRows * C;
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int r = g + k * G;
-        if (r < kFirstRows)
+    for (int j = 0; j < NJ; ++j) {
+        const int col = 16 * j + r;
+        if (col < kFirstRows)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) partial[((size_t)blockIdx.x * kFirstRows + r) * C + 4 * c4 + e] = acc[k][e];
+            for (int i = 0; i < NCB; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) out[(size_t)col * C + 16 * i + 4 * q + e] = acc[i][j][e];
     }
-}
-
-// out[j] = sum over rows i of partial[i * ld + j] for j < ncols, one workgroup per column, in a
-// fixed tree order (deterministic)
-__global__ __launch_bounds__(256) void k_sum_rows(const float *__restrict__ partial, int nrows, int ld, int ncols,
-                                                  float *__restrict__ out)
-{
-    __shared__ float red[256];
-    const int j = blockIdx.x;
-    if (j >= ncols) return;
-    float a = 0;
-    for (int i = threadIdx.x; i < nrows; i += 256) a += partial[(size_t)i * ld + j];
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[j] = red[0];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -900,40 +901,65 @@ __global__ __launch_bounds__(kThreads) void k_conv_dw(const __bf16 *__restrict__
 // Weight gradient of a layer with 64 input channels, all 9 taps in one pass: partial[g][t][ci][co]
 // = sum over the pixels p of work unit g of X[p + d_t][ci] dZ[p][co].  A work unit is a run of
 // rows of one 32-column strip of one sample, walked row by row.  The pixels are the K dimension
-// of the MFMAs and must be the packed one of both operands, so the rows of X are kept in LDS
-// transposed (channel-major), in a ring of three rows (y - 1, y, y + 1) with three copies of each
-// shifted by dx = -1, 0, 1: every A fragment is then one aligned 16-byte read.  The row of dZ is
-// staged transposed as well.  Wave w owns input channels [16 w, 16 w + 16) and keeps the 9 taps x
-// COUT / 16 output blocks in registers; per row it reads its COUT / 16 B fragments once and one A
-// fragment per tap (9 x COUT / 16 MFMAs).  The global loads of a row are issued kDwAhead rows
-// before it is needed.  The unit's bias gradient (sum of dZ over its pixels) goes to
-// db_partial[g][co].
+// of the MFMAs while the activations are channel-packed (NHWC); the rows are staged in LDS as they
+// are (34 pixels of X from column sx - 1, 32 of dZ, 16-byte copies) and the operands are read
+// with the transposing LDS load ds_read_b64_tr_b16: within each 16 lanes, lane 4 i + a receives
+// element a of the 8-byte reads of lanes i, i + 4, i + 8, i + 12.  So lane S reads the four
+// channels 4 (S % 4) .. + 3 of pixel 8 (S / 16) + 4 h + (S % 16) / 4 for half h of the fragment,
+// and lane (r, q) ends with the pixels 8 q .. 8 q + 7 of channel r, the MFMA's K layout; a tap's
+// column shift dx is an offset of the pixel.  X rows are kept in a ring of four (row y reads
+// y - 1 .. y + 1 while y + 2 is written) and dZ rows in two buffers, so one barrier per row
+// suffices; each thread copies one or two 16-byte chunks per row, loaded kDwAhead rows ahead.
+// Wave w owns input channels [16 (w % 4), + 16) and the taps [5 (w / 4), min(9, 5 (w / 4) + 5)),
+// keeping those taps x COUT / 16 output blocks in registers.  The unit's bias gradient (sum of dZ
+// over its pixels) rides along with the dZ staging and goes to db_partial[g][co].
 
-constexpr int kDwStrip = 32;                 // strip width: one MFMA K step
-constexpr int kDwRS = kDwStrip + 8;          // LDS stride (bf16) of a transposed row
-constexpr int kDwThreads = 256;              // four waves: one per 16 input channels
-constexpr int kDwRowChunks = (kDwStrip + 2) * 8;  // 16-byte chunks of one X row (34 pixels x 64 channels)
-constexpr int kDwAhead = 4;                  // rows of global loads in flight
+constexpr int kDwStrip = 32;            // strip width: one MFMA K step
+constexpr int kDwXPix = kDwStrip + 2;   // staged X pixels per row
+constexpr int kDwPSX = 64 + 8;          // LDS pixel stride (bf16) of X
+constexpr int kDwThreads = 512;         // eight waves
+constexpr int kDwSlots = 4;             // X rows in the LDS ring
+constexpr int kDwAhead = 4;             // rows of global loads in flight
+constexpr int kDwXChunks = kDwXPix * 8;  // 16-byte chunks of one X row
 
 template <int COUT>
 struct DwLds {
-    static constexpr int ring_elems = 3 * 3 * 64 * kDwRS;  // [slot][dx + 1][ci][column]
-    static constexpr int z_elems = COUT * kDwRS;           // [co][column]
-    static constexpr size_t bytes = (size_t)(ring_elems + z_elems) * sizeof(__bf16);
+    static constexpr int PSZ = COUT + 8;                           // LDS pixel stride of dZ
+    static constexpr int x_elems = kDwSlots * kDwXPix * kDwPSX;    // [slot][pixel][ci]
+    static constexpr int z_elems = 2 * kDwStrip * PSZ;             // [buffer][pixel][co]
+    static constexpr size_t bytes = (size_t)(x_elems + z_elems) * sizeof(__bf16);
 };
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4i16 lds_v4i16;
+
+// one MFMA operand (K = 8 pixels x 16 channels) from a [pixel][channel] LDS block: the two halves
+// read with the transposing load at this lane's pixel offsets o0 (h = 0) and o0 + 4 PS (h = 1)
+__device__ __forceinline__ bf16x8 ld_tr(const __bf16 *p, int o0, int ps)
+{
+    const auto *base = (const __attribute__((address_space(3))) char *)(p);
+    const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16 *)(base + 2 * o0));
+    const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16 *)(base + 2 * (o0 + 4 * ps)));
+    typedef short v8i16 __attribute__((ext_vector_type(8)));
+    const v8i16 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(bf16x8, v);
+}
 
 template <int COUT>
 __global__ __launch_bounds__(kDwThreads) void k_conv_dw_strip(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dZ, int H,
                                                               int W, int seg, int units_per_strip, float *__restrict__ partial,
                                                               float *__restrict__ db_partial)
 {
-    constexpr int NJ = COUT / 16, NZ = kDwStrip * COUT / 8;  // output blocks, 16-byte chunks of a dZ row
-    static_assert(NZ <= kDwThreads && kDwRowChunks <= 2 * kDwThreads, "one or two chunks per thread");
-    __shared__ __align__(16) __bf16 ring[DwLds<COUT>::ring_elems];
-    __shared__ __align__(16) __bf16 zt[DwLds<COUT>::z_elems];
+    using L = DwLds<COUT>;
+    constexpr int NJ = COUT / 16, PSZ = L::PSZ;
+    constexpr int ZCH = COUT / 8, NZC = kDwStrip * ZCH;  // 16-byte chunks of a dZ pixel and row
+    constexpr int NCH = kDwXChunks + NZC;                // chunks of a row of both
+    static_assert(NCH <= 2 * kDwThreads, "one or two chunks per thread");
+    __bf16 *xs = lbcm_conv_lds, *zs = lbcm_conv_lds + L::x_elems;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = lane & 15, q = lane >> 4;
+    const int cg = w & 3;
     const int nstrips = (W + kDwStrip - 1) / kDwStrip;
     const int strip = blockIdx.x / units_per_strip, part = blockIdx.x % units_per_strip;
     const int n = strip / nstrips, sx = (strip % nstrips) * kDwStrip;
@@ -941,151 +967,217 @@ __global__ __launch_bounds__(kDwThreads) void k_conv_dw_strip(const __bf16 *__re
     const __bf16 *Xn = X + (size_t)n * H * W * 64;
     const __bf16 *Zn = dZ + (size_t)n * H * W * COUT;
 
-    // The loads carry no branches (clamped indices, zeros selected afterwards), so that the
-    // compiler can wait for exactly the row it stores while later rows stay in flight.
-    // One X row (34 pixels from column sx - 1, wrapped): chunk c = pixel c % 34, channels 8 (c / 34).
-    auto load_x = [&](int y, u32x4 (&xv)[2]) {
-        const int yy = wrap(y, H);
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int c = min((int)threadIdx.x + i * kDwThreads, kDwRowChunks - 1);
-            const int j = c % (kDwStrip + 2), g = c / (kDwStrip + 2);
-            xv[i] = *(const u32x4 *)(Xn + ((size_t)yy * W + wrap(sx - 1 + j, W)) * 64 + 8 * g);
+    // staging: thread t copies chunk t and, if t + kDwThreads < NCH, chunk t + kDwThreads; chunk c
+    // < kDwXChunks is X pixel c / 8 (column sx - 1 + c / 8, wrapped), channels 8 (c % 8) ..; the
+    // rest are dZ pixel c' / ZCH (column sx + c' / ZCH), channels 8 (c' % ZCH) .., c' = c - kDwXChunks
+    struct Chunk {
+        bool x, valid, inside;  // X or dZ; a chunk at all; dZ column inside the box
+        int gcol, ch, lds;      // global column, channel, LDS offset within a row (slot/buffer 0)
+    };
+    auto chunk = [&](int c) {
+        Chunk k;
+        k.valid = c < NCH;
+        c = min(c, NCH - 1);
+        k.x = c < kDwXChunks;
+        if (k.x) {
+            const int j = c / 8;
+            k.gcol = wrap(sx - 1 + j, W);
+            k.ch = 8 * (c % 8);
+            k.lds = j * kDwPSX + k.ch;
+            k.inside = true;
+        } else {
+            const int cz = c - kDwXChunks, j = cz / ZCH;
+            k.inside = sx + j < W;
+            k.gcol = min(sx + j, W - 1);
+            k.ch = 8 * (cz % ZCH);
+            k.lds = L::x_elems + j * PSZ + k.ch;
         }
+        return k;
     };
-    // copy dx + 1 = d holds X[y][sx + col + dx] at column col: pixel j goes to column j - d
-    auto store_x = [&](int slot, const u32x4 (&xv)[2]) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int c = threadIdx.x + i * kDwThreads;
-            if (c < kDwRowChunks) {
-                const int j = c % (kDwStrip + 2), g = c / (kDwStrip + 2);
-                const bf16x8 v = __builtin_bit_cast(bf16x8, xv[i]);
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const int col = j - d;
-                    if (col < 0 || col >= kDwStrip) continue;
-                    __bf16 *dst = ring + ((slot * 3 + d) * 64 + 8 * g) * kDwRS + col;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) dst[e * kDwRS] = v[e];
-                }
-            }
-        }
+    const Chunk c0 = chunk(threadIdx.x), c1 = chunk(threadIdx.x + kDwThreads);
+    constexpr bool TWO = NCH > kDwThreads;
+    // For the argument y an X chunk loads X row y + 1 and a dZ chunk dZ row y: what iteration
+    // y - 1 stores.  No branches around the loads (clamped indices), so that the compiler waits
+    // for exactly the row it stores while later rows stay in flight.
+    auto load1 = [&](const Chunk &k, int y) {
+        const __bf16 *src = k.x ? Xn + ((size_t)wrap(y + 1, H) * W + k.gcol) * 64 + k.ch
+                                : Zn + ((size_t)min(y, H - 1) * W + k.gcol) * COUT + k.ch;
+        return *(const u32x4 *)src;
     };
-    // one dZ row of the strip: chunk c = pixel c % 32, channels 8 (c / 32); stored as zero past
-    // the box and for rows at or past yb (the row loop runs to a multiple of kDwAhead)
-    auto load_z = [&](int y, u32x4 &zv) {
-        const int c = min((int)threadIdx.x, NZ - 1);
-        const int j = c % kDwStrip, g = c / kDwStrip;
-        zv = *(const u32x4 *)(Zn + ((size_t)min(y, H - 1) * W + min(sx + j, W - 1)) * COUT + 8 * g);
-    };
-    // the bias gradient rides along: thread c sums channels 8 (c / 32) .. + 7 of pixel c % 32 of
-    // every stored dZ row, in row order
+    auto slot_off = [&](int yx) { return ((yx - ya + 1) % kDwSlots) * kDwXPix * kDwPSX; };  // yx >= ya - 1
+    auto buf_off = [&](int yz) { return ((yz - ya) & 1) * kDwStrip * PSZ; };
+    // the bias gradient: a dZ chunk's thread sums its eight channels of its pixel over the stored
+    // rows, in row order
     float bsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    auto store_z = [&](int y, const u32x4 &zv) {
-        const int c = threadIdx.x;
-        if (c < NZ) {
-            const int j = c % kDwStrip, g = c / kDwStrip;
-            const bf16x8 v = __builtin_bit_cast(bf16x8, (sx + j < W && y < yb) ? zv : u32x4{0, 0, 0, 0});
+    auto store1 = [&](const Chunk &k, int yx, int yz, const u32x4 &v) {
+        const bool zero = !k.x && !(k.inside && yz < yb);
+        const u32x4 s = zero ? u32x4{0, 0, 0, 0} : v;
+        if (k.valid) *(u32x4 *)(lbcm_conv_lds + k.lds + (k.x ? slot_off(yx) : buf_off(yz))) = s;
+        if (!k.x && k.valid) {
+            const bf16x8 b = __builtin_bit_cast(bf16x8, s);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                zt[(8 * g + e) * kDwRS + j] = v[e];
-                bsum[e] += (float)v[e];
-            }
+            for (int e = 0; e < 8; ++e) bsum[e] += (float)b[e];
         }
     };
-    auto slot_of = [&](int y) { return (y - ya + 1) % 3; };  // y >= ya - 1
+    struct Row {
+        u32x4 v0, v1;
+    };
+    auto load = [&](int y, Row &f) {
+        f.v0 = load1(c0, y);
+        if (TWO) f.v1 = load1(c1, y);
+    };
+    auto store = [&](int yx, int yz, const Row &f) {
+        store1(c0, yx, yz, f.v0);
+        if (TWO) store1(c1, yx, yz, f.v1);
+    };
 
-    f32x4 acc[9][NJ];
-#pragma unroll
-    for (int t = 0; t < 9; ++t)
-#pragma unroll
-        for (int jn = 0; jn < NJ; ++jn) acc[t][jn] = f32x4{0, 0, 0, 0};
-    // FIFO slot u holds the loads of the rows that iteration y stores when y = ya + u (mod
-    // kDwAhead): X row y + 2 and dZ row y + 1, requested kDwAhead iterations earlier (one row of
-    // MFMAs is much shorter than a global load)
-    u32x4 fx[kDwAhead][2], fz[kDwAhead];
+    // this lane's operand offsets (pixel offset of half 0 times the stride, plus the channel)
+    const int opix = 8 * (lane >> 4) + ((lane & 15) >> 2), och = 4 * (lane & 3);
+    Row fifo[kDwAhead];
     {
-        u32x4 xv[2], zv;
-        for (int y = ya - 1; y <= ya + 1; ++y) {
-            load_x(y, xv);
-            store_x(slot_of(y), xv);
+        // X rows ya - 1 .. ya + 1 and dZ row ya before the loop (the dZ row stored once)
+        Row f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            f.v0 = load1(c0, c0.x ? ya - 2 + k : ya);
+            if (TWO) f.v1 = load1(c1, c1.x ? ya - 2 + k : ya);
+            if (c0.x || k == 0) store1(c0, ya - 1 + k, ya, f.v0);
+            if (TWO && (c1.x || k == 0)) store1(c1, ya - 1 + k, ya, f.v1);
         }
-        load_z(ya, zv);
-        store_z(ya, zv);
     }
 #pragma unroll
-    for (int u = 0; u < kDwAhead; ++u) {
-        load_x(ya + u + 2, fx[u]);
-        load_z(ya + u + 1, fz[u]);
-    }
+    for (int u = 0; u < kDwAhead; ++u) load(ya + u + 1, fifo[u]);
     lds_barrier();
     const int yend = ya + (yb - ya + kDwAhead - 1) / kDwAhead * kDwAhead;  // rows past yb add zero
-    for (int y0 = ya; y0 < yend; y0 += kDwAhead) {
+    // the row loop and the output of taps [T0, T0 + NT), compile-time constants of each half of
+    // the waves
+    auto rows = [&](auto t0c, auto ntc) {
+        constexpr int T0 = decltype(t0c)::value, NT = decltype(ntc)::value;
+        f32x4 acc[NT][NJ];
 #pragma unroll
-        for (int u = 0; u < kDwAhead; ++u) {
-            const int y = y0 + u;
-            bf16x8 b[NJ];
+        for (int i = 0; i < NT; ++i)
 #pragma unroll
-            for (int jn = 0; jn < NJ; ++jn) b[jn] = ld8(zt + (16 * jn + r) * kDwRS + 8 * q);
+            for (int jn = 0; jn < NJ; ++jn) acc[i][jn] = f32x4{0, 0, 0, 0};
+        for (int y0 = ya; y0 < yend; y0 += kDwAhead) {
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int slot = slot_of(y + t / 3 - 1), d = t % 3;
-                const bf16x8 a = ld8(ring + ((slot * 3 + d) * 64 + 16 * w + r) * kDwRS + 8 * q);
+            for (int u = 0; u < kDwAhead; ++u) {
+                const int y = y0 + u;
+                bf16x8 b[NJ], a[NT];
 #pragma unroll
-                for (int jn = 0; jn < NJ; ++jn) acc[t][jn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[jn], acc[t][jn], 0, 0, 0);
+                for (int jn = 0; jn < NJ; ++jn) b[jn] = ld_tr(zs + buf_off(y), opix * PSZ + 16 * jn + och, PSZ);
+#pragma unroll
+                for (int i = 0; i < NT; ++i) {
+                    const int t = T0 + i;
+                    a[i] = ld_tr(xs + slot_off(y + t / 3 - 1), (opix + t % 3) * kDwPSX + 16 * cg + och, kDwPSX);
+                }
+#pragma unroll
+                for (int i = 0; i < NT; ++i)
+#pragma unroll
+                    for (int jn = 0; jn < NJ; ++jn)
+                        acc[i][jn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[jn], acc[i][jn], 0, 0, 0);
+                store(y + 2, y + 1, fifo[u]);
+                load(y + kDwAhead + 1, fifo[u]);
+                lds_barrier();
             }
-            lds_barrier();  // every wave is done with row y - 1 and the dZ row
-            store_x(slot_of(y + 2), fx[u]);
-            store_z(y + 1, fz[u]);
-            load_x(y + kDwAhead + 2, fx[u]);
-            load_z(y + kDwAhead + 1, fz[u]);
-            lds_barrier();
         }
-    }
-    // bias partial of this unit: the 32 pixel lanes of a channel group (one half of a wave) in a
-    // fixed butterfly
+        // D of block (t, jn): lane (r, q) holds ci = 16 cg + 4 q + e, co = 16 jn + r
+        float *out = partial + (size_t)blockIdx.x * 9 * 64 * COUT;
 #pragma unroll
-    for (int m = 16; m >= 1; m >>= 1)
+        for (int i = 0; i < NT; ++i)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bsum[e] += __shfl_xor(bsum[e], m, 64);
-    if ((int)threadIdx.x < NZ && threadIdx.x % kDwStrip == 0) {
+            for (int jn = 0; jn < NJ; ++jn)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) db_partial[(size_t)blockIdx.x * 64 + 8 * (threadIdx.x / kDwStrip) + e] = bsum[e];
-    }
-    // D of block (t, jn): lane (r, q) holds ci = 16 w + 4 q + e, co = 16 jn + r
-    float *out = partial + (size_t)blockIdx.x * 9 * 64 * COUT;
+                for (int e = 0; e < 4; ++e)
+                    out[((size_t)(T0 + i) * 64 + 16 * cg + 4 * q + e) * COUT + 16 * jn + r] = acc[i][jn][e];
+    };
+    if (w < 4)
+        rows(std::integral_constant<int, 0>{}, std::integral_constant<int, 5>{});
+    else
+        rows(std::integral_constant<int, 5>{}, std::integral_constant<int, 4>{});
+    // bias partial of this unit: each dZ chunk thread's sums to LDS (the dZ buffers are free after
+    // the last barrier), then thread co adds the 32 pixels' sums of channel co in pixel order
+    float *red = (float *)(lbcm_conv_lds + L::x_elems);  // [pixel][COUT]
+    static_assert(kDwStrip * COUT * sizeof(float) <= L::z_elems * sizeof(__bf16), "bias sums fit the dZ buffers");
+    auto put = [&](const Chunk &k, int c) {
+        if (!k.x && k.valid) {
+            const int cz = c - kDwXChunks;
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
-#pragma unroll
-        for (int jn = 0; jn < NJ; ++jn)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) out[((size_t)t * 64 + 16 * w + 4 * q + e) * COUT + 16 * jn + r] = acc[t][jn][e];
-}
-
-// sum of the per-chunk partials in chunk order (deterministic), into the real-size gradient
-// dW[t][ci][co] (ci < cin_r, co < cout_r) of the padded partials
-__global__ __launch_bounds__(256) void k_dw_reduce(const float *__restrict__ partial, int nchunks, int cin, int cout, int cin_r,
-                                                   int cout_r, float *__restrict__ dW)
-{
-    // 64 outputs per block; wave p sums the chunks p, p + 4, ... and the four sums are added in
-    // a fixed order
-    __shared__ float red[4][64];
-    const int n = 9 * cin_r * cout_r, l = threadIdx.x & 63, part = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + l;
-    float s = 0;
-    if (i < n) {
-        const int t = i / (cin_r * cout_r), rem = i % (cin_r * cout_r), ci = rem / cout_r, co = rem % cout_r;
-        const float *src = partial + ((size_t)t * cin + ci) * cout + co;
-        const size_t stride = (size_t)9 * cin * cout;
-        for (int c = part; c < nchunks; c += 4) s += src[c * stride];
-    }
-    red[part][l] = s;
+            for (int e = 0; e < 8; ++e) red[(cz / ZCH) * COUT + k.ch + e] = bsum[e];
+        }
+    };
+    put(c0, threadIdx.x);
+    if (TWO && threadIdx.x + kDwThreads < NCH) put(c1, threadIdx.x + kDwThreads);
     __syncthreads();
-    if (part == 0 && i < n) dW[i] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
+    if ((int)threadIdx.x < COUT) {
+        float sb = 0;
+        for (int j = 0; j < kDwStrip; ++j) sb += red[j * COUT + threadIdx.x];
+        db_partial[(size_t)blockIdx.x * 64 + threadIdx.x] = sb;
+    }
 }
 
-// bias gradient db[co] = sum_p dZ[p][co]: per-block partial sums (then k_sum_rows)
+// Gradient sums of one layer in one launch, each in a fixed order (two runs give bitwise equal
+// gradients):
+//   dW[t][ci][co] = sum_c wp[c][t][ci][co] over the nw_rows per-unit partials (padded cin x cout,
+//                   written at the real size cin_r x cout_r), in the first ceil(9 cin_r cout_r / 64)
+//                   workgroups;
+//   db[j] = sum_i bp[i ld_b + j] (j < ncols_b), in the workgroups after them.
+// A workgroup owns 64 outputs, one per lane; wave v of its kSumWaves sums the rows v, v + kSumWaves,
+// ... in row order with four loads in flight, and the wave sums are then added in a fixed tree.
+constexpr int kSumWaves = 16;
+__global__ __launch_bounds__(kSumWaves * 64) void k_grad_reduce(const float *__restrict__ wp, int nw_rows, int cin, int cout,
+                                                                int cin_r, int cout_r, float *__restrict__ dW,
+                                                                const float *__restrict__ bp, int nb_rows, int ld_b, int ncols_b,
+                                                                float *__restrict__ db)
+{
+    __shared__ float red[kSumWaves][64];
+    const int l = threadIdx.x & 63, v = threadIdx.x >> 6;
+    const int nw = 9 * cin_r * cout_r, wblocks = (nw + 63) / 64;
+    const float *src;
+    size_t ld;
+    int rows, j;
+    bool ok;
+    float *dst;
+    if ((int)blockIdx.x < wblocks) {
+        j = blockIdx.x * 64 + l;
+        ok = j < nw;
+        const int jj = ok ? j : 0;
+        const int t = jj / (cin_r * cout_r), rem = jj % (cin_r * cout_r), ci = rem / cout_r, co = rem % cout_r;
+        src = wp + ((size_t)t * cin + ci) * cout + co;
+        ld = (size_t)9 * cin * cout;
+        rows = nw_rows;
+        dst = dW;
+    } else {
+        j = (blockIdx.x - wblocks) * 64 + l;
+        ok = j < ncols_b;
+        src = bp + (ok ? j : 0);
+        ld = (size_t)ld_b;
+        rows = nb_rows;
+        dst = db;
+    }
+    float sum = 0;
+    if (ok) {
+        int i = v;
+        for (; i + 3 * kSumWaves < rows; i += 4 * kSumWaves) {
+            const float a0 = src[(size_t)i * ld], a1 = src[(size_t)(i + kSumWaves) * ld];
+            const float a2 = src[(size_t)(i + 2 * kSumWaves) * ld], a3 = src[(size_t)(i + 3 * kSumWaves) * ld];
+            sum += a0;
+            sum += a1;
+            sum += a2;
+            sum += a3;
+        }
+        for (; i < rows; i += kSumWaves) sum += src[(size_t)i * ld];
+    }
+    red[v][l] = sum;
+    __syncthreads();
+#pragma unroll
+    for (int k = kSumWaves / 2; k > 0; k >>= 1) {
+        if (v < k) red[v][l] += red[v + k][l];
+        __syncthreads();
+    }
+    if (v == 0 && ok) dst[j] = red[0][l];
+}
+
+// bias gradient db[co] = sum_p dZ[p][co]: per-block partial sums (then k_grad_reduce)
 __global__ __launch_bounds__(256) void k_db_partial(const __bf16 *__restrict__ dZ, int cout, uint32_t P,
                                                     float *__restrict__ partial)
 {
@@ -1346,6 +1438,19 @@ int launch_pair_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wa, const float *b
     return LBCM_OK;
 }
 
+template <int COUT>
+int launch_dw_strip(lbcm_net *n, const __bf16 *X, const __bf16 *dz)
+{
+    constexpr size_t bytes = DwLds<COUT>::bytes;
+    static bool done[kMaxDevices] = {};
+    int rc = allow_dynamic_lds(n, reinterpret_cast<const void *>(&k_conv_dw_strip<COUT>), bytes, done);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_conv_dw_strip<COUT>, dim3(n->dw_units), dim3(kDwThreads), bytes, n->stream, X, dz, n->H, n->W, n->dw_seg,
+                       n->dw_units_per_strip, n->dw_partial, n->db_partial);
+    NHIP(n, hipGetLastError());
+    return LBCM_OK;
+}
+
 int launch_first_pair(lbcm_net *n, const PlaneIO *io, const OutArgs &o)
 {
     constexpr size_t bytes = (size_t)(PairLds::z_elems + PairLds::w_elems) * sizeof(__bf16);
@@ -1544,7 +1649,7 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
     if (!dmalloc((void **)&n->dw_partial, npartials * 9 * 64 * 64 * sizeof(float))) return bail("out of device memory (dW)");
     if (!dmalloc((void **)&n->db_partial, std::max<size_t>((P + 1023) / 1024, (size_t)n->dw_units) * 64 * sizeof(float)))
         return bail("out of device memory (db)");
-    if (!dmalloc((void **)&n->first_partial, ntiles * kFirstRows * channels * sizeof(float)))
+    if (!dmalloc((void **)&n->first_partial, 4 * std::min<size_t>(ntiles, kFirstDwBlocks) * kFirstRows * channels * sizeof(float)))
         return bail("out of device memory (first layer)");
     n->loss_blocks = grid_of(P, 256) > 1024 ? 1024 : grid_of(P, 256);
     if (!dmalloc((void **)&n->loss_partial, n->loss_blocks * sizeof(float))) return bail("out of device memory (loss)");
@@ -1655,19 +1760,12 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
         const bool strip = n->cin[l] == 64 && (n->cout[l] == 64 || n->cout[l] == 32);
         if (strip) {
             parts = n->dw_units;
-            if (n->cout[l] == 64)
-                hipLaunchKernelGGL(k_conv_dw_strip<64>, dim3(parts), dim3(kDwThreads), 0, n->stream, n->act[l], dz, n->H, n->W,
-                                   n->dw_seg, n->dw_units_per_strip, n->dw_partial, n->db_partial);
-            else
-                hipLaunchKernelGGL(k_conv_dw_strip<32>, dim3(parts), dim3(kDwThreads), 0, n->stream, n->act[l], dz, n->H, n->W,
-                                   n->dw_seg, n->dw_units_per_strip, n->dw_partial, n->db_partial);
+            const int rc = n->cout[l] == 64 ? launch_dw_strip<64>(n, n->act[l], dz) : launch_dw_strip<32>(n, n->act[l], dz);
+            if (rc) return rc;
         } else {
             hipLaunchKernelGGL(k_conv_dw, dim3(nchunks, 9), dim3(kThreads), 0, n->stream, n->act[l], n->cin[l], dz, n->cout[l], P,
                                n->H, n->W, n->dw_partial);
         }
-        NHIP(n, hipGetLastError());
-        hipLaunchKernelGGL(k_dw_reduce, dim3((9 * n->cin_r[l] * n->cout_r[l] + 63) / 64), dim3(256), 0, n->stream, n->dw_partial,
-                           parts, n->cin[l], n->cout[l], n->cin_r[l], n->cout_r[l], n->grads + n->w_off[l]);
         NHIP(n, hipGetLastError());
         int db_rows = parts;  // the strip kernel left one bias partial per work unit
         if (!strip) {
@@ -1675,8 +1773,10 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
             NHIP(n, hipGetLastError());
             db_rows = dbb;
         }
-        hipLaunchKernelGGL(k_sum_rows, dim3(n->cout[l]), dim3(256), 0, n->stream, n->db_partial, db_rows, 64, n->cout[l],
-                           n->grads + n->b_off[l]);
+        const int wblocks = (9 * n->cin_r[l] * n->cout_r[l] + 63) / 64, bblocks = (n->cout[l] + 63) / 64;
+        hipLaunchKernelGGL(k_grad_reduce, dim3(wblocks + bblocks), dim3(kSumWaves * 64), 0, n->stream, n->dw_partial, parts,
+                           n->cin[l], n->cout[l], n->cin_r[l], n->cout_r[l], n->grads + n->w_off[l], n->db_partial, db_rows, 64,
+                           n->cout[l], n->grads + n->b_off[l]);
         NHIP(n, hipGetLastError());
         // gradient of the layer input times the ReLU derivative of that input (act[l] > 0)
         OutArgs o{};
@@ -1686,16 +1786,17 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
         if (rc) return rc;
         std::swap(dz, dn);
     }
-    // layer 0 gradients on the vector ALU, per tile: its 36 x C weights and C biases are contiguous in the vector
+    // layer 0 gradients (its 36 x C weights and C biases are contiguous in the vector)
+    const int fblocks = std::min(n->ntiles, kFirstDwBlocks);
     if (n->C == 64)
-        hipLaunchKernelGGL(k_first_dw<64>, dim3(n->ntiles), dim3(kThreads), 0, n->stream, n->resid, dz, n->H, n->W,
+        hipLaunchKernelGGL(k_first_dw<64>, dim3(fblocks), dim3(kThreads), 0, n->stream, n->resid, dz, n->H, n->W, n->ntiles,
                            n->first_partial);
     else
-        hipLaunchKernelGGL(k_first_dw<32>, dim3(n->ntiles), dim3(kThreads), 0, n->stream, n->resid, dz, n->H, n->W,
+        hipLaunchKernelGGL(k_first_dw<32>, dim3(fblocks), dim3(kThreads), 0, n->stream, n->resid, dz, n->H, n->W, n->ntiles,
                            n->first_partial);
     NHIP(n, hipGetLastError());
-    hipLaunchKernelGGL(k_sum_rows, dim3(kFirstRows * n->C), dim3(256), 0, n->stream, n->first_partial, n->ntiles,
-                       kFirstRows * n->C, kFirstRows * n->C, n->grads + n->w_off[0]);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((kFirstRows * n->C + 63) / 64), dim3(kSumWaves * 64), 0, n->stream, nullptr, 0, 0, 0, 0,
+                       0, nullptr, n->first_partial, 4 * fblocks, kFirstRows * n->C, kFirstRows * n->C, n->grads + n->w_off[0]);
     NHIP(n, hipGetLastError());
     if (loss) {
         std::vector<float> part(n->loss_blocks);
