@@ -263,18 +263,26 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
         for (int i = 0; i < NIZ; ++i) *(u32x4 *)(sd + (threadIdx.x + i * kThreads) * 8) = vz[i];
         __syncthreads();
         if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
-        for (int k = w; k < kTileH * kTileW / 4; k += 4) {
+        // the operands of K step k (LDS reads), one step ahead of the MFMAs that use them
+        constexpr int NK = kTileH * kTileW / 16;  // K steps of this wave per tile
+        float bv[2][NJ], av[2][NCB];
+        auto operands = [&](int k, float (&b)[NJ], float (&a)[NCB]) {
             const int px = 4 * k + q;
             const int base = ((px / kTileW) * kPatchW + px % kTileW) * kStateC;
-            float bv[NJ], av[NCB];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) bv[j] = fmaf(sp[base + boff[j]], bm[j], ba[j]);  // exact: x, 1 or 0
+            for (int j = 0; j < NJ; ++j) b[j] = fmaf(sp[base + boff[j]], bm[j], ba[j]);  // exact: x, 1 or 0
 #pragma unroll
-            for (int i = 0; i < NCB; ++i) av[i] = (float)sd[px * C + 16 * i + r];
+            for (int i = 0; i < NCB; ++i) a[i] = (float)sd[px * C + 16 * i + r];
+        };
+        operands(w, bv[0], av[0]);
+#pragma unroll
+        for (int it = 0; it < NK; ++it) {
+            if (it + 1 < NK) operands(w + 4 * (it + 1), bv[(it + 1) & 1], av[(it + 1) & 1]);
 #pragma unroll
             for (int i = 0; i < NCB; ++i)
 #pragma unroll
-                for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < NJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[it & 1][i], bv[it & 1][j], acc[i][j], 0, 0, 0);
         }
     }
     // D of block (i, j): lane (r, q) holds co = 16 i + 4 q + e, col = 16 j + r
@@ -1199,7 +1207,7 @@ __global__ __launch_bounds__(256) void k_db_partial(const __bf16 *__restrict__ d
 // ------------------------------------------------------------------------------------------
 // loss: mean over pixels and the kStateC state channels of ((pred - target) / alpha_c)^2; the
 // gradient of the last layer's pre-scale output is 2 (pred - target) / (alpha_c kStateC P), stored
-// padded to kOutC channels.
+// in the first kStateC of kOutC channels of a buffer whose other channels are zero (cleared once).
 __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ pred, const float *__restrict__ target, uint32_t P,
                                               float ia0, float ia1, float ia2, float ia3, __bf16 *__restrict__ dZ,
                                               float *__restrict__ partial)
@@ -1209,17 +1217,15 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ pred, co
     const float ia[kStateC] = {ia0, ia1, ia2, ia3};
     float s = 0;
     for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < P; p += gridDim.x * 256u) {
-        bf16x8 g[kOutC / 8];
-#pragma unroll
-        for (int c = 0; c < kOutC; ++c) g[c / 8][c % 8] = (__bf16)0.f;
+        const f32x4 a = *(const f32x4 *)(pred + (size_t)p * kStateC), b = *(const f32x4 *)(target + (size_t)p * kStateC);
+        bf16x4 g;
 #pragma unroll
         for (int c = 0; c < kStateC; ++c) {
-            const float d = (pred[(size_t)p * kStateC + c] - target[(size_t)p * kStateC + c]) * ia[c];
+            const float d = (a[c] - b[c]) * ia[c];
             s += d * d;
-            g[0][c] = (__bf16)(scale * d);
+            g[c] = (__bf16)(scale * d);
         }
-#pragma unroll
-        for (int k = 0; k < kOutC / 8; ++k) *(u32x4 *)(dZ + (size_t)p * kOutC + 8 * k) = __builtin_bit_cast(u32x4, g[k]);
+        *(u32x2 *)(dZ + (size_t)p * kOutC) = __builtin_bit_cast(u32x2, g);  // channels kStateC .. kOutC - 1 stay zero
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -1232,6 +1238,13 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ pred, co
 
 // ------------------------------------------------------------------------------------------
 // packing and optimiser
+
+// where the weights of one layer >= 1 sit in the parameter vector and in its two packs
+struct PackEntry {
+    int64_t w_off;                 // first weight W[0][0][0] in the parameter vector
+    int nw, cin_r, cout_r, cin, cout;  // 9 cin_r cout_r weights; real and padded channel counts
+    __bf16 *Wf, *Wb;
+};
 
 // master W[t][ci][co] (ci < cin_r, co < cout_r) -> Wf[t][co][ci] and Wb[t'][ci][co] = W[8 - t'][ci][co]
 // in BF16, padded to (cin, cout) with zeros
@@ -1253,8 +1266,11 @@ __global__ void k_pack(const float *__restrict__ Wm, int cin_r, int cout_r, int 
     }
 }
 
+// Adam on the FP32 masters; with a pack table (packs already made, their zero padding in place)
+// each updated weight of layers 1 .. L-1 is also written to its two BF16 packs, as k_pack would.
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
-                       size_t n, float lr, float b1, float b2, float eps, float c1, float c2)
+                       size_t n, float lr, float b1, float b2, float eps, float c1, float c2, const PackEntry *__restrict__ tab,
+                       int ntab)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const float gi = g[i];
@@ -1262,7 +1278,17 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
         const float vi = b2 * v[i] + (1 - b2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        for (int k = 0; k < ntab; ++k) {
+            const PackEntry e = tab[k];
+            const int64_t j = (int64_t)i - e.w_off;
+            if (j < 0 || j >= e.nw) continue;
+            const int t = (int)(j / (e.cin_r * e.cout_r)), rem = (int)(j % (e.cin_r * e.cout_r));
+            const int ci = rem / e.cout_r, co = rem % e.cout_r;
+            e.Wf[((size_t)t * e.cout + co) * e.cin + ci] = (__bf16)pi;
+            e.Wb[((size_t)(8 - t) * e.cin + ci) * e.cout + co] = (__bf16)pi;
+        }
     }
 }
 
@@ -1358,6 +1384,8 @@ struct lbcm_net {
     std::vector<__bf16 *> Wf, Wb;               // BF16 packs of layers 1 .. L-1
     std::vector<__bf16 *> act;                  // act[l] = input of layer l >= 1 (relu output of layer l - 1)
     __bf16 *dz_a = nullptr, *dz_b = nullptr;    // gradient ping-pong buffers (P x 64)
+    __bf16 *dz_last = nullptr;                  // gradient of the last layer's output (P x kOutC, padding zero)
+    PackEntry *pack_table = nullptr;            // where the Adam update writes the BF16 packs of layers 1 .. L-1
     int32_t *gather_idx = nullptr;              // frame indices of lbcm_net_gather_states (batch)
     float *resid = nullptr, *out = nullptr;     // FP32 [P][kStateC]: input state, output state
     float *dw_partial = nullptr, *db_partial = nullptr, *loss_partial = nullptr, *first_partial = nullptr;
@@ -1632,8 +1660,21 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
     n->act.assign(layers, nullptr);
     for (int l = 1; l < layers; ++l)
         if (!dmalloc((void **)&n->act[l], P * channels * sizeof(__bf16))) return bail("out of device memory (activations)");
-    if (!dmalloc((void **)&n->dz_a, P * 64 * sizeof(__bf16)) || !dmalloc((void **)&n->dz_b, P * 64 * sizeof(__bf16)))
+    if (!dmalloc((void **)&n->dz_a, P * 64 * sizeof(__bf16)) || !dmalloc((void **)&n->dz_b, P * 64 * sizeof(__bf16)) ||
+        !dmalloc((void **)&n->dz_last, P * kOutC * sizeof(__bf16)))
         return bail("out of device memory (gradients)");
+    if (hipMemsetAsync(n->dz_last, 0, P * kOutC * sizeof(__bf16), n->stream) != hipSuccess) return bail("hipMemsetAsync failed");
+    {
+        std::vector<PackEntry> tab;
+        for (int l = 1; l < layers; ++l)
+            tab.push_back({(int64_t)n->w_off[l], 9 * n->cin_r[l] * n->cout_r[l], n->cin_r[l], n->cout_r[l], n->cin[l], n->cout[l],
+                           n->Wf[l], n->Wb[l]});
+        if (!dmalloc((void **)&n->pack_table, tab.size() * sizeof(PackEntry))) return bail("out of device memory (pack table)");
+        if (hipMemcpyAsync(n->pack_table, tab.data(), tab.size() * sizeof(PackEntry), hipMemcpyHostToDevice, n->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(n->stream) != hipSuccess)
+            return bail("pack table copy failed");
+    }
     if (!dmalloc((void **)&n->resid, P * kStateC * sizeof(float)) || !dmalloc((void **)&n->out, P * kStateC * sizeof(float)) ||
         !dmalloc((void **)&n->gather_idx, (size_t)batch * sizeof(int32_t)))
         return bail("out of device memory (state)");
@@ -1749,9 +1790,9 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
     const uint32_t P = n->P;
     const int L = n->L;
     hipLaunchKernelGGL(k_loss, dim3(n->loss_blocks), dim3(256), 0, n->stream, n->out, target, P, 1.f / n->alpha[0],
-                       1.f / n->alpha[1], 1.f / n->alpha[2], 1.f / n->alpha[3], n->dz_a, n->loss_partial);
+                       1.f / n->alpha[1], 1.f / n->alpha[2], 1.f / n->alpha[3], n->dz_last, n->loss_partial);
     NHIP(n, hipGetLastError());
-    __bf16 *dz = n->dz_a, *dn = n->dz_b;
+    __bf16 *dz = n->dz_last, *dn = n->dz_a;
     const int nchunks = (int)((P + kDwChunk - 1) / kDwChunk);
     const int dbb = (int)((P + 1023) / 1024);
     for (int l = L - 1; l >= 1; --l) {
@@ -1784,7 +1825,9 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
         o.Y = dn;
         int rc = launch_conv(n, dz, n->cout[l], n->Wb[l], n->cin[l], 2, o);
         if (rc) return rc;
-        std::swap(dz, dn);
+        __bf16 *spare = dz == n->dz_last ? n->dz_b : dz;  // the next layer's input gradient goes to a 64-channel buffer
+        dz = dn;
+        dn = spare;
     }
     // layer 0 gradients (its 36 x C weights and C biases are contiguous in the vector)
     const int fblocks = std::min(n->ntiles, kFirstDwBlocks);
@@ -1813,10 +1856,11 @@ int lbcm_net_adam(lbcm_net *n, float lr, float beta1, float beta2, float eps, in
 {
     if (!n || t < 1) return LBCM_EINVAL;
     const float c1 = 1.f - std::pow(beta1, (float)t), c2 = 1.f - std::pow(beta2, (float)t);
+    // packs already made: update them in the same pass; otherwise the next forward makes them
+    const int ntab = n->packed ? n->L - 1 : 0;
     hipLaunchKernelGGL(k_adam, dim3(grid_of(n->nparams, 256)), dim3(256), 0, n->stream, n->params, n->grads, n->adam_m, n->adam_v,
-                       n->nparams, lr, beta1, beta2, eps, c1, c2);
+                       n->nparams, lr, beta1, beta2, eps, c1, c2, n->pack_table, ntab);
     NHIP(n, hipGetLastError());
-    n->packed = false;
     return LBCM_OK;
 }
 
@@ -1835,6 +1879,8 @@ int lbcm_net_destroy(lbcm_net *n)
     for (auto p : n->act) f(p);
     f(n->dz_a);
     f(n->dz_b);
+    f(n->dz_last);
+    f(n->pack_table);
     f(n->resid);
     f(n->out);
     f(n->gather_idx);

@@ -318,6 +318,32 @@ def test_training_steps_follow_the_oracle():
         losses.append(loss)
 
 
+@pytest.mark.parametrize("C,L", [(64, 6), (32, 3)])
+def test_adam_updates_the_packs_as_a_fresh_pack(C, L):
+    """Adam writes the updated weights into the BF16 packs in the same pass once they exist; the
+    next forward must equal a forward from packs made anew from the same parameters, bit for bit."""
+    import torch
+
+    _note(f"adam packs C={C} L={L}")
+    B, H, W = 2, 16, 40
+    m = net.Surrogate(B, H, W, channels=C, layers=L)
+    m.set_params(_params(C, L, seed=91))
+    m.set_output_scale(ALPHA)
+    s = torch.from_numpy(_state(B, H, W, seed=92)).cuda()
+    tgt = torch.from_numpy(_state(B, H, W, seed=93)).cuda()
+    for _ in range(3):  # the first forward makes the packs; the later updates go through them
+        m.forward(s)
+        m.backward(tgt, want_loss=False)
+        m.adam(1e-2, 0.9, 0.999, 1e-8)
+    out = torch.empty(B, H, W, S, dtype=torch.float32, device="cuda")
+    m.forward(s, out)
+    a = out.cpu().numpy().copy()
+    m.set_params(m.params())  # packs made again on the next forward
+    m.forward(s, out)
+    assert np.array_equal(a, out.cpu().numpy())
+    m.close()
+
+
 def test_adam_matches_oracle():
     import torch
 
