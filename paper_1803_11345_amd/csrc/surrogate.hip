@@ -46,6 +46,19 @@ typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(2 * sizeof(unsigned int)))) unsigned int u32x2;
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, not for its
+// global loads or stores, so loads issued before it (weights or patches prefetched into registers)
+// and earlier output stores stay in flight across it.  (__syncthreads also waits for every
+// outstanding global load and store.)
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// raw buffer resource over [p, p + bytes) (gfx9-family word 3); accesses past its end are dropped
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
 constexpr int kStateC = 4;        // phi, v_x, v_y, rho (channel order of the state)
 constexpr int kFirstRows = 9 * kStateC + 1;  // layer-0 weight rows (tap, channel) and the bias row
 constexpr int kOutC = 32;         // padded output channels of the last layer (a K step of its input gradient)
@@ -336,25 +349,35 @@ struct Patch {
     static constexpr int NV = kPatchH * kPatchW * (CIN / 8), NI = (NV + kConvThreads - 1) / kConvThreads;
     u32x4 v[NI];
 
+    // Branch-free (every thread issues NI loads, the last chunk repeated past NV), so that a wait
+    // for these registers counts exactly the memory operations issued after them.  With WIDE (box
+    // of at least 8 rows and 32 columns) the circular halo indices stay in [-n, 2n) and wrap with
+    // selects; otherwise wrap_near.
+    template <bool WIDE>
     __device__ __forceinline__ void load(const __bf16 *__restrict__ X, TileCoord tc, int H, int W)
     {
         const __bf16 *Xn = X + (size_t)tc.n * H * W * CIN;
+        auto wrap1 = [](int v, int n) {
+            if (!WIDE) return wrap_near(v, n);
+            const int a = v < 0 ? v + n : v;
+            return a >= n ? a - n : a;
+        };
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
-            const int k = threadIdx.x + i * kConvThreads;
-            if (k < NV) {
-                const int px = k / (CIN / 8), ch = (k % (CIN / 8)) * 8;
-                const int gy = wrap_near(tc.y0 - 1 + px / kPatchW, H), gx = wrap_near(tc.x0 - 1 + px % kPatchW, W);
-                v[i] = *(const u32x4 *)(Xn + ((size_t)gy * W + gx) * CIN + ch);
-            }
+            const int k = min((int)threadIdx.x + i * kConvThreads, NV - 1);
+            const int px = k / (CIN / 8), ch = (k % (CIN / 8)) * 8;
+            const int gy = wrap1(tc.y0 - 1 + px / kPatchW, H), gx = wrap1(tc.x0 - 1 + px % kPatchW, W);
+            v[i] = *(const u32x4 *)(Xn + ((size_t)gy * W + gx) * CIN + ch);
         }
     }
+    // also branch-free: a thread past NV stores the last chunk again (the same value to the same
+    // place), so that no load is sunk into a conditional block and waited for there
     __device__ __forceinline__ void store(__bf16 *patch) const
     {
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
-            const int k = threadIdx.x + i * kConvThreads;
-            if (k < NV) *(u32x4 *)(patch + (k / (CIN / 8)) * PS + (k % (CIN / 8)) * 8) = v[i];
+            const int k = min((int)threadIdx.x + i * kConvThreads, NV - 1);
+            *(u32x4 *)(patch + (k / (CIN / 8)) * PS + (k % (CIN / 8)) * 8) = v[i];
         }
     }
 };
@@ -447,50 +470,85 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
         __builtin_amdgcn_sched_barrier(0);
     }
     // D[co][pixel]: lane (r, q) holds channels cbase + 16 g + 4 q .. + 3 of pixel r of each block
+    if constexpr (MODE == 0 || MODE == 2) {
+        // BF16 activations (MODE 0: bias + ReLU) or input gradients (MODE 2: times the ReLU mask of
+        // the forward activation), stored branch-free through a buffer resource spanning the
+        // tile's rows inside the box: a pixel past the right edge gets an offset past the
+        // resource, which the hardware drops, and rows past the bottom edge lie past it anyway.
+        // (The waits for the next tile's prefetched loads then count exactly, instead of also
+        // waiting for these stores.)  The mask loads are issued together, from clamped pixels.
+        const int rows = min(kTileH, H - tc.y0);
+        const rsrc_t ry = make_rsrc(o.Y + ((size_t)tc.n * H + tc.y0) * W * COUT, (uint32_t)rows * W * COUT * sizeof(__bf16));
+        u32x2 mv[GPW][RW][HPW];
+        if (MODE == 2) {
 #pragma unroll
-    for (int g = 0; g < GPW; ++g)
+            for (int g = 0; g < GPW; ++g)
 #pragma unroll
-        for (int rho = 0; rho < RW; ++rho)
+                for (int rho = 0; rho < RW; ++rho)
 #pragma unroll
-            for (int h = 0; h < HPW; ++h) {
-            const int c0 = cbase + 16 * g + 4 * q;
-            const int yy = tc.y0 + RW * mg + rho, xx = tc.x0 + 16 * (half0 + h) + r;
-            if (yy >= H || xx >= W) continue;
-            const size_t p = ((size_t)tc.n * H + yy) * W + xx;
-            const f32x4 &a = acc[g][rho][h];
-            if (MODE == 1 || MODE == 3) {
-                if (c0 == 0) {  // the 4 state channels are those of the q = 0 lanes of the first channel group
-                    static_assert(kStateC == 4, "one lane holds the four state channels of a pixel");
-                    const f32x4 rs = *(const f32x4 *)(o.resid + p * kStateC);
-                    f32x4 v;
-                    v[0] = rs[0] + o.alpha0 * (a[0] + bias[g][0]);
-                    v[1] = rs[1] + o.alpha1 * (a[1] + bias[g][1]);
-                    v[2] = rs[2] + o.alpha2 * (a[2] + bias[g][2]);
-                    v[3] = rs[3] + o.alpha3 * (a[3] + bias[g][3]);
-                    if (MODE == 1) {
-                        *(f32x4 *)(o.Yf + p * kStateC) = v;
-                    } else {
-                        o.phi[p] = v[0];
-                        o.ux[p] = v[1] * o.u_scale;
-                        o.uy[p] = v[2] * o.u_scale;
-                        o.rho[p] = 1.0 + v[3] * o.r_scale;
+                    for (int h = 0; h < HPW; ++h) {
+                        const int yy = min(tc.y0 + RW * mg + rho, H - 1), xx = min(tc.x0 + 16 * (half0 + h) + r, W - 1);
+                        const size_t p = ((size_t)tc.n * H + yy) * W + xx;
+                        mv[g][rho][h] = *(const u32x2 *)(o.mask + p * COUT + cbase + 16 * g + 4 * q);
+                    }
+        }
+#pragma unroll
+        for (int g = 0; g < GPW; ++g)
+#pragma unroll
+            for (int rho = 0; rho < RW; ++rho)
+#pragma unroll
+                for (int h = 0; h < HPW; ++h) {
+                    const int c0 = cbase + 16 * g + 4 * q;
+                    const int xx = tc.x0 + 16 * (half0 + h) + r;
+                    const f32x4 &a = acc[g][rho][h];
+                    const bf16x4 m4 = __builtin_bit_cast(bf16x4, MODE == 2 ? mv[g][rho][h] : u32x2{0, 0});
+                    bf16x4 v4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float v = a[e] + bias[g][e];
+                        v4[e] = (__bf16)(MODE == 2 ? (((float)m4[e] > 0.f) ? v : 0.f) : fmaxf(v, 0.f));
+                    }
+                    const int off = xx < W ? (((RW * mg + rho) * W + xx) * COUT + c0) * (int)sizeof(__bf16) : 0x7fffffff;
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v4), ry, off, 0, 0);
+                }
+    } else {
+        // the last layer: FP32 residual + alpha of the four state channels (MODE 1), or the same
+        // written into the FP64 field planes (MODE 3)
+        static_assert(MODE == 1 || MODE == 3, "output modes");
+#pragma unroll
+        for (int g = 0; g < GPW; ++g)
+#pragma unroll
+            for (int rho = 0; rho < RW; ++rho)
+#pragma unroll
+                for (int h = 0; h < HPW; ++h) {
+                    const int c0 = cbase + 16 * g + 4 * q;
+                    const int yy = tc.y0 + RW * mg + rho, xx = tc.x0 + 16 * (half0 + h) + r;
+                    if (yy >= H || xx >= W) continue;
+                    const size_t p = ((size_t)tc.n * H + yy) * W + xx;
+                    const f32x4 &a = acc[g][rho][h];
+                    if (c0 == 0) {  // the 4 state channels are those of the q = 0 lanes of the first channel group
+                        static_assert(kStateC == 4, "one lane holds the four state channels of a pixel");
+                        const f32x4 rs = *(const f32x4 *)(o.resid + p * kStateC);
+                        f32x4 v;
+                        v[0] = rs[0] + o.alpha0 * (a[0] + bias[g][0]);
+                        v[1] = rs[1] + o.alpha1 * (a[1] + bias[g][1]);
+                        v[2] = rs[2] + o.alpha2 * (a[2] + bias[g][2]);
+                        v[3] = rs[3] + o.alpha3 * (a[3] + bias[g][3]);
+                        if (MODE == 1) {
+                            *(f32x4 *)(o.Yf + p * kStateC) = v;
+                        } else {
+                            o.phi[p] = v[0];
+                            o.ux[p] = v[1] * o.u_scale;
+                            o.uy[p] = v[2] * o.u_scale;
+                            o.rho[p] = 1.0 + v[3] * o.r_scale;
+                        }
                     }
                 }
-            } else {
-                bf16x4 m4 = {};
-                if (MODE == 2) m4 = __builtin_bit_cast(bf16x4, *(const u32x2 *)(o.mask + p * COUT + c0));
-                bf16x4 v4;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float v = a[e] + bias[g][e];
-                    v4[e] = (__bf16)(MODE == 2 ? (((float)m4[e] > 0.f) ? v : 0.f) : fmaxf(v, 0.f));
-                }
-                *(u32x2 *)(o.Y + p * COUT + c0) = __builtin_bit_cast(u32x2, v4);
-            }
-        }
+    }
 }
 
-template <int CIN, int COUT, int MODE>
+// WIDE: the box has at least 8 rows and 32 columns (see Patch::load).
+template <int CIN, int COUT, int MODE, bool WIDE>
 __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wp, OutArgs o,
                                                        int ntiles, int H, int W)
 {
@@ -524,9 +582,15 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
             if (k < NV) *(u32x4 *)(wl + (k / (CIN / 8)) * WS + (k % (CIN / 8)) * 8) = v[i];
         }
     }
+    // this lane's output channels: cbase + 16 g + 4 q + e
+    float bias[GPW][4];
+#pragma unroll
+    for (int g = 0; g < GPW; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[g][e] = (MODE != 2) ? o.bias[cbase + 16 * g + 4 * q + e] : 0.f;
     Patch<CIN> pre;
-    pre.load(X, tile_coord(tile, H, W), H, W);
-    __syncthreads();
+    pre.template load<WIDE>(X, tile_coord(tile, H, W), H, W);
+    __syncthreads();  // also waits for the bias loads, so that no wait in the loop is for them
     bf16x8 wa[GPW][9][KS];
 #pragma unroll
     for (int g = 0; g < GPW; ++g)
@@ -534,20 +598,20 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
         for (int t = 0; t < 9; ++t)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) wa[g][t][ks] = ld8(wl + (t * COUT + cbase + 16 * g + r) * WS + 32 * ks + 8 * q);
-    // this lane's output channels: cbase + 16 g + 4 q + e
-    float bias[GPW][4];
-#pragma unroll
-    for (int g = 0; g < GPW; ++g)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) bias[g][e] = (MODE != 2) ? o.bias[cbase + 16 * g + 4 * q + e] : 0.f;
 
+    pre.store(patch);
+    lds_barrier();
+    // Per tile: the next tile's patch loads (the last iteration repeats the last tile's: no branch
+    // around the loads), the MFMAs and output stores, then the patch exchange.  Barriers for LDS
+    // only: the wait for the patch registers then counts just the loads, and this tile's output
+    // stores, issued after them, stay in flight into the next tile's MFMAs.
     for (; tile < ntiles; tile += gridDim.x) {
         const TileCoord tc = tile_coord(tile, H, W);
-        __syncthreads();  // the previous tile's readers are done
-        pre.store(patch);
-        __syncthreads();
-        if (tile + (int)gridDim.x < ntiles) pre.load(X, tile_coord(tile + gridDim.x, H, W), H, W);
+        pre.template load<WIDE>(X, tile_coord(min(tile + (int)gridDim.x, ntiles - 1), H, W), H, W);
         conv_tile<CIN, COUT, MODE>(patch, wa, bias, tc, o, H, W);
+        lds_barrier();  // every wave is done with this tile's patch
+        pre.store(patch);
+        lds_barrier();
     }
 }
 
@@ -619,10 +683,6 @@ __device__ __forceinline__ void lds_frags(const __bf16 *wl, int co, int q, bf16x
         for (int ks = 0; ks < CIN / 32; ++ks) wa[t][ks] = ld8(wl + (t * COUT + co) * (CIN + 8) + 32 * ks + 8 * q);
 }
 
-// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, not for its
-// global loads, so loads issued before it (weights prefetched into registers) stay in flight
-// across it.  (__syncthreads also waits for every outstanding global load.)
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <int COUT, int MODE, int PACK = COUT>
 __global__ __launch_bounds__(kConvThreads) void k_pair(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wa,
@@ -1444,11 +1504,18 @@ template <int CI, int CO, int MO>
 int launch_conv_t(lbcm_net *n, const __bf16 *X, const __bf16 *Wp, const OutArgs &o)
 {
     constexpr size_t bytes = ConvLds<CI, CO>::bytes;
-    static bool done[kMaxDevices] = {};
-    int rc = allow_dynamic_lds(n, reinterpret_cast<const void *>(&k_conv<CI, CO, MO>), bytes, done);
+    static bool done[kMaxDevices] = {}, done_wide[kMaxDevices] = {};
+    const bool wide = n->H >= kTileH && n->W >= kTileW;
+    int rc = allow_dynamic_lds(n, wide ? reinterpret_cast<const void *>(&k_conv<CI, CO, MO, true>)
+                                       : reinterpret_cast<const void *>(&k_conv<CI, CO, MO, false>),
+                               bytes, wide ? done_wide : done);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_conv<CI, CO, MO>), dim3(n->conv_grid), dim3(kConvThreads), bytes, n->stream, X, Wp, o, n->ntiles,
-                       n->H, n->W);
+    if (wide)
+        hipLaunchKernelGGL((k_conv<CI, CO, MO, true>), dim3(n->conv_grid), dim3(kConvThreads), bytes, n->stream, X, Wp, o, n->ntiles,
+                           n->H, n->W);
+    else
+        hipLaunchKernelGGL((k_conv<CI, CO, MO, false>), dim3(n->conv_grid), dim3(kConvThreads), bytes, n->stream, X, Wp, o, n->ntiles,
+                           n->H, n->W);
     NHIP(n, hipGetLastError());
     return LBCM_OK;
 }
