@@ -113,11 +113,12 @@ __device__ __forceinline__ TileCoord tile_coord(int tile, int H, int W)
 
 // ------------------------------------------------------------------------------------------
 // layer 0 on the matrix cores in FP32 over 8 x 32 tiles: Y[p][co] = bf16(relu(b[co] + sum_{t, ci}
-// s[p + d_t][ci] W0[t][ci][co])), one tile per workgroup.  v_mfma_f32_16x16x4_f32 takes K = 4,
+// s[p + d_t][ci] W0[t][ci][co])), a workgroup taking the tiles b, b + G, ... (G the grid) with the
+// next tile's patch in flight during the current one.  v_mfma_f32_16x16x4_f32 takes K = 4,
 // exactly the state channels of one tap, so each tap is one MFMA per 16-channel x 16-pixel block
 // with FP32 products and sums.  Wave w computes tile row w (two 16-pixel blocks) for all C / 16
 // channel blocks; its A operands (W0 of 9 taps x C / 16 blocks, one value per lane) stay in
-// registers.  The state patch (tile plus circular halo) is staged in LDS.  With PLANES the
+// registers for all tiles.  The state patch (tile plus circular halo) is staged in LDS.  With PLANES the
 // patch is read from the four FP64 field planes and converted to the state (phi, v / u_scale,
 // (rho - 1) / rho_scale) as k_from_planes does, and the tile's own state goes to s_out (the
 // residual of the last layer).
@@ -129,33 +130,44 @@ struct PlaneIn {
     float inv_u, inv_r;
 };
 
-template <int C, bool PLANES>
+template <int C, bool PLANES, bool WIDE>
 __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict__ s, PlaneIn pin, float *__restrict__ s_out,
-                                                         const float *__restrict__ W0, const float *__restrict__ b0, int H, int W,
-                                                         __bf16 *__restrict__ Y)
+                                                         const float *__restrict__ W0, const float *__restrict__ b0, int ntiles,
+                                                         int H, int W, __bf16 *__restrict__ Y)
 {
     constexpr int NB = C / 16;  // channel blocks
-    __shared__ __align__(16) float sp[kPatchH * kPatchW * kStateC];
+    constexpr int NP = kPatchH * kPatchW;
+    static_assert(NP <= kFirstThreads, "one patch pixel per thread");
+    __shared__ __align__(16) float sp[NP * kStateC];
     const int lane = threadIdx.x & 63;
     const int row = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = lane & 15, q = lane >> 4;
-    const TileCoord tc = tile_coord(blockIdx.x, H, W);
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
     // A operand of block cb at tap t: lane (r, q) holds W0[t][ci = q][co = 16 cb + r]
     float wa[9][NB];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) wa[t][cb] = W0[(kStateC * t + q) * C + 16 * cb + r];
-    // D of a block: lane (r, q) holds channels 16 cb + 4 q + e of pixel r
-    f32x4 acc[2][NB];
+    // D of a block: lane (r, q) holds channels 16 cb + 4 q + e of pixel r; the sums start at the bias
+    float bias[NB][4];
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) {
+    for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[0][cb][e] = acc[1][cb][e] = b0[16 * cb + 4 * q + e];
-    }
-    for (int k = threadIdx.x; k < kPatchH * kPatchW; k += kFirstThreads) {
-        const int py = k / kPatchW, px = k % kPatchW;
-        const int gy = wrap_near(tc.y0 - 1 + py, H), gx = wrap_near(tc.x0 - 1 + px, W);
+        for (int e = 0; e < 4; ++e) bias[cb][e] = b0[16 * cb + 4 * q + e];
+    // this thread's patch pixel (threads past the patch repeat its last pixel: no branch around
+    // the loads, so that their wait counts exactly); with WIDE (box of at least 8 rows and 32
+    // columns) the circular halo indices wrap with selects
+    const int k = min((int)threadIdx.x, NP - 1), py = k / kPatchW, px = k % kPatchW;
+    auto wrap1 = [](int v, int n) {
+        if (!WIDE) return wrap_near(v, n);
+        const int a = v < 0 ? v + n : v;
+        return a >= n ? a - n : a;
+    };
+    auto load = [&](int t) {
+        const TileCoord tc = tile_coord(t, H, W);
+        const int gy = wrap1(tc.y0 - 1 + py, H), gx = wrap1(tc.x0 - 1 + px, W);
         const size_t p = ((size_t)tc.n * H + gy) * W + gx;
         f32x4 v;
         if constexpr (PLANES) {
@@ -169,33 +181,54 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
         } else {
             v = *(const f32x4 *)(s + p * kStateC);
         }
-        *(f32x4 *)(sp + k * kStateC) = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        float x[2];  // B operand: lane (r, q) holds channel q of pixel r of the block
+        return v;
+    };
+    f32x4 pv = load(tile);
+    __syncthreads();  // also waits for the weight and bias loads, so that no wait in the loop is for them
+    *(f32x4 *)(sp + k * kStateC) = pv;
+    lds_barrier();
+    // Per tile: the next tile's patch pixel (the last iteration repeats the last tile's), the
+    // MFMAs and the output stores, then the patch exchange; LDS-only barriers, so that the output
+    // stores stay in flight into the next tile.
+    for (; tile < ntiles; tile += gridDim.x) {
+        const TileCoord tc = tile_coord(tile, H, W);
+        pv = load(min(tile + (int)gridDim.x, ntiles - 1));
+        f32x4 acc[2][NB];
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-            x[h] = sp[((row + 1 + tap_dy(t)) * kPatchW + 16 * h + r + 1 + tap_dx(t)) * kStateC + q];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+            for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-            for (int cb = 0; cb < NB; ++cb) acc[h][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[t][cb], x[h], acc[h][cb], 0, 0, 0);
-    }
-    const int y = tc.y0 + row;
+                for (int e = 0; e < 4; ++e) acc[h][cb][e] = bias[cb][e];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int xg = tc.x0 + 16 * h + r;
-        if (y >= H || xg >= W) continue;
-        __bf16 *out = Y + (((size_t)tc.n * H + y) * W + xg) * C + 4 * q;
+        for (int t = 0; t < 9; ++t) {
+            float x[2];  // B operand: lane (r, q) holds channel q of pixel r of the block
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) {
-            bf16x4 v;
+            for (int h = 0; h < 2; ++h) x[h] = sp[((row + 1 + tap_dy(t)) * kPatchW + 16 * h + r + 1 + tap_dx(t)) * kStateC + q];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = (__bf16)fmaxf(acc[h][cb][e], 0.f);
-            *(u32x2 *)(out + 16 * cb) = __builtin_bit_cast(u32x2, v);
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb) acc[h][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[t][cb], x[h], acc[h][cb], 0, 0, 0);
         }
+        // bf16(relu) through a buffer resource over the tile's rows inside the box: a pixel past
+        // the right edge gets an offset past it (dropped), rows past the bottom lie past it
+        const int rows = min(kTileH, H - tc.y0);
+        const rsrc_t ry = make_rsrc(Y + ((size_t)tc.n * H + tc.y0) * W * C, (uint32_t)rows * W * C * sizeof(__bf16));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int xg = tc.x0 + 16 * h + r;
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                bf16x4 v;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = (__bf16)fmaxf(acc[h][cb][e], 0.f);
+                const int off = xg < W ? ((row * W + xg) * C + 16 * cb + 4 * q) * (int)sizeof(__bf16) : 0x7fffffff;
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), ry, off, 0, 0);
+            }
+        }
+        lds_barrier();  // every wave is done with this tile's patch
+        *(f32x4 *)(sp + k * kStateC) = pv;
+        lds_barrier();
     }
 }
 
@@ -1587,12 +1620,25 @@ int pack_all(lbcm_net *n)
 template <int C>
 void launch_first(lbcm_net *n, const PlaneIO *io)
 {
-    const dim3 g(n->ntiles), b(kFirstThreads);
+    // two resident workgroups per CU, each taking several tiles in turn
+    const dim3 g(std::min(n->ntiles, 512)), b(kFirstThreads);
     const float *W0 = n->params + n->w_off[0], *b0 = n->params + n->b_off[0];
-    if (io)
-        hipLaunchKernelGGL((k_first<C, true>), g, b, 0, n->stream, nullptr, io->in, n->resid, W0, b0, n->H, n->W, n->act[1]);
-    else
-        hipLaunchKernelGGL((k_first<C, false>), g, b, 0, n->stream, n->resid, PlaneIn{}, nullptr, W0, b0, n->H, n->W, n->act[1]);
+    const bool wide = n->H >= kTileH && n->W >= kTileW;
+    if (io) {
+        if (wide)
+            hipLaunchKernelGGL((k_first<C, true, true>), g, b, 0, n->stream, nullptr, io->in, n->resid, W0, b0, n->ntiles, n->H, n->W,
+                               n->act[1]);
+        else
+            hipLaunchKernelGGL((k_first<C, true, false>), g, b, 0, n->stream, nullptr, io->in, n->resid, W0, b0, n->ntiles, n->H,
+                               n->W, n->act[1]);
+    } else {
+        if (wide)
+            hipLaunchKernelGGL((k_first<C, false, true>), g, b, 0, n->stream, n->resid, PlaneIn{}, nullptr, W0, b0, n->ntiles, n->H,
+                               n->W, n->act[1]);
+        else
+            hipLaunchKernelGGL((k_first<C, false, false>), g, b, 0, n->stream, n->resid, PlaneIn{}, nullptr, W0, b0, n->ntiles, n->H,
+                               n->W, n->act[1]);
+    }
 }
 
 // forward from the FP32 state in n->resid ([P][kStateC]) into n->out, or with io from and into
