@@ -133,12 +133,13 @@ struct PlaneIn {
 template <int C, bool PLANES, bool WIDE>
 __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict__ s, PlaneIn pin, float *__restrict__ s_out,
                                                          const float *__restrict__ W0, const float *__restrict__ b0, int ntiles,
-                                                         int H, int W, __bf16 *__restrict__ Y)
+                                                         int H, int W, __bf16 *__restrict__ Y, uint8_t *__restrict__ mask_out)
 {
     constexpr int NB = C / 16;  // channel blocks
     constexpr int NP = kPatchH * kPatchW;
     static_assert(NP <= kFirstThreads, "one patch pixel per thread");
     __shared__ __align__(16) float sp[NP * kStateC];
+    __shared__ __align__(16) uint8_t mstage[kTileH * kTileW * (C / 4)];  // ReLU mask bytes of a tile
     const int lane = threadIdx.x & 63;
     const int row = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = lane & 15, q = lane >> 4;
@@ -213,20 +214,39 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
         // bf16(relu) through a buffer resource over the tile's rows inside the box: a pixel past
         // the right edge gets an offset past it (dropped), rows past the bottom lie past it
         const int rows = min(kTileH, H - tc.y0);
-        const rsrc_t ry = make_rsrc(Y + ((size_t)tc.n * H + tc.y0) * W * C, (uint32_t)rows * W * C * sizeof(__bf16));
+        const size_t tile_px = ((size_t)tc.n * H + tc.y0) * W;
+        const rsrc_t ry = make_rsrc(Y + tile_px * C, (uint32_t)rows * W * C * sizeof(__bf16));
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int xg = tc.x0 + 16 * h + r;
 #pragma unroll
             for (int cb = 0; cb < NB; ++cb) {
                 bf16x4 v;
+                uint32_t bits = 0;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = (__bf16)fmaxf(acc[h][cb][e], 0.f);
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = (__bf16)fmaxf(acc[h][cb][e], 0.f);
+                    bits |= ((float)v[e] > 0.f ? 1u : 0u) << e;
+                }
                 const int off = xg < W ? ((row * W + xg) * C + 16 * cb + 4 * q) * (int)sizeof(__bf16) : 0x7fffffff;
                 __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), ry, off, 0, 0);
+                mstage[(row * kTileW + 16 * h + r) * (C / 4) + 4 * cb + q] = (uint8_t)bits;
             }
         }
-        lds_barrier();  // every wave is done with this tile's patch
+        lds_barrier();  // every wave is done with this tile's patch, the mask bytes are in LDS
+        {
+            // ReLU mask bytes of the training forward (bit e of byte [p][c / 4]): C / 4 bytes per
+            // tile pixel (thread t: pixel t), dropped past the box, and all of them without masks
+            // (a resource of size 0)
+            const rsrc_t rm = make_rsrc(mask_out ? mask_out + tile_px * (C / 4) : nullptr, mask_out ? (uint32_t)rows * W * (C / 4) : 0u);
+            const int t = min((int)threadIdx.x, kTileH * kTileW - 1), ty = t / kTileW, tx = t % kTileW;
+            const bool ok = (int)threadIdx.x < kTileH * kTileW && tc.x0 + tx < W;
+            const int off = ok ? (ty * W + tc.x0 + tx) * (C / 4) : 0x7fffffff;
+            if constexpr (C == 64)
+                __builtin_amdgcn_raw_buffer_store_b128(*(const u32x4 *)(mstage + t * 16), rm, off, 0, 0);
+            else
+                __builtin_amdgcn_raw_buffer_store_b64(*(const u32x2 *)(mstage + t * 8), rm, off, 0, 0);
+        }
         *(f32x4 *)(sp + k * kStateC) = pv;
         lds_barrier();
     }
@@ -367,7 +387,8 @@ constexpr int kConvThreads = 512;
 
 struct OutArgs {
     const float *bias;
-    const __bf16 *mask;
+    const uint8_t *mask;  // MODE 2: ReLU mask of the forward activation (see mask_out)
+    uint8_t *mask_out;    // MODE 0 (training forward): bit e of byte [p][c / 4] = (Y[p][c + e] > 0); null: none
     __bf16 *Y;
     const float *resid;
     float *Yf;
@@ -421,7 +442,8 @@ struct ConvLds {
     static constexpr int WS = CIN + 8;               // weight row stride (bf16), padded like the patch
     static constexpr int patch_elems = kPatchH * kPatchW * PS;
     static constexpr int weight_elems = 9 * COUT * WS;
-    static constexpr size_t bytes = (size_t)(patch_elems + weight_elems) * sizeof(__bf16);
+    static constexpr int mask_bytes = kTileH * kTileW * (COUT / 4);  // ReLU mask bytes of a tile (training forward)
+    static constexpr size_t bytes = (size_t)(patch_elems + weight_elems) * sizeof(__bf16) + mask_bytes;
 };
 
 // Work split of a conv layer over the 8 waves (the layers a of the fused pairs keep their own):
@@ -451,10 +473,12 @@ struct WaveSplit {
 // Stage s covers patch row s (3 horizontal taps x KS fragments); the fragments of stage s + 1 are
 // read before the MFMAs of stage s, in a second register buffer.  Every output sums its taps in
 // the order t = 0 .. 8 and K-steps within a tap.
-template <int CIN, int COUT, int MODE>
+// With mstage (MODE 0 of the training forward) the ReLU mask bits of the tile go to LDS,
+// mstage[tile pixel][c / 4] (bit e: Y[p][c + e] > 0), for a coalesced store by the caller.
+template <int CIN, int COUT, int MODE, bool MASKS = false>
 __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa)[WaveSplit<COUT, MODE>::GPW][9][CIN / 32],
                                           const float (&bias)[WaveSplit<COUT, MODE>::GPW][4], TileCoord tc, const OutArgs &o,
-                                          int H, int W)
+                                          int H, int W, uint8_t *mstage = nullptr)
 {
     constexpr int PS = CIN + 8, KS = CIN / 32;
     using S = WaveSplit<COUT, MODE>;
@@ -511,8 +535,9 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
         // (The waits for the next tile's prefetched loads then count exactly, instead of also
         // waiting for these stores.)  The mask loads are issued together, from clamped pixels.
         const int rows = min(kTileH, H - tc.y0);
-        const rsrc_t ry = make_rsrc(o.Y + ((size_t)tc.n * H + tc.y0) * W * COUT, (uint32_t)rows * W * COUT * sizeof(__bf16));
-        u32x2 mv[GPW][RW][HPW];
+        const size_t tile_px = ((size_t)tc.n * H + tc.y0) * W;
+        const rsrc_t ry = make_rsrc(o.Y + tile_px * COUT, (uint32_t)rows * W * COUT * sizeof(__bf16));
+        uint32_t mv[GPW][RW][HPW];
         if (MODE == 2) {
 #pragma unroll
             for (int g = 0; g < GPW; ++g)
@@ -522,7 +547,7 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
                     for (int h = 0; h < HPW; ++h) {
                         const int yy = min(tc.y0 + RW * mg + rho, H - 1), xx = min(tc.x0 + 16 * (half0 + h) + r, W - 1);
                         const size_t p = ((size_t)tc.n * H + yy) * W + xx;
-                        mv[g][rho][h] = *(const u32x2 *)(o.mask + p * COUT + cbase + 16 * g + 4 * q);
+                        mv[g][rho][h] = o.mask[p * (COUT / 4) + (cbase + 16 * g + 4 * q) / 4];
                     }
         }
 #pragma unroll
@@ -534,15 +559,18 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
                     const int c0 = cbase + 16 * g + 4 * q;
                     const int xx = tc.x0 + 16 * (half0 + h) + r;
                     const f32x4 &a = acc[g][rho][h];
-                    const bf16x4 m4 = __builtin_bit_cast(bf16x4, MODE == 2 ? mv[g][rho][h] : u32x2{0, 0});
                     bf16x4 v4;
+                    uint32_t bits = 0;
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const float v = a[e] + bias[g][e];
-                        v4[e] = (__bf16)(MODE == 2 ? (((float)m4[e] > 0.f) ? v : 0.f) : fmaxf(v, 0.f));
+                        v4[e] = (__bf16)(MODE == 2 ? (((mv[g][rho][h] >> e) & 1u) ? v : 0.f) : fmaxf(v, 0.f));
+                        bits |= ((float)v4[e] > 0.f ? 1u : 0u) << e;
                     }
-                    const int off = xx < W ? (((RW * mg + rho) * W + xx) * COUT + c0) * (int)sizeof(__bf16) : 0x7fffffff;
+                    const int pix = (RW * mg + rho) * W + xx;
+                    const int off = xx < W ? (pix * COUT + c0) * (int)sizeof(__bf16) : 0x7fffffff;
                     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v4), ry, off, 0, 0);
+                    if (MASKS) mstage[((RW * mg + rho) * kTileW + 16 * (half0 + h) + r) * (COUT / 4) + c0 / 4] = (uint8_t)bits;
                 }
     } else {
         // the last layer: FP32 residual + alpha of the four state channels (MODE 1), or the same
@@ -638,11 +666,32 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
     // around the loads), the MFMAs and output stores, then the patch exchange.  Barriers for LDS
     // only: the wait for the patch registers then counts just the loads, and this tile's output
     // stores, issued after them, stay in flight into the next tile's MFMAs.
+    // ReLU mask bytes of the training forward: staged in LDS by conv_tile, then one store of COUT / 4
+    // bytes per tile pixel (thread t: pixel t; threads past the tile or pixels past the box get an
+    // offset past the resource, which is dropped; without masks the resource is empty)
+    uint8_t *mstage = (uint8_t *)(wl + Lds::weight_elems);
+    constexpr bool MASKS = MODE == 0;
     for (; tile < ntiles; tile += gridDim.x) {
         const TileCoord tc = tile_coord(tile, H, W);
         pre.template load<WIDE>(X, tile_coord(min(tile + (int)gridDim.x, ntiles - 1), H, W), H, W);
-        conv_tile<CIN, COUT, MODE>(patch, wa, bias, tc, o, H, W);
-        lds_barrier();  // every wave is done with this tile's patch
+        conv_tile<CIN, COUT, MODE, MASKS>(patch, wa, bias, tc, o, H, W, mstage);
+        lds_barrier();  // every wave is done with this tile's patch, the mask bytes are in LDS
+        if (MASKS) {
+            const int rows = min(kTileH, H - tc.y0);
+            const size_t tile_px = ((size_t)tc.n * H + tc.y0) * W;
+            const rsrc_t rm = make_rsrc(o.mask_out ? o.mask_out + tile_px * (COUT / 4) : nullptr,
+                                        o.mask_out ? (uint32_t)rows * W * (COUT / 4) : 0u);
+            const int t = min((int)threadIdx.x, kTileH * kTileW - 1), ty = t / kTileW, tx = t % kTileW;
+            const bool ok = (int)threadIdx.x < kTileH * kTileW && tc.x0 + tx < W;
+            const int off = ok ? (ty * W + tc.x0 + tx) * (COUT / 4) : 0x7fffffff;
+            if constexpr (COUT == 64) {
+                const u32x4 m = *(const u32x4 *)(mstage + t * 16);
+                __builtin_amdgcn_raw_buffer_store_b128(m, rm, off, 0, 0);
+            } else {
+                const u32x2 m = *(const u32x2 *)(mstage + t * 8);
+                __builtin_amdgcn_raw_buffer_store_b64(m, rm, off, 0, 0);
+            }
+        }
         pre.store(patch);
         lds_barrier();
     }
@@ -1476,6 +1525,7 @@ struct lbcm_net {
     float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     std::vector<__bf16 *> Wf, Wb;               // BF16 packs of layers 1 .. L-1
     std::vector<__bf16 *> act;                  // act[l] = input of layer l >= 1 (relu output of layer l - 1)
+    std::vector<uint8_t *> mask8;               // ReLU mask of act[l] from the training forward (bit e of byte [p][c / 4]: act > 0)
     __bf16 *dz_a = nullptr, *dz_b = nullptr;    // gradient ping-pong buffers (P x 64)
     __bf16 *dz_last = nullptr;                  // gradient of the last layer's output (P x kOutC, padding zero)
     PackEntry *pack_table = nullptr;            // where the Adam update writes the BF16 packs of layers 1 .. L-1
@@ -1627,17 +1677,17 @@ void launch_first(lbcm_net *n, const PlaneIO *io)
     if (io) {
         if (wide)
             hipLaunchKernelGGL((k_first<C, true, true>), g, b, 0, n->stream, nullptr, io->in, n->resid, W0, b0, n->ntiles, n->H, n->W,
-                               n->act[1]);
+                               n->act[1], nullptr);
         else
             hipLaunchKernelGGL((k_first<C, true, false>), g, b, 0, n->stream, nullptr, io->in, n->resid, W0, b0, n->ntiles, n->H,
-                               n->W, n->act[1]);
+                               n->W, n->act[1], nullptr);
     } else {
         if (wide)
             hipLaunchKernelGGL((k_first<C, false, true>), g, b, 0, n->stream, n->resid, PlaneIn{}, nullptr, W0, b0, n->ntiles, n->H,
-                               n->W, n->act[1]);
+                               n->W, n->act[1], n->mask8[1]);
         else
             hipLaunchKernelGGL((k_first<C, false, false>), g, b, 0, n->stream, n->resid, PlaneIn{}, nullptr, W0, b0, n->ntiles, n->H,
-                               n->W, n->act[1]);
+                               n->W, n->act[1], n->mask8[1]);
     }
 }
 
@@ -1655,6 +1705,7 @@ int forward(lbcm_net *n, const PlaneIO *io = nullptr)
         OutArgs o{};
         o.bias = n->params + n->b_off[lb];
         o.Y = last ? nullptr : n->act[lb + 1];
+        o.mask_out = (last || io) ? nullptr : n->mask8[lb + 1];  // the training forward keeps the ReLU masks
         o.resid = n->resid;
         o.Yf = n->out;
         o.alpha0 = n->alpha[0];
@@ -1771,8 +1822,10 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
         if (!dmalloc((void **)&n->Wf[l], wb) || !dmalloc((void **)&n->Wb[l], wb)) return bail("out of device memory (packs)");
     }
     n->act.assign(layers, nullptr);
+    n->mask8.assign(layers, nullptr);
     for (int l = 1; l < layers; ++l)
-        if (!dmalloc((void **)&n->act[l], P * channels * sizeof(__bf16))) return bail("out of device memory (activations)");
+        if (!dmalloc((void **)&n->act[l], P * channels * sizeof(__bf16)) || !dmalloc((void **)&n->mask8[l], P * (channels / 4)))
+            return bail("out of device memory (activations)");
     if (!dmalloc((void **)&n->dz_a, P * 64 * sizeof(__bf16)) || !dmalloc((void **)&n->dz_b, P * 64 * sizeof(__bf16)) ||
         !dmalloc((void **)&n->dz_last, P * kOutC * sizeof(__bf16)))
         return bail("out of device memory (gradients)");
@@ -1934,7 +1987,7 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
         NHIP(n, hipGetLastError());
         // gradient of the layer input times the ReLU derivative of that input (act[l] > 0)
         OutArgs o{};
-        o.mask = n->act[l];
+        o.mask = n->mask8[l];
         o.Y = dn;
         int rc = launch_conv(n, dz, n->cout[l], n->Wb[l], n->cin[l], 2, o);
         if (rc) return rc;
@@ -1990,6 +2043,7 @@ int lbcm_net_destroy(lbcm_net *n)
     for (auto p : n->Wf) f(p);
     for (auto p : n->Wb) f(p);
     for (auto p : n->act) f(p);
+    for (auto p : n->mask8) f(p);
     f(n->dz_a);
     f(n->dz_b);
     f(n->dz_last);
