@@ -127,14 +127,14 @@ SURROGATE_WORK = {
     "k_first_pair": (2 * _PX1 * 9 * (4 * 64 * 1.0 + 64 * 64) * _HALO, "BF16 MFMA (+ FP32 layer 0)", 2500.0),
     "k_pair<64, 0, 64>": (2 * _PX1 * 9 * 64 * 64 * (_HALO + 1), "BF16 MFMA", 2500.0),
     "k_pair<16, 3, 32>": (2 * _PX1 * 9 * (64 * 64 * _HALO + 64 * 16), "BF16 MFMA", 2500.0),
-    "k_first<64, false>": (2 * _PX8 * 9 * 4 * 64, "FP32 MFMA", 157.3),
+    "k_first<64, false, true>": (2 * _PX8 * 9 * 4 * 64, "FP32 MFMA", 157.3),
     "k_conv<64, 64, 0>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
     "k_conv<64, 32, 1>": (2 * _PX8 * 9 * 64 * 32, "BF16 MFMA", 2500.0),
     "k_conv<64, 64, 2>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
     "k_conv<32, 64, 2>": (2 * _PX8 * 9 * 32 * 64, "BF16 MFMA", 2500.0),
     "k_conv_dw_strip<64>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
     "k_conv_dw_strip<32>": (2 * _PX8 * 9 * 64 * 32, "BF16 MFMA", 2500.0),
-    "k_first_dw<64>": (2 * _PX8 * 9 * 4 * 64, "FP32 vector", 157.3),
+    "k_first_dw<64>": (2 * _PX8 * 9 * 4 * 64, "FP32 MFMA", 157.3),
 }
 
 

@@ -514,6 +514,27 @@ def test_hybrid_bookkeeping_with_identity_network(threshold):
     lat.close()
 
 
+def test_hybrid_reports_divergence_of_the_lattice():
+    """A caller's lattice created with check_every > 0 turns a non-finite state into
+    LBCM_EDIVERGED from lbcm_hybrid_advance (here a NaN in the starting phi: the check rejects the
+    window, and the lattice's own steps over it report the divergence)."""
+    _note("hybrid divergence")
+    n = 64
+    lat = lbcm.Lattice(n, n, precision="fp32", check_every=4, a=0.04, gamma=0.08, mobility=0.1, nu_l=0.05, nu_g=0.05)
+    phi = inputs.droplet(n, n, 16, inputs.interface_width(0.04, 0.08))
+    phi[10, 10] = np.nan
+    lat.init(phi)
+    m = net.Surrogate(1, n, n, channels=32, layers=3, stream=lat.stream)
+    m.set_params(np.zeros(m.nparams, dtype=np.float32))  # identity jumps
+    hy = net.Hybrid(lat, m, steps_per_jump=8, jumps_per_check=4, u_scale=1e-3, rho_scale=1e-3, threshold=0.0)
+    with pytest.raises(lbcm.LbcmError) as e:
+        hy.advance(2)
+    assert e.value.code == lbcm.LBCM_EDIVERGED
+    hy.close()
+    m.close()
+    lat.close()
+
+
 def test_hybrid_check_error_is_the_relative_phi_l2():
     """With identity jumps the check compares the window's starting phi (after the FP32 round
     trip of a jump) with K lattice steps from equilibrium populations of that state; recompute it
