@@ -370,18 +370,18 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
 //
 // The workgroup (8 waves) stages the layer's weights once and the 10 x 34 input patch (tile plus
 // circular halo) of each tile in dynamic LDS, with row strides padded by 16 bytes so that the 16
-// rows of a fragment fall in distinct banks; a thread issues all its global loads of a patch
-// before storing any, and the next tile's during the current tile's MFMAs.  Wave (mg, ng) computes
-// output channels [16 ng, 16 ng + 16) for the tile rows of row group mg (COUT / 16 channel groups
-// times 8 / (COUT / 16) row groups).  It keeps its weight fragments (9 taps x CIN / 32 K-steps) in
-// registers for the whole launch, as the MFMA A operand, and takes 16 pixels as the B operand, so
-// that each lane ends with 4 consecutive output channels of one pixel (one 8-byte store).
-// Tiles past the grid are taken in a grid-stride loop.  Dynamic LDS: ConvLds<CIN, COUT>::bytes.
+// rows of a fragment fall in distinct banks; the next tile's patch is loaded during the current
+// tile's MFMAs (WaveSplit below gives each wave its output channels and rows).  A wave keeps its
+// weight fragments (9 taps x CIN / 32 K-steps per channel group) in registers for the whole
+// launch, as the MFMA A operand, and takes 16 pixels as the B operand, so that each lane ends
+// with 4 consecutive output channels of one pixel (one 8-byte store).  Tiles past the grid are
+// taken in a grid-stride loop.  Dynamic LDS: ConvLds<CIN, COUT>::bytes.
 //
-// MODE 0: Y = bf16(relu(bias + conv));  MODE 2: Y = bf16(conv * [mask > 0]) (the input gradient
-// times the ReLU derivative of the layer input);  MODE 1: Yf[p][c] = resid[p][c] + alpha_c (bias
-// + conv) for c < kStateC (the last layer, FP32);  MODE 3: the same state written to the FP64
-// field planes (phi, v = u_scale v', rho = 1 + rho_scale rho').
+// MODE 0: Y = bf16(relu(bias + conv)), and in the training forward the ReLU mask of Y (bit e of
+// byte [p][c / 4]: Y[p][c + e] > 0);  MODE 2: Y = bf16(conv * mask) (the input gradient times the
+// ReLU derivative of the layer input, from that mask);  MODE 1: Yf[p][c] = resid[p][c] + alpha_c
+// (bias + conv) for c < kStateC (the last layer, FP32);  MODE 3: the same state written to the
+// FP64 field planes (phi, v = u_scale v', rho = 1 + rho_scale rho').
 
 constexpr int kConvThreads = 512;
 
