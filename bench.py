@@ -284,8 +284,9 @@ def small_report(lbcm, steps, warmup):
 def ensemble_report(lbcm, args) -> dict:
     """Ensemble of independent boxes (sides 64..1024, droplets or layered channels, viscosity
     ratio 1..1000, FP16-shifted storage) advanced by one launch per step under a hipGraph with
-    autotuned tiles, against the same steps as single-box launches, and against one persistent
-    launch per call (grid barrier per step, and per-tile dataflow)."""
+    autotuned tiles, against the same steps as single-box launches (on the batch's stream, and
+    dealt over 4 and 8 streams), and against one persistent launch per call (grid barrier per
+    step, and per-tile dataflow)."""
     import torch
 
     from paper_1803_11345_amd import inputs
@@ -313,6 +314,12 @@ def ensemble_report(lbcm, args) -> dict:
     sec = timed(bt.step, args.ens_steps)
     timed(bt.step_looped, 2)
     sec_loop = timed(bt.step_looped, args.ens_looped_steps)
+    # the same single-box launches over several streams (boxes of one step may then overlap)
+    loop_streams = {}
+    for ns in (4, 8):
+        timed(lambda k: bt.step_looped_streams(k, ns), 2)
+        sl = timed(lambda k: bt.step_looped_streams(k, ns), args.ens_looped_steps)
+        loop_streams[str(ns)] = round(nodes * args.ens_looped_steps / sl / 1e6, 1)
     persistent = {}
     if args.ens_persistent_steps > 0:
         for mode, name in ((1, "barrier_per_step"), (2, "dataflow")):
@@ -329,6 +336,8 @@ def ensemble_report(lbcm, args) -> dict:
     return {"boxes": args.ens_boxes, "nodes": nodes, "precision": "fp16s", "steps": args.ens_steps,
             "value": round(mlups, 1), "unit": "MLUPS", "hbm_gbs_alg": round(mlups * 76 / 1e3, 1),
             "looped_single_box_mlups": round(mlups_loop, 1),
+            "looped_single_box_over_streams_mlups": loop_streams,
+            "speedup_vs_looped_over_streams": round(mlups / max(loop_streams.values()), 3),
             "persistent_launch": persistent,
             "speedup_vs_looped": round(mlups / mlups_loop, 3), "graph": True,
             "tuned": {"waves": info["waves"], "order": ["box order", "largest first", "one XCD per box"][info["order"]],

@@ -245,6 +245,15 @@ int lbcm_batch_step(lbcm_batch *b, int64_t nsteps);
    measured against). */
 int lbcm_batch_step_looped(lbcm_batch *b, int64_t nsteps);
 
+/* The same steps as single-box launches, the boxes of each step dealt round-robin to nstreams
+   streams (1 .. 64; default priority, created for the call) forked from and joined back to the
+   batch's stream after every step, so that the boxes of one step may run concurrently: the
+   baseline that separates what one launch per step gains from concurrency and from launch count.
+   The result equals lbcm_batch_step's bit for bit.  nstreams = 1 is lbcm_batch_step_looped.
+   Synchronises.  Errors: LBCM_EINVAL for nsteps < 0 or nstreams outside [1, 64], LBCM_EHIP,
+   and a box's own LBCM_EDIVERGED (check_every > 0) naming the box. */
+int lbcm_batch_step_looped_streams(lbcm_batch *b, int64_t nsteps, int32_t nstreams);
+
 /* Autotuner: for each box size, the fastest tile split of a workgroup of 8, 12 or 16 waves (timed
    on that box), then the workgroup size and the tile order (see lbcm_batch_set_order)
    of the batched launch by timing whole launches; the boxes' own tiles (lbcm_step,

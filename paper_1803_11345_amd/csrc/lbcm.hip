@@ -2581,6 +2581,62 @@ int lbcm_batch_step_looped(lbcm_batch *b, int64_t nsteps)
     return LBCM_OK;
 }
 
+int lbcm_batch_step_looped_streams(lbcm_batch *b, int64_t nsteps, int32_t nstreams)
+{
+    if (!b) return LBCM_EINVAL;
+    if (nsteps < 0) return bfail(b, LBCM_EINVAL, "nsteps must be >= 0");
+    if (nstreams < 1 || nstreams > 64) return bfail(b, LBCM_EINVAL, "nstreams must be in [1, 64]");
+    if (nstreams == 1) return lbcm_batch_step_looped(b, nsteps);
+    std::vector<hipStream_t> side(nstreams, nullptr);
+    std::vector<hipEvent_t> done(nstreams, nullptr);
+    hipEvent_t fork = nullptr;
+    int rc = LBCM_OK;
+    auto cleanup = [&]() {
+        // the batch's stream has waited for every side stream already; destroying them is safe
+        for (auto &e : done)
+            if (e) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto &st : side)
+            if (st) (void)hipStreamDestroy(st);
+    };
+    auto hip_ok = [&](hipError_t e, const char *what) {
+        if (e == hipSuccess) return true;
+        rc = bfail(b, LBCM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+        return false;
+    };
+    // streams of default priority (different priorities have hung on these parts)
+    bool ok = hip_ok(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreateWithFlags");
+    for (int k = 0; ok && k < nstreams; ++k)
+        ok = hip_ok(hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking), "hipStreamCreateWithFlags") &&
+             hip_ok(hipEventCreateWithFlags(&done[k], hipEventDisableTiming), "hipEventCreateWithFlags");
+    for (int64_t s = 0; ok && s < nsteps; ++s) {
+        // fork from the batch's stream, box i on side stream i mod nstreams, join back
+        ok = hip_ok(hipEventRecord(fork, b->stream), "hipEventRecord");
+        for (int k = 0; ok && k < nstreams; ++k) ok = hip_ok(hipStreamWaitEvent(side[k], fork, 0), "hipStreamWaitEvent");
+        for (int i = 0; ok && i < b->n; ++i) {
+            lbcm_handle *h = b->box[i];
+            const hipStream_t own = h->stream;
+            h->stream = side[i % nstreams];
+            const int r = lbcm_step(h, 1);
+            h->stream = own;
+            if (r) {
+                rc = bfail(b, r, "box " + std::to_string(i) + ": " + h->err);
+                ok = false;
+            }
+        }
+        for (int k = 0; k < nstreams && side[k]; ++k) {
+            // joined even after an error, so that the batch's stream orders everything queued
+            if (!hip_ok(hipEventRecord(done[k], side[k]), "hipEventRecord") ||
+                !hip_ok(hipStreamWaitEvent(b->stream, done[k], 0), "hipStreamWaitEvent"))
+                ok = false;
+        }
+    }
+    if (!ok && rc == LBCM_OK) rc = LBCM_EHIP;
+    if (hipStreamSynchronize(b->stream) != hipSuccess && rc == LBCM_OK) rc = bfail(b, LBCM_EHIP, "hipStreamSynchronize failed");
+    cleanup();
+    return rc;
+}
+
 int lbcm_batch_info(const lbcm_batch *b, int32_t *waves, int32_t *order, int32_t *ntiles, int32_t *wx, int32_t *rows)
 {
     if (!b) return LBCM_EINVAL;

@@ -119,6 +119,7 @@ def load():
     lib.lbcm_batch_box.restype = _H
     lib.lbcm_batch_step.argtypes = [_H, ctypes.c_int64]
     lib.lbcm_batch_step_looped.argtypes = [_H, ctypes.c_int64]
+    lib.lbcm_batch_step_looped_streams.argtypes = [_H, ctypes.c_int64, ctypes.c_int32]
     lib.lbcm_batch_autotune.argtypes = [_H, I32]
     lib.lbcm_batch_set_graph.argtypes = [_H, I32]
     lib.lbcm_batch_set_order.argtypes = [_H, I32]
@@ -315,6 +316,10 @@ def lbcm_batch_step_looped(b, nsteps: int = 1):
     return _bcheck(b, load().lbcm_batch_step_looped(b, int(nsteps)))
 
 
+def lbcm_batch_step_looped_streams(b, nsteps: int = 1, nstreams: int = 4):
+    return _bcheck(b, load().lbcm_batch_step_looped_streams(b, int(nsteps), int(nstreams)))
+
+
 def lbcm_batch_autotune(b, trials: int = 5):
     return _bcheck(b, load().lbcm_batch_autotune(b, int(trials)))
 
@@ -430,6 +435,10 @@ class Batch:
 
     def step_looped(self, n=1):
         lbcm_batch_step_looped(self.b, n)
+        return self
+
+    def step_looped_streams(self, n=1, nstreams=4):
+        lbcm_batch_step_looped_streams(self.b, n, nstreams)
         return self
 
     def autotune(self, trials=5):

@@ -87,6 +87,24 @@ def test_batch_looped_equals_batched():
     b.close()
 
 
+@pytest.mark.parametrize("nstreams", [1, 3, 8])
+def test_batch_looped_over_streams_equals_batched(nstreams):
+    """Single-box launches dealt to several streams (forked from and joined to the batch's
+    stream every step) give the batched result bit for bit; bad stream counts are rejected."""
+    a = _batch("fp32", 61)
+    b = _batch("fp32", 61)
+    a.step(5)
+    b.step_looped_streams(5, nstreams)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.get_state(), y.get_state())
+    for bad in (0, 65):
+        with pytest.raises(lbcm.LbcmError) as e:
+            b.step_looped_streams(1, bad)
+        assert e.value.code == lbcm.LBCM_EINVAL
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp16s"])
 def test_batch_autotune_keeps_state_and_results(prec):
     """Autotuning changes no state; afterwards the batched launch and the boxes' own tuned
