@@ -285,6 +285,46 @@ def test_gradients_are_deterministic(B, H, W, C, L):
     assert np.abs(runs[0][0]).max() > 0
 
 
+def test_batched_pass_equals_single_sample_passes():
+    """A batch large enough that every kernel's workgroups take several tiles in turn (32 samples
+    of 64 x 96: 768 tiles against grids of 256 and 512), against the same samples one at a time
+    (one tile per workgroup): the forward outputs are equal bit for bit, and the batch's weight
+    and bias gradients equal the mean of the single-sample ones up to FP32 summation order (the
+    batch of 32 scales each sample's output gradient by exactly 2^-5, so every BF16 rounding on the
+    way scales with it)."""
+    import torch
+
+    _note("batched vs single-sample passes")
+    B, H, W, C, L = 32, 64, 96, 64, 6
+    p = _params(C, L, seed=51)
+    s = _state(B, H, W, seed=52)
+    tgt = (s + _state(B, H, W, seed=53, amp=0.3)).astype(np.float32)
+    mb = net.Surrogate(B, H, W, channels=C, layers=L)
+    mb.set_params(p)
+    mb.set_output_scale(ALPHA)
+    out = torch.empty(B, H, W, S, dtype=torch.float32, device="cuda")
+    mb.forward(torch.from_numpy(s).cuda(), out)
+    loss_b = mb.backward(torch.from_numpy(tgt).cuda())
+    ob, gb = out.cpu().numpy(), mb.grads().astype(np.float64)
+    mb.close()
+    m1 = net.Surrogate(1, H, W, channels=C, layers=L)
+    m1.set_params(p)
+    m1.set_output_scale(ALPHA)
+    o1 = torch.empty(1, H, W, S, dtype=torch.float32, device="cuda")
+    gsum, lsum = np.zeros_like(gb), 0.0
+    for b in range(B):
+        m1.forward(torch.from_numpy(s[b:b + 1].copy()).cuda(), o1)
+        lsum += m1.backward(torch.from_numpy(tgt[b:b + 1].copy()).cuda())
+        assert np.array_equal(o1.cpu().numpy()[0], ob[b]), b
+        gsum += m1.grads().astype(np.float64)
+    m1.close()
+    g1 = gsum / B
+    rel = np.linalg.norm(gb - g1) / np.linalg.norm(g1)
+    _note(f"  grads rel L2 {rel:.2e}, loss {loss_b:.6e} vs {lsum / B:.6e}")
+    assert rel < 1e-5
+    assert abs(loss_b - lsum / B) <= 1e-5 * abs(loss_b)
+
+
 def test_training_steps_follow_the_oracle():
     """Five Adam iterations (forward, backward, update) of the kernels against the same
     iterations of the oracle, each started from the device parameters."""
