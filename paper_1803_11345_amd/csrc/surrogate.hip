@@ -1192,18 +1192,20 @@ __global__ __launch_bounds__(kDwThreads) void k_conv_dw_strip(const __bf16 *__re
     const int opix = 8 * (lane >> 4) + ((lane & 15) >> 2), och = 4 * (lane & 3);
     Row fifo[kDwAhead];
     {
-        // X rows ya - 1 .. ya + 1 and dZ row ya before the loop (the dZ row stored once)
+        // X rows ya - 1 .. ya + 2 and dZ rows ya, ya + 1 before the loop (each dZ row stored once)
         Row f;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            f.v0 = load1(c0, c0.x ? ya - 2 + k : ya);
-            if (TWO) f.v1 = load1(c1, c1.x ? ya - 2 + k : ya);
-            if (c0.x || k == 0) store1(c0, ya - 1 + k, ya, f.v0);
-            if (TWO && (c1.x || k == 0)) store1(c1, ya - 1 + k, ya, f.v1);
+        for (int k = 0; k < 4; ++k) {
+            f.v0 = load1(c0, c0.x ? ya - 2 + k : ya + min(k, 1));
+            if (TWO) f.v1 = load1(c1, c1.x ? ya - 2 + k : ya + min(k, 1));
+            if (c0.x || k < 2) store1(c0, ya - 1 + k, ya + k, f.v0);
+            if (TWO && (c1.x || k < 2)) store1(c1, ya - 1 + k, ya + k, f.v1);
         }
     }
+    // FIFO slot u: what iteration y stores when y = ya + u (mod kDwAhead), X row y + 3 and dZ row
+    // y + 2, requested kDwAhead iterations earlier
 #pragma unroll
-    for (int u = 0; u < kDwAhead; ++u) load(ya + u + 1, fifo[u]);
+    for (int u = 0; u < kDwAhead; ++u) load(ya + u + 2, fifo[u]);
     lds_barrier();
     const int yend = ya + (yb - ya + kDwAhead - 1) / kDwAhead * kDwAhead;  // rows past yb add zero
     // the row loop and the output of taps [T0, T0 + NT), compile-time constants of each half of
@@ -1215,25 +1217,37 @@ __global__ __launch_bounds__(kDwThreads) void k_conv_dw_strip(const __bf16 *__re
         for (int i = 0; i < NT; ++i)
 #pragma unroll
             for (int jn = 0; jn < NJ; ++jn) acc[i][jn] = f32x4{0, 0, 0, 0};
+        // The operands of row y + 1 are read during row y's MFMAs (two register sets): row y + 1
+        // needs X rows y .. y + 2 and dZ row y + 1, stored one iteration ahead, while this
+        // iteration writes X row y + 3 and dZ row y + 2 into the slot and buffer that row y's
+        // operands (read in the previous iteration, before its barrier) came from.
+        bf16x8 b[2][NJ], a[2][NT];
+        auto operands = [&](int y, bf16x8 (&bo)[NJ], bf16x8 (&ao)[NT]) {
+#pragma unroll
+            for (int jn = 0; jn < NJ; ++jn) bo[jn] = ld_tr(zs + buf_off(y), opix * PSZ + 16 * jn + och, PSZ);
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
+                const int t = T0 + i;
+                ao[i] = ld_tr(xs + slot_off(y + t / 3 - 1), (opix + t % 3) * kDwPSX + 16 * cg + och, kDwPSX);
+            }
+        };
+        static_assert(kDwAhead % 2 == 0, "the register set of row y is y - ya mod 2");
+        operands(ya, b[0], a[0]);
+        // every wave's reads of row ya are done before the first iteration overwrites the slot of
+        // X row ya - 1 and the buffer of dZ row ya (later iterations get this from their barrier)
+        lds_barrier();
         for (int y0 = ya; y0 < yend; y0 += kDwAhead) {
 #pragma unroll
             for (int u = 0; u < kDwAhead; ++u) {
-                const int y = y0 + u;
-                bf16x8 b[NJ], a[NT];
-#pragma unroll
-                for (int jn = 0; jn < NJ; ++jn) b[jn] = ld_tr(zs + buf_off(y), opix * PSZ + 16 * jn + och, PSZ);
-#pragma unroll
-                for (int i = 0; i < NT; ++i) {
-                    const int t = T0 + i;
-                    a[i] = ld_tr(xs + slot_off(y + t / 3 - 1), (opix + t % 3) * kDwPSX + 16 * cg + och, kDwPSX);
-                }
+                const int y = y0 + u, cur = u & 1;
+                operands(y + 1, b[cur ^ 1], a[cur ^ 1]);  // the last iteration reads rows past yend: stored, unused
 #pragma unroll
                 for (int i = 0; i < NT; ++i)
 #pragma unroll
                     for (int jn = 0; jn < NJ; ++jn)
-                        acc[i][jn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[jn], acc[i][jn], 0, 0, 0);
-                store(y + 2, y + 1, fifo[u]);
-                load(y + kDwAhead + 1, fifo[u]);
+                        acc[i][jn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cur][i], b[cur][jn], acc[i][jn], 0, 0, 0);
+                store(y + 3, y + 2, fifo[u]);
+                load(y + kDwAhead + 2, fifo[u]);
                 lds_barrier();
             }
         }
