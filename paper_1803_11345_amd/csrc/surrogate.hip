@@ -89,6 +89,23 @@ __device__ __forceinline__ uint32_t shift_pix(uint32_t p, int dy, int dx, int H,
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16 *p) { return __builtin_bit_cast(bf16x8, *(const u32x4 *)p); }
 
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4i16 lds_v4i16;
+
+// One 16 x 32 MFMA operand (16 channels, K = 32 pixels) from a [pixel][channel] LDS block of
+// pixel stride ps: lane (r, q) gets channel r of pixels 8q .. 8q + 7.  Its offset o0 is opix ps +
+// the block's first channel + och (opix = 8 (lane / 16) + (lane % 16) / 4, och = 4 (lane % 4)); the
+// two halves of its eight pixels are read with the transposing load at o0 and o0 + 4 ps.
+__device__ __forceinline__ bf16x8 ld_tr(const __bf16 *p, int o0, int ps)
+{
+    const auto *base = (const __attribute__((address_space(3))) char *)(p);
+    const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16 *)(base + 2 * o0));
+    const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16 *)(base + 2 * (o0 + 4 * ps)));
+    typedef short v8i16 __attribute__((ext_vector_type(8)));
+    const v8i16 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
 // wrap v into [0, n) for v in [-1, n + 40] (the rows and columns a tile and its halo touch)
 __device__ __forceinline__ int wrap_near(int v, int n)
 {
@@ -252,15 +269,18 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
     }
 }
 
-// layer 0 gradients on the matrix cores in FP32 (as its forward): D[co][col] = sum_p dZ[p][co] B[p][col]
-// with col = kStateC t + ci < 36 (B = s[p + d_t][ci], the weight gradient), col 36 (B = 1, the
-// bias gradient) and cols 37 .. 47 (B = 0, padding to three 16-column blocks).
-// v_mfma_f32_16x16x4_f32 takes four pixels as its K: lane (r, q) holds A = dZ[pixel q][co0 + r]
-// (BF16 widened, exact) and B = B[pixel q][col0 + r].  Workgroup b takes the tiles b, b + G, ...
-// (G = the grid), staging each tile's FP32 state patch and dZ in LDS with the next tile's global
-// loads in flight; wave w takes the K steps (four pixels each) w, w + 4, ... of every tile and keeps
-// all C / 16 x 3 output blocks in registers.  Its sums go to partial row 4 b + w ([row][col][co],
-// cols < kFirstRows), added in a fixed order by k_grad_reduce.
+// layer 0 gradients on the BF16 matrix cores: D[co][col] = sum_p dZ[p][co] B[p][col] with col =
+// kStateC t + ci < 36 (B = s[p + d_t][ci], the weight gradient), col 36 (B = 1, the bias gradient)
+// and cols 37 .. 47 (B = 0, padding to three 16-column blocks).  Each FP32 state value splits
+// exactly into three BF16 parts (hi = bf16(x), mid = bf16(x - hi), lo = x - hi - mid: three 8-bit
+// significands hold FP32's 24), so every product with the BF16 dZ is exact and the sums are FP32,
+// as with FP32 operands, at three BF16 MFMAs per 32 pixels where the FP32 MFMA took eight.
+// v_mfma_f32_16x16x32_bf16 takes one tile row (32 pixels) as its K: lane (r, q) holds A =
+// dZ[pixels 8q .. 8q + 7][co0 + r] (transposing LDS reads) and B = one part of B[the same
+// pixels][col0 + r].  Workgroup b takes the tiles b, b + G, ... (G = the grid), staging each
+// tile's FP32 state patch and dZ in LDS with the next tile's global loads in flight; wave w takes
+// tile rows w and w + 4 and keeps all C / 16 x 3 output blocks in registers.  Its sums go to
+// partial row 4 b + w ([row][col][co], cols < kFirstRows), added in a fixed order by k_grad_reduce.
 constexpr int kFirstDwBlocks = 256;  // workgroups of k_first_dw at most
 constexpr int kFirstCols = 48;       // kFirstRows columns padded to three 16-column blocks
 
@@ -268,12 +288,13 @@ template <int C>
 __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__ s, const __bf16 *__restrict__ dz, int H,
                                                        int W, int ntiles, float *__restrict__ partial)
 {
-    constexpr int NCB = C / 16, NJ = kFirstCols / 16;
+    constexpr int NCB = C / 16, NJ = kFirstCols / 16, PSD = C + 8;  // PSD: LDS pixel stride of dZ
     constexpr int NS = kPatchH * kPatchW * kStateC, NIS = (NS + kThreads - 1) / kThreads;
     constexpr int NZ = kTileH * kTileW * C / 8, NIZ = NZ / kThreads;
     static_assert(NZ % kThreads == 0, "whole dZ chunks per thread");
+    static_assert(kTileW == 32 && kTileH == 2 * (kThreads / 64), "a K step is one tile row; each wave takes two");
     __shared__ float sp[NS];
-    __shared__ __align__(16) __bf16 sd[kTileH * kTileW * C];
+    __shared__ __align__(16) __bf16 sd[kTileH * kTileW * PSD];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = lane & 15, q = lane >> 4;
     // this lane's three B columns: patch offset from the pixel's position, and x m + a = B
@@ -288,6 +309,8 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
         bm[j] = prod ? 1.f : 0.f;
         ba[j] = col == kFirstRows - 1 ? 1.f : 0.f;
     }
+    // the transposing reads' offsets of this lane (pixel of the first half, times the stride, and channel)
+    const int opix = 8 * (lane >> 4) + ((lane & 15) >> 2), och = 4 * (lane & 3);
     f32x4 acc[NCB][NJ];
 #pragma unroll
     for (int i = 0; i < NCB; ++i)
@@ -326,29 +349,37 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
             if (k < NS) sp[k] = vs[i];
         }
 #pragma unroll
-        for (int i = 0; i < NIZ; ++i) *(u32x4 *)(sd + (threadIdx.x + i * kThreads) * 8) = vz[i];
+        for (int i = 0; i < NIZ; ++i) {
+            const int k = threadIdx.x + i * kThreads;
+            *(u32x4 *)(sd + (k / (C / 8)) * PSD + (k % (C / 8)) * 8) = vz[i];
+        }
         __syncthreads();
         if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
-        // the operands of K step k (LDS reads), one step ahead of the MFMAs that use them
-        constexpr int NK = kTileH * kTileW / 16;  // K steps of this wave per tile
-        float bv[2][NJ], av[2][NCB];
-        auto operands = [&](int k, float (&b)[NJ], float (&a)[NCB]) {
-            const int px = 4 * k + q;
-            const int base = ((px / kTileW) * kPatchW + px % kTileW) * kStateC;
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) b[j] = fmaf(sp[base + boff[j]], bm[j], ba[j]);  // exact: x, 1 or 0
+        for (int h = 0; h < 2; ++h) {
+            const int y = w + (kThreads / 64) * h;  // tile row
+            bf16x8 a[NCB], b[3][NJ];
 #pragma unroll
-            for (int i = 0; i < NCB; ++i) a[i] = (float)sd[px * C + 16 * i + r];
-        };
-        operands(w, bv[0], av[0]);
+            for (int i = 0; i < NCB; ++i) a[i] = ld_tr(sd + y * kTileW * PSD, opix * PSD + 16 * i + och, PSD);
 #pragma unroll
-        for (int it = 0; it < NK; ++it) {
-            if (it + 1 < NK) operands(w + 4 * (it + 1), bv[(it + 1) & 1], av[(it + 1) & 1]);
+            for (int j = 0; j < NJ; ++j)
 #pragma unroll
-            for (int i = 0; i < NCB; ++i)
+                for (int e = 0; e < 8; ++e) {
+                    const float v = fmaf(sp[(y * kPatchW + 8 * q + e) * kStateC + boff[j]], bm[j], ba[j]);  // exact: x, 1 or 0
+                    const __bf16 hi = (__bf16)v;
+                    const float r1 = v - (float)hi;
+                    const __bf16 mid = (__bf16)r1;
+                    b[0][j][e] = hi;
+                    b[1][j][e] = mid;
+                    b[2][j][e] = (__bf16)(r1 - (float)mid);
+                }
 #pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[it & 1][i], bv[it & 1][j], acc[i][j], 0, 0, 0);
+            for (int part = 0; part < 3; ++part)
+#pragma unroll
+                for (int i = 0; i < NCB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[part][j], acc[i][j], 0, 0, 0);
         }
     }
     // D of block (i, j): lane (r, q) holds co = 16 i + 4 q + e, col = 16 j + r
@@ -1087,21 +1118,6 @@ struct DwLds {
     static constexpr size_t bytes = (size_t)(x_elems + z_elems) * sizeof(__bf16);
 };
 
-typedef short v4i16 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) v4i16 lds_v4i16;
-
-// one MFMA operand (K = 8 pixels x 16 channels) from a [pixel][channel] LDS block: the two halves
-// read with the transposing load at this lane's pixel offsets o0 (h = 0) and o0 + 4 PS (h = 1)
-__device__ __forceinline__ bf16x8 ld_tr(const __bf16 *p, int o0, int ps)
-{
-    const auto *base = (const __attribute__((address_space(3))) char *)(p);
-    const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16 *)(base + 2 * o0));
-    const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16 *)(base + 2 * (o0 + 4 * ps)));
-    typedef short v8i16 __attribute__((ext_vector_type(8)));
-    const v8i16 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-    return __builtin_bit_cast(bf16x8, v);
-}
-
 template <int COUT>
 __global__ __launch_bounds__(kDwThreads) void k_conv_dw_strip(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dZ, int H,
                                                               int W, int seg, int units_per_strip, float *__restrict__ partial,
@@ -1474,26 +1490,44 @@ __global__ void k_from_planes(const double *__restrict__ phi, const double *__re
 // planes frames[c][f][y][x] (c = phi, v_x, v_y, rho), under symmetry k of the square lattice
 // (transpose if k & 4, then flip y if k & 2, then flip x if k & 1, velocity components swapped and
 // negated with it), converted as k_from_planes does.  The transform only moves and negates
-// values, so the result equals transforming the planes first.
-__global__ void k_gather_states(const double *__restrict__ frames, int64_t nframes, const int32_t *__restrict__ idx, int k, int B,
-                                int H, int W, float inv_u, float inv_r, float *__restrict__ s)
+// values, so the result equals transforming the planes first.  One workgroup per 32 x 32 tile of
+// one sample: the tile's source pixels are read along source rows (under a transposing symmetry
+// consecutive threads take consecutive tile rows, which are consecutive source columns), kept in
+// LDS converted, and written along state rows, so both sides stay coalesced.  Coordinates past
+// the box are clamped on the read side (branch-free) and skipped on the write side.
+constexpr int kGatherTile = 32;
+__global__ __launch_bounds__(256) void k_gather_states(const double *__restrict__ frames, int64_t nframes, const int32_t *__restrict__ idx, int k,
+                                                       int H, int W, float inv_u, float inv_r, float *__restrict__ s)
 {
-    const uint32_t hw = (uint32_t)H * W, total = (uint32_t)B * hw;
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
-        const uint32_t b = p / hw, rem = p - b * hw;
-        int y = (int)(rem / W), x = (int)(rem % W);
-        if (k & 2) y = H - 1 - y;
-        if (k & 1) x = W - 1 - x;
-        const int ys = (k & 4) ? x : y, xs = (k & 4) ? y : x;
-        const size_t plane = (size_t)nframes * hw, at = (size_t)idx[b] * hw + (size_t)ys * W + xs;
+    constexpr int T = kGatherTile, RPP = 256 / T;  // tile rows per pass of the workgroup
+    __shared__ f32x4 tile[T][T + 1];
+    const int tiles_x = (W + T - 1) / T, tiles = tiles_x * ((H + T - 1) / T);
+    const int b = blockIdx.x / tiles, rem = blockIdx.x % tiles;
+    const int ty0 = rem / tiles_x * T, tx0 = rem % tiles_x * T;
+    const size_t hw = (size_t)H * W, plane = (size_t)nframes * hw, base = (size_t)idx[b] * hw;
+    const bool tr = k & 4;
+    const int a = threadIdx.x % T, c = threadIdx.x / T;
+#pragma unroll
+    for (int m = 0; m < T / RPP; ++m) {
+        const int i = tr ? a : c + RPP * m, j = tr ? c + RPP * m : a;  // tile row, tile column
+        const int y = min(ty0 + i, H - 1), x = min(tx0 + j, W - 1);
+        const int yf = (k & 2) ? H - 1 - y : y, xf = (k & 1) ? W - 1 - x : x;
+        const int ys = tr ? xf : yf, xs = tr ? yf : xf;
+        const size_t at = base + (size_t)ys * W + xs;
         const double vx = frames[plane + at], vy = frames[2 * plane + at];
-        const double ux = (k & 4) ? vy : vx, uy = (k & 4) ? vx : vy;
+        const double ux = tr ? vy : vx, uy = tr ? vx : vy;
         f32x4 v;
         v[0] = (float)frames[at];
         v[1] = (float)((k & 1) ? -ux : ux) * inv_u;
         v[2] = (float)((k & 2) ? -uy : uy) * inv_u;
         v[3] = (float)(frames[3 * plane + at] - 1.0) * inv_r;
-        *(f32x4 *)(s + (size_t)p * kStateC) = v;
+        tile[i][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < T / RPP; ++m) {
+        const int i = c + RPP * m, y = ty0 + i, x = tx0 + a;
+        if (y < H && x < W) *(f32x4 *)(s + (((size_t)b * H + y) * W + x) * kStateC) = tile[i][a];
     }
 }
 
@@ -1965,8 +1999,9 @@ int lbcm_net_gather_states(lbcm_net *n, const double *frames, int64_t nframes, c
     for (int b = 0; b < n->batch; ++b)
         if (frame_index[b] < 0 || frame_index[b] >= nframes) return nfail(n, LBCM_EINVAL, "frame index out of range");
     NHIP(n, hipMemcpyAsync(n->gather_idx, frame_index, (size_t)n->batch * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
-    hipLaunchKernelGGL(k_gather_states, dim3(grid_of(n->P, 256)), dim3(256), 0, n->stream, frames, nframes, n->gather_idx, symmetry,
-                       n->batch, n->H, n->W, (float)(1.0 / u_scale), (float)(1.0 / rho_scale), state);
+    const int tiles = ((n->H + kGatherTile - 1) / kGatherTile) * ((n->W + kGatherTile - 1) / kGatherTile);
+    hipLaunchKernelGGL(k_gather_states, dim3(n->batch * tiles), dim3(256), 0, n->stream, frames, nframes, n->gather_idx, symmetry,
+                       n->H, n->W, (float)(1.0 / u_scale), (float)(1.0 / rho_scale), state);
     NHIP(n, hipGetLastError());
     return LBCM_OK;
 }

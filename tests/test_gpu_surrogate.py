@@ -485,18 +485,20 @@ def _dihedral(ph, vx, vy, rho, k):
     return ph, vx, vy, rho
 
 
-@pytest.mark.parametrize("k", range(8))
-def test_gather_states_applies_the_symmetry(k):
+@pytest.mark.parametrize("h,w,k", [(12, 12, k) for k in range(8)] + [(40, 40, k) for k in range(8)] +
+                         [(40, 72, k) for k in range(4)])
+def test_gather_states_applies_the_symmetry(h, w, k):
     """The training batch kernel equals, bit for bit, the symmetry applied to the FP64 planes
-    followed by the state conversion, for every element of the group."""
+    followed by the state conversion, for every element of the group (flips only on a
+    rectangle): one partial 32 x 32 tile, and several tiles with ragged edges."""
     import torch
 
-    _note(f"gather states k={k}")
-    n, nf, us, rs = 12, 5, 0.03, 0.01
-    frames = np.stack([np.stack(inputs.smooth_state(n, n, seed=40 + f)) for f in range(nf)], axis=1)
+    _note(f"gather states {h}x{w} k={k}")
+    nf, us, rs = 5, 0.03, 0.01
+    frames = np.stack([np.stack(inputs.smooth_state(w, h, seed=40 + f)) for f in range(nf)], axis=1)
     frames = frames[[0, 2, 3, 1]]  # smooth_state gives (phi, rho, ux, uy): reorder to (phi, vx, vy, rho)
-    m = net.Surrogate(2, n, n, channels=32, layers=2)
-    st = torch.empty(2, n, n, S, dtype=torch.float32, device="cuda")
+    m = net.Surrogate(2, h, w, channels=32, layers=2)
+    st = torch.empty(2, h, w, S, dtype=torch.float32, device="cuda")
     idx = [3, 1]
     m.gather_states(torch.from_numpy(np.ascontiguousarray(frames)).cuda(), idx, k, us, rs, st)
     got = st.cpu().numpy()
