@@ -279,9 +279,11 @@ __global__ __launch_bounds__(kFirstThreads) void k_first(const float *__restrict
 // dZ[pixels 8q .. 8q + 7][co0 + r] (transposing LDS reads) and B = one part of B[the same
 // pixels][col0 + r].  Workgroup b takes the tiles b, b + G, ... (G = the grid), staging each
 // tile's FP32 state patch and dZ in LDS with the next tile's global loads in flight; wave w takes
-// tile rows w and w + 4 and keeps all C / 16 x 3 output blocks in registers.  Its sums go to
-// partial row 4 b + w ([row][col][co], cols < kFirstRows), added in a fixed order by k_grad_reduce.
-constexpr int kFirstDwBlocks = 256;  // workgroups of k_first_dw at most
+// tile rows w and w + 4 and keeps all C / 16 x 3 output blocks in registers.  The workgroup's
+// sums go to partial row b ([row][col][co], cols < kFirstRows), added in a fixed order by
+// k_grad_reduce.  Two workgroups per CU keep twice the tile loads in flight (the loads of the
+// next tile are all that overlaps a tile's short MFMA work).
+constexpr int kFirstDwBlocks = 512;  // workgroups of k_first_dw at most
 constexpr int kFirstCols = 48;       // kFirstRows columns padded to three 16-column blocks
 
 template <int C>
@@ -382,8 +384,25 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[part][j], acc[i][j], 0, 0, 0);
         }
     }
-    // D of block (i, j): lane (r, q) holds co = 16 i + 4 q + e, col = 16 j + r
-    float *out = partial + ((size_t)blockIdx.x * 4 + w) * kFirstRows * C;
+    // D of block (i, j): lane (r, q) holds co = 16 i + 4 q + e, col = 16 j + r.  Waves 1 .. 3 hand
+    // their sums to wave 0 through LDS (over the dZ tile), which adds them in wave order and writes
+    // the workgroup's partial row b.
+    static_assert((kThreads / 64 - 1) * kFirstRows * C * sizeof(float) <= sizeof(sd), "three waves' sums fit the dZ tile");
+    float *red = reinterpret_cast<float *>(sd);
+    __syncthreads();  // every wave is done with the last tile
+    if (w > 0)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int col = 16 * j + r;
+            if (col < kFirstRows)
+#pragma unroll
+                for (int i = 0; i < NCB; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) red[((w - 1) * kFirstRows + col) * C + 16 * i + 4 * q + e] = acc[i][j][e];
+        }
+    __syncthreads();
+    if (w > 0) return;
+    float *out = partial + (size_t)blockIdx.x * kFirstRows * C;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const int col = 16 * j + r;
@@ -391,7 +410,13 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
 #pragma unroll
             for (int i = 0; i < NCB; ++i)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) out[(size_t)col * C + 16 * i + 4 * q + e] = acc[i][j][e];
+                for (int e = 0; e < 4; ++e) {
+                    const int o = col * C + 16 * i + 4 * q + e;
+                    float v = acc[i][j][e];
+#pragma unroll
+                    for (int u = 0; u < kThreads / 64 - 1; ++u) v += red[u * kFirstRows * C + o];
+                    out[o] = v;
+                }
     }
 }
 
@@ -1911,7 +1936,7 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
     if (!dmalloc((void **)&n->dw_partial, npartials * 9 * 64 * 64 * sizeof(float))) return bail("out of device memory (dW)");
     if (!dmalloc((void **)&n->db_partial, std::max<size_t>((P + 1023) / 1024, (size_t)n->dw_units) * 64 * sizeof(float)))
         return bail("out of device memory (db)");
-    if (!dmalloc((void **)&n->first_partial, 4 * std::min<size_t>(ntiles, kFirstDwBlocks) * kFirstRows * channels * sizeof(float)))
+    if (!dmalloc((void **)&n->first_partial, std::min<size_t>(ntiles, kFirstDwBlocks) * kFirstRows * channels * sizeof(float)))
         return bail("out of device memory (first layer)");
     n->loss_blocks = grid_of(P, 256) > 1024 ? 1024 : grid_of(P, 256);
     if (!dmalloc((void **)&n->loss_partial, n->loss_blocks * sizeof(float))) return bail("out of device memory (loss)");
@@ -2061,7 +2086,7 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
                            n->first_partial);
     NHIP(n, hipGetLastError());
     hipLaunchKernelGGL(k_grad_reduce, dim3((kFirstRows * n->C + 63) / 64), dim3(kSumWaves * 64), 0, n->stream, nullptr, 0, 0, 0, 0,
-                       0, nullptr, n->first_partial, 4 * fblocks, kFirstRows * n->C, kFirstRows * n->C, n->grads + n->w_off[0]);
+                       0, nullptr, n->first_partial, fblocks, kFirstRows * n->C, kFirstRows * n->C, n->grads + n->w_off[0]);
     NHIP(n, hipGetLastError());
     if (loss) {
         std::vector<float> part(n->loss_blocks);
