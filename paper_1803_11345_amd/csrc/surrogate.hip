@@ -671,6 +671,28 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
     }
 }
 
+// A BF16 output tile staged in LDS (pixel stride C + 8) to Y, in whole pixels: 16 bytes per
+// thread, consecutive threads on consecutive bytes of a tile row, through a buffer resource
+// spanning the tile's rows inside the box (pixels past the right edge get an offset past it,
+// which the hardware drops).
+template <int C>
+__device__ __forceinline__ void stage_store(const __bf16 *ystage, __bf16 *Y, TileCoord tc, int H, int W)
+{
+    constexpr int NCK = kTileH * kTileW * C / 8;  // 16-byte chunks of the tile
+    static_assert(NCK % kConvThreads == 0, "whole chunks per thread");
+    const int rows = min(kTileH, H - tc.y0);
+    const size_t tile_px = ((size_t)tc.n * H + tc.y0) * W;
+    const rsrc_t ry = make_rsrc(Y + tile_px * C, (uint32_t)rows * W * C * sizeof(__bf16));
+#pragma unroll
+    for (int i = 0; i < NCK / kConvThreads; ++i) {
+        const int k = threadIdx.x + i * kConvThreads, px = k / (C / 8), ch = (k % (C / 8)) * 8;
+        const int ty = px / kTileW, x = tc.x0 + px % kTileW;
+        const u32x4 v = *(const u32x4 *)(ystage + px * (C + 8) + ch);
+        const int off = x < W ? ((ty * W + x) * C + ch) * (int)sizeof(__bf16) : 0x7fffffff;
+        __builtin_amdgcn_raw_buffer_store_b128(v, ry, off, 0, 0);
+    }
+}
+
 // WIDE: the box has at least 8 rows and 32 columns (see Patch::load).
 template <int CIN, int COUT, int MODE, bool WIDE>
 __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict__ X, const __bf16 *__restrict__ Wp, OutArgs o,
@@ -1044,6 +1066,107 @@ __global__ __launch_bounds__(kConvThreads) void k_first_pair(PlaneIn pin, float 
 #pragma unroll
     for (int g = 0; g < GPW; ++g) lds_frags<C, C>(wl, cb + 16 * g + r, q, wb[g]);
     conv_tile<C, C, 0>(zs, wb, bias1, tc, o, H, W);
+}
+
+// ------------------------------------------------------------------------------------------
+// Input gradient of the last layer (training): dX[p][ci] = mask(p, ci) sum_t sum_co Wb[t][ci][co]
+// dZ[p + d_t][co] with Wb the mirrored pack (as k_conv's MODE 2), where only the kStateC state
+// channels of dZ can be nonzero.  The contraction runs over (tap, state channel), k = kStateC t + co
+// < 36 padded to two MFMA K steps of 32, instead of over the 32 padded channels of each tap (nine K
+// steps): lane (r, q) of K step s holds taps 8 s + 2 q and 8 s + 2 q + 1 (zero past tap 8), four
+// channels each, of weight row ci = 16 g + r (A) and of the pixel r of a 16-pixel block (B).  Only
+// the state channels of dZ are read (8 of the 64 bytes of a pixel).  A workgroup takes the tiles
+// b, b + G, ... (G the grid); wave w computes tile row w for every channel group; the dZ patch
+// (tile plus circular halo, 8 bytes per pixel) goes through LDS, the next tile's requested during
+// this one, and so does the output tile, stored in whole pixels.  Products are exact (BF16 x BF16) and summed in FP32, in another order than a
+// per-tap K step would take.
+constexpr int kLastDgradBlocks = 1024;  // workgroups of k_last_dgrad at most
+template <int C>
+__global__ __launch_bounds__(kConvThreads) void k_last_dgrad(const __bf16 *__restrict__ dZ, const __bf16 *__restrict__ Wb,
+                                                             const uint8_t *__restrict__ mask, __bf16 *__restrict__ dX, int ntiles,
+                                                             int H, int W)
+{
+    constexpr int NG = C / 16, NPX = kPatchH * kPatchW;
+    static_assert(kStateC == 4 && NPX <= kConvThreads && kConvThreads / 64 == kTileH && kTileW == 32,
+                  "one patch pixel per thread, one tile row per wave, two 16-pixel blocks per row");
+    constexpr int PSY = C + 8;  // pixel stride of the staged output tile (bf16)
+    __shared__ u32x2 zp[NPX];  // the patch's state channels, four BF16 per pixel
+    __shared__ __align__(16) __bf16 ys[kTileH * kTileW * PSY];  // the output tile
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = lane & 15, q = lane >> 4;
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    // taps of this lane's two halves of K step s (t >= 9 is padding: read tap 8, use zero)
+    auto tap = [&](int s, int h) { return 8 * s + 2 * q + h; };
+    bf16x8 wa[NG][2];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            u32x2 v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = tap(s, h);
+                const u32x2 x = *(const u32x2 *)(Wb + ((size_t)min(t, 8) * C + 16 * g + r) * kOutC);
+                v[h] = t < 9 ? x : u32x2{0, 0};
+            }
+            wa[g][s] = __builtin_bit_cast(bf16x8, u32x4{v[0][0], v[0][1], v[1][0], v[1][1]});
+        }
+    auto load = [&](int tl) {
+        const TileCoord tc = tile_coord(tl, H, W);
+        const int k = min((int)threadIdx.x, NPX - 1);
+        const int gy = wrap_near(tc.y0 - 1 + k / kPatchW, H), gx = wrap_near(tc.x0 - 1 + k % kPatchW, W);
+        return *(const u32x2 *)(dZ + (((size_t)tc.n * H + gy) * W + gx) * kOutC);
+    };
+    u32x2 pre = load(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const TileCoord tc = tile_coord(tile, H, W);
+        if ((int)threadIdx.x < NPX) zp[threadIdx.x] = pre;
+        __syncthreads();
+        pre = load(min(tile + (int)gridDim.x, ntiles - 1));
+        f32x4 acc[2][NG];
+#pragma unroll
+        for (int hb = 0; hb < 2; ++hb) {
+            bf16x8 b[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                u32x2 v[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int t = min(tap(s, h), 8);
+                    const u32x2 x = zp[(w + 1 + tap_dy(t)) * kPatchW + 16 * hb + r + 1 + tap_dx(t)];
+                    v[h] = tap(s, h) < 9 ? x : u32x2{0, 0};
+                }
+                b[s] = __builtin_bit_cast(bf16x8, u32x4{v[0][0], v[0][1], v[1][0], v[1][1]});
+            }
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                acc[hb][g] = f32x4{0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < 2; ++s) acc[hb][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[g][s], b[s], acc[hb][g], 0, 0, 0);
+            }
+        }
+        // lane (r, q) holds channels 16 g + 4 q .. + 3 of pixel r of block hb: times the ReLU mask of
+        // the layer input, staged in LDS, then stored in whole pixels
+        const int yy = min(tc.y0 + w, H - 1);
+#pragma unroll
+        for (int hb = 0; hb < 2; ++hb) {
+            const size_t p = ((size_t)tc.n * H + yy) * W + min(tc.x0 + 16 * hb + r, W - 1);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const int c0 = 16 * g + 4 * q;
+                const uint32_t m = mask[p * (C / 4) + c0 / 4];
+                bf16x4 v4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v4[e] = (__bf16)(((m >> e) & 1u) ? acc[hb][g][e] : 0.f);
+                *(u32x2 *)(ys + (w * kTileW + 16 * hb + r) * PSY + c0) = __builtin_bit_cast(u32x2, v4);
+            }
+        }
+        __syncthreads();
+        stage_store<C>(ys, dX, tc, H, W);
+        __syncthreads();  // every wave is done with the patch and the staged tile
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1727,7 +1850,6 @@ int launch_conv(lbcm_net *n, const __bf16 *X, int cin, const __bf16 *Wp, int cou
     if (cin == 64 && cout == 64 && mode == 2) return launch_conv_t<64, 64, 2>(n, X, Wp, o);
     if (cin == 64 && cout == 32 && mode == 1) return launch_conv_t<64, 32, 1>(n, X, Wp, o);
     if (cin == 64 && cout == 32 && mode == 3) return launch_conv_t<64, 32, 3>(n, X, Wp, o);
-    if (cin == 32 && cout == 64 && mode == 2) return launch_conv_t<32, 64, 2>(n, X, Wp, o);
     if (cin == 32 && cout == 32 && mode == 0) return launch_conv_t<32, 32, 0>(n, X, Wp, o);
     if (cin == 32 && cout == 32 && mode == 1) return launch_conv_t<32, 32, 1>(n, X, Wp, o);
     if (cin == 32 && cout == 32 && mode == 3) return launch_conv_t<32, 32, 3>(n, X, Wp, o);
@@ -2066,12 +2188,22 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
                            n->cin[l], n->cout[l], n->cin_r[l], n->cout_r[l], n->grads + n->w_off[l], n->db_partial, db_rows, 64,
                            n->cout[l], n->grads + n->b_off[l]);
         NHIP(n, hipGetLastError());
-        // gradient of the layer input times the ReLU derivative of that input (act[l] > 0)
-        OutArgs o{};
-        o.mask = n->mask8[l];
-        o.Y = dn;
-        int rc = launch_conv(n, dz, n->cout[l], n->Wb[l], n->cin[l], 2, o);
-        if (rc) return rc;
+        // gradient of the layer input times the ReLU derivative of that input (act[l] > 0); the last
+        // layer's contracts over (tap, state channel) only
+        if (dz == n->dz_last) {
+            const dim3 g(std::min(n->ntiles, kLastDgradBlocks)), b(kConvThreads);
+            if (n->cin[l] == 64)
+                hipLaunchKernelGGL(k_last_dgrad<64>, g, b, 0, n->stream, dz, n->Wb[l], n->mask8[l], dn, n->ntiles, n->H, n->W);
+            else
+                hipLaunchKernelGGL(k_last_dgrad<32>, g, b, 0, n->stream, dz, n->Wb[l], n->mask8[l], dn, n->ntiles, n->H, n->W);
+            NHIP(n, hipGetLastError());
+        } else {
+            OutArgs o{};
+            o.mask = n->mask8[l];
+            o.Y = dn;
+            int rc = launch_conv(n, dz, n->cout[l], n->Wb[l], n->cin[l], 2, o);
+            if (rc) return rc;
+        }
         __bf16 *spare = dz == n->dz_last ? n->dz_b : dz;  // the next layer's input gradient goes to a 64-channel buffer
         dz = dn;
         dn = spare;
