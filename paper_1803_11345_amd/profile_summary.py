@@ -131,10 +131,10 @@ SURROGATE_WORK = {
     "k_conv<64, 64, 0>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
     "k_conv<64, 32, 1>": (2 * _PX8 * 9 * 64 * 32, "BF16 MFMA", 2500.0),
     "k_conv<64, 64, 2>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
-    "k_conv<32, 64, 2>": (2 * _PX8 * 9 * 32 * 64, "BF16 MFMA", 2500.0),
+    "k_last_dgrad<64>": (2 * _PX8 * 64 * 64, "BF16 MFMA (K = 36 taps x state channels, padded to 64)", 2500.0),
     "k_conv_dw_strip<64>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
     "k_conv_dw_strip<32>": (2 * _PX8 * 9 * 64 * 32, "BF16 MFMA", 2500.0),
-    "k_first_dw<64>": (2 * _PX8 * 9 * 4 * 64, "FP32 MFMA", 157.3),
+    "k_first_dw<64>": (3 * 2 * _PX8 * 48 * 64, "BF16 MFMA (state split in three parts, 48 columns)", 2500.0),
 }
 
 
