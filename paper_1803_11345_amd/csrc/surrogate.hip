@@ -1170,6 +1170,158 @@ __global__ __launch_bounds__(kConvThreads) void k_last_dgrad(const __bf16 *__res
 }
 
 // ------------------------------------------------------------------------------------------
+// Weight and bias gradients of the last layer (training), whose output gradient dZ can be nonzero
+// only in its kStateC state channels.  dW[t][ci][co] = sum_p X[p + d_t][ci] dZ[p][co] = sum_p
+// X[p][ci] dZ[p - d_t][co] (the box is periodic), so the tap shifts dZ instead of X and one GEMM
+// covers every tap: M = ci (C / 16 blocks), N = (tap, state channel), col = kStateC t + co < 36 in
+// three 16-column blocks, K = the 32 pixels of a tile row.  Lane (r, q) holds A = X[pixels 8q ..
+// 8q + 7][ci0 + r] (transposing LDS reads of the unshifted tile) and B = dZ[those pixels - d_t][co]
+// of its column (zero past column 35).  db[co] = sum_p dZ[p][co]: thread t sums tile pixel t.  A
+// workgroup takes the tiles b, b + G, ... (G the grid), staging the X tile (zero past the box
+// edge) and the state channels of dZ on the tile plus its circular halo in LDS, with the next
+// tile's loads in flight; wave w takes tile rows w and w + 4.  The waves' sums are added in LDS in
+// wave order: partial row b holds dW[t][ci][co < kStateC], bias row b db[co < 64] (zero past
+// kStateC), both added in a fixed order by k_grad_reduce.
+constexpr int kLastDwBlocks = 512;  // workgroups of k_last_dw at most
+template <int C>
+__global__ __launch_bounds__(kThreads) void k_last_dw(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dZ, int H, int W,
+                                                      int ntiles, float *__restrict__ partial, float *__restrict__ db_partial)
+{
+    constexpr int NI = C / 16, NJ = 3, NCOL = 9 * kStateC, PSX = C + 8, NPX = kPatchH * kPatchW;
+    constexpr int NX = kTileH * kTileW * C / 8, NIX = NX / kThreads;  // 16-byte chunks of the X tile
+    constexpr int NIZ = (NPX + kThreads - 1) / kThreads;
+    static_assert(kStateC == 4 && NCOL <= 16 * NJ && NX % kThreads == 0, "column blocks and X chunks");
+    static_assert(kTileW == 32 && kTileH == 2 * (kThreads / 64) && kThreads == kTileH * kTileW,
+                  "a K step is one tile row, each wave takes two, one thread per tile pixel");
+    __shared__ __align__(16) __bf16 xs[kTileH * kTileW * PSX];
+    __shared__ u32x2 zp[NPX];  // state channels of dZ on the patch, four BF16 per pixel
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = lane & 15, q = lane >> 4;
+    const int opix = 8 * (lane >> 4) + ((lane & 15) >> 2), och = 4 * (lane & 3);
+    // this lane's B columns: offset of patch pixel p - d_t from that of p, and the state channel
+    int zoff[NJ], zco[NJ];
+    bool zok[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int col = 16 * j + r, t = min(col / kStateC, 8);
+        zok[j] = col < NCOL;
+        zoff[j] = (1 - tap_dy(t)) * kPatchW + 1 - tap_dx(t);
+        zco[j] = col % kStateC;
+    }
+    f32x4 acc[NI][NJ];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    float bsum[kStateC] = {0, 0, 0, 0};
+    u32x4 vx[NIX];
+    u32x2 vz[NIZ];
+    auto load = [&](int tile) {
+        const TileCoord tc = tile_coord(tile, H, W);
+#pragma unroll
+        for (int i = 0; i < NIX; ++i) {
+            const int k = threadIdx.x + i * kThreads, px = k / (C / 8), ch = (k % (C / 8)) * 8;
+            const int y = tc.y0 + px / kTileW, x = tc.x0 + px % kTileW;
+            vx[i] = u32x4{0, 0, 0, 0};
+            if (y < H && x < W) vx[i] = *(const u32x4 *)(X + (((size_t)tc.n * H + y) * W + x) * C + ch);
+        }
+#pragma unroll
+        for (int i = 0; i < NIZ; ++i) {
+            const int k = min((int)threadIdx.x + i * kThreads, NPX - 1);
+            const int gy = wrap_near(tc.y0 - 1 + k / kPatchW, H), gx = wrap_near(tc.x0 - 1 + k % kPatchW, W);
+            vz[i] = *(const u32x2 *)(dZ + (((size_t)tc.n * H + gy) * W + gx) * kOutC);
+        }
+    };
+    int tile = blockIdx.x;
+    if (tile < ntiles) load(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const TileCoord tc = tile_coord(tile, H, W);
+        __syncthreads();  // every wave is done with the previous tile's LDS
+#pragma unroll
+        for (int i = 0; i < NIX; ++i) {
+            const int k = threadIdx.x + i * kThreads;
+            *(u32x4 *)(xs + (k / (C / 8)) * PSX + (k % (C / 8)) * 8) = vx[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NIZ; ++i) {
+            const int k = threadIdx.x + i * kThreads;
+            if (k < NPX) zp[k] = vz[i];
+        }
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
+        {
+            const int ty = threadIdx.x / kTileW, tx = threadIdx.x % kTileW;
+            if (tc.y0 + ty < H && tc.x0 + tx < W) {
+                const bf16x4 z = __builtin_bit_cast(bf16x4, zp[(ty + 1) * kPatchW + tx + 1]);
+#pragma unroll
+                for (int c = 0; c < kStateC; ++c) bsum[c] += (float)z[c];
+            }
+        }
+        const __bf16 *zb = reinterpret_cast<const __bf16 *>(zp);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int y = w + (kThreads / 64) * h;  // tile row
+            bf16x8 a[NI], b[NJ];
+#pragma unroll
+            for (int i = 0; i < NI; ++i) a[i] = ld_tr(xs + y * kTileW * PSX, opix * PSX + 16 * i + och, PSX);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const __bf16 v = zb[((y * kPatchW + 8 * q + e) + zoff[j]) * kStateC + zco[j]];
+                    b[j][e] = zok[j] ? v : (__bf16)0.f;
+                }
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // D of block (i, j): lane (r, q) holds ci = 16 i + 4 q + e, col = 16 j + r.  Waves 1 .. 3 and
+    // every thread's bias sums go to LDS (over the X tile); wave 0 adds them in order.
+    constexpr int NW = kThreads / 64;
+    static_assert(((NW - 1) * NCOL * C + kThreads * kStateC) * sizeof(float) <= sizeof(xs), "the sums fit the X tile");
+    float *red = reinterpret_cast<float *>(xs), *bred = red + (NW - 1) * NCOL * C;
+    __syncthreads();
+    if (w > 0)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int col = 16 * j + r;
+            if (col < NCOL)
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) red[((w - 1) * NCOL + col) * C + 16 * i + 4 * q + e] = acc[i][j][e];
+        }
+#pragma unroll
+    for (int c = 0; c < kStateC; ++c) bred[threadIdx.x * kStateC + c] = bsum[c];
+    __syncthreads();
+    if (w > 0) return;
+    {
+        float sb = 0;
+        if (lane < kStateC)
+            for (int t = 0; t < kThreads; ++t) sb += bred[t * kStateC + lane];
+        db_partial[(size_t)blockIdx.x * 64 + lane] = sb;
+    }
+    float *out = partial + (size_t)blockIdx.x * 9 * C * kStateC;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int col = 16 * j + r;
+        if (col < NCOL)
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ci = 16 * i + 4 * q + e;
+                    float v = acc[i][j][e];
+#pragma unroll
+                    for (int u = 0; u < NW - 1; ++u) v += red[(u * NCOL + col) * C + ci];
+                    out[((col / kStateC) * C + ci) * kStateC + col % kStateC] = v;
+                }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // weight gradient of layers with 32 input channels (64: k_conv_dw_strip below):
 // partial[chunk][t][ci][co] = sum over the chunk's pixels p of X[p + d_t][ci] dZ[p][co].  A
 // workgroup owns one tap and one chunk; it stages 64 pixels of X (shifted) and dZ in LDS with
@@ -2054,9 +2206,13 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
         n->dw_units_per_strip = (height + n->dw_seg - 1) / n->dw_seg;
         n->dw_units = (int)((size_t)batch * nstrips * n->dw_units_per_strip);
     }
-    const size_t npartials = std::max<size_t>(nchunks, (size_t)n->dw_units);
-    if (!dmalloc((void **)&n->dw_partial, npartials * 9 * 64 * 64 * sizeof(float))) return bail("out of device memory (dW)");
-    if (!dmalloc((void **)&n->db_partial, std::max<size_t>((P + 1023) / 1024, (size_t)n->dw_units) * 64 * sizeof(float)))
+    // weight partial rows: of the generic and strip kernels (up to 9 x 64 x 64 each) and of the last
+    // layer's (9 x 64 x kStateC each); bias partial rows of 64
+    const size_t last_rows = std::min<size_t>(ntiles, kLastDwBlocks);
+    const size_t wfloats = std::max<size_t>(std::max<size_t>(nchunks, (size_t)n->dw_units) * 9 * 64 * 64, last_rows * 9 * 64 * kStateC);
+    if (!dmalloc((void **)&n->dw_partial, wfloats * sizeof(float))) return bail("out of device memory (dW)");
+    if (!dmalloc((void **)&n->db_partial,
+                 std::max<size_t>(std::max<size_t>((P + 1023) / 1024, (size_t)n->dw_units), last_rows) * 64 * sizeof(float)))
         return bail("out of device memory (db)");
     if (!dmalloc((void **)&n->first_partial, std::min<size_t>(ntiles, kFirstDwBlocks) * kFirstRows * channels * sizeof(float)))
         return bail("out of device memory (first layer)");
@@ -2166,26 +2322,33 @@ int lbcm_net_backward(lbcm_net *n, const float *target, float *loss)
     const int dbb = (int)((P + 1023) / 1024);
     for (int l = L - 1; l >= 1; --l) {
         // weight and bias gradients of layer l from its input act[l] and dz (gradient of its output)
-        int parts = nchunks;
-        const bool strip = n->cin[l] == 64 && (n->cout[l] == 64 || n->cout[l] == 32);
-        if (strip) {
-            parts = n->dw_units;
-            const int rc = n->cout[l] == 64 ? launch_dw_strip<64>(n, n->act[l], dz) : launch_dw_strip<32>(n, n->act[l], dz);
+        // (partial rows of the padded shape wcin x wcout, and bias partial rows)
+        int parts = nchunks, db_rows = 0, wcout = n->cout[l];
+        if (dz == n->dz_last) {
+            // the last layer: only the state channels of dz
+            parts = db_rows = std::min(n->ntiles, kLastDwBlocks);
+            wcout = kStateC;
+            if (n->cin[l] == 64)
+                hipLaunchKernelGGL(k_last_dw<64>, dim3(parts), dim3(kThreads), 0, n->stream, n->act[l], dz, n->H, n->W, n->ntiles,
+                                   n->dw_partial, n->db_partial);
+            else
+                hipLaunchKernelGGL(k_last_dw<32>, dim3(parts), dim3(kThreads), 0, n->stream, n->act[l], dz, n->H, n->W, n->ntiles,
+                                   n->dw_partial, n->db_partial);
+        } else if (n->cin[l] == 64 && n->cout[l] == 64) {
+            parts = db_rows = n->dw_units;  // the strip kernel leaves one bias partial per work unit
+            const int rc = launch_dw_strip<64>(n, n->act[l], dz);
             if (rc) return rc;
         } else {
             hipLaunchKernelGGL(k_conv_dw, dim3(nchunks, 9), dim3(kThreads), 0, n->stream, n->act[l], n->cin[l], dz, n->cout[l], P,
                                n->H, n->W, n->dw_partial);
-        }
-        NHIP(n, hipGetLastError());
-        int db_rows = parts;  // the strip kernel left one bias partial per work unit
-        if (!strip) {
-            hipLaunchKernelGGL(k_db_partial, dim3(dbb), dim3(256), 0, n->stream, dz, n->cout[l], P, n->db_partial);
             NHIP(n, hipGetLastError());
+            hipLaunchKernelGGL(k_db_partial, dim3(dbb), dim3(256), 0, n->stream, dz, n->cout[l], P, n->db_partial);
             db_rows = dbb;
         }
+        NHIP(n, hipGetLastError());
         const int wblocks = (9 * n->cin_r[l] * n->cout_r[l] + 63) / 64, bblocks = (n->cout[l] + 63) / 64;
         hipLaunchKernelGGL(k_grad_reduce, dim3(wblocks + bblocks), dim3(kSumWaves * 64), 0, n->stream, n->dw_partial, parts,
-                           n->cin[l], n->cout[l], n->cin_r[l], n->cout_r[l], n->grads + n->w_off[l], n->db_partial, db_rows, 64,
+                           n->cin[l], wcout, n->cin_r[l], n->cout_r[l], n->grads + n->w_off[l], n->db_partial, db_rows, 64,
                            n->cout[l], n->grads + n->b_off[l]);
         NHIP(n, hipGetLastError());
         // gradient of the layer input times the ReLU derivative of that input (act[l] > 0); the last
