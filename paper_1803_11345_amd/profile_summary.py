@@ -133,7 +133,7 @@ SURROGATE_WORK = {
     "k_conv<64, 64, 2>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
     "k_last_dgrad<64>": (2 * _PX8 * 64 * 64, "BF16 MFMA (K = 36 taps x state channels, padded to 64)", 2500.0),
     "k_conv_dw_strip<64>": (2 * _PX8 * 9 * 64 * 64, "BF16 MFMA", 2500.0),
-    "k_conv_dw_strip<32>": (2 * _PX8 * 9 * 64 * 32, "BF16 MFMA", 2500.0),
+    "k_last_dw<64>": (2 * _PX8 * 64 * 48, "BF16 MFMA (N = 36 taps x state channels, padded to 48)", 2500.0),
     "k_first_dw<64>": (3 * 2 * _PX8 * 48 * 64, "BF16 MFMA (state split in three parts, 48 columns)", 2500.0),
 }
 
