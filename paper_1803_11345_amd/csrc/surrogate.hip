@@ -61,7 +61,7 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
 
 constexpr int kStateC = 4;        // phi, v_x, v_y, rho (channel order of the state)
 constexpr int kFirstRows = 9 * kStateC + 1;  // layer-0 weight rows (tap, channel) and the bias row
-constexpr int kOutC = 32;         // padded output channels of the last layer (a K step of its input gradient)
+constexpr int kOutC = 32;         // padded output channels of the last layer (two groups: the forward's wave split)
 constexpr int kThreads = 256;     // four waves
 constexpr int kTileH = 8;         // conv tile: 8 rows x 32 columns of one sample
 constexpr int kTileW = 32;
@@ -1074,8 +1074,8 @@ __global__ __launch_bounds__(kConvThreads) void k_first_pair(PlaneIn pin, float 
 // channels of dZ can be nonzero.  The contraction runs over (tap, state channel), k = kStateC t + co
 // < 36 padded to two MFMA K steps of 32, instead of over the 32 padded channels of each tap (nine K
 // steps): lane (r, q) of K step s holds taps 8 s + 2 q and 8 s + 2 q + 1 (zero past tap 8), four
-// channels each, of weight row ci = 16 g + r (A) and of the pixel r of a 16-pixel block (B).  Only
-// the state channels of dZ are read (8 of the 64 bytes of a pixel).  A workgroup takes the tiles
+// channels each, of weight row ci = 16 g + r (A) and of the pixel r of a 16-pixel block (B).  dZ
+// holds only the state channels ([P][kStateC], as the loss writes it).  A workgroup takes the tiles
 // b, b + G, ... (G the grid); wave w computes tile row w for every channel group; the dZ patch
 // (tile plus circular halo, 8 bytes per pixel) goes through LDS, the next tile's requested during
 // this one, and so does the output tile, stored in whole pixels.  Products are exact (BF16 x BF16) and summed in FP32, in another order than a
@@ -1117,11 +1117,21 @@ __global__ __launch_bounds__(kConvThreads) void k_last_dgrad(const __bf16 *__res
         const TileCoord tc = tile_coord(tl, H, W);
         const int k = min((int)threadIdx.x, NPX - 1);
         const int gy = wrap_near(tc.y0 - 1 + k / kPatchW, H), gx = wrap_near(tc.x0 - 1 + k % kPatchW, W);
-        return *(const u32x2 *)(dZ + (((size_t)tc.n * H + gy) * W + gx) * kOutC);
+        return *(const u32x2 *)(dZ + (((size_t)tc.n * H + gy) * W + gx) * kStateC);
     };
     u32x2 pre = load(tile);
     for (; tile < ntiles; tile += gridDim.x) {
         const TileCoord tc = tile_coord(tile, H, W);
+        // the ReLU mask bytes of this lane's outputs, requested first (channels 16 g + 4 q .. + 3 of
+        // pixel r of block hb in tile row w; clamped into the box)
+        uint32_t mv[2][NG];
+        const int yy = min(tc.y0 + w, H - 1);
+#pragma unroll
+        for (int hb = 0; hb < 2; ++hb) {
+            const size_t p = ((size_t)tc.n * H + yy) * W + min(tc.x0 + 16 * hb + r, W - 1);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) mv[hb][g] = mask[p * (C / 4) + 4 * g + q];
+        }
         if ((int)threadIdx.x < NPX) zp[threadIdx.x] = pre;
         __syncthreads();
         pre = load(min(tile + (int)gridDim.x, ntiles - 1));
@@ -1149,14 +1159,12 @@ __global__ __launch_bounds__(kConvThreads) void k_last_dgrad(const __bf16 *__res
         }
         // lane (r, q) holds channels 16 g + 4 q .. + 3 of pixel r of block hb: times the ReLU mask of
         // the layer input, staged in LDS, then stored in whole pixels
-        const int yy = min(tc.y0 + w, H - 1);
 #pragma unroll
         for (int hb = 0; hb < 2; ++hb) {
-            const size_t p = ((size_t)tc.n * H + yy) * W + min(tc.x0 + 16 * hb + r, W - 1);
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                 const int c0 = 16 * g + 4 * q;
-                const uint32_t m = mask[p * (C / 4) + c0 / 4];
+                const uint32_t m = mv[hb][g];
                 bf16x4 v4;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v4[e] = (__bf16)(((m >> e) & 1u) ? acc[hb][g][e] : 0.f);
@@ -1229,7 +1237,7 @@ __global__ __launch_bounds__(kThreads) void k_last_dw(const __bf16 *__restrict__
         for (int i = 0; i < NIZ; ++i) {
             const int k = min((int)threadIdx.x + i * kThreads, NPX - 1);
             const int gy = wrap_near(tc.y0 - 1 + k / kPatchW, H), gx = wrap_near(tc.x0 - 1 + k % kPatchW, W);
-            vz[i] = *(const u32x2 *)(dZ + (((size_t)tc.n * H + gy) * W + gx) * kOutC);
+            vz[i] = *(const u32x2 *)(dZ + (((size_t)tc.n * H + gy) * W + gx) * kStateC);
         }
     };
     int tile = blockIdx.x;
@@ -1686,7 +1694,7 @@ __global__ __launch_bounds__(256) void k_db_partial(const __bf16 *__restrict__ d
 // ------------------------------------------------------------------------------------------
 // loss: mean over pixels and the kStateC state channels of ((pred - target) / alpha_c)^2; the
 // gradient of the last layer's pre-scale output is 2 (pred - target) / (alpha_c kStateC P), stored
-// in the first kStateC of kOutC channels of a buffer whose other channels are zero (cleared once).
+// as [P][kStateC] BF16 (the last layer's gradient kernels read only these channels).
 __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ pred, const float *__restrict__ target, uint32_t P,
                                               float ia0, float ia1, float ia2, float ia3, __bf16 *__restrict__ dZ,
                                               float *__restrict__ partial)
@@ -1704,7 +1712,7 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ pred, co
             s += d * d;
             g[c] = (__bf16)(scale * d);
         }
-        *(u32x2 *)(dZ + (size_t)p * kOutC) = __builtin_bit_cast(u32x2, g);  // channels kStateC .. kOutC - 1 stay zero
+        *(u32x2 *)(dZ + (size_t)p * kStateC) = __builtin_bit_cast(u32x2, g);
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -1882,7 +1890,7 @@ struct lbcm_net {
     std::vector<__bf16 *> act;                  // act[l] = input of layer l >= 1 (relu output of layer l - 1)
     std::vector<uint8_t *> mask8;               // ReLU mask of act[l] from the training forward (bit e of byte [p][c / 4]: act > 0)
     __bf16 *dz_a = nullptr, *dz_b = nullptr;    // gradient ping-pong buffers (P x 64)
-    __bf16 *dz_last = nullptr;                  // gradient of the last layer's output (P x kOutC, padding zero)
+    __bf16 *dz_last = nullptr;                  // gradient of the last layer's output, state channels (P x kStateC)
     PackEntry *pack_table = nullptr;            // where the Adam update writes the BF16 packs of layers 1 .. L-1
     int32_t *gather_idx = nullptr;              // frame indices of lbcm_net_gather_states (batch)
     float *resid = nullptr, *out = nullptr;     // FP32 [P][kStateC]: input state, output state
@@ -2181,9 +2189,8 @@ int lbcm_net_create(int32_t batch, int32_t height, int32_t width, int32_t channe
         if (!dmalloc((void **)&n->act[l], P * channels * sizeof(__bf16)) || !dmalloc((void **)&n->mask8[l], P * (channels / 4)))
             return bail("out of device memory (activations)");
     if (!dmalloc((void **)&n->dz_a, P * 64 * sizeof(__bf16)) || !dmalloc((void **)&n->dz_b, P * 64 * sizeof(__bf16)) ||
-        !dmalloc((void **)&n->dz_last, P * kOutC * sizeof(__bf16)))
+        !dmalloc((void **)&n->dz_last, P * kStateC * sizeof(__bf16)))
         return bail("out of device memory (gradients)");
-    if (hipMemsetAsync(n->dz_last, 0, P * kOutC * sizeof(__bf16), n->stream) != hipSuccess) return bail("hipMemsetAsync failed");
     {
         std::vector<PackEntry> tab;
         for (int l = 1; l < layers; ++l)
