@@ -425,9 +425,9 @@ __global__ __launch_bounds__(kThreads) void k_first_dw(const float *__restrict__
 // gradient with the mirrored pack).
 //
 // The workgroup (8 waves) stages the layer's weights once and the 10 x 34 input patch (tile plus
-// circular halo) of each tile in dynamic LDS, with row strides padded by 16 bytes so that the 16
-// rows of a fragment fall in distinct banks; the next tile's patch is loaded during the current
-// tile's MFMAs (WaveSplit below gives each wave its output channels and rows).  A wave keeps its
+// circular halo) of each tile in dynamic LDS, with pixel strides padded by 32 bytes (weight rows
+// by 16) to spread the rows of a fragment over the banks; the next tile's patch is loaded during
+// the current tile's MFMAs (WaveSplit below gives each wave its output channels and rows).  A wave keeps its
 // weight fragments (9 taps x CIN / 32 K-steps per channel group) in registers for the whole
 // launch, as the MFMA A operand, and takes 16 pixels as the B operand, so that each lane ends
 // with 4 consecutive output channels of one pixel (one 8-byte store).  Tiles past the grid are
@@ -455,7 +455,7 @@ struct OutArgs {
 
 template <int CIN>
 struct Patch {
-    static constexpr int PS = CIN + 8;  // LDS pixel stride (bf16)
+    static constexpr int PS = CIN + 16;  // LDS pixel stride (bf16)
     static constexpr int NV = kPatchH * kPatchW * (CIN / 8), NI = (NV + kConvThreads - 1) / kConvThreads;
     u32x4 v[NI];
 
@@ -495,7 +495,7 @@ struct Patch {
 template <int CIN, int COUT>
 struct ConvLds {
     static constexpr int PS = Patch<CIN>::PS;        // patch pixel stride (bf16)
-    static constexpr int WS = CIN + 8;               // weight row stride (bf16), padded like the patch
+    static constexpr int WS = CIN + 8;               // weight row stride (bf16)
     static constexpr int patch_elems = kPatchH * kPatchW * PS;
     static constexpr int weight_elems = 9 * COUT * WS;
     static constexpr int mask_bytes = kTileH * kTileW * (COUT / 4);  // ReLU mask bytes of a tile (training forward)
@@ -522,7 +522,7 @@ struct WaveSplit {
 };
 
 // One output tile of a conv layer from its input patch in LDS (the tile plus a one-pixel halo,
-// 10 x 34 pixels, pixel stride CIN + 8), with this wave's A fragments wa[g] (W[t][co = cbase +
+// 10 x 34 pixels, pixel stride CIN + 16), with this wave's A fragments wa[g] (W[t][co = cbase +
 // 16 g + r][ci = 32 ks + 8 q .. + 8] in lane (r, q)) and the biases of its output channels.
 // Input-stationary order: each pixel fragment of the wave's RW + 2 patch rows (its column half) is
 // read from LDS once and applied to every output row (tap dy) and channel group that uses it.
@@ -536,7 +536,7 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
                                           const float (&bias)[WaveSplit<COUT, MODE>::GPW][4], TileCoord tc, const OutArgs &o,
                                           int H, int W, uint8_t *mstage = nullptr)
 {
-    constexpr int PS = CIN + 8, KS = CIN / 32;
+    constexpr int PS = CIN + 16, KS = CIN / 32;
     using S = WaveSplit<COUT, MODE>;
     constexpr int RW = S::RW, GPW = S::GPW, HPW = S::HPW;
     const int lane = threadIdx.x & 63;
@@ -800,7 +800,7 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const __bf16 *__restrict_
 // done, when Z also replaces the patch.  LDS: patch (then Z) and one layer's weights.
 
 struct PairLds {
-    static constexpr int C = 64, PS = C + 8, WS = C + 8;
+    static constexpr int C = 64, PS = C + 16, WS = C + 8;
     static constexpr int XH = kTileH + 4, XW = kTileW + 4;  // input patch
     static constexpr int ZH = kTileH + 2, ZW = kTileW + 2;  // intermediate (written over the patch)
     static constexpr int x_elems = XH * XW * PS, z_elems = ZH * ZW * PS;
@@ -811,7 +811,7 @@ static_assert(PairLds::z_elems <= PairLds::x_elems, "Z fits where the patch was"
 static_assert(PairLds::ZW == kPatchW && PairLds::ZH == kPatchH, "layer b reads Z as a conv patch");
 
 // One layer's packed weights Wp[t][co][ci] (PACK output channels per tap, of which the first
-// COUT are staged) on their way to LDS (rows of CIN padded to CIN + 8, as the patch), in the
+// COUT are staged) on their way to LDS (rows of CIN padded to CIN + 8), in the
 // registers of all threads of the workgroup: load() issues the global loads, store() writes
 // them to LDS once they have arrived.
 template <int CIN, int COUT, int PACK = COUT>

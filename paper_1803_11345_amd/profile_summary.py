@@ -138,6 +138,23 @@ SURROGATE_WORK = {
 }
 
 
+# Algorithmic HBM bytes per launch of the training kernels at batch 8 x 256^2 (each tensor once:
+# BF16 activations and gradients of 64 channels 128 B per pixel, ReLU masks 16 B, FP32 states
+# 16 B, the 4 state channels of the last layer's output gradient 8 B, FP32 partial sums as
+# written; halo re-reads not counted), against the 8 TB/s HBM peak.
+_A64, _MASK, _ST, _DZ4 = 128 * _PX8, 16 * _PX8, 16 * _PX8, 8 * _PX8
+SURROGATE_BYTES = {
+    "k_first<64, false, true>": _ST + _A64 + _MASK,
+    "k_conv<64, 64, 0>": _A64 + _A64 + _MASK,
+    "k_conv<64, 32, 1>": _A64 + _ST + _ST,
+    "k_conv<64, 64, 2>": _A64 + _MASK + _A64,
+    "k_last_dgrad<64>": _DZ4 + _MASK + _A64,
+    "k_conv_dw_strip<64>": _A64 + _A64 + 256 * 9 * 64 * 64 * 4,
+    "k_last_dw<64>": _A64 + _DZ4 + 512 * 9 * 64 * 4 * 4,
+    "k_first_dw<64>": _ST + _A64 + 512 * 37 * 64 * 4,
+}
+
+
 def mfma_md(stats_csv: str, counters_csv: str, command: str, xcds: int = 8, simds: int = 1024) -> str:
     """Per-kernel TF/s (kernel time from a --kernel-trace --stats run) and MFMA busy fraction
     (SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / xcds x simds): the counter of GPU-active clocks
@@ -159,6 +176,13 @@ def mfma_md(stats_csv: str, counters_csv: str, command: str, xcds: int = 8, simd
         if busy.get(k) and active.get(k):
             mb = f"{statistics.mean(busy[k]) / (statistics.mean(active[k]) / xcds * simds):.2f}"
         lines.append(f"| `{k}` | {calls} | {us:.2f} | {flop / 1e9:.2f} | {tf:.0f} | {unit} | {tf / peak:.3f} | {mb} |")
+    lines += ["", "The training kernels against HBM (algorithmic bytes: each tensor once, halo re-reads not counted):", "",
+              "| kernel | MB per launch | GB/s | fraction of 8 TB/s |", "|---|---|---|---|"]
+    for k, nbytes in SURROGATE_BYTES.items():
+        if k not in times:
+            continue
+        gbs = nbytes / times[k][1] / 1e3
+        lines.append(f"| `{k}` | {nbytes / 1e6:.1f} | {gbs:.0f} | {gbs / 8000:.3f} |")
     return "\n".join(lines) + "\n"
 
 
