@@ -4,8 +4,9 @@
  * periodic boxes to the state K lattice steps later, as state + alpha * network(state) with a
  * fixed per-channel output scale alpha.  The density carries the pressure field, without which
  * the velocity K steps on is not determined by the state.  The first layer runs in FP32 on the
- * matrix cores; the others run on them in BF16 (BF16 activations and weights, FP32
- * accumulation); master parameters,
+ * matrix cores (its weight gradient on the BF16 ones with every FP32 state value split exactly
+ * into three BF16 parts, so that the products stay exact and the sums FP32); the others run on
+ * them in BF16 (BF16 activations and weights, FP32 accumulation); master parameters,
  * gradients and the Adam moments are FP32.  This is not part of the paper's method: it is
  * trained on trajectories of the method and checked against it (see lbcm_step).
  *
