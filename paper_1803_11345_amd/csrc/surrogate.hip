@@ -1394,8 +1394,9 @@ __global__ __launch_bounds__(kThreads) void k_conv_dw(const __bf16 *__restrict__
     }
 }
 
-// Weight gradient of a layer with 64 input channels, all 9 taps in one pass: partial[g][t][ci][co]
-// = sum over the pixels p of work unit g of X[p + d_t][ci] dZ[p][co].  A work unit is a run of
+// Weight gradient of a layer with 64 input channels (the 64 -> 64 layers; the last layer has
+// k_last_dw), all 9 taps in one pass: partial[g][t][ci][co] = sum over the pixels p of work unit
+// g of X[p + d_t][ci] dZ[p][co].  A work unit is a run of
 // rows of one 32-column strip of one sample, walked row by row.  The pixels are the K dimension
 // of the MFMAs while the activations are channel-packed (NHWC); the rows are staged in LDS as they
 // are (34 pixels of X from column sx - 1, 32 of dZ, 16-byte copies) and the operands are read
