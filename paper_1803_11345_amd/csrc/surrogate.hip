@@ -566,6 +566,32 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
             for (int ks = 0; ks < KS; ++ks)
                 f[dxi][ks] = ld8(patch + ((RW * mg + py) * kPatchW + 16 * half + r + dxi) * PS + 32 * ks + 8 * q);
     };
+    // global loads of the epilogue, requested before the MFMAs so that their latency hides behind
+    // them (clamped pixels, every lane): MODE 2 the ReLU mask bytes of this lane's outputs, MODE 1
+    // and 3 the residual state of its pixels (used by the q = 0 lanes of the first channel group)
+    uint32_t mv[GPW][RW][HPW];
+    f32x4 rsv[RW][HPW];
+    if constexpr (MODE == 1 || MODE == 3) {
+#pragma unroll
+        for (int rho = 0; rho < RW; ++rho)
+#pragma unroll
+            for (int h = 0; h < HPW; ++h) {
+                const int yy = min(tc.y0 + RW * mg + rho, H - 1), xx = min(tc.x0 + 16 * (half0 + h) + r, W - 1);
+                rsv[rho][h] = *(const f32x4 *)(o.resid + (((size_t)tc.n * H + yy) * W + xx) * kStateC);
+            }
+    }
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int g = 0; g < GPW; ++g)
+#pragma unroll
+            for (int rho = 0; rho < RW; ++rho)
+#pragma unroll
+                for (int h = 0; h < HPW; ++h) {
+                    const int yy = min(tc.y0 + RW * mg + rho, H - 1), xx = min(tc.x0 + 16 * (half0 + h) + r, W - 1);
+                    const size_t p = ((size_t)tc.n * H + yy) * W + xx;
+                    mv[g][rho][h] = o.mask[p * (COUT / 4) + (cbase + 16 * g + 4 * q) / 4];
+                }
+    }
     if (NB == 2) load_stage(0, fr[0]);
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
@@ -600,19 +626,6 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
         const int rows = min(kTileH, H - tc.y0);
         const size_t tile_px = ((size_t)tc.n * H + tc.y0) * W;
         const rsrc_t ry = make_rsrc(o.Y + tile_px * COUT, (uint32_t)rows * W * COUT * sizeof(__bf16));
-        uint32_t mv[GPW][RW][HPW];
-        if (MODE == 2) {
-#pragma unroll
-            for (int g = 0; g < GPW; ++g)
-#pragma unroll
-                for (int rho = 0; rho < RW; ++rho)
-#pragma unroll
-                    for (int h = 0; h < HPW; ++h) {
-                        const int yy = min(tc.y0 + RW * mg + rho, H - 1), xx = min(tc.x0 + 16 * (half0 + h) + r, W - 1);
-                        const size_t p = ((size_t)tc.n * H + yy) * W + xx;
-                        mv[g][rho][h] = o.mask[p * (COUT / 4) + (cbase + 16 * g + 4 * q) / 4];
-                    }
-        }
 #pragma unroll
         for (int g = 0; g < GPW; ++g)
 #pragma unroll
@@ -652,7 +665,7 @@ __device__ __forceinline__ void conv_tile(const __bf16 *patch, const bf16x8 (&wa
                     const f32x4 &a = acc[g][rho][h];
                     if (c0 == 0) {  // the 4 state channels are those of the q = 0 lanes of the first channel group
                         static_assert(kStateC == 4, "one lane holds the four state channels of a pixel");
-                        const f32x4 rs = *(const f32x4 *)(o.resid + p * kStateC);
+                        const f32x4 rs = rsv[rho][h];
                         f32x4 v;
                         v[0] = rs[0] + o.alpha0 * (a[0] + bias[g][0]);
                         v[1] = rs[1] + o.alpha1 * (a[1] + bias[g][1]);
