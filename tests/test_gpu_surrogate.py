@@ -285,17 +285,18 @@ def test_gradients_are_deterministic(B, H, W, C, L):
     assert np.abs(runs[0][0]).max() > 0
 
 
-def test_batched_pass_equals_single_sample_passes():
+@pytest.mark.parametrize("B,H,W", [(32, 64, 96), (8, 256, 256)])
+def test_batched_pass_equals_single_sample_passes(B, H, W):
     """A batch large enough that every kernel's workgroups take several tiles in turn (32 samples
-    of 64 x 96: 768 tiles against grids of 256 and 512), against the same samples one at a time
-    (one tile per workgroup): the forward outputs are equal bit for bit, and the batch's weight
-    and bias gradients equal the mean of the single-sample ones up to FP32 summation order (the
-    batch of 32 scales each sample's output gradient by exactly 2^-5, so every BF16 rounding on the
-    way scales with it)."""
+    of 64 x 96: 768 tiles; 8 of 256 x 256, the training batch: 2048 tiles; grids of 256 to 1024),
+    against the same samples one at a time: the forward outputs are equal bit for bit, and the
+    batch's weight and bias gradients equal the mean of the single-sample ones up to FP32 summation
+    order (a batch of 2^k scales each sample's output gradient by exactly 2^-k, so every BF16
+    rounding on the way scales with it)."""
     import torch
 
-    _note("batched vs single-sample passes")
-    B, H, W, C, L = 32, 64, 96, 64, 6
+    _note(f"batched vs single-sample passes B={B} H={H} W={W}")
+    C, L = 64, 6
     p = _params(C, L, seed=51)
     s = _state(B, H, W, seed=52)
     tgt = (s + _state(B, H, W, seed=53, amp=0.3)).astype(np.float32)
